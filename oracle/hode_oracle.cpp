@@ -1,0 +1,433 @@
+// Plain FP64 CPU oracle for explicit Runge-Kutta time stepping.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+// baseline leg of the benchmark may load this library.  It shares no source
+// with the HIP path: tableaux, right-hand sides, the error norm and the step
+// controller are written out here on their own.
+//
+// What it follows (Ahnert et al. 2011 / the paper's "Architecture and
+// nomenclature of Boost Odeint" section): a *state* is advanced in place by a
+// *stepper* that calls a *System* right-hand side once per stage; stages are
+// combined by an *Algebra* (linear combinations of states); adaptive steppers
+// bound the error with the L-infinity norm of the embedded error estimate.
+//
+//  * Steppers: classical Runge-Kutta 4 and Runge-Kutta-Dopri 5 (the paper's
+//    Table 1, fixed and dynamic step size).  Tableaux: Kutta 1901 and
+//    Dormand & Prince 1980 (Hairer, Norsett & Wanner, Solving ODEs I, Table
+//    II.5.2).  Dopri 5 is first-same-as-last: k7 of an accepted step is k1 of
+//    the next.
+//  * Systems: exponential dx/dt = x and sigmoidal (logistic) dx/dt = x(1-x),
+//    the two families of the accuracy benchmark read as autonomous ODEs whose
+//    solutions are x0 e^t and the logistic curve; and the 3D Gray-Scott
+//    reaction-diffusion system of the scalability benchmark (equation of the
+//    Gray-Scott model), with the Laplacian discretised by the periodic
+//    7-point finite-difference stencil of spacing h = L/N.  The second
+//    Gray-Scott equation is taken as +u v^2 - (F+k) v (the System listing).
+//  * Error norm: max_i |e_i| / (atol + rtol max(|y_i|, |ynew_i|)).
+//  * Controller (the paper gives none): Gustafsson's PI controller
+//    (Hairer & Wanner, Solving ODEs II, section IV.2) with alpha = 0.7/5,
+//    beta = 0.4/5, safety 0.9, factor clamp [0.2, 5], no growth right after a
+//    reject, error floor 1e-10, err_prev starting at 1.  The I variant sets
+//    alpha = 1/5, beta = 0.
+//
+// Serial loops define the semantics.  The OpenMP pragmas only parallelise
+// loops whose iterations are independent (and a max reduction, which is
+// order-independent), so serial and threaded runs are bitwise identical.
+// Build with -O2 -ffp-contract=off so no FMA contraction changes rounding.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+extern "C" {
+
+enum { ORC_EXP = 1, ORC_LOGISTIC = 2, ORC_GRAYSCOTT = 3 };
+enum { ORC_RK4 = 1, ORC_DOPRI5 = 2 };
+enum { ORC_CTRL_PI = 1, ORC_CTRL_I = 2 };
+enum {
+  ORC_OK = 0,
+  ORC_EINVAL = -1,
+  ORC_EDT_UNDERFLOW = -5,
+  ORC_EMAXSTEPS = -6,
+  ORC_ENONFINITE = -7,
+};
+
+struct orc_system {
+  int32_t kind;
+  int32_t pad;
+  int64_t n;   // number of state elements (for Gray-Scott: 2 N^3)
+  int64_t N;   // Gray-Scott grid edge
+  double Du, Dv, F, k, L;
+};
+
+struct orc_stats {
+  int64_t accepted, rejected, rhs_evals;
+  double t, dt_next, last_err;
+  int32_t status;
+  int32_t pad;
+};
+
+}  // extern "C"
+
+namespace {
+
+// ---- Butcher tableaux -------------------------------------------------------
+
+// Classical RK4.
+const double RK4_C[4] = {0.0, 1.0 / 2.0, 1.0 / 2.0, 1.0};
+const double RK4_A[4][4] = {
+    {0, 0, 0, 0},
+    {1.0 / 2.0, 0, 0, 0},
+    {0, 1.0 / 2.0, 0, 0},
+    {0, 0, 1.0, 0},
+};
+const double RK4_B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+
+// Dormand-Prince 5(4), 7 stages, FSAL.
+const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
+const double DP_A[7][7] = {
+    {0, 0, 0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0, 0},
+    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0, 0},
+    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0, 0},
+    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0, 0},
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0},
+};
+// 5th-order weights (equal to the last row of A) and 4th-order embedded weights.
+const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
+const double DP_BHAT[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
+                           -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
+
+// ---- the System: right-hand sides -----------------------------------------
+
+inline int64_t wrap(int64_t i, int64_t N) { return ((i % N) + N) % N; }
+
+// Gray-Scott on an N^3 periodic grid, x fastest, u in [0, N^3), v in [N^3, 2N^3).
+void gs_rhs(const orc_system& s, const double* y, double* f) {
+  const int64_t N = s.N, n3 = N * N * N;
+  const double h = s.L / (double)N;
+  const double h2 = h * h;
+  const double* u = y;
+  const double* v = y + n3;
+  double* du = f;
+  double* dv = f + n3;
+#pragma omp parallel for schedule(static)
+  for (int64_t kz = 0; kz < N; ++kz) {
+    for (int64_t jy = 0; jy < N; ++jy) {
+      for (int64_t ix = 0; ix < N; ++ix) {
+        const int64_t c = ix + N * (jy + N * kz);
+        const int64_t xm = wrap(ix - 1, N) + N * (jy + N * kz);
+        const int64_t xp = wrap(ix + 1, N) + N * (jy + N * kz);
+        const int64_t ym = ix + N * (wrap(jy - 1, N) + N * kz);
+        const int64_t yp = ix + N * (wrap(jy + 1, N) + N * kz);
+        const int64_t zm = ix + N * (jy + N * wrap(kz - 1, N));
+        const int64_t zp = ix + N * (jy + N * wrap(kz + 1, N));
+        const double lap_u = (u[xm] + u[xp] + u[ym] + u[yp] + u[zm] + u[zp] - 6.0 * u[c]) / h2;
+        const double lap_v = (v[xm] + v[xp] + v[ym] + v[yp] + v[zm] + v[zp] - 6.0 * v[c]) / h2;
+        const double uvv = u[c] * v[c] * v[c];
+        du[c] = s.Du * lap_u - uvv + s.F * (1.0 - u[c]);
+        dv[c] = s.Dv * lap_v + uvv - (s.F + s.k) * v[c];
+      }
+    }
+  }
+}
+
+void rhs(const orc_system& s, const double* y, double* f) {
+  const int64_t n = s.n;
+  switch (s.kind) {
+    case ORC_EXP:
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < n; ++i) f[i] = y[i];
+      break;
+    case ORC_LOGISTIC:
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < n; ++i) f[i] = y[i] * (1.0 - y[i]);
+      break;
+    default:
+      gs_rhs(s, y, f);
+      break;
+  }
+}
+
+bool valid(const orc_system* s) {
+  if (!s) return false;
+  if (s->kind == ORC_EXP || s->kind == ORC_LOGISTIC) return s->n >= 0;
+  if (s->kind == ORC_GRAYSCOTT) return s->N >= 1 && s->n == 2 * s->N * s->N * s->N && s->L > 0;
+  return false;
+}
+
+// ---- the Algebra: w = y + h * sum_j a_j k_j --------------------------------
+
+void stage_input(int64_t n, const double* y, double h, int nk, const double* a, double* const* k, double* w) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < nk; ++j)
+      if (a[j] != 0.0) s += a[j] * k[j][i];
+    w[i] = y[i] + h * s;
+  }
+}
+
+// ---- the L-infinity error norm ----------------------------------------------
+
+double err_norm(int64_t n, const double* y, const double* ynew, const double* e, double atol, double rtol) {
+  double m = 0.0;
+  bool nan = false;
+#pragma omp parallel for schedule(static) reduction(max : m) reduction(|| : nan)
+  for (int64_t i = 0; i < n; ++i) {
+    const double sc = atol + rtol * std::max(std::fabs(y[i]), std::fabs(ynew[i]));
+    const double r = std::fabs(e[i]) / sc;
+    if (std::isnan(r)) nan = true;
+    else m = std::max(m, r);
+  }
+  return nan ? NAN : m;
+}
+
+// ---- steppers -----------------------------------------------------------------
+
+struct Work {
+  std::vector<std::vector<double>> k;
+  std::vector<double> w;
+  explicit Work(int64_t n, int nk) : k(nk, std::vector<double>(n)), w(n) {}
+};
+
+// One classical RK4 step in place.
+void rk4_step(const orc_system& s, double* y, double h, Work& W) {
+  const int64_t n = s.n;
+  double* kp[4] = {W.k[0].data(), W.k[1].data(), W.k[2].data(), W.k[3].data()};
+  rhs(s, y, kp[0]);
+  for (int st = 1; st < 4; ++st) {
+    stage_input(n, y, h, st, RK4_A[st], kp, W.w.data());
+    rhs(s, W.w.data(), kp[st]);
+  }
+  stage_input(n, y, h, 4, RK4_B, kp, W.w.data());
+  std::memcpy(y, W.w.data(), sizeof(double) * n);
+}
+
+// One Dopri5 attempt from (y, k1): writes ynew, k7 = f(ynew) and (if e != null)
+// the embedded error e = h * sum_j (b_j - bhat_j) k_j.
+void dopri5_attempt(const orc_system& s, const double* y, const double* k1, double h, double* ynew, double* k7,
+                    double* e, Work& W) {
+  const int64_t n = s.n;
+  double* kp[7];
+  for (int j = 0; j < 7; ++j) kp[j] = W.k[j].data();
+  std::memcpy(kp[0], k1, sizeof(double) * n);
+  for (int st = 1; st < 6; ++st) {
+    stage_input(n, y, h, st, DP_A[st], kp, W.w.data());
+    rhs(s, W.w.data(), kp[st]);
+  }
+  stage_input(n, y, h, 6, DP_A[6], kp, ynew);  // stage-7 input is the 5th-order solution
+  rhs(s, ynew, kp[6]);
+  std::memcpy(k7, kp[6], sizeof(double) * n);
+  if (e) {
+    double d[7];
+    for (int j = 0; j < 7; ++j) d[j] = DP_B[j] - DP_BHAT[j];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < 7; ++j)
+        if (d[j] != 0.0) acc += d[j] * kp[j][i];
+      e[i] = h * acc;
+    }
+  }
+}
+
+// ---- step-size controller -------------------------------------------------------
+
+struct Ctrl {
+  double alpha, beta, safety = 0.9, fac_min = 0.2, fac_max = 5.0;
+  double err_prev = 1.0;
+  bool last_rejected = false;
+  explicit Ctrl(int kind) {
+    if (kind == ORC_CTRL_I) { alpha = 1.0 / 5.0; beta = 0.0; }
+    else { alpha = 0.7 / 5.0; beta = 0.4 / 5.0; }
+  }
+  // Returns whether the attempt is accepted and the factor for the next step.
+  bool decide(double err, double* fac) {
+    if (err <= 1.0) {
+      const double e = std::max(err, 1e-10);
+      double f = safety * std::pow(e, -alpha) * std::pow(err_prev, beta);
+      f = std::min(fac_max, std::max(fac_min, f));
+      if (last_rejected) f = std::min(f, 1.0);
+      err_prev = e;
+      last_rejected = false;
+      *fac = f;
+      return true;
+    }
+    *fac = std::isnan(err) ? fac_min : std::max(fac_min, safety * std::pow(err, -1.0 / 5.0));
+    last_rejected = true;
+    return false;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int orc_rhs(const orc_system* s, const double* y, double* f) {
+  if (!valid(s)) return ORC_EINVAL;
+  rhs(*s, y, f);
+  return ORC_OK;
+}
+
+void orc_tableau(int method, double* a, double* b, double* bhat, double* c) {
+  if (method == ORC_RK4) {
+    for (int i = 0; i < 4; ++i) {
+      for (int j = 0; j < 4; ++j) a[i * 4 + j] = RK4_A[i][j];
+      b[i] = RK4_B[i];
+      c[i] = RK4_C[i];
+      if (bhat) bhat[i] = 0.0;
+    }
+  } else {
+    for (int i = 0; i < 7; ++i) {
+      for (int j = 0; j < 7; ++j) a[i * 7 + j] = DP_A[i][j];
+      b[i] = DP_B[i];
+      bhat[i] = DP_BHAT[i];
+      c[i] = DP_C[i];
+    }
+  }
+}
+
+double orc_err_norm(int64_t n, const double* y, const double* ynew, const double* e, double atol, double rtol) {
+  return err_norm(n, y, ynew, e, atol, rtol);
+}
+
+// One controller decision: returns 1 if accepted; writes the step factor and the
+// updated (err_prev, last_rejected).
+int orc_ctrl_decide(int kind, double err, double* err_prev, int* last_rejected, double* fac) {
+  Ctrl c(kind);
+  c.err_prev = *err_prev;
+  c.last_rejected = *last_rejected != 0;
+  const bool acc = c.decide(err, fac);
+  *err_prev = c.err_prev;
+  *last_rejected = c.last_rejected ? 1 : 0;
+  return acc ? 1 : 0;
+}
+
+int orc_rk4_step(const orc_system* s, double* y, double h) {
+  if (!valid(s)) return ORC_EINVAL;
+  Work W(s->n, 4);
+  rk4_step(*s, y, h, W);
+  return ORC_OK;
+}
+
+// One Dopri5 attempt from y (k1 computed here).  ynew, k7 and e are outputs.
+int orc_dopri5_attempt(const orc_system* s, const double* y, double h, double* ynew, double* k7, double* e) {
+  if (!valid(s)) return ORC_EINVAL;
+  Work W(s->n, 7);
+  std::vector<double> k1(s->n);
+  rhs(*s, y, k1.data());
+  dopri5_attempt(*s, y, k1.data(), h, ynew, k7, e, W);
+  return ORC_OK;
+}
+
+// Fixed steps: t_n = t0 + n dt (Odeint integrate_const / do_step).
+int orc_integrate_n_steps(const orc_system* s, int method, double* y, double t0, double dt, int64_t nsteps,
+                          double* t_end) {
+  if (!valid(s) || nsteps < 0 || !(method == ORC_RK4 || method == ORC_DOPRI5)) return ORC_EINVAL;
+  const int64_t n = s->n;
+  if (method == ORC_RK4) {
+    Work W(n, 4);
+    for (int64_t i = 0; i < nsteps; ++i) rk4_step(*s, y, dt, W);
+  } else {
+    Work W(n, 7);
+    std::vector<double> k1(n), k7(n), ynew(n);
+    rhs(*s, y, k1.data());
+    for (int64_t i = 0; i < nsteps; ++i) {
+      dopri5_attempt(*s, y, k1.data(), dt, ynew.data(), k7.data(), nullptr, W);
+      std::swap_ranges(ynew.begin(), ynew.end(), y);
+      k1.swap(k7);
+    }
+  }
+  if (t_end) *t_end = t0 + (double)nsteps * dt;
+  return ORC_OK;
+}
+
+// Error-controlled Dopri5 from t0 to t1 (Odeint integrate_adaptive).  The trace,
+// if given, receives 4 doubles per attempt: h, err, accepted (0/1), t after.
+int orc_integrate_adaptive(const orc_system* s, double* y, double t0, double t1, double dt0, double atol,
+                           double rtol, int ctrl_kind, int64_t max_steps, orc_stats* st, double* trace,
+                           int64_t trace_cap) {
+  if (!valid(s) || !(t1 >= t0) || !(dt0 > 0) || !(atol >= 0) || !(rtol >= 0) || (atol == 0 && rtol == 0))
+    return ORC_EINVAL;
+  const int64_t n = s->n;
+  Work W(n, 7);
+  std::vector<double> k1(n), k7(n), ynew(n), e(n);
+  rhs(*s, y, k1.data());
+  Ctrl c(ctrl_kind);
+  double t = t0, dt = dt0, last_err = 0.0;
+  int64_t acc = 0, rej = 0, evals = 1, att = 0;
+  int status = ORC_OK;
+  while (t < t1) {
+    if (att >= max_steps) { status = ORC_EMAXSTEPS; break; }
+    const bool last = dt >= t1 - t;
+    const double h = last ? t1 - t : dt;
+    if (h < 1e-12 * std::max(1.0, std::fabs(t))) {
+      status = std::isfinite(last_err) ? ORC_EDT_UNDERFLOW : ORC_ENONFINITE;
+      break;
+    }
+    dopri5_attempt(*s, y, k1.data(), h, ynew.data(), k7.data(), e.data(), W);
+    evals += 6;
+    ++att;
+    const double err = err_norm(n, y, ynew.data(), e.data(), atol, rtol);
+    last_err = err;
+    double fac;
+    const bool ok = c.decide(err, &fac);
+    if (ok) {
+      std::swap_ranges(ynew.begin(), ynew.end(), y);
+      k1.swap(k7);
+      t = last ? t1 : t + h;
+      ++acc;
+    } else {
+      ++rej;
+    }
+    dt = h * fac;
+    if (trace && att <= trace_cap) {
+      double* r = trace + 4 * (att - 1);
+      r[0] = h; r[1] = err; r[2] = ok ? 1.0 : 0.0; r[3] = t;
+    }
+  }
+  if (st) {
+    st->accepted = acc; st->rejected = rej; st->rhs_evals = evals;
+    st->t = t; st->dt_next = dt; st->last_err = last_err; st->status = status;
+  }
+  return status;
+}
+
+// Replays a recorded step sequence: attempt i uses step h[i] and is accepted iff
+// accepted[i] != 0 (the controller is bypassed).  errs (optional) receives the
+// error norm of every attempt.
+int orc_integrate_replay(const orc_system* s, double* y, double t0, const double* hs, const int32_t* accepted,
+                         int64_t n_att, double atol, double rtol, double* t_end, double* errs) {
+  if (!valid(s) || n_att < 0) return ORC_EINVAL;
+  const int64_t n = s->n;
+  Work W(n, 7);
+  std::vector<double> k1(n), k7(n), ynew(n), e(n);
+  rhs(*s, y, k1.data());
+  double t = t0;
+  for (int64_t i = 0; i < n_att; ++i) {
+    dopri5_attempt(*s, y, k1.data(), hs[i], ynew.data(), k7.data(), e.data(), W);
+    if (errs) errs[i] = err_norm(n, y, ynew.data(), e.data(), atol, rtol);
+    if (accepted[i]) {
+      std::swap_ranges(ynew.begin(), ynew.end(), y);
+      k1.swap(k7);
+      t += hs[i];
+    }
+  }
+  if (t_end) *t_end = t;
+  return ORC_OK;
+}
+
+int orc_num_threads(void);
+
+}  // extern "C"
+
+#ifdef _OPENMP
+#include <omp.h>
+extern "C" int orc_num_threads(void) { return omp_get_max_threads(); }
+#else
+extern "C" int orc_num_threads(void) { return 1; }
+#endif

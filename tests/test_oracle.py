@@ -1,0 +1,443 @@
+"""Pins for the FP64 CPU oracle, checked against what the mathematics fixes.
+
+Each test names what it pins: exact-rational order conditions of the tableaux,
+closed-form one-step amplification of the linear test equation, convergence
+order under step halving (the paper's accuracy benchmark: every fixed-step
+method reaches its expected order down to round-off), closed-form solutions of
+the exponential and logistic families, the Fourier eigenvalues of the periodic
+7-point Laplacian, conservation and reduction invariants of Gray-Scott, brute
+force on tiny grids, and textbook controller behaviour.
+"""
+import json
+import math
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+from paper_2309_05331_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- tableaux
+
+def _rational(M):
+    return [[Fr(x).limit_denominator(10 ** 7) for x in row] for row in M]
+
+
+def _check_rounding(x, q):
+    # the stored double must be the correctly rounded value of the rational
+    assert abs(Fr(float(x)) - q) <= Fr(math.ulp(float(x))) / 2
+
+
+def _elementary_weights(A, b, c):
+    s = len(b)
+
+    def Av(v):
+        return [sum(A[i][j] * v[j] for j in range(s)) for i in range(s)]
+
+    def mul(*vs):
+        out = [Fr(1)] * s
+        for v in vs:
+            out = [o * x for o, x in zip(out, v)]
+        return out
+
+    one = [Fr(1)] * s
+    env = {"A": Av, "c": c}
+    conds = json.load(open(os.path.join(GOLDEN, "rk_order_conditions.json")))["conditions"]
+    res = []
+    for cd in conds:
+        expr = cd["expr"]
+        if expr == "1":
+            vec = one
+        else:
+            # tiny evaluator: products of factors, each factor 'c' or 'A(...)'
+            vec = _eval(expr, env, s)
+        w = sum(bi * vi for bi, vi in zip(b, vec))
+        res.append((cd["order"], w, Fr(1, cd["gamma"])))
+    return res
+
+
+def _eval(expr, env, s):
+    # split top-level '*' factors
+    depth, parts, cur = 0, [], ""
+    for ch in expr:
+        if ch == "(":
+            depth += 1
+        elif ch == ")":
+            depth -= 1
+        if ch == "*" and depth == 0:
+            parts.append(cur)
+            cur = ""
+        else:
+            cur += ch
+    parts.append(cur)
+    out = [Fr(1)] * s
+    for p in parts:
+        if p == "c":
+            v = env["c"]
+        else:
+            assert p.startswith("A(") and p.endswith(")")
+            v = env["A"](_eval(p[2:-1], env, s))
+        out = [o * x for o, x in zip(out, v)]
+    return out
+
+
+def test_rk4_tableau_order4(orc):
+    a, b, bh, c = orc.tableau(orc.RK4)
+    A, B, Cc = _rational(a), [Fr(x).limit_denominator(10 ** 7) for x in b], [Fr(x).limit_denominator(10 ** 7) for x in c]
+    for i in range(4):
+        assert sum(A[i]) == Cc[i]
+    for order, w, want in _elementary_weights(A, B, Cc):
+        if order <= 4:
+            assert w == want, (order, w, want)
+    # not order 5
+    assert any(w != want for order, w, want in _elementary_weights(A, B, Cc) if order == 5)
+
+
+def test_dopri5_tableau_orders(orc):
+    a, b, bh, c = orc.tableau(orc.DOPRI5)
+    A = _rational(a)
+    B = [Fr(x).limit_denominator(10 ** 7) for x in b]
+    BH = [Fr(x).limit_denominator(10 ** 7) for x in bh]
+    Cc = [Fr(x).limit_denominator(10 ** 7) for x in c]
+    for M, Mq in ((a, A), ([b], [B]), ([bh], [BH]), ([c], [Cc])):
+        for row, rowq in zip(M, Mq):
+            for x, q in zip(row, rowq):
+                _check_rounding(x, q)
+    for i in range(7):
+        assert sum(A[i]) == Cc[i], i
+    assert A[6][:6] == B[:6] and B[6] == 0 and Cc[6] == 1  # first same as last
+    for order, w, want in _elementary_weights(A, B, Cc):
+        assert w == want, ("b", order)
+    emb = _elementary_weights(A, BH, Cc)
+    for order, w, want in emb:
+        if order <= 4:
+            assert w == want, ("bhat", order)
+    assert any(w != want for order, w, want in emb if order == 5)
+
+
+# ------------------------------------------------- linear test equation
+
+@pytest.mark.parametrize("h", [0.05, 0.3, 1.1, -2.0])
+def test_rk4_one_step_amplification(orc, h):
+    x0 = inputs.exp_family_x0(257, seed=11)
+    y = orc.rk4_step(orc.ew_system(orc.EXP, x0.size), x0, h)
+    R4 = 1 + h + h ** 2 / 2 + h ** 3 / 6 + h ** 4 / 24
+    mag = 1 + abs(h) + h ** 2 / 2 + abs(h) ** 3 / 6 + h ** 4 / 24  # rounding scale under cancellation
+    assert np.all(np.abs(y - R4 * x0) <= 16 * 2.0 ** -52 * mag * x0)
+
+
+@pytest.mark.parametrize("h", [0.05, 0.3, 1.1, -2.0])
+def test_dopri5_one_step_amplification_and_error(orc, h):
+    x0 = inputs.exp_family_x0(257, seed=12)
+    yn, k7, e = orc.dopri5_attempt(orc.ew_system(orc.EXP, x0.size), x0, h)
+    R5 = 1 + h + h ** 2 / 2 + h ** 3 / 6 + h ** 4 / 24 + h ** 5 / 120 + h ** 6 / 600
+    E = (-97 * h ** 5 + 39 * h ** 6 - 5 * h ** 7) / 120000
+    mag = sum(abs(h) ** j / math.factorial(j) for j in range(6)) + abs(h) ** 6 / 600
+    tol = 64 * 2.0 ** -52 * mag * x0  # rounding scale under cancellation
+    assert np.all(np.abs(yn - R5 * x0) <= tol)
+    assert np.all(np.abs(k7 - R5 * x0) <= tol)  # f(x) = x
+    assert np.all(np.abs(e - E * x0) <= tol)
+
+
+# -------------------------------------------------- closed forms, order
+
+def _closed(kind, x0, t):
+    if kind == 1:
+        return x0 * np.exp(t)
+    return x0 / (x0 + (1 - x0) * np.exp(-t))
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("method,order", [(1, 4), (2, 5)])
+def test_fixed_step_convergence_order(orc, kind, method, order):
+    x0 = inputs.exp_family_x0(4096, seed=2)
+    sysd = orc.ew_system(kind, x0.size)
+    exact = _closed(kind, x0, 5.0)
+    errs = []
+    for n in (20, 40, 80, 160):
+        y, te = orc.integrate_n_steps(sysd, method, x0, 0.0, 5.0 / n, n)
+        assert te == pytest.approx(5.0, abs=1e-15)
+        errs.append(np.max(np.abs(y - exact)))
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    # ratios rise towards 2**order; the last halving is within 10 percent of it
+    assert abs(ratios[-1] / 2 ** order - 1) < 0.10, (errs, ratios)
+    assert all(r > 2 ** order * 0.75 for r in ratios)
+    assert all(ratios[i] < ratios[i + 1] * 1.02 for i in range(len(ratios) - 1))
+
+
+def test_fixed_step_roundoff_floor(orc):
+    x0 = inputs.exp_family_x0(1024, seed=2)
+    sysd = orc.ew_system(orc.EXP, x0.size)
+    y, _ = orc.integrate_n_steps(sysd, orc.DOPRI5, x0, 0.0, 5.0 / 2000, 2000)
+    exact = _closed(1, x0, 5.0)
+    rel = np.max(np.abs(y - exact) / exact)
+    assert rel < 5e-13  # converged down to double round-off
+
+
+def test_logistic_fixed_points_exact(orc):
+    y0 = np.array([0.0, 1.0, 0.0, 1.0])
+    for m in (orc.RK4, orc.DOPRI5):
+        y, _ = orc.integrate_n_steps(orc.ew_system(orc.LOGISTIC, 4), m, y0, 0.0, 0.37, 50)
+        assert np.array_equal(y, y0)
+
+
+# ------------------------------------------------------ Gray-Scott RHS
+
+def _mode(N, m):
+    i = np.arange(N)
+    z, yy, x = np.meshgrid(i, i, i, indexing="ij")
+    return np.cos(2 * np.pi * (m[0] * x + m[1] * yy + m[2] * z) / N)
+
+
+@pytest.mark.parametrize("N,m", [(8, (1, 0, 0)), (8, (0, 2, 1)), (9, (1, 3, 4)), (5, (2, 2, 2)), (4, (2, 0, 0))])
+def test_gs_laplacian_fourier_eigen(orc, N, m):
+    L = 2.5
+    h = L / N
+    lam = -(4 / h ** 2) * sum(math.sin(math.pi * md / N) ** 2 for md in m)
+    w = _mode(N, m)
+    zero = np.zeros_like(w)
+    sysd = orc.gs_system(N, Du=0.7, Dv=0.3, F=0.0, k=0.0, L=L)
+    f = orc.rhs(sysd, np.stack([w, zero])).reshape(2, N, N, N)
+    np.testing.assert_allclose(f[0], 0.7 * lam * w, atol=1e-11 * abs(lam))
+    assert np.all(f[1] == 0)
+    f = orc.rhs(sysd, np.stack([zero, w])).reshape(2, N, N, N)
+    np.testing.assert_allclose(f[1], 0.3 * lam * w, atol=1e-11 * abs(lam))
+    assert np.all(f[0] == 0)
+
+
+def test_gs_pure_diffusion_rk4_matches_amplification(orc):
+    N, L, D, dt, n = 8, 2.5, 1e-3, 0.5, 40
+    m = (1, 2, 0)
+    h = L / N
+    lam = -(4 / h ** 2) * sum(math.sin(math.pi * md / N) ** 2 for md in m)
+    w = _mode(N, m)
+    sysd = orc.gs_system(N, Du=D, Dv=D, F=0.0, k=0.0, L=L)
+    y, _ = orc.integrate_n_steps(sysd, orc.RK4, np.stack([w, 0 * w]), 0.0, dt, n)
+    z = dt * D * lam
+    R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    np.testing.assert_allclose(y[: N ** 3].reshape(N, N, N), R ** n * w, atol=1e-12)
+
+
+def _gs_rhs_roll(y, N, Du, Dv, F, k, L):
+    # brute force with numpy.roll over the [z, y, x] axes
+    u, v = y.reshape(2, N, N, N)
+    h2 = (L / N) ** 2
+
+    def lap(w):
+        s = sum(np.roll(w, sh, axis=ax) for ax in range(3) for sh in (1, -1))
+        return (s - 6 * w) / h2
+
+    uvv = u * v * v
+    return np.stack([Du * lap(u) - uvv + F * (1 - u), Dv * lap(v) + uvv - (F + k) * v]).ravel()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 8])
+def test_gs_rhs_brute_force_tiny(orc, N):
+    y = inputs.gray_scott_ic(N, seed=7).ravel()
+    prm = dict(Du=0.02, Dv=0.01, F=0.053, k=0.014, L=2.5)
+    f = orc.rhs(orc.gs_system(N, **prm), y)
+    np.testing.assert_allclose(f, _gs_rhs_roll(y, N, **prm), rtol=1e-13, atol=1e-13)
+
+
+def test_gs_n1_laplacian_vanishes(orc):
+    y = np.array([0.7, 0.2])
+    f = orc.rhs(orc.gs_system(1, Du=5.0, Dv=3.0, F=0.0, k=0.0, L=2.5), y)
+    uvv = 0.7 * 0.2 * 0.2
+    # every neighbour is the cell itself: the stencil cancels up to the rounding
+    # of a six-term sum
+    h2 = 2.5 ** 2
+    assert abs(f[0] + uvv) <= 8 * 2.0 ** -52 * 6 * 0.7 * 5.0 / h2
+    assert abs(f[1] - uvv) <= 8 * 2.0 ** -52 * 6 * 0.2 * 3.0 / h2
+
+
+def test_gs_mass_conservation_without_feed(orc):
+    N = 8
+    y0 = inputs.gray_scott_ic(N, seed=3).ravel()
+    sysd = orc.gs_system(N, Du=2e-3, Dv=1e-3, F=0.0, k=0.0, L=2.5)
+    y, _ = orc.integrate_n_steps(sysd, orc.RK4, y0, 0.0, 0.1, 200)
+    assert abs(y.sum() - y0.sum()) < 1e-11 * y0.sum()
+
+
+def test_gs_uniform_state_reduces_to_two_variable_ode(orc):
+    from scipy.integrate import solve_ivp
+    F, k = 0.053, 0.014
+
+    def ode(t, w):
+        u, v = w
+        return [-u * v * v + F * (1 - u), u * v * v - (F + k) * v]
+
+    ref = solve_ivp(ode, (0, 20), [0.5, 0.25], method="DOP853", rtol=1e-13, atol=1e-15).y[:, -1]
+    N = 3
+    y0 = np.concatenate([np.full(N ** 3, 0.5), np.full(N ** 3, 0.25)])
+    sysd = orc.gs_system(N, F=F, k=k)
+    errs = []
+    for n in (50, 100, 200):
+        y, _ = orc.integrate_n_steps(sysd, orc.RK4, y0, 0.0, 20.0 / n, n)
+        u, v = y.reshape(2, -1)
+        assert np.ptp(u) == 0 and np.ptp(v) == 0  # stays uniform exactly
+        errs.append(max(abs(u[0] - ref[0]), abs(v[0] - ref[1])))
+    assert errs[-1] < 1e-8
+    assert errs[0] / errs[1] > 12 and errs[1] / errs[2] > 12  # order 4
+
+
+def test_gs_no_diffusion_is_pointwise(orc):
+    N = 4
+    y0 = inputs.gray_scott_ic(N, seed=9).ravel()
+    sysd = orc.gs_system(N, Du=0.0, Dv=0.0)
+    y, _ = orc.integrate_n_steps(sysd, orc.DOPRI5, y0, 0.0, 0.25, 40)
+    n3 = N ** 3
+    for c in (0, 5, 17, 63):
+        yc, _ = orc.integrate_n_steps(orc.gs_system(1, Du=0.0, Dv=0.0), orc.DOPRI5,
+                                      np.array([y0[c], y0[n3 + c]]), 0.0, 0.25, 40)
+        assert yc[0] == y[c] and yc[1] == y[n3 + c]
+
+
+def test_gs_shift_equivariance_bitwise(orc):
+    N = 6
+    y0 = inputs.gray_scott_ic(N, seed=5).reshape(2, N, N, N)
+    sysd = orc.gs_system(N, Du=2e-3, Dv=1e-3)
+    a, _ = orc.integrate_n_steps(sysd, orc.RK4, y0, 0.0, 0.2, 20)
+    sh = np.roll(y0, (1, -2, 3), axis=(1, 2, 3))
+    b, _ = orc.integrate_n_steps(sysd, orc.RK4, sh, 0.0, 0.2, 20)
+    assert np.array_equal(np.roll(a.reshape(2, N, N, N), (1, -2, 3), axis=(1, 2, 3)), b.reshape(2, N, N, N))
+
+
+# ------------------------------------------------------- error norm
+
+def test_err_norm_definition_and_nan(orc):
+    y = np.array([1.0, -2.0, 0.0, 3.0])
+    yn = np.array([1.5, -1.0, 0.0, 2.0])
+    e = np.array([1e-7, -4e-6, 1e-9, 0.0])
+    atol, rtol = 1e-6, 1e-3
+    want = max(1e-7 / (atol + rtol * 1.5), 4e-6 / (atol + rtol * 2.0), 1e-9 / atol, 0.0)
+    assert orc.err_norm(y, yn, e, atol, rtol) == want
+    e2 = e.copy()
+    e2[2] = np.nan
+    assert math.isnan(orc.err_norm(y, yn, e2, atol, rtol))
+    e3 = e.copy()
+    e3[1] = np.inf
+    assert orc.err_norm(y, yn, e3, atol, rtol) == math.inf
+
+
+# -------------------------------------------------------- controller
+
+def test_controller_i_exact_values(orc):
+    # I controller: factor 0.9 * err^(-1/5); err = 2^-5 gives exactly 1.8
+    acc, fac, ep, lr = orc.ctrl_decide(orc.CTRL_I, 2.0 ** -5, 1.0, False)
+    assert acc and fac == pytest.approx(1.8, rel=1e-15) and ep == 2.0 ** -5 and not lr
+    # reject with err = 32: factor 0.9 / 2 = 0.45
+    acc, fac, ep, lr = orc.ctrl_decide(orc.CTRL_I, 32.0, 0.5, False)
+    assert not acc and fac == pytest.approx(0.45, rel=1e-15) and ep == 0.5 and lr
+
+
+def test_controller_pi_values_and_limits(orc):
+    # PI with err_prev = 1: 0.9 * (2^-5)^(-0.14) = 0.9 * 2^0.7 = 1.46205431344...
+    acc, fac, _, _ = orc.ctrl_decide(orc.CTRL_PI, 2.0 ** -5, 1.0, False)
+    assert acc and fac == pytest.approx(1.4620543134412239, rel=1e-14)
+    # previous error 2^-5 damps the growth: times (2^-5)^0.08 = 2^-0.4
+    _, fac2, _, _ = orc.ctrl_decide(orc.CTRL_PI, 2.0 ** -5, 2.0 ** -5, False)
+    assert fac2 == pytest.approx(1.4620543134412239 * 2 ** -0.4, rel=1e-14)
+    # accept at exactly 1, reject just above
+    assert orc.ctrl_decide(orc.CTRL_PI, 1.0, 1.0, False)[0]
+    assert not orc.ctrl_decide(orc.CTRL_PI, 1.0 + 2e-16, 1.0, False)[0]
+    # growth clamp at 5, shrink clamp at 0.2, NaN -> 0.2, no growth after a reject
+    assert orc.ctrl_decide(orc.CTRL_PI, 0.0, 1.0, False)[1] == 5.0
+    assert orc.ctrl_decide(orc.CTRL_PI, 1e9, 1.0, False)[1] == 0.2
+    acc, fac, ep, lr = orc.ctrl_decide(orc.CTRL_PI, float("nan"), 0.3, False)
+    assert not acc and fac == 0.2 and ep == 0.3 and lr
+    acc, fac, _, lr = orc.ctrl_decide(orc.CTRL_PI, 1e-6, 1.0, True)
+    assert acc and fac == 1.0 and not lr
+
+
+# ------------------------------------------------------------ adaptive
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_adaptive_dopri5_accuracy_and_landing(orc, kind):
+    x0 = inputs.exp_family_x0(4096, seed=2)
+    sysd = orc.ew_system(kind, x0.size)
+    exact = _closed(kind, x0, 5.0)
+    prev = None
+    for tol in (1e-4, 1e-6, 1e-8):
+        y, st, tr = orc.integrate_adaptive(sysd, x0, 0.0, 5.0, 0.01, tol, tol, trace_cap=10000)
+        assert st["status"] == 0 and st["t"] == 5.0
+        acc = tr[tr[:, 2] == 1]
+        assert np.all(acc[:, 1] <= 1.0) and np.all(tr[tr[:, 2] == 0][:, 1] > 1.0)
+        assert abs(acc[:, 0].sum() - 5.0) < 1e-13
+        err = np.max(np.abs(y - exact) / (1 + np.abs(exact)))
+        assert err < 30 * tol
+        if prev is not None:
+            assert err < prev
+        prev = err
+        assert st["rhs_evals"] == 1 + 6 * (st["accepted"] + st["rejected"])
+
+
+@pytest.mark.parametrize("ctrl,target", [(1, 0.9 ** (1 / 0.06)), (2, 0.9 ** 5)])
+def test_adaptive_exp_steady_step_matches_error_model(orc, ctrl, target):
+    # Dopri5 on x' = x estimates |E(h)| x with E(z) = (-97 z^5 + 39 z^6 - 5 z^7)/120000.
+    # Once x >> 1 the scaled error is |E(h)| e^-h / tol.  The controller's fixed
+    # point is err = s^(1/(alpha-beta)) (PI: 0.9^(1/0.06)) or s^5 (I: 0.9^5), so the
+    # late steps must sit at the h solving |E(h)| e^-h / tol = target.
+    tol = 1e-6
+    x0 = inputs.exp_family_x0(1 << 12, seed=2)
+    y, st, tr = orc.integrate_adaptive(orc.ew_system(orc.EXP, x0.size), x0, 0.0, 5.0, 0.01, tol, tol,
+                                       ctrl=ctrl, trace_cap=1000)
+    lo, hi = 0.05, 0.5
+    for _ in range(60):
+        h = 0.5 * (lo + hi)
+        E = abs(-97 * h ** 5 + 39 * h ** 6 - 5 * h ** 7) / 120000
+        if E * math.exp(-h) / tol < target:
+            lo = h
+        else:
+            hi = h
+    late = tr[(tr[:, 3] > 3.5) & (tr[:, 3] < 4.99), 0]
+    assert late.size >= 3
+    assert np.all(np.abs(late / h - 1) < 0.03), (late, h)
+    assert st["status"] == 0 and st["rejected"] == 0
+
+
+def test_adaptive_replay_reproduces_free_run(orc):
+    N = 6
+    y0 = inputs.gray_scott_ic(N, seed=1).ravel()
+    sysd = orc.gs_system(N)
+    y, st, tr = orc.integrate_adaptive(sysd, y0, 0.0, 30.0, 0.1, 1e-6, 1e-6, trace_cap=10000)
+    yr, te, errs = orc.integrate_replay(sysd, y0, 0.0, tr[:, 0], tr[:, 2].astype(np.int32), 1e-6, 1e-6)
+    assert np.array_equal(y, yr)
+    assert np.array_equal(errs, tr[:, 1])
+    assert st["rejected"] >= 0
+
+
+def test_adaptive_failure_modes(orc):
+    x0 = inputs.exp_family_x0(64, seed=2)
+    sysd = orc.ew_system(orc.EXP, 64)
+    _, st, _ = orc.integrate_adaptive(sysd, x0, 0.0, 5.0, 0.01, 1e-6, 1e-6, max_steps=5)
+    assert st["status"] == orc.EMAXSTEPS and st["accepted"] + st["rejected"] == 5
+    bad = x0.copy()
+    bad[7] = np.nan
+    _, st, _ = orc.integrate_adaptive(sysd, bad, 0.0, 5.0, 0.01, 1e-6, 1e-6)
+    assert st["status"] == orc.ENONFINITE and st["accepted"] == 0
+    _, st, _ = orc.integrate_adaptive(sysd, x0, 0.0, 5.0, 0.01, 1e-300, 1e-300)
+    assert st["status"] == orc.EDT_UNDERFLOW and st["t"] < 5.0
+
+
+def test_parallel_and_serial_runs_identical(orc, tmp_path):
+    # the paper's process-count invariance, on the oracle: 1 thread vs many
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np, oracle; from paper_2309_05331_amd import inputs;"
+        "y0=inputs.gray_scott_ic(12,seed=3).ravel();"
+        "y,st,_=oracle.integrate_adaptive(oracle.gs_system(12),y0,0.0,20.0,0.1,1e-6,1e-6);"
+        "np.save(r'%s', y)"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = []
+    for nt in (1, 4):
+        p = tmp_path / ("y%d.npy" % nt)
+        env = dict(os.environ, OMP_NUM_THREADS=str(nt), PYTHONPATH=root)
+        subprocess.check_call([sys.executable, "-c", code % p], env=env, cwd=root)
+        outs.append(np.load(p))
+    assert np.array_equal(outs[0], outs[1])
