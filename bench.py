@@ -1,0 +1,237 @@
+"""Benchmark: cell-updates/s and HBM roofline fraction of the Runge-Kutta hot
+path on one MI355X, with the FP64 CPU oracle timed beside it.
+
+Default workload: 3D periodic Gray-Scott, 512^3 grid, FP32 state with FP64
+time/step control, adaptive Dormand-Prince 5(4) with rtol = atol = 1e-6,
+Du = 2e-5, Dv = 1e-5, F = 0.053, k = 0.014, box edge 2.5, initial condition a
+central 128^3 cube (u = 0.5, v = 0.25) in u = 1, v = 0 plus seeded uniform
+noise +-0.01 (seed 5).  One benchmark step integrates one window of `--window`
+time units along the same trajectory (the next window starts where the last
+ended, with the last proposed step); the value is cells x accepted steps /
+wall time over the timed windows.  Other workloads: --workload
+gs256-rk4 | gs256-dp5 | ew24-dp5 | gs32-rk4-fp64.
+
+Prints ONE JSON line.  Inputs are resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s & %HBM peak; wall-time to rtol 1e-6, learned vs PI controller"
+PEAK_HBM_GBS = 8000.0
+GS_PRM = [2e-5, 1e-5, 0.053, 0.014, 2.5]
+
+# arrays (each 2 N^3 elements) each Gray-Scott stage kernel must read + write
+GS_ARRAYS = {0: 2, 1: 3, 2: 3, 3: 5, 4: 3, 5: 4, 6: 5, 7: 6, 8: 7, 9: 8, 10: 8}
+GS_NAMES = {0: "D1", 1: "R2", 2: "R3", 3: "R4", 4: "D2", 5: "D3", 6: "D4", 7: "D5", 8: "D6", 9: "D7", 10: "D7F"}
+
+WORKLOADS = {
+    "gs512-dp5": dict(kind="gs", N=512, dtype="f32", method="dp5", window=10.0, seed=5, dt0=0.1),
+    "gs256-dp5": dict(kind="gs", N=256, dtype="f32", method="dp5", window=10.0, seed=3, dt0=0.1),
+    "gs256-rk4": dict(kind="gs", N=256, dtype="f32", method="rk4", steps_per=100, dt=0.1, seed=3),
+    "gs32-rk4-fp64": dict(kind="gs", N=32, dtype="f64", method="rk4", steps_per=500, dt=0.1, seed=1),
+    "ew24-dp5": dict(kind="ew", n=1 << 24, dtype="f64", method="dp5", t1=5.0, seed=2, dt0=0.01),
+}
+
+
+def traffic_from_profiles(kernel_tag: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "counters_%s.json" % kernel_tag)
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2309_05331_amd", "csrc", rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["hbm_bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline_leg(wl, budget_s=10.0):
+    """Times the FP64 oracle on a bounded sample of the workload (test
+    infrastructure; nothing else in this file touches the oracle)."""
+    import oracle
+    from paper_2309_05331_amd import inputs
+    if wl["kind"] == "gs":
+        Ns = min(wl["N"], 128)
+        y = inputs.gray_scott_ic(Ns, seed=wl["seed"]).ravel()
+        sysd = oracle.gs_system(Ns, *GS_PRM)
+        done, t0, units, t = 0, time.perf_counter(), 0, 0.0
+        while time.perf_counter() - t0 < budget_s:
+            if wl["method"] == "rk4":
+                y, t = oracle.integrate_n_steps(sysd, oracle.RK4, y, t, 0.1, 5)
+                units += 5 * Ns ** 3
+            else:
+                y, st, _ = oracle.integrate_adaptive(sysd, y, t, 1e9, 0.3, 1e-6, 1e-6, max_steps=4)
+                t = st["t"]
+                units += st["accepted"] * Ns ** 3
+            done += 1
+        el = time.perf_counter() - t0
+        sample = "%s on a %d^3 grid (same parameters), %d calls, %.1f s" % (
+            "RK4 steps" if wl["method"] == "rk4" else "adaptive Dopri5 accepted steps", Ns, done, el)
+        unit = "cell-updates/s"
+    else:
+        n = 1 << 20
+        x0 = inputs.exp_family_x0(n, seed=wl["seed"])
+        sysd = oracle.ew_system(oracle.EXP, n)
+        t0, units, reps = time.perf_counter(), 0, 0
+        while time.perf_counter() - t0 < budget_s:
+            _, st, _ = oracle.integrate_adaptive(sysd, x0, 0.0, 5.0, 0.01, 1e-6, 1e-6)
+            units += st["accepted"] * n
+            reps += 1
+        el = time.perf_counter() - t0
+        sample = "%d adaptive Dopri5 runs t 0->5 on 2^20 components, %.1f s" % (reps, el)
+        unit = "component-updates/s"
+    return {"value": units / el, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle", "sample": sample}
+
+
+def run_gs(wl, steps, warmup, ctrl_kind, weights=None):
+    import torch
+    from paper_2309_05331_amd import hode, inputs
+    N = wl["N"]
+    np_dt = np.float32 if wl["dtype"] == "f32" else np.float64
+    y0 = inputs.gray_scott_ic(N, seed=wl["seed"], dtype=np_dt).ravel()
+    dev = torch.from_numpy(y0).to("cuda:0")
+    ctx = hode.Context(0)
+    ctx.set_rhs(hode.RHS_GRAYSCOTT3D, GS_PRM)
+    ctx.init_state(dev, grid=N)
+    del dev
+    torch.cuda.synchronize()
+    ctx.set_tolerances(1e-6, 1e-6)
+    ctx.set_controller(ctrl_kind, weights)
+    state = {"t": 0.0, "dt": wl.get("dt0", 0.1), "acc": 0, "rej": 0}
+
+    def one_step():
+        if wl["method"] == "rk4":
+            ctx.integrate_n_steps(hode.RK4, state["t"], wl["dt"], wl["steps_per"])
+            state["t"] += wl["steps_per"] * wl["dt"]
+            state["acc"] += wl["steps_per"]
+        else:
+            st = ctx.integrate_adaptive(state["t"], state["t"] + wl["window"], state["dt"])
+            assert st["status"] == 0, st
+            state["t"] = st["t"]
+            state["dt"] = st["dt_next"]
+            state["acc"] += st["accepted"]
+            state["rej"] += st["rejected"]
+
+    for _ in range(warmup):
+        one_step()
+    state["acc"] = state["rej"] = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # dominant kernel: per-launch HIP-event timing of each stage on the
+    # library's stream, right after the timed region
+    kinds = [0, 1, 2, 3] if wl["method"] == "rk4" else [4, 5, 6, 7, 8, 9]
+    ms = {k: ctx.time_kernel(k, 10) for k in kinds}
+    dom = max(kinds, key=lambda k: ms[k])
+    esz = 4 if wl["dtype"] == "f32" else 8
+    arr_bytes = 2 * N ** 3 * esz
+    bytes_dom = GS_ARRAYS[dom] * arr_bytes
+    stage_gbs = {GS_NAMES[k]: round(GS_ARRAYS[k] * arr_bytes / (ms[k] * 1e-3) / 1e9, 1) for k in kinds}
+    step_bytes = sum(GS_ARRAYS[k] for k in kinds) * arr_bytes
+    attempt_ms = sum(ms.values())
+    ry, zc = ctx.get_tile()
+    ctx.close()
+    return dict(elapsed=el, cells=N ** 3, accepted=state["acc"], rejected=state["rej"], t_end=state["t"],
+                dom=GS_NAMES[dom], dom_ms=ms[dom], dom_bytes=bytes_dom, stage_gbs=stage_gbs,
+                attempt_gbs=step_bytes / (attempt_ms * 1e-3) / 1e9, tile=[ry, zc])
+
+
+def run_ew(wl, steps, warmup):
+    import torch
+    from paper_2309_05331_amd import hode, inputs
+    n = wl["n"]
+    x0 = inputs.exp_family_x0(n, seed=wl["seed"])
+    dev = torch.from_numpy(x0).to("cuda:0")
+    ctx = hode.Context(0)
+    ctx.set_rhs(hode.RHS_EXP)
+    acc = [0]
+
+    def one_step():
+        ctx.init_state(dev)  # device-to-device copy of the initial values
+        st = ctx.integrate_adaptive(0.0, wl["t1"], wl["dt0"])
+        assert st["status"] == 0
+        acc[0] += st["accepted"]
+
+    for _ in range(warmup):
+        one_step()
+    acc[0] = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = ctx.time_kernel(hode.DOPRI5, 20)
+    ctx.close()
+    return dict(elapsed=el, cells=n, accepted=acc[0], rejected=0, dom="ew_step_dp5", dom_ms=ms,
+                dom_bytes=2 * n * 8, stage_gbs=None, attempt_gbs=2 * n * 8 / (ms * 1e-3) / 1e9, tile=None)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gs512-dp5", choices=sorted(WORKLOADS))
+    ap.add_argument("--controller", default="pi", choices=["pi", "i"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+    from paper_2309_05331_amd import hode
+    wl = WORKLOADS[args.workload]
+    ctrl = {"pi": hode.CTRL_PI, "i": hode.CTRL_I}[args.controller]
+    if wl["kind"] == "gs":
+        r = run_gs(wl, args.steps, args.warmup, ctrl)
+        unit = "cell-updates/s"
+        cfg = {"workload": args.workload, "grid": [wl["N"]] * 3, "fields": 2,
+               "method": "dopri5-adaptive" if wl["method"] == "dp5" else "rk4-fixed",
+               "rtol": 1e-6 if wl["method"] == "dp5" else None, "controller": args.controller,
+               "window_time_units": wl.get("window"), "dt": wl.get("dt"), "tile_ry_zc": r["tile"],
+               "params": {"Du": GS_PRM[0], "Dv": GS_PRM[1], "F": GS_PRM[2], "k": GS_PRM[3], "L": GS_PRM[4]}}
+    else:
+        r = run_ew(wl, args.steps, args.warmup)
+        unit = "component-updates/s"
+        cfg = {"workload": args.workload, "components": wl["n"], "rhs": "exp", "method": "dopri5-adaptive",
+               "rtol": 1e-6, "t": [0.0, wl["t1"]]}
+    value = r["cells"] * r["accepted"] / r["elapsed"]
+    achieved = r["dom_bytes"] / (r["dom_ms"] * 1e-3) / 1e9
+    tag = "%s_%s" % (r["dom"], args.workload)
+    out = {
+        "metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["elapsed"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": wl["dtype"], "data": "synthetic", "config": cfg,
+        "accepted_steps": r["accepted"], "rejected_steps": r["rejected"],
+        "roofline": {"bound": "hbm", "kernel": r["dom"], "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic_from_profiles(tag)},
+        "stage_gbs": r["stage_gbs"], "attempt_gbs": round(r["attempt_gbs"], 1),
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline_leg(wl)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

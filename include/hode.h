@@ -1,0 +1,169 @@
+/*
+ * hode — explicit Runge-Kutta time stepping on one AMD Instinct MI355X.
+ *
+ * C ABI of libhode.so.  Every function returns an int status (HODE_OK = 0,
+ * negative on error) unless stated otherwise; no C++ exception crosses this
+ * boundary.  After an error, hode_last_error() describes it.
+ *
+ * Concepts follow the paper's description of Odeint ("Architecture and
+ * nomenclature of Boost Odeint"; "The distributed OpenFPM state type and
+ * algebra"; the Reuse-potential listings):
+ *   - a *state* (the solution vector at time t) is initialised by the caller
+ *     and updated in place;
+ *   - a *System* right-hand side F(t, u) is selected from a closed set
+ *     (exponential, sigmoidal/logistic, 3D Gray-Scott);
+ *   - a *stepper* is chosen by type (classical RK4, Runge-Kutta-Dopri5 of
+ *     Table 1), and the state is advanced by do_step, integrate_n_steps
+ *     (integrate_const) or integrate_adaptive with a tolerance, which returns
+ *     the number of steps performed;
+ *   - adaptive steppers bound the error with the L-infinity norm of the
+ *     embedded error estimate.
+ *
+ * Ownership: the context owns every device buffer it allocates.  Pointers
+ * passed in are borrowed for the duration of the call only (data is copied).
+ * Threading: one context per host thread; calls on one context must not
+ * overlap.  All device work runs on the context's stream; every call returns
+ * after that stream has synchronised.
+ *
+ * State layout: element-wise systems hold n independent components (nfields
+ * 1, ndim 1, shape {n}).  Gray-Scott holds two fields on an N^3 periodic grid
+ * (nfields 2, ndim 3, shape {N, N, N}), field-major (u then v), each field
+ * with x fastest: element (f, z, y, x) at f*N^3 + x + N*(y + N*z).
+ * dtype selects the state precision; time, step size, step control and the
+ * error-norm reduction are always FP64.
+ */
+#ifndef HODE_H
+#define HODE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hode_ctx hode_ctx;
+
+enum { HODE_F32 = 1, HODE_F64 = 2 };
+enum { HODE_RHS_EXP = 1, HODE_RHS_LOGISTIC = 2, HODE_RHS_GRAYSCOTT3D = 3 };
+enum { HODE_RK4 = 1, HODE_DOPRI5 = 2 };
+enum { HODE_CTRL_PI = 1, HODE_CTRL_I = 2, HODE_CTRL_MLP = 3 };
+enum {
+  HODE_OK = 0,
+  HODE_EINVAL = -1,        /* bad argument */
+  HODE_ESTATE = -2,        /* call out of order: no state / RHS set, or buffer too small */
+  HODE_EHIP = -3,          /* HIP runtime error (text in hode_last_error) */
+  HODE_ENOMEM = -4,        /* device allocation failed */
+  HODE_EDT_UNDERFLOW = -5, /* adaptive step fell below 1e-12 * max(1, |t|) */
+  HODE_EMAXSTEPS = -6,     /* attempt budget exhausted before t1 */
+  HODE_ENONFINITE = -7     /* step underflow while the error norm was NaN/inf */
+};
+
+/* Result of an adaptive integration (also filled for fixed-step runs). */
+typedef struct {
+  int64_t accepted;  /* steps performed (the paper's return value) */
+  int64_t rejected;  /* rejected attempts */
+  int64_t rhs_evals; /* System evaluations per element */
+  double t;          /* time reached */
+  double dt_next;    /* proposed next step */
+  double last_err;   /* error norm of the last attempt */
+  int32_t status;    /* HODE_OK or the error that ended the run */
+  int32_t pad;
+} hode_stats;
+
+/* Creates a context on HIP device `device`.  `stream` is a hipStream_t to run
+ * on (borrowed, must outlive the context) or NULL for a context-owned
+ * stream. */
+int hode_create(hode_ctx **out, int device, void *stream);
+
+/* Frees every device buffer and the context.  NULL is ignored. */
+void hode_destroy(hode_ctx *ctx);
+
+/* Selects the System.  HODE_RHS_GRAYSCOTT3D takes params = {Du, Dv, F, k, L}
+ * (diffusivities, feed, kill, box edge; the paper's Gray-Scott equation with
+ * the System listing's +u v^2 - (F+k) v term) with nparams = 5; the
+ * element-wise systems take none (params may be NULL).  Invalidates the
+ * cached first stage. */
+int hode_set_rhs(hode_ctx *ctx, int rhs, const double *params, int nparams);
+
+/* Allocates the state and its stage buffers and copies `src` in (host memory
+ * if src_on_device == 0, else device memory).  Element-wise: nfields 1,
+ * ndim 1, shape {n}, n >= 0.  Gray-Scott: nfields 2, ndim 3, shape {N,N,N},
+ * 1 <= N <= 2048.  The RHS must be set first (HODE_ESTATE otherwise). */
+int hode_init_state(hode_ctx *ctx, int dtype, int nfields, int ndim, const int64_t *shape, const void *src,
+                    int src_on_device);
+
+/* Copies the current state out; dst_bytes must be at least the state size
+ * (HODE_ESTATE otherwise). */
+int hode_read_state(hode_ctx *ctx, void *dst, size_t dst_bytes, int dst_on_device);
+
+/* Size of the state in bytes (0 before init). */
+size_t hode_state_bytes(const hode_ctx *ctx);
+
+/* Absolute and relative tolerance of the error norm
+ * max_i |e_i| / (atol + rtol * max(|y_i|, |ynew_i|)).  Both >= 0, not both 0.
+ * Defaults: 1e-6, 1e-6. */
+int hode_set_tolerances(hode_ctx *ctx, double atol, double rtol);
+
+/* Step-size controller for adaptive runs: HODE_CTRL_PI (default,
+ * Gustafsson PI), HODE_CTRL_I (elementary), or HODE_CTRL_MLP with `weights`
+ * the packed bf16 parameters of the 16-64-64-1 network (nbytes = 2 * 5249:
+ * W1[64][16], b1[64], W2[64][64], b2[64], w3[64], b3), copied in.  The PI
+ * proposal remains the fallback and retry rule. */
+int hode_set_controller(hode_ctx *ctx, int kind, const void *weights, size_t nbytes);
+
+/* One fixed step of size dt from time t, in place (Odeint do_step). */
+int hode_do_step(hode_ctx *ctx, int method, double t, double dt);
+
+/* n fixed steps (Odeint integrate_const with n = (tf - t0)/dt):
+ * t_n = t0 + n dt.  *t_end (may be NULL) receives t_n. */
+int hode_integrate_n_steps(hode_ctx *ctx, int method, double t0, double dt, int64_t n, double *t_end);
+
+/* One error-controlled Dopri5 attempt of size *dt from *t.  On acceptance *t
+ * advances and the state is updated; either way *dt receives the proposed
+ * next step and *accepted 0/1.  Controller history carries over between
+ * calls until the next integrate call. */
+int hode_try_step(hode_ctx *ctx, double *t, double *dt, int *accepted);
+
+/* Error-controlled Dopri5 from t0 to t1 (Odeint integrate_adaptive), first
+ * trial step dt0, at most max_steps attempts.  The last step is clipped to
+ * land on t1 exactly.  Returns HODE_OK or the status that ended the run; the
+ * state holds the last accepted step either way.  `out` may be NULL. */
+int hode_integrate_adaptive(hode_ctx *ctx, double t0, double t1, double dt0, int64_t max_steps, hode_stats *out);
+
+/* Statistics of the last run. */
+int hode_get_stats(hode_ctx *ctx, hode_stats *out);
+
+/* Records one 8-double entry per adaptive attempt (h, err, accepted, t after,
+ * dt proposed, PI log-ratio, learned log-ratio or NaN, landed-on-t1 flag) for
+ * the next runs, up to `capacity` attempts (0 disables). */
+int hode_set_trace(hode_ctx *ctx, int64_t capacity);
+
+/* Copies up to `cap` recorded entries to host `dst`; *n receives the number
+ * of attempts of the last run (may exceed cap). */
+int hode_read_trace(hode_ctx *ctx, double *dst, int64_t cap, int64_t *n);
+
+/* Evaluates the System at the current state into dst (same layout/dtype as
+ * the state). */
+int hode_eval_rhs(hode_ctx *ctx, void *dst, size_t dst_bytes, int dst_on_device);
+
+/* Gray-Scott tile configuration: ry in {1, 2, 4} (tile of 64 x 4*ry cells per
+ * workgroup), zc >= 1 z-planes per workgroup.  Element-wise: `ry` is ignored
+ * and zc is the workgroup count cap. */
+int hode_set_tile(hode_ctx *ctx, int ry, int zc);
+int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);
+
+/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..10 as D1,
+ * R2, R3, R4, D2..D7, D7F; element-wise: kind = method) on the context's
+ * stream with HIP events and returns the mean duration in milliseconds.
+ * The state is left unchanged for Gray-Scott non-final kinds only. */
+int hode_time_kernel(hode_ctx *ctx, int kind, int reps, double *avg_ms);
+
+/* Text of the last error on this context (valid until the next call). */
+const char *hode_last_error(const hode_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HODE_H */

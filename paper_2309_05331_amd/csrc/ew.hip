@@ -1,0 +1,182 @@
+// Whole-step kernel for the element-wise families of the accuracy benchmark:
+// exponential dx/dt = x and sigmoidal (logistic) dx/dt = x (1 - x), one
+// independent ODE per component.  With no spatial coupling every stage of a
+// step needs only the component itself, so the entire RK4 step or Dopri5
+// attempt (7 stages, first same as last) runs in registers: each component is
+// read once and written once per attempt, and the embedded error's L-infinity
+// norm is reduced on the fly (wavefront shuffle, LDS, one atomic per
+// workgroup).  The one-wavefront control kernel then takes the decision.
+#include "hode_internal.h"
+
+namespace hode {
+
+namespace {
+
+template <typename T, int RHS>
+__device__ __forceinline__ T frhs(T x) {
+  if constexpr (RHS == 1) return x;
+  else return x * ((T)1 - x);
+}
+
+template <typename T>
+struct DPCoef {
+  T a21, a31, a32, a41, a42, a43, a51, a52, a53, a54, a61, a62, a63, a64, a65, b1, b3, b4, b5, b6;
+  double e1, e3, e4, e5, e6, e7;
+};
+
+template <typename T>
+__device__ inline DPCoef<T> dp_coef(double h) {
+  DPCoef<T> q;
+  q.a21 = (T)(h * (1.0 / 5.0));
+  q.a31 = (T)(h * (3.0 / 40.0));
+  q.a32 = (T)(h * (9.0 / 40.0));
+  q.a41 = (T)(h * (44.0 / 45.0));
+  q.a42 = (T)(h * (-56.0 / 15.0));
+  q.a43 = (T)(h * (32.0 / 9.0));
+  q.a51 = (T)(h * (19372.0 / 6561.0));
+  q.a52 = (T)(h * (-25360.0 / 2187.0));
+  q.a53 = (T)(h * (64448.0 / 6561.0));
+  q.a54 = (T)(h * (-212.0 / 729.0));
+  q.a61 = (T)(h * (9017.0 / 3168.0));
+  q.a62 = (T)(h * (-355.0 / 33.0));
+  q.a63 = (T)(h * (46732.0 / 5247.0));
+  q.a64 = (T)(h * (49.0 / 176.0));
+  q.a65 = (T)(h * (-5103.0 / 18656.0));
+  q.b1 = (T)(h * (35.0 / 384.0));
+  q.b3 = (T)(h * (500.0 / 1113.0));
+  q.b4 = (T)(h * (125.0 / 192.0));
+  q.b5 = (T)(h * (-2187.0 / 6784.0));
+  q.b6 = (T)(h * (11.0 / 84.0));
+  q.e1 = h * (35.0 / 384.0 - 5179.0 / 57600.0);
+  q.e3 = h * (500.0 / 1113.0 - 7571.0 / 16695.0);
+  q.e4 = h * (125.0 / 192.0 - 393.0 / 640.0);
+  q.e5 = h * (-2187.0 / 6784.0 + 92097.0 / 339200.0);
+  q.e6 = h * (11.0 / 84.0 - 187.0 / 2100.0);
+  q.e7 = h * (-1.0 / 40.0);
+  return q;
+}
+
+template <typename T, int RHS, int MODE>
+__device__ __forceinline__ T step_one(T x, const DPCoef<T>& q, T r2, T r1, T r16, T r13, double atol, double rtol,
+                                      uint64_t& emax) {
+  if constexpr (MODE == MODE_FIXED_RK4) {
+    const T k1 = frhs<T, RHS>(x);
+    const T k2 = frhs<T, RHS>(x + r2 * k1);
+    const T k3 = frhs<T, RHS>(x + r2 * k2);
+    const T k4 = frhs<T, RHS>(x + r1 * k3);
+    return x + r16 * k1 + r13 * k2 + r13 * k3 + r16 * k4;
+  } else {
+    const T k1 = frhs<T, RHS>(x);
+    const T k2 = frhs<T, RHS>(x + q.a21 * k1);
+    const T k3 = frhs<T, RHS>(x + q.a31 * k1 + q.a32 * k2);
+    const T k4 = frhs<T, RHS>(x + q.a41 * k1 + q.a42 * k2 + q.a43 * k3);
+    const T k5 = frhs<T, RHS>(x + q.a51 * k1 + q.a52 * k2 + q.a53 * k3 + q.a54 * k4);
+    const T k6 = frhs<T, RHS>(x + q.a61 * k1 + q.a62 * k2 + q.a63 * k3 + q.a64 * k4 + q.a65 * k5);
+    const T xn = x + q.b1 * k1 + q.b3 * k3 + q.b4 * k4 + q.b5 * k5 + q.b6 * k6;
+    if constexpr (MODE == MODE_ADAPTIVE) {
+      const T k7 = frhs<T, RHS>(xn);
+      const double e = q.e1 * (double)k1 + q.e3 * (double)k3 + q.e4 * (double)k4 + q.e5 * (double)k5 +
+                       q.e6 * (double)k6 + q.e7 * (double)k7;
+      const double ratio = fabs(e) / (atol + rtol * fmax(fabs((double)x), fabs((double)xn)));
+      const uint64_t bits = (uint64_t)__double_as_longlong(ratio);
+      emax = bits > emax ? bits : emax;
+    }
+    return xn;
+  }
+}
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+  using V = float4;
+  static constexpr int W = 4;
+};
+template <>
+struct Vec<double> {
+  using V = double2;
+  static constexpr int W = 2;
+};
+
+template <typename T, int RHS, int MODE>
+__global__ __launch_bounds__(256) void ew_step(DevCtrl* __restrict__ c, T* __restrict__ b0, T* __restrict__ b1,
+                                               int64_t n) {
+  if (c->done) return;
+  const double h = c->h;
+  const T* __restrict__ y = c->parity ? b1 : b0;
+  T* __restrict__ yn = c->parity ? b0 : b1;
+  const double atol = c->atol, rtol = c->rtol;
+  DPCoef<T> q = dp_coef<T>(h);
+  const T r2 = (T)(h * 0.5), r1 = (T)h, r16 = (T)(h * (1.0 / 6.0)), r13 = (T)(h * (1.0 / 3.0));
+  uint64_t emax = 0;
+
+  using V = typename Vec<T>::V;
+  constexpr int W = Vec<T>::W;
+  const int64_t nv = n / W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    V v = reinterpret_cast<const V*>(y)[i];
+    T* e = reinterpret_cast<T*>(&v);
+#pragma unroll
+    for (int j = 0; j < W; ++j) e[j] = step_one<T, RHS, MODE>(e[j], q, r2, r1, r16, r13, atol, rtol, emax);
+    reinterpret_cast<V*>(yn)[i] = v;
+  }
+  // ragged tail
+  const int64_t tail = nv * W;
+  if (blockIdx.x == gridDim.x - 1 && tail + threadIdx.x < n) {
+    const int64_t i = tail + threadIdx.x;
+    yn[i] = step_one<T, RHS, MODE>(y[i], q, r2, r1, r16, r13, atol, rtol, emax);
+  }
+  if constexpr (MODE == MODE_ADAPTIVE) block_max_to<256>(emax, &c->errmax_bits);
+}
+
+__global__ __launch_bounds__(64) void ctrl_kernel(DevCtrl* c) {
+  if (c->done) return;
+  ctrl_step(c);
+}
+
+template <typename T, int RHS>
+__global__ __launch_bounds__(256) void ew_rhs(const T* __restrict__ y, T* __restrict__ out, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = frhs<T, RHS>(y[i]);
+}
+
+template <typename T, int RHS>
+hipError_t launch_rhs(int mode, T* y0, T* y1, int64_t n, int grid, DevCtrl* c, hipStream_t s) {
+  if (mode == MODE_FIXED_RK4) ew_step<T, RHS, MODE_FIXED_RK4><<<grid, 256, 0, s>>>(c, y0, y1, n);
+  else if (mode == MODE_FIXED_DP5) ew_step<T, RHS, MODE_FIXED_DP5><<<grid, 256, 0, s>>>(c, y0, y1, n);
+  else ew_step<T, RHS, MODE_ADAPTIVE><<<grid, 256, 0, s>>>(c, y0, y1, n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_ctrl(DevCtrl* c, hipStream_t s) {
+  ctrl_kernel<<<1, 64, 0, s>>>(c);
+  return hipGetLastError();
+}
+
+hipError_t launch_ew_rhs(int dtype, int rhs, const void* y, void* out, int64_t n, int grid, hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  if (dtype == 1) {
+    if (rhs == 1) ew_rhs<float, 1><<<grid, 256, 0, s>>>((const float*)y, (float*)out, n);
+    else ew_rhs<float, 2><<<grid, 256, 0, s>>>((const float*)y, (float*)out, n);
+  } else {
+    if (rhs == 1) ew_rhs<double, 1><<<grid, 256, 0, s>>>((const double*)y, (double*)out, n);
+    else ew_rhs<double, 2><<<grid, 256, 0, s>>>((const double*)y, (double*)out, n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ew(int dtype, int rhs, int mode, void* y0, void* y1, int64_t n, int grid, DevCtrl* c,
+                     hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  if (dtype == 1) {
+    if (rhs == 1) return launch_rhs<float, 1>(mode, (float*)y0, (float*)y1, n, grid, c, s);
+    return launch_rhs<float, 2>(mode, (float*)y0, (float*)y1, n, grid, c, s);
+  }
+  if (rhs == 1) return launch_rhs<double, 1>(mode, (double*)y0, (double*)y1, n, grid, c, s);
+  return launch_rhs<double, 2>(mode, (double*)y0, (double*)y1, n, grid, c, s);
+}
+
+}  // namespace hode

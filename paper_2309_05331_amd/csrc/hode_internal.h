@@ -1,0 +1,46 @@
+// Host-side declarations shared by the hode translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hode_dev.h"
+
+namespace hode {
+
+// Stage kernels of the Gray-Scott path.  D1 computes k1 = f(y) (also the
+// first RK4 stage); R2..R4 are the remaining RK4 stages (R4 also forms the new
+// state); D2..D7 are the Dopri5 stages (D7 forms the new state, k7 and the
+// error norm; D7F is the fixed-step variant without the error norm).  The
+// control kernel follows the final stage of every attempt.
+enum GSKind : int {
+  K_D1 = 0, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_COUNT
+};
+
+struct GSLaunch {
+  void* y[2];    // state, indexed by the device-side parity
+  void* ks[2];   // first-same-as-last pair: k1 = ks[k1slot], k7 = ks[k1slot ^ 1]
+  void* k[7];    // k[2] .. k[6]
+  int64_t n3;    // N^3, the stride between the u and v fields
+  int32_t N;
+  int32_t zc;    // z-planes marched by one workgroup
+  double Du_h2, Dv_h2, F, kk;
+};
+
+// ry: rows of the x-y tile per wavefront (tile = 64 x 4*ry cells).
+hipError_t launch_gs(int kind, int dtype, int ry, const GSLaunch& a, DevCtrl* c, hipStream_t s);
+bool gs_ry_supported(int ry);
+
+// Element-wise families: the whole step runs in registers (one kernel per
+// attempt).  mode: MODE_FIXED_RK4, MODE_FIXED_DP5 or MODE_ADAPTIVE.
+hipError_t launch_ew(int dtype, int rhs, int mode, void* y0, void* y1, int64_t n, int grid, DevCtrl* c,
+                     hipStream_t s);
+
+// The step controller: one wavefront, run after the final stage kernel of
+// every attempt or fixed step.
+hipError_t launch_ctrl(DevCtrl* c, hipStream_t s);
+
+// out = f(y) for the element-wise systems (no control block involved).
+hipError_t launch_ew_rhs(int dtype, int rhs, const void* y, void* out, int64_t n, int grid, hipStream_t s);
+
+}  // namespace hode

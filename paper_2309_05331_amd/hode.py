@@ -1,0 +1,213 @@
+"""ctypes binding of libhode.so (argument marshalling only).
+
+Functions carry the C names of ``include/hode.h``.  Device work runs in the
+library's HIP kernels; this module only converts Python/numpy/torch arguments
+to plain pointers and sizes and raises on error codes.  If the library has not
+been built the import of :func:`lib` fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libhode.so")
+
+F32, F64 = 1, 2
+RHS_EXP, RHS_LOGISTIC, RHS_GRAYSCOTT3D = 1, 2, 3
+RK4, DOPRI5 = 1, 2
+CTRL_PI, CTRL_I, CTRL_MLP = 1, 2, 3
+OK, EINVAL, ESTATE, EHIP, ENOMEM, EDT_UNDERFLOW, EMAXSTEPS, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
+TRACE_W = 8
+MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
+
+# Gray-Scott stage kernels, as numbered by hode_time_kernel
+K_D1, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F = range(11)
+
+
+class hode_stats(C.Structure):
+    _fields_ = [("accepted", C.c_int64), ("rejected", C.c_int64), ("rhs_evals", C.c_int64), ("t", C.c_double),
+                ("dt_next", C.c_double), ("last_err", C.c_double), ("status", C.c_int32), ("pad", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+class HodeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("hode error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads libhode.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError("libhode.so is not built: run python -m paper_2309_05331_amd.build")
+        L = C.CDLL(LIBPATH)
+        P, I, I64, D, S = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_size_t
+        sig = {
+            "hode_create": ([C.POINTER(P), I, P], I),
+            "hode_destroy": ([P], None),
+            "hode_set_rhs": ([P, I, C.POINTER(D), I], I),
+            "hode_init_state": ([P, I, I, I, C.POINTER(I64), P, I], I),
+            "hode_read_state": ([P, P, S, I], I),
+            "hode_state_bytes": ([P], S),
+            "hode_set_tolerances": ([P, D, D], I),
+            "hode_set_controller": ([P, I, P, S], I),
+            "hode_do_step": ([P, I, D, D], I),
+            "hode_integrate_n_steps": ([P, I, D, D, I64, C.POINTER(D)], I),
+            "hode_try_step": ([P, C.POINTER(D), C.POINTER(D), C.POINTER(I)], I),
+            "hode_integrate_adaptive": ([P, D, D, D, I64, C.POINTER(hode_stats)], I),
+            "hode_get_stats": ([P, C.POINTER(hode_stats)], I),
+            "hode_set_trace": ([P, I64], I),
+            "hode_read_trace": ([P, P, I64, C.POINTER(I64)], I),
+            "hode_eval_rhs": ([P, P, S, I], I),
+            "hode_set_tile": ([P, I, I], I),
+            "hode_get_tile": ([P, C.POINTER(I), C.POINTER(I)], I),
+            "hode_time_kernel": ([P, I, I, C.POINTER(D)], I),
+            "hode_last_error": ([P], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names declared in include/hode.h (for the export check)."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "hode.h")
+    return sorted(set(re.findall(r"\b(hode_[a-z_0-9]+)\s*\(", open(hdr).read())))
+
+
+def _ptr_of(buf):
+    """(pointer, nbytes, on_device) for a numpy array or a torch tensor."""
+    if isinstance(buf, np.ndarray):
+        assert buf.flags["C_CONTIGUOUS"]
+        return buf.ctypes.data_as(C.c_void_p), buf.nbytes, 0
+    # torch tensor
+    assert buf.is_contiguous()
+    on_dev = 1 if buf.is_cuda else 0
+    return C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(), on_dev
+
+
+class Context:
+    """A hode_ctx* with the C functions as methods (same names minus the prefix)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.L = lib()
+        self.h = C.c_void_p()
+        self._check(self.L.hode_create(C.byref(self.h), device, C.c_void_p(stream) if stream else None))
+
+    def close(self):
+        if self.h:
+            self.L.hode_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != OK and rc not in allow:
+            msg = self.L.hode_last_error(self.h).decode() if self.h else ""
+            raise HodeError(rc, msg)
+        return rc
+
+    def set_rhs(self, rhs, params=None):
+        if params is None:
+            return self._check(self.L.hode_set_rhs(self.h, rhs, None, 0))
+        arr = (C.c_double * len(params))(*params)
+        return self._check(self.L.hode_set_rhs(self.h, rhs, arr, len(params)))
+
+    def init_state(self, src, dtype=None, grid=None):
+        """src: numpy array or torch tensor (float32/float64), flat or (2,N,N,N)."""
+        is_f32 = str(src.dtype) in ("float32", "torch.float32")
+        dt = dtype or (F32 if is_f32 else F64)
+        if grid is not None:
+            shape = (C.c_int64 * 3)(grid, grid, grid)
+            nf, nd = 2, 3
+        else:
+            n = src.size if isinstance(src, np.ndarray) else src.numel()
+            shape = (C.c_int64 * 1)(n)
+            nf, nd = 1, 1
+        p, _, on_dev = _ptr_of(src)
+        return self._check(self.L.hode_init_state(self.h, dt, nf, nd, shape, p, on_dev))
+
+    def state_bytes(self):
+        return self.L.hode_state_bytes(self.h)
+
+    def read_state(self, dst):
+        p, nb, on_dev = _ptr_of(dst)
+        return self._check(self.L.hode_read_state(self.h, p, nb, on_dev))
+
+    def set_tolerances(self, atol, rtol):
+        return self._check(self.L.hode_set_tolerances(self.h, atol, rtol))
+
+    def set_controller(self, kind, weights_bf16=None):
+        if weights_bf16 is None:
+            return self._check(self.L.hode_set_controller(self.h, kind, None, 0))
+        w = np.ascontiguousarray(weights_bf16, dtype=np.uint16)
+        return self._check(self.L.hode_set_controller(self.h, kind, w.ctypes.data_as(C.c_void_p), w.nbytes))
+
+    def do_step(self, method, t, dt):
+        return self._check(self.L.hode_do_step(self.h, method, t, dt))
+
+    def integrate_n_steps(self, method, t0, dt, n):
+        te = C.c_double()
+        self._check(self.L.hode_integrate_n_steps(self.h, method, t0, dt, n, C.byref(te)))
+        return te.value
+
+    def try_step(self, t, dt):
+        tt, dd, acc = C.c_double(t), C.c_double(dt), C.c_int()
+        self._check(self.L.hode_try_step(self.h, C.byref(tt), C.byref(dd), C.byref(acc)))
+        return tt.value, dd.value, bool(acc.value)
+
+    def integrate_adaptive(self, t0, t1, dt0, max_steps=10 ** 9, allow=(EMAXSTEPS, EDT_UNDERFLOW, ENONFINITE)):
+        st = hode_stats()
+        self._check(self.L.hode_integrate_adaptive(self.h, t0, t1, dt0, max_steps, C.byref(st)), allow)
+        return st.as_dict()
+
+    def get_stats(self):
+        st = hode_stats()
+        self._check(self.L.hode_get_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def set_trace(self, capacity):
+        return self._check(self.L.hode_set_trace(self.h, capacity))
+
+    def read_trace(self, cap=None):
+        n = C.c_int64()
+        self._check(self.L.hode_read_trace(self.h, None, 0, C.byref(n)))
+        m = n.value if cap is None else min(cap, n.value)
+        out = np.zeros((max(m, 1), TRACE_W))
+        self._check(self.L.hode_read_trace(self.h, out.ctypes.data_as(C.c_void_p), m, C.byref(n)))
+        return out[:m]
+
+    def eval_rhs(self, dst):
+        p, nb, on_dev = _ptr_of(dst)
+        return self._check(self.L.hode_eval_rhs(self.h, p, nb, on_dev))
+
+    def set_tile(self, ry, zc):
+        return self._check(self.L.hode_set_tile(self.h, ry, zc))
+
+    def get_tile(self):
+        a, b = C.c_int(), C.c_int()
+        self._check(self.L.hode_get_tile(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def time_kernel(self, kind, reps):
+        ms = C.c_double()
+        self._check(self.L.hode_time_kernel(self.h, kind, reps, C.byref(ms)))
+        return ms.value

@@ -1,0 +1,158 @@
+"""GPU parity: element-wise families (exponential, logistic) through the C ABI
+against the FP64 oracle.  FP64 runs must agree within 1e-12 relative; FP32
+runs are compared with the oracle replaying the GPU's step sequence from the
+FP32-rounded initial condition, max-abs bound 1e-4."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_05331_amd import hode, inputs
+from gpu_util import ew_ctx, read, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12   # same step sequence (fixed steps, or the oracle replaying the GPU's)
+FREE64 = 1e-10  # free-running adaptive: step sizes differ by error-estimate rounding
+TOL32_ABS = 1e-4
+
+
+@pytest.mark.parametrize("kind", [hode.RHS_EXP, hode.RHS_LOGISTIC])
+@pytest.mark.parametrize("n", [1, 3, 1000, 100003])
+def test_fixed_steps_fp64(orc, kind, n):
+    x0 = inputs.exp_family_x0(n, seed=21)
+    for method in (hode.RK4, hode.DOPRI5):
+        ctx = ew_ctx(kind, x0)
+        te = ctx.integrate_n_steps(method, 0.0, 0.05, 100)
+        assert te == pytest.approx(5.0)
+        g = read(ctx, np.float64, n)
+        o, _ = orc.integrate_n_steps(orc.ew_system(kind, n), method, x0, 0.0, 0.05, 100)
+        assert rel_err(g, o) <= TOL64, (method, rel_err(g, o))
+        st = ctx.get_stats()
+        assert st["accepted"] == 100 and st["status"] == 0
+
+
+@pytest.mark.parametrize("kind", [hode.RHS_EXP, hode.RHS_LOGISTIC])
+@pytest.mark.parametrize("n", [257, 100003])
+def test_adaptive_fp64_free_and_replay(orc, kind, n):
+    x0 = inputs.exp_family_x0(n, seed=2)
+    ctx = ew_ctx(kind, x0)
+    ctx.set_tolerances(1e-6, 1e-6)
+    ctx.set_trace(10000)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+    g = read(ctx, np.float64, n)
+    tr = ctx.read_trace()
+    sysd = orc.ew_system(kind, n)
+    o, ost, otr = orc.integrate_adaptive(sysd, x0, 0.0, 5.0, 0.01, 1e-6, 1e-6, trace_cap=10000)
+    # free-running: same decisions, same counts, same end time.  The error
+    # estimate is a sum with heavy cancellation, so its rounding differs
+    # between the two summation orders by ~1e-9 relative; the controller
+    # turns that into ~1e-7 relative differences of later step sizes.
+    assert (st["accepted"], st["rejected"]) == (ost["accepted"], ost["rejected"])
+    assert st["t"] == 5.0 and st["status"] == 0
+    assert rel_err(g, o) <= FREE64
+    np.testing.assert_allclose(tr[:, 0], otr[:, 0], rtol=1e-5)
+    assert np.array_equal(tr[:, 2], otr[:, 2])
+    # replay: the oracle consumes the GPU step sequence
+    r, te, errs = orc.integrate_replay(sysd, x0, 0.0, tr[:, 0], tr[:, 2].astype(np.int32), 1e-6, 1e-6)
+    assert rel_err(g, r) <= TOL64
+    np.testing.assert_allclose(tr[:, 1], errs, rtol=1e-6, atol=1e-9)
+    assert st["rhs_evals"] == 1 + 6 * (st["accepted"] + st["rejected"])  # first-same-as-last count
+
+
+@pytest.mark.parametrize("kind", [hode.RHS_EXP, hode.RHS_LOGISTIC])
+def test_adaptive_fp32_replay_maxabs(orc, kind):
+    n = 1 << 20
+    x0 = inputs.exp_family_x0(n, seed=2)
+    x32 = x0.astype(np.float32)
+    ctx = ew_ctx(kind, x32)
+    ctx.set_trace(10000)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+    assert st["status"] == 0 and st["t"] == 5.0
+    g = read(ctx, np.float32, n)
+    tr = ctx.read_trace()
+    sysd = orc.ew_system(kind, n)
+    r, te, errs = orc.integrate_replay(sysd, x32.astype(np.float64), 0.0, tr[:, 0], tr[:, 2].astype(np.int32))
+    err = np.max(np.abs(g.astype(np.float64) - r))
+    print("fp32 %s max-abs vs fp64 oracle (replay): %.3e" % ("exp" if kind == 1 else "logistic", err))
+    assert err <= TOL32_ABS
+    # the closed form, to the accuracy the tolerance buys
+    exact = x32.astype(np.float64) * np.exp(5.0) if kind == 1 else \
+        x32 / (x32 + (1 - x32.astype(np.float64)) * np.exp(-5.0))
+    assert np.max(np.abs(g - exact) / (1 + np.abs(exact))) < 3e-5
+
+
+def test_full_size_fp64_adaptive_exp(orc):
+    # 2^24 components, exp and logistic, the benchmark launch configuration
+    n = 1 << 24
+    x0 = inputs.exp_family_x0(n, seed=2)
+    for kind in (hode.RHS_EXP, hode.RHS_LOGISTIC):
+        ctx = ew_ctx(kind, x0)
+        st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+        g = read(ctx, np.float64, n)
+        o, ost, _ = orc.integrate_adaptive(orc.ew_system(kind, n), x0, 0.0, 5.0, 0.01, 1e-6, 1e-6)
+        assert (st["accepted"], st["rejected"]) == (ost["accepted"], ost["rejected"])
+        assert rel_err(g, o) <= FREE64
+        ctx.close()
+
+
+def test_failure_modes_and_edges(orc):
+    x0 = inputs.exp_family_x0(1000, seed=3)
+    ctx = ew_ctx(hode.RHS_EXP, x0)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01, max_steps=5)
+    assert st["status"] == hode.EMAXSTEPS and st["accepted"] + st["rejected"] == 5
+    bad = x0.copy()
+    bad[17] = np.nan
+    ctx = ew_ctx(hode.RHS_EXP, bad)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+    assert st["status"] == hode.ENONFINITE and st["accepted"] == 0
+    assert np.isnan(read(ctx, np.float64, 1000)[17])
+    ctx = ew_ctx(hode.RHS_EXP, x0)
+    ctx.set_tolerances(1e-300, 1e-300)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+    assert st["status"] == hode.EDT_UNDERFLOW and st["t"] < 5.0
+    # t1 == t0: nothing happens
+    ctx = ew_ctx(hode.RHS_EXP, x0)
+    st = ctx.integrate_adaptive(1.0, 1.0, 0.01)
+    assert st["accepted"] == 0 and st["status"] == 0
+    assert np.array_equal(read(ctx, np.float64, 1000), x0)
+    # empty state
+    ctx = ew_ctx(hode.RHS_EXP, np.zeros(0))
+    st = ctx.integrate_adaptive(0.0, 1.0, 0.1)
+    assert st["status"] == 0 and st["t"] == 1.0
+    # argument errors
+    with pytest.raises(hode.HodeError):
+        ctx.set_tolerances(0.0, 0.0)
+    with pytest.raises(hode.HodeError):
+        ctx.integrate_adaptive(1.0, 0.0, 0.1)
+    ctx = ew_ctx(hode.RHS_EXP, x0)
+    with pytest.raises(hode.HodeError):
+        ctx.read_state(np.empty(999))  # destination too small
+
+
+def test_try_step_and_do_step(orc):
+    n = 4099
+    x0 = inputs.exp_family_x0(n, seed=5)
+    ctx = ew_ctx(hode.RHS_LOGISTIC, x0)
+    t, dt, acc = ctx.try_step(0.0, 0.3)
+    assert acc and t == 0.3 and dt > 0
+    yn, _, e = orc.dopri5_attempt(orc.ew_system(orc.LOGISTIC, n), x0, 0.3)
+    assert rel_err(read(ctx, np.float64, n), yn) <= TOL64
+    # a step far too large is rejected and leaves the state alone
+    before = read(ctx, np.float64, n)
+    ctx.set_tolerances(1e-12, 1e-12)
+    t2, dt2, acc2 = ctx.try_step(t, 5.0)
+    assert not acc2 and t2 == t and dt2 < 5.0
+    assert np.array_equal(read(ctx, np.float64, n), before)
+    ctx.do_step(hode.RK4, t, 0.1)
+    o = orc.rk4_step(orc.ew_system(orc.LOGISTIC, n), before, 0.1)
+    assert rel_err(read(ctx, np.float64, n), o) <= TOL64
+
+
+def test_eval_rhs(orc):
+    n = 1001
+    x0 = inputs.exp_family_x0(n, seed=6)
+    for kind in (hode.RHS_EXP, hode.RHS_LOGISTIC):
+        ctx = ew_ctx(kind, x0)
+        f = np.empty(n)
+        ctx.eval_rhs(f)
+        assert rel_err(f, orc.rhs(orc.ew_system(kind, n), x0)) <= 1e-15

@@ -1,0 +1,171 @@
+"""GPU parity: 3D periodic Gray-Scott stage kernels through the C ABI against
+the FP64 oracle.  FP64: 1e-12 relative per field.  FP32 state (FP64 step
+control): max-abs against the FP64 oracle from the FP32-rounded initial
+condition, target 1e-4.  Also: every tile shape gives bitwise-identical
+results, and a circular shift of the input gives the shifted output
+bitwise."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_05331_amd import hode, inputs
+from gpu_util import gs_ctx, read, rel_err_fields
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12   # same step sequence (fixed steps, or the oracle replaying the GPU's)
+FREE64 = 1e-10  # free-running adaptive: step sizes differ by error-estimate rounding
+TOL32_ABS = 1e-4
+PRM = dict(Du=2e-5, Dv=1e-5, F=0.053, k=0.014, L=2.5)
+# stronger diffusion so the stencil matters on short runs
+PRM_D = dict(Du=2e-3, Dv=1e-3, F=0.053, k=0.014, L=2.5)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 8, 33, 70])
+def test_rhs_matches_oracle_tiny_and_ragged(orc, N):
+    y0 = inputs.gray_scott_ic(N, seed=31)
+    for prm in (PRM, PRM_D):
+        ctx = gs_ctx(y0, N, prm)
+        f = np.empty(2 * N ** 3)
+        ctx.eval_rhs(f)
+        o = orc.rhs(orc.gs_system(N, **prm), y0.ravel())
+        scale = np.max(np.abs(o)) + 1e-300
+        assert np.max(np.abs(f - o)) / scale <= 1e-13, N
+
+
+@pytest.mark.parametrize("N,tile", [(5, (1, 8)), (33, (2, 8)), (33, (4, 5)), (70, (4, 16)), (70, (1, 70))])
+def test_rk4_fp64_ragged_tiles(orc, N, tile):
+    y0 = inputs.gray_scott_ic(N, seed=32)
+    ctx = gs_ctx(y0, N, PRM_D, tile)
+    ctx.integrate_n_steps(hode.RK4, 0.0, 0.1, 20)
+    g = read(ctx, np.float64, 2 * N ** 3)
+    o, _ = orc.integrate_n_steps(orc.gs_system(N, **PRM_D), orc.RK4, y0, 0.0, 0.1, 20)
+    assert rel_err_fields(g, o, 2) <= TOL64
+
+
+def test_rk4_fp64_32cube_500_steps(orc):
+    # the small parity workload: 32^3, FP64, dt 0.1, 500 steps
+    N = 32
+    y0 = inputs.gray_scott_ic(N, seed=1)
+    ctx = gs_ctx(y0, N, PRM)
+    te = ctx.integrate_n_steps(hode.RK4, 0.0, 0.1, 500)
+    assert te == pytest.approx(50.0)
+    g = read(ctx, np.float64, 2 * N ** 3)
+    o, _ = orc.integrate_n_steps(orc.gs_system(N, **PRM), orc.RK4, y0, 0.0, 0.1, 500)
+    err = rel_err_fields(g, o, 2)
+    print("32^3 FP64 RK4 x500 relative error vs oracle: %.3e" % err)
+    assert err <= TOL64
+
+
+def test_dopri5_fixed_fp64(orc):
+    N = 20
+    y0 = inputs.gray_scott_ic(N, seed=33)
+    ctx = gs_ctx(y0, N, PRM_D)
+    ctx.integrate_n_steps(hode.DOPRI5, 0.0, 0.2, 30)
+    g = read(ctx, np.float64, 2 * N ** 3)
+    o, _ = orc.integrate_n_steps(orc.gs_system(N, **PRM_D), orc.DOPRI5, y0, 0.0, 0.2, 30)
+    assert rel_err_fields(g, o, 2) <= TOL64
+
+
+@pytest.mark.parametrize("N", [16, 37])
+def test_dopri5_adaptive_fp64_free_and_replay(orc, N):
+    y0 = inputs.gray_scott_ic(N, seed=34)
+    ctx = gs_ctx(y0, N, PRM_D)
+    ctx.set_tolerances(1e-6, 1e-6)
+    ctx.set_trace(100000)
+    st = ctx.integrate_adaptive(0.0, 60.0, 0.1)
+    g = read(ctx, np.float64, 2 * N ** 3)
+    tr = ctx.read_trace()
+    sysd = orc.gs_system(N, **PRM_D)
+    o, ost, otr = orc.integrate_adaptive(sysd, y0, 0.0, 60.0, 0.1, 1e-6, 1e-6, trace_cap=100000)
+    assert st["status"] == 0 and st["t"] == 60.0
+    assert (st["accepted"], st["rejected"]) == (ost["accepted"], ost["rejected"])
+    assert rel_err_fields(g, o, 2) <= FREE64
+    np.testing.assert_allclose(tr[:, 0], otr[:, 0], rtol=1e-5)
+    r, _, errs = orc.integrate_replay(sysd, y0, 0.0, tr[:, 0], tr[:, 2].astype(np.int32), 1e-6, 1e-6)
+    assert rel_err_fields(g, r, 2) <= TOL64
+    # the error norm is O(1); its rounding noise (cancellation in the embedded
+    # difference) is ~1e-11 absolute, visible only on tiny clipped last steps
+    np.testing.assert_allclose(tr[:, 1], errs, rtol=1e-6, atol=1e-9)
+
+
+def test_dopri5_adaptive_fp32_replay(orc):
+    N = 32
+    y0 = inputs.gray_scott_ic(N, seed=35)
+    y32 = y0.astype(np.float32)
+    ctx = gs_ctx(y32, N, PRM_D)
+    ctx.set_trace(100000)
+    st = ctx.integrate_adaptive(0.0, 100.0, 0.1)
+    assert st["status"] == 0
+    g = read(ctx, np.float32, 2 * N ** 3)
+    tr = ctx.read_trace()
+    r, _, _ = orc.integrate_replay(orc.gs_system(N, **PRM_D), y32.astype(np.float64), 0.0, tr[:, 0],
+                                   tr[:, 2].astype(np.int32), 1e-6, 1e-6)
+    err = np.max(np.abs(g.astype(np.float64) - r))
+    print("32^3 FP32 Dopri5 adaptive max-abs vs FP64 oracle (replay): %.3e" % err)
+    assert err <= TOL32_ABS
+
+
+def test_rk4_fp32_maxabs(orc):
+    N = 32
+    y0 = inputs.gray_scott_ic(N, seed=1)
+    y32 = y0.astype(np.float32)
+    ctx = gs_ctx(y32, N, PRM)
+    ctx.integrate_n_steps(hode.RK4, 0.0, 0.1, 500)
+    g = read(ctx, np.float32, 2 * N ** 3)
+    o, _ = orc.integrate_n_steps(orc.gs_system(N, **PRM), orc.RK4, y32.astype(np.float64), 0.0, 0.1, 500)
+    err = np.max(np.abs(g - o))
+    print("32^3 FP32 RK4 x500 max-abs vs FP64 oracle: %.3e" % err)
+    assert err <= TOL32_ABS
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_tile_shapes_bitwise_identical(dtype):
+    N = 48
+    y0 = inputs.gray_scott_ic(N, seed=36).astype(dtype)
+    outs = []
+    for tile in [(1, 8), (2, 16), (4, 48), (4, 7), (1, 1)]:
+        ctx = gs_ctx(y0, N, PRM_D, tile)
+        ctx.set_trace(1000)
+        ctx.integrate_adaptive(0.0, 10.0, 0.1)
+        outs.append((read(ctx, dtype, 2 * N ** 3), ctx.read_trace()))
+    for g, tr in outs[1:]:
+        assert np.array_equal(g, outs[0][0])
+        assert np.array_equal(tr, outs[0][1], equal_nan=True)
+
+
+def test_shift_equivariance_bitwise():
+    N = 40
+    y0 = inputs.gray_scott_ic(N, seed=37).reshape(2, N, N, N)
+    sh = (3, -7, 11)
+    ctx = gs_ctx(y0, N, PRM_D)
+    ctx.integrate_n_steps(hode.RK4, 0.0, 0.2, 10)
+    a = read(ctx, np.float64, 2 * N ** 3).reshape(2, N, N, N)
+    ctx = gs_ctx(np.roll(y0, sh, axis=(1, 2, 3)), N, PRM_D)
+    ctx.integrate_n_steps(hode.RK4, 0.0, 0.2, 10)
+    b = read(ctx, np.float64, 2 * N ** 3).reshape(2, N, N, N)
+    assert np.array_equal(np.roll(a, sh, axis=(1, 2, 3)), b)
+
+
+def test_full_size_256_fp32_one_step(orc):
+    # 256^3 FP32 in the benchmark's launch configuration: one RK4 step and one
+    # Dopri5 attempt against the FP64 oracle
+    N = 256
+    y32 = inputs.gray_scott_ic(N, seed=3, dtype=np.float32)
+    y64 = y32.astype(np.float64).ravel()
+    sysd = orc.gs_system(N, **PRM)
+    ctx = gs_ctx(y32, N, PRM)
+    ctx.do_step(hode.RK4, 0.0, 0.1)
+    g = read(ctx, np.float32, 2 * N ** 3)
+    o = orc.rk4_step(sysd, y64, 0.1)
+    assert np.max(np.abs(g - o)) <= 1e-6
+    ctx = gs_ctx(y32, N, PRM)
+    ctx.do_step(hode.DOPRI5, 0.0, 0.5)
+    g = read(ctx, np.float32, 2 * N ** 3)
+    yn, _, e = orc.dopri5_attempt(sysd, y64, 0.5)
+    assert np.max(np.abs(g - yn)) <= 1e-6
+    # one controlled attempt takes the same accept decision as the oracle
+    ctx = gs_ctx(y32, N, PRM)
+    t, dt, acc = ctx.try_step(0.0, 0.5)
+    err = orc.err_norm(y64, yn, e, 1e-6, 1e-6)
+    assert acc == (err <= 1.0)
