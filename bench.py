@@ -31,9 +31,15 @@ METRIC = "cell-updates/s & %HBM peak; wall-time to rtol 1e-6, learned vs PI cont
 PEAK_HBM_GBS = 8000.0
 GS_PRM = [2e-5, 1e-5, 0.053, 0.014, 2.5]
 
-# arrays (each 2 N^3 elements) each Gray-Scott stage kernel must read + write
-GS_ARRAYS = {0: 2, 1: 3, 2: 3, 3: 5, 4: 3, 5: 4, 6: 5, 7: 6, 8: 7, 9: 8, 10: 8}
-GS_NAMES = {0: "D1", 1: "R2", 2: "R3", 3: "R4", 4: "D2", 5: "D3", 6: "D4", 7: "D5", 8: "D6", 9: "D7", 10: "D7F"}
+# Algorithmic traffic: arrays (each 2 N^3 elements of the state precision)
+# each Gray-Scott stage kernel must read once and write once.
+#   D1: y -> k1                      R2: y,k1 -> k2     R3: y,k2 -> k3
+#   R4: y,k3,k1,k2 -> ynew           D2: y,k1 -> k2     D3: y,k1,k2 -> k3
+#   D4: y,k1..k3 -> k4               D5: y,k1..k4 -> k5
+#   D6: y,k1..k5 -> ynew, partial error                D7: ynew,partial error,y -> k7
+GS_ARRAYS = {0: 2, 1: 3, 2: 3, 3: 5, 4: 3, 5: 4, 6: 5, 7: 6, 8: 8, 9: 4, 10: 2, 11: 7}
+GS_NAMES = {0: "D1", 1: "R2", 2: "R3", 3: "R4", 4: "D2", 5: "D3", 6: "D4", 7: "D5", 8: "D6", 9: "D7", 10: "D7F",
+            11: "D6F"}
 
 WORKLOADS = {
     "gs512-dp5": dict(kind="gs", N=512, dtype="f32", method="dp5", window=10.0, seed=5, dt0=0.1),
@@ -98,7 +104,7 @@ def cpu_baseline_leg(wl, budget_s=10.0):
     return {"value": units / el, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle", "sample": sample}
 
 
-def run_gs(wl, steps, warmup, ctrl_kind, weights=None):
+def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     import torch
     from paper_2309_05331_amd import hode, inputs
     N = wl["N"]
@@ -112,6 +118,11 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None):
     torch.cuda.synchronize()
     ctx.set_tolerances(1e-6, 1e-6)
     ctx.set_controller(ctrl_kind, weights)
+    method = hode.RK4 if wl["method"] == "rk4" else hode.DOPRI5
+    if tile is None:
+        ctx.autotune(method, 3)  # project autotuner: fastest (ry, zc) for this grid
+    else:
+        ctx.set_tile(*tile)
     state = {"t": 0.0, "dt": wl.get("dt0", 0.1), "acc": 0, "rej": 0}
 
     def one_step():
@@ -136,10 +147,12 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None):
         one_step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    # dominant kernel: per-launch HIP-event timing of each stage on the
-    # library's stream, right after the timed region
+    # per-stage durations: HIP events around every stage kernel of attempts
+    # replayed in the same order on the library's stream, right after the
+    # timed region
     kinds = [0, 1, 2, 3] if wl["method"] == "rk4" else [4, 5, 6, 7, 8, 9]
-    ms = {k: ctx.time_kernel(k, 10) for k in kinds}
+    prof = ctx.profile_attempt(method, 10)
+    ms = dict(zip(kinds, prof))
     dom = max(kinds, key=lambda k: ms[k])
     esz = 4 if wl["dtype"] == "f32" else 8
     arr_bytes = 2 * N ** 3 * esz
@@ -193,16 +206,28 @@ def main():
     ap.add_argument("--workload", default="gs512-dp5", choices=sorted(WORKLOADS))
     ap.add_argument("--controller", default="pi", choices=["pi", "i"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default="auto", help="auto (autotune) or RY,ZC")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="time only the plain 16-byte streaming copy of 1 GiB (bandwidth ceiling, counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
               file=sys.stderr)
         sys.exit(2)
     from paper_2309_05331_amd import hode
+    if args.copy_reference:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        ms, gbs = hode.stream_copy(dst, src, reps=max(args.steps, 1))
+        print(json.dumps({"reference": "stream_copy", "bytes_read": src.numel() * 4, "bytes_written": src.numel() * 4,
+                          "ms_per_copy": ms, "GBps": gbs, "frac_of_8TBps": gbs / PEAK_HBM_GBS}), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     ctrl = {"pi": hode.CTRL_PI, "i": hode.CTRL_I}[args.controller]
     if wl["kind"] == "gs":
-        r = run_gs(wl, args.steps, args.warmup, ctrl)
+        tile = None if args.tile == "auto" else tuple(int(v) for v in args.tile.split(","))
+        r = run_gs(wl, args.steps, args.warmup, ctrl, tile=tile)
         unit = "cell-updates/s"
         cfg = {"workload": args.workload, "grid": [wl["N"]] * 3, "fields": 2,
                "method": "dopri5-adaptive" if wl["method"] == "dp5" else "rk4-fixed",

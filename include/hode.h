@@ -159,6 +159,26 @@ int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);
  * The state is left unchanged for Gray-Scott non-final kinds only. */
 int hode_time_kernel(hode_ctx *ctx, int kind, int reps, double *avg_ms);
 
+/* Gray-Scott: runs `reps` attempts of `method` (RK4: stages D1 R2 R3 R4;
+ * DOPRI5: stages D2..D7 of an adaptive attempt) with the control kernel in a
+ * no-op timing mode, HIP events around every stage kernel on the context's
+ * stream, and writes the mean duration of each stage in milliseconds to
+ * ms[0..3] or ms[0..5].  The current state and k1 are left unchanged. */
+int hode_profile_attempt(hode_ctx *ctx, int method, int reps, double *ms);
+
+/* Gray-Scott: times one attempt of `method` for every tile configuration
+ * (ry in {1,2,4}, zc in {8..256}) with hode_profile_attempt and keeps the
+ * fastest; the choice and its attempt time (ms) are returned (any output
+ * pointer may be NULL).  Results are bitwise identical for every tile. */
+int hode_autotune(hode_ctx *ctx, int method, int reps, int *best_ry, int *best_zc, double *best_ms);
+
+/* Measurement reference: copies `bytes` (a multiple of 16) from device
+ * buffer src to device buffer dst with a plain 16-byte-per-lane streaming
+ * kernel, `reps` times after one warm-up, on a stream of its own; returns the
+ * mean duration per copy in milliseconds.  Used as the achievable-bandwidth
+ * ceiling and to calibrate HBM traffic counters. */
+int hode_stream_copy(void *dst, const void *src, size_t bytes, int reps, double *avg_ms);
+
 /* Text of the last error on this context (valid until the next call). */
 const char *hode_last_error(const hode_ctx *ctx);
 

@@ -5,80 +5,150 @@
 //   dv/dt = Dv Lap(v) + u v^2 - (F + k) v
 // with Lap the 7-point finite-difference Laplacian on an N^3 periodic grid of
 // spacing L/N.  One kernel per Runge-Kutta stage fuses the Algebra (the stage
-// input y + h sum_j a_sj k_j, formed on the fly, halo cells included), the
-// System (stencil + reaction) and the stage's outputs.
+// input y + h sum_j a_sj k_j, formed on the fly, neighbour cells included),
+// the System (stencil + reaction) and the stage's outputs.
 //
 // Layout: field-major SoA, u then v, each N^3 with x fastest.
-// Tiling: a workgroup of 4 wavefronts owns a 64 x (4 ry) tile of an x-y plane
-// and marches a chunk of zc planes in z.  Each wavefront covers one 64-cell x
-// row per load (coalesced 256 B fp32 / 512 B fp64 rows).  The stage input of
-// the current plane, with a one-cell x-y halo, sits in LDS (double buffered:
-// one barrier per plane); the z neighbours stay in registers.  Periodic wrap
-// is folded into per-thread in-plane offsets computed once, so ragged tiles
-// (N not a multiple of the tile) read wrapped cells where the halo needs them.
+//
+// Work decomposition (2.5D blocking): a workgroup of 4 wavefronts owns a tile
+// of 64*VW x 4*RY cells of an x-y plane and marches a chunk of zc planes in z.
+// Each wavefront owns a strip of RY consecutive x-rows, VW cells per lane (one
+// 16-byte load per lane per row).  Per plane, every row is loaded from memory
+// once: the stage input is formed in registers, the z neighbours stay in
+// registers (planes z-1, z, z+1), x neighbours come across lanes by shuffle,
+// y neighbours inside a strip are the wave's own rows, and only the strips'
+// first and last rows plus the tile halo (the rows above and below the tile,
+// the two x-halo columns) pass through a small double-buffered LDS area: one
+// barrier per plane.  Periodic wrap is folded into precomputed offsets; lanes
+// and rows beyond a ragged edge load wrapped cells, which are exactly the
+// neighbours the edge cells need, and write nothing.
+//
+// Block order is XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so
+// the linear block id is remapped to give each XCD a contiguous range of
+// tiles, keeping y- and z-adjacent tiles (whose halo rows overlap) on one L2.
+//
+// Dopri5 stages 6 and 7 are restructured so stage 7 reads 3 arrays instead of
+// 6: stage 6 forms the new state y + h sum b_j k_j (= the stage-7 input, first
+// same as last) and the partial error h sum_{j<=6} (b_j - bhat_j) k_j at the
+// own cell and stores both instead of k6; stage 7 evaluates k7 = f(ynew) and
+// completes the error with h (b_7 - bhat_7) k7.
 #include "hode_internal.h"
 
 namespace hode {
 
 namespace {
 
-// Array ids: 0 = y, 1..7 = k1..k7.
+// array ids
+enum : int { A_Y = 0, A_K1 = 1, A_K2, A_K3, A_K4, A_K5, A_E6 = 6, A_K7 = 7, A_YN = 8 };
+
 struct KindDesc {
-  int ns;          // source arrays forming the stage input (first is y)
+  int ns;          // source arrays forming the stage input (first has coefficient 1)
   int src[6];
-  double a[6];     // stage-input coefficients (times h); a[0] unused (y)
+  double a[6];     // stage-input coefficients (times h); a[0] unused
   int nx;          // extra arrays needed at the own cell only
   int extra[2];
-  int out;         // array id written with f(stage input); -1 none
-  int final_kind;  // 0 no; 1 RK4 new state; 2 Dopri5 new state + k7 (+ error)
-  bool err;
+  int out;         // array receiving f(stage input), -1 none
+  int fin;         // own-cell finish: 0 none, 1 RK4 new state, 2 Dopri5 new state (+ partial error),
+                   // 3 Dopri5 error completion
+  bool err;        // error norm computed
 };
+
+constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0, B5 = -2187.0 / 6784.0,
+                 B6 = 11.0 / 84.0;
+constexpr double D1 = 35.0 / 384.0 - 5179.0 / 57600.0, D3 = 500.0 / 1113.0 - 7571.0 / 16695.0,
+                 D4 = 125.0 / 192.0 - 393.0 / 640.0, D5 = -2187.0 / 6784.0 + 92097.0 / 339200.0,
+                 D6 = 11.0 / 84.0 - 187.0 / 2100.0, D7 = -1.0 / 40.0;
 
 constexpr KindDesc kDesc[K_COUNT] = {
-    /* D1 */ {1, {0}, {0}, 0, {0, 0}, 1, 0, false},
-    /* R2 */ {2, {0, 1}, {0, 0.5}, 0, {0, 0}, 2, 0, false},
-    /* R3 */ {2, {0, 2}, {0, 0.5}, 0, {0, 0}, 3, 0, false},
-    /* R4 */ {2, {0, 3}, {0, 1.0}, 2, {1, 2}, -1, 1, false},
-    /* D2 */ {2, {0, 1}, {0, 1.0 / 5.0}, 0, {0, 0}, 2, 0, false},
-    /* D3 */ {3, {0, 1, 2}, {0, 3.0 / 40.0, 9.0 / 40.0}, 0, {0, 0}, 3, 0, false},
-    /* D4 */ {4, {0, 1, 2, 3}, {0, 44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0}, 0, {0, 0}, 4, 0, false},
-    /* D5 */ {5, {0, 1, 2, 3, 4},
-              {0, 19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0}, 0, {0, 0}, 5, 0, false},
-    /* D6 */ {6, {0, 1, 2, 3, 4, 5},
-              {0, 9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0}, 0, {0, 0}, 6,
-              0, false},
-    /* D7 */ {6, {0, 1, 3, 4, 5, 6},
-              {0, 35.0 / 384.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}, 0, {0, 0}, 7, 2, true},
-    /* D7F */ {6, {0, 1, 3, 4, 5, 6},
-               {0, 35.0 / 384.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}, 0, {0, 0}, 7, 2,
+    /* D1  */ {1, {A_Y}, {0}, 0, {0, 0}, A_K1, 0, false},
+    /* R2  */ {2, {A_Y, A_K1}, {0, 0.5}, 0, {0, 0}, A_K2, 0, false},
+    /* R3  */ {2, {A_Y, A_K2}, {0, 0.5}, 0, {0, 0}, A_K3, 0, false},
+    /* R4  */ {2, {A_Y, A_K3}, {0, 1.0}, 2, {A_K1, A_K2}, -1, 1, false},
+    /* D2  */ {2, {A_Y, A_K1}, {0, 1.0 / 5.0}, 0, {0, 0}, A_K2, 0, false},
+    /* D3  */ {3, {A_Y, A_K1, A_K2}, {0, 3.0 / 40.0, 9.0 / 40.0}, 0, {0, 0}, A_K3, 0, false},
+    /* D4  */ {4, {A_Y, A_K1, A_K2, A_K3}, {0, 44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0}, 0, {0, 0}, A_K4, 0, false},
+    /* D5  */ {5, {A_Y, A_K1, A_K2, A_K3, A_K4},
+               {0, 19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0}, 0, {0, 0}, A_K5, 0,
                false},
+    /* D6  */ {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
+               {0, 9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0}, 0, {0, 0},
+               -1, 2, true},
+    /* D7  */ {1, {A_YN}, {0}, 2, {A_E6, A_Y}, A_K7, 3, true},
+    /* D7F */ {1, {A_YN}, {0}, 0, {0, 0}, A_K7, 0, false},
 };
+// D6 in fixed-step mode: the new state only (no partial error).
+constexpr KindDesc kD6F = {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
+                           {0, 9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0},
+                           0, {0, 0}, -1, 2, false};
 
-template <typename T>
-struct Ptrs {
-  const T* src[6];
-  const T* extra[2];
-  T* out;
-  T* ynew;
-};
+template <int KIND>
+__host__ __device__ constexpr KindDesc desc() {
+  return KIND == K_COUNT ? kD6F : kDesc[KIND];
+}
 
 template <typename T>
 __device__ inline T* array_ptr(const GSLaunch& a, int id, int p, int ks) {
-  if (id == 0) return (T*)a.y[p];
-  if (id == 1) return (T*)a.ks[ks];
-  if (id == 7) return (T*)a.ks[ks ^ 1];
-  return (T*)a.k[id];
+  switch (id) {
+    case A_Y: return (T*)a.y[p];
+    case A_YN: return (T*)a.y[p ^ 1];
+    case A_K1: return (T*)a.ks[ks];
+    case A_K7: return (T*)a.ks[ks ^ 1];
+    default: return (T*)a.k[id];
+  }
 }
 
-constexpr int TX = 64;
+template <typename T, int VW>
+struct VecT;
+template <>
+struct VecT<float, 4> { using type = float4; };
+template <>
+struct VecT<float, 1> { using type = float; };
+template <>
+struct VecT<double, 2> { using type = double2; };
+template <>
+struct VecT<double, 1> { using type = double; };
 
-template <typename T, int KIND, int RY>
+template <typename T, int VW>
+struct Pk {
+  T v[VW];
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ Pk<T, VW> ldv(const T* __restrict__ p, int64_t g) {
+  using V = typename VecT<T, VW>::type;
+  const V x = *reinterpret_cast<const V*>(p + g);
+  Pk<T, VW> r;
+  __builtin_memcpy(&r, &x, sizeof(r));
+  return r;
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void stv(T* __restrict__ p, int64_t g, const Pk<T, VW>& r) {
+  using V = typename VecT<T, VW>::type;
+  V x;
+  __builtin_memcpy(&x, &r, sizeof(r));
+  *reinterpret_cast<V*>(p + g) = x;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_up1(T v) {
+  return __shfl_up(v, 1, 64);
+}
+template <typename T>
+__device__ __forceinline__ T shfl_down1(T v) {
+  return __shfl_down(v, 1, 64);
+}
+
+template <typename T, int KIND, int RY, int VW>
 __global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __restrict__ c) {
-  constexpr KindDesc D = kDesc[KIND];
+  constexpr KindDesc D = desc<KIND>();
+  constexpr int TX = 64 * VW;
   constexpr int TY = 4 * RY;
-  // raw own-cell values kept for the final combination / error
-  constexpr int NR = D.final_kind == 1 ? (D.ns + D.nx) : (D.err ? D.ns : 0);
-  __shared__ T lds[2][2][TY + 2][TX + 2];
+  using P = Pk<T, VW>;
+  // LDS per buffer and field: 10 row slots (tile halo above, first and last
+  // row of each wave's strip, tile halo below) and the 2 x 16 x-halo cells
+  __shared__ P rows[2][2][10][64];
+  __shared__ T xh[2][2][2][TY];
 
   if (c->done) return;
   const double h = c->h;
@@ -87,221 +157,304 @@ __global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __res
   const int64_t n3 = a.n3;
   const int64_t NN = (int64_t)N * N;
 
-  Ptrs<T> P;
+  // ---- which tile: XCD-aware remap of the linear block id
+  const int nx = (N + TX - 1) / TX;
+  const int ny = (N + TY - 1) / TY;
+  const int nz = (N + a.zc - 1) / a.zc;
+  const int per = (gridDim.x + 7) / 8;
+  const int bb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (bb >= nx * ny * nz) return;  // padding block of the remap (whole block)
+  const int tx = bb % nx;
+  const int ty = (bb / nx) % ny;
+  const int tz = bb / (nx * ny);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x0 = tx * TX, yt = ty * TY;
+  const int y0 = yt + wv * RY;  // first row of this wave's strip
+  const int zbeg = tz * a.zc;
+  const int zend = min(N, zbeg + a.zc);
+
+  const T* src[6];
 #pragma unroll
-  for (int i = 0; i < D.ns; ++i) P.src[i] = array_ptr<T>(a, D.src[i], p, ksl);
+  for (int i = 0; i < D.ns; ++i) src[i] = array_ptr<T>(a, D.src[i], p, ksl);
+  const T* ext[2];
 #pragma unroll
-  for (int i = 0; i < D.nx; ++i) P.extra[i] = array_ptr<T>(a, D.extra[i], p, ksl);
-  P.out = D.out >= 0 ? array_ptr<T>(a, D.out, p, ksl) : nullptr;
-  P.ynew = D.final_kind ? (T*)a.y[p ^ 1] : nullptr;
+  for (int i = 0; i < D.nx; ++i) ext[i] = array_ptr<T>(a, D.extra[i], p, ksl);
+  T* out = D.out >= 0 ? array_ptr<T>(a, D.out, p, ksl) : nullptr;
+  T* ynew = (D.fin == 1 || D.fin == 2) ? (T*)a.y[p ^ 1] : nullptr;
+  T* e6 = (D.fin == 2 && D.err) ? (T*)a.k[A_E6] : nullptr;
 
   T cf[6];
 #pragma unroll
   for (int i = 1; i < D.ns; ++i) cf[i] = (T)(h * D.a[i]);
-  // RK4 final combination weights: y + h/6 k1 + h/3 k2 + h/3 k3 + h/6 k4
-  const T b16 = (T)(h * (1.0 / 6.0)), b13 = (T)(h * (1.0 / 3.0));
-  // Dopri5 error weights d_j = b_j - bhat_j (times h), in fp64
-  constexpr double d1 = 35.0 / 384.0 - 5179.0 / 57600.0, d3 = 500.0 / 1113.0 - 7571.0 / 16695.0,
-                   d4 = 125.0 / 192.0 - 393.0 / 640.0, d5 = -2187.0 / 6784.0 + 92097.0 / 339200.0,
-                   d6 = 11.0 / 84.0 - 187.0 / 2100.0, d7 = -1.0 / 40.0;
-  const double e1 = h * d1, e3 = h * d3, e4 = h * d4, e5 = h * d5, e6 = h * d6, e7 = h * d7;
-  const double atol = c->atol, rtol = c->rtol;
   const T Du = (T)a.Du_h2, Dv = (T)a.Dv_h2, F = (T)a.F, Fk = (T)(a.F + a.kk);
+  const double atol = c->atol, rtol = c->rtol;
+  (void)atol;
+  (void)rtol;
+  const T b16 = (T)(h * (1.0 / 6.0)), b13 = (T)(h * (1.0 / 3.0));
+  const T q1 = (T)(h * B1), q3 = (T)(h * B3), q4 = (T)(h * B4), q5 = (T)(h * B5), q6 = (T)(h * B6);
+  const double h1 = h * D1, h3 = h * D3, h4 = h * D4, h5 = h * D5, h6 = h * D6, h7 = h * D7;
 
-  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  const int zbeg = blockIdx.z * a.zc;
-  const int zend = min(N, zbeg + a.zc);
-
-  // per-thread in-plane offsets (periodic wrap folded in)
-  const int gx = (x0 + lx) % N;
-  int off[RY];
-  bool valid[RY];
+  // ---- offsets (periodic wrap folded in)
+  const int xl = x0 + VW * lane;
+  const int gx = xl % N;  // N % VW == 0, so gx .. gx+VW-1 are one aligned run
+  const bool xval = xl < N;
+  int rowoff[RY];
 #pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const int yy = y0 + ly + 4 * r;
-    off[r] = gx + N * (yy % N);
-    valid[r] = (x0 + lx < N) && (yy < N);
-  }
-  // halo cell of this thread: wave 0 row above, wave 1 row below, waves 2/3
-  // the left/right columns (first TY lanes)
-  int hoff = 0, hrow = 0, hcol = 0;
-  bool hval = true;
-  if (ly == 0) { hoff = gx + N * ((y0 - 1 + N) % N); hrow = 0; hcol = lx + 1; }
-  else if (ly == 1) { hoff = gx + N * ((y0 + TY) % N); hrow = TY + 1; hcol = lx + 1; }
-  else {
-    hval = lx < TY;
-    const int xx = (ly == 2) ? (x0 - 1 + N) % N : (x0 + TX) % N;
-    hoff = xx + N * ((y0 + (hval ? lx : 0)) % N);
-    hrow = (hval ? lx : 0) + 1;
-    hcol = (ly == 2) ? 0 : TX + 1;
+  for (int r = 0; r < RY; ++r) rowoff[r] = N * ((y0 + r) % N);
+  // halo role of this wave: 0 the row above the tile, 1 the row below,
+  // 2 the x-halo cells (lanes < TY left column, TY .. 2TY-1 right column)
+  int hoff = 0;
+  bool hact = false;
+  if (wv == 0) { hoff = N * ((yt - 1 + N) % N) + gx; hact = true; }
+  else if (wv == 1) { hoff = N * ((yt + TY) % N) + gx; hact = true; }
+  else if (wv == 2 && lane < 2 * TY) {
+    const int side = lane >= TY, rr = lane - side * TY;
+    hoff = N * ((yt + rr) % N) + (side ? (x0 + TX) % N : (x0 - 1 + N) % N);
+    hact = true;
   }
 
-  T wp[2][RY], wc[2][RY], wn[2][RY];
-  T rawc[NR > 0 ? NR : 1][2][RY], rawn[NR > 0 ? NR : 1][2][RY];
-  T hw[2];
-  uint64_t emax = 0;
+  // Partial own-cell finish of one row-field, formed at load time so the raw
+  // sources need not stay live: RK4 y + h/6 k1 + h/3 k2 + h/3 k3; Dopri5
+  // stage 6 y + h sum_{j<6} b_j k_j and (fp64) h sum_{j<6} (b_j - bhat_j) k_j;
+  // stage 7 the stored partial error and y.
+  struct Fin {
+    T a[VW];
+    double e[(D.fin == 2 && D.err) ? VW : 1];
+    T b[D.fin == 3 ? VW : 1];
+  };
 
-  auto stage_in = [&](int64_t g, T* raw, bool keep) -> T {
-    T v0 = P.src[0][g];
-    T w = v0;
-    if (keep) raw[0] = v0;
+  auto stage_in = [&](int64_t g, Fin* fin) -> P {
+    P s[6];
 #pragma unroll
-    for (int i = 1; i < D.ns; ++i) {
-      const T s = P.src[i][g];
-      if (keep) raw[i] = s;
-      w += cf[i] * s;
+    for (int i = 0; i < D.ns; ++i) s[i] = ldv<T, VW>(src[i], g);
+    P w = s[0];
+#pragma unroll
+    for (int i = 1; i < D.ns; ++i)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) w.v[e] += cf[i] * s[i].v[e];
+    if constexpr (D.fin != 0) {
+      if (fin == nullptr) return w;  // halo cells need no finish
+      P x[2];
+#pragma unroll
+      for (int i = 0; i < D.nx; ++i) x[i] = ldv<T, VW>(ext[i], g);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        if constexpr (D.fin == 1) {
+          // sources y, k3; extras k1, k2
+          fin->a[e] = s[0].v[e] + b16 * x[0].v[e] + b13 * x[1].v[e] + b13 * s[1].v[e];
+        } else if constexpr (D.fin == 2) {
+          // sources y, k1 .. k5
+          fin->a[e] = s[0].v[e] + q1 * s[1].v[e] + q3 * s[3].v[e] + q4 * s[4].v[e] + q5 * s[5].v[e];
+          if constexpr (D.err)
+            fin->e[e] = h1 * (double)s[1].v[e] + h3 * (double)s[3].v[e] + h4 * (double)s[4].v[e] +
+                        h5 * (double)s[5].v[e];
+        } else {
+          // source ynew; extras partial error, y
+          fin->a[e] = x[0].v[e];
+          fin->b[e] = x[1].v[e];
+        }
+      }
     }
     return w;
   };
-  auto load_plane = [&](int z, T (&w)[2][RY], T (&raw)[NR > 0 ? NR : 1][2][RY], bool with_halo) {
+  auto stage_in1 = [&](int64_t g) -> T {
+    T w = src[0][g];
+#pragma unroll
+    for (int i = 1; i < D.ns; ++i) w += cf[i] * src[i][g];
+    return w;
+  };
+
+  P wp[2][RY], wc[2][RY], wn[2][RY];
+  Fin fc[2][RY], fn[2][RY];
+  P hv[2];  // halo data of this wave's role (scalar in .v[0] for the x-halo role)
+  uint64_t emax = 0;
+
+  auto load_plane = [&](int z, P (&w)[2][RY], Fin (&fin)[2][RY], bool halo) {
     const int64_t zb = (int64_t)z * NN;
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
+      const int64_t fb = f * n3 + zb;
 #pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        const int64_t g = f * n3 + zb + off[r];
-        T tmp[6 + 2];
-        w[f][r] = stage_in(g, tmp, NR > 0);
-        if constexpr (NR > 0) {
-#pragma unroll
-          for (int i = 0; i < D.ns; ++i) raw[i][f][r] = tmp[i];
-#pragma unroll
-          for (int i = 0; i < D.nx; ++i) raw[D.ns + i][f][r] = P.extra[i][g];
-        }
-      }
-      if (with_halo && hval) {
-        T tmp[6 + 2];
-        hw[f] = stage_in(f * n3 + zb + hoff, tmp, false);
+      for (int r = 0; r < RY; ++r) w[f][r] = stage_in(fb + rowoff[r] + gx, &fin[f][r]);
+      if (halo && hact) {
+        if (wv < 2) hv[f] = stage_in(fb + hoff, nullptr);
+        else hv[f].v[0] = stage_in1(fb + hoff);
       }
     }
   };
-  auto store_lds = [&](int b, const T (&w)[2][RY]) {
+  // boundary rows of the strip and the halo role's data go to LDS buffer b
+  auto publish = [&](int b, const P (&w)[2][RY]) {
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-#pragma unroll
-      for (int r = 0; r < RY; ++r) lds[b][f][ly + 4 * r + 1][lx + 1] = w[f][r];
-      if (hval) lds[b][f][hrow][hcol] = hw[f];
+      rows[b][f][1 + 2 * wv][lane] = w[f][0];
+      rows[b][f][2 + 2 * wv][lane] = w[f][RY - 1];
+      if (hact) {
+        if (wv == 0) rows[b][f][0][lane] = hv[f];
+        else if (wv == 1) rows[b][f][9][lane] = hv[f];
+        else xh[b][f][lane >= TY][lane - (lane >= TY) * TY] = hv[f].v[0];
+      }
     }
   };
 
-  if (zbeg < zend) {
-    // prologue: centre of plane zbeg-1, plane zbeg with halo
-    {
-      T dummy[NR > 0 ? NR : 1][2][RY];
-      load_plane((zbeg - 1 + N) % N, wp, dummy, false);
-    }
-    load_plane(zbeg, wc, rawc, true);
-    store_lds(0, wc);
+  // prologue: own rows of plane zbeg-1 (z neighbours), plane zbeg in full
+  {
+    Fin tmpf[2][RY];
+    load_plane((zbeg - 1 + N) % N, wp, tmpf, false);
+  }
+  load_plane(zbeg, wc, fc, true);
+  publish(0, wc);
 
-    for (int z = zbeg; z < zend; ++z) {
-      const int b = (z - zbeg) & 1;
-      load_plane(z + 1 == N ? 0 : z + 1, wn, rawn, true);
-      __syncthreads();
-      const int64_t zb = (int64_t)z * NN;
+  for (int z = zbeg; z < zend; ++z) {
+    const int b = (z - zbeg) & 1;
+    load_plane(z + 1 == N ? 0 : z + 1, wn, fn, true);
+    __syncthreads();
+    const int64_t zb = (int64_t)z * NN;
+    // neighbours across strip boundaries and the x-halo of the strip rows
+    P above[2], below[2];
+    T xlft[2][RY], xrgt[2][RY];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      above[f] = rows[b][f][2 * wv][lane];
+      below[f] = rows[b][f][2 * wv + 3][lane];
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        const int row = ly + 4 * r + 1;
-        T lap[2];
+        xlft[f][r] = xh[b][f][0][wv * RY + r];
+        xrgt[f][r] = xh[b][f][1][wv * RY + r];
+      }
+    }
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
-          const T s = lds[b][f][row][lx] + lds[b][f][row][lx + 2] + lds[b][f][row - 1][lx + 1] +
-                      lds[b][f][row + 1][lx + 1];
-          lap[f] = (s + wp[f][r] + wn[f][r]) - (T)6 * wc[f][r];
+    for (int r = 0; r < RY; ++r) {
+      P fo[2];
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const P& cc = wc[f][r];
+        const P& up = r == 0 ? above[f] : wc[f][r - 1];
+        const P& dn = r == RY - 1 ? below[f] : wc[f][r + 1];
+        const T left = shfl_up1(cc.v[VW - 1]);
+        const T right = shfl_down1(cc.v[0]);
+        const T xm0 = lane == 0 ? xlft[f][r] : left;
+        const T xpN = lane == 63 ? xrgt[f][r] : right;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const T xm = e == 0 ? xm0 : cc.v[e - 1];
+          const T xp = e == VW - 1 ? xpN : cc.v[e + 1];
+          const T s = (xm + xp + up.v[e] + dn.v[e]);
+          fo[f].v[e] = (s + wp[f][r].v[e] + wn[f][r].v[e]) - (T)6 * cc.v[e];
         }
-        const T u = wc[0][r], v = wc[1][r];
+      }
+      // reaction terms
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const T u = wc[0][r].v[e], v = wc[1][r].v[e];
         const T uvv = u * v * v;
-        const T fu = Du * lap[0] - uvv + F * ((T)1 - u);
-        const T fv = Dv * lap[1] + uvv - Fk * v;
-        if (valid[r]) {
-          const int64_t g = zb + off[r];
-          if constexpr (D.final_kind == 0) {
-            P.out[g] = fu;
-            P.out[n3 + g] = fv;
-          } else if constexpr (D.final_kind == 1) {
-            // raw: [0]=y [1]=k3 [2]=k1 [3]=k2
+        const T lu = fo[0].v[e], lv = fo[1].v[e];
+        fo[0].v[e] = Du * lu - uvv + F * ((T)1 - u);
+        fo[1].v[e] = Dv * lv + uvv - Fk * v;
+      }
+      const bool valid = xval && (y0 + r < N);
+      if (valid) {
+        const int64_t g = zb + rowoff[r] + gx;
+        if (D.out >= 0) {
+          stv<T, VW>(out, g, fo[0]);
+          stv<T, VW>(out, n3 + g, fo[1]);
+        }
+        if constexpr (D.fin == 1) {
+          // RK4 new state
 #pragma unroll
-            for (int f = 0; f < 2; ++f) {
-              const T k4 = f ? fv : fu;
-              const T yv = rawc[0][f][r], k3 = rawc[1][f][r], k1 = rawc[2][f][r], k2 = rawc[3][f][r];
-              P.ynew[f * n3 + g] = yv + b16 * k1 + b13 * k2 + b13 * k3 + b16 * k4;
+          for (int f = 0; f < 2; ++f) {
+            P yn;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) yn.v[e] = fc[f][r].a[e] + b16 * fo[f].v[e];
+            stv<T, VW>(ynew, f * n3 + g, yn);
+          }
+        } else if constexpr (D.fin == 2) {
+          // Dopri5 new state (and partial error)
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            P yn, ep;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+              yn.v[e] = fc[f][r].a[e] + q6 * fo[f].v[e];
+              if constexpr (D.err) ep.v[e] = (T)(fc[f][r].e[e] + h6 * (double)fo[f].v[e]);
             }
-          } else {
-            P.ynew[g] = u;
-            P.ynew[n3 + g] = v;
-            P.out[g] = fu;
-            P.out[n3 + g] = fv;
-            if constexpr (D.err) {
-              // raw: [0]=y [1]=k1 [2]=k3 [3]=k4 [4]=k5 [5]=k6
+            stv<T, VW>(ynew, f * n3 + g, yn);
+            if constexpr (D.err) stv<T, VW>(e6, f * n3 + g, ep);
+          }
+        } else if constexpr (D.fin == 3) {
+          // Dopri5 error completion: |E6 + h d7 k7| / (atol + rtol max(|y|, |ynew|))
 #pragma unroll
-              for (int f = 0; f < 2; ++f) {
-                const double k7 = (double)(f ? fv : fu);
-                const double e = e1 * (double)rawc[1][f][r] + e3 * (double)rawc[2][f][r] +
-                                 e4 * (double)rawc[3][f][r] + e5 * (double)rawc[4][f][r] +
-                                 e6 * (double)rawc[5][f][r] + e7 * k7;
-                const double yo = fabs((double)rawc[0][f][r]), yn = fabs((double)(f ? v : u));
-                const double ratio = fabs(e) / (atol + rtol * fmax(yo, yn));
-                const uint64_t bits = (uint64_t)__double_as_longlong(ratio);
-                emax = bits > emax ? bits : emax;
-              }
+          for (int f = 0; f < 2; ++f) {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+              const double err = (double)fc[f][r].a[e] + h7 * (double)fo[f].v[e];
+              const double sc = atol + rtol * fmax(fabs((double)fc[f][r].b[e]), fabs((double)wc[f][r].v[e]));
+              const uint64_t bits = (uint64_t)__double_as_longlong(fabs(err) / sc);
+              emax = bits > emax ? bits : emax;
             }
           }
         }
       }
-      store_lds(b ^ 1, wn);
+    }
+    publish(b ^ 1, wn);
+    // rotate planes
 #pragma unroll
-      for (int f = 0; f < 2; ++f)
+    for (int f = 0; f < 2; ++f) {
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-          wp[f][r] = wc[f][r];
-          wc[f][r] = wn[f][r];
-        }
-      if constexpr (NR > 0) {
-#pragma unroll
-        for (int i = 0; i < NR; ++i)
-#pragma unroll
-          for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int r = 0; r < RY; ++r) rawc[i][f][r] = rawn[i][f][r];
+      for (int r = 0; r < RY; ++r) {
+        wp[f][r] = wc[f][r];
+        wc[f][r] = wn[f][r];
+        if constexpr (D.fin != 0) fc[f][r] = fn[f][r];
       }
     }
   }
 
-  if constexpr (D.err) block_max_to<256>(emax, &c->errmax_bits);
+  if constexpr (D.err && D.fin == 3) {
+    emax = wave_max_u64(emax);
+    if (lane == 0 && emax) atomicMax((unsigned long long*)&c->errmax_bits, (unsigned long long)emax);
+  }
 }
 
-template <typename T, int RY>
+template <typename T, int RY, int VW>
 hipError_t launch_t(int kind, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
-  const int TY = 4 * RY;
-  dim3 grid((a.N + TX - 1) / TX, (a.N + TY - 1) / TY, (a.N + a.zc - 1) / a.zc);
-  dim3 block(256);
+  constexpr int TX = 64 * VW;
+  const int nx = (a.N + TX - 1) / TX;
+  const int ny = (a.N + 4 * RY - 1) / (4 * RY);
+  const int nz = (a.N + a.zc - 1) / a.zc;
+  const int64_t nb = (int64_t)nx * ny * nz;
+  const int64_t grid = (nb + 7) / 8 * 8;  // whole rounds of the XCD remap
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
   switch (kind) {
 #define HODE_CASE(K) \
-  case K: gs_stage<T, K, RY><<<grid, block, 0, s>>>(a, c); break;
+  case K: gs_stage<T, K, RY, VW><<<dim3((unsigned)grid), dim3(256), 0, s>>>(a, c); break;
     HODE_CASE(K_D1) HODE_CASE(K_R2) HODE_CASE(K_R3) HODE_CASE(K_R4) HODE_CASE(K_D2) HODE_CASE(K_D3)
-    HODE_CASE(K_D4) HODE_CASE(K_D5) HODE_CASE(K_D6) HODE_CASE(K_D7) HODE_CASE(K_D7F)
+    HODE_CASE(K_D4) HODE_CASE(K_D5) HODE_CASE(K_D6) HODE_CASE(K_D7) HODE_CASE(K_D7F) HODE_CASE(K_COUNT)
 #undef HODE_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <typename T, int VW>
+hipError_t launch_vw(int kind, int ry, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
+  if (ry == 1) return launch_t<T, 1, VW>(kind, a, c, s);
+  if (ry == 2) return launch_t<T, 2, VW>(kind, a, c, s);
+  if (ry == 4) return launch_t<T, 4, VW>(kind, a, c, s);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 bool gs_ry_supported(int ry) { return ry == 1 || ry == 2 || ry == 4; }
 
+// kind K_COUNT is the fixed-step stage 6 (new state only).
 hipError_t launch_gs(int kind, int dtype, int ry, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
-  if (a.N < 1 || a.zc < 1) return hipErrorInvalidValue;
+  if (a.N < 1 || a.zc < 1 || kind < 0 || kind > K_COUNT) return hipErrorInvalidValue;
   if (dtype == 1) {
-    if (ry == 1) return launch_t<float, 1>(kind, a, c, s);
-    if (ry == 2) return launch_t<float, 2>(kind, a, c, s);
-    if (ry == 4) return launch_t<float, 4>(kind, a, c, s);
-  } else {
-    if (ry == 1) return launch_t<double, 1>(kind, a, c, s);
-    if (ry == 2) return launch_t<double, 2>(kind, a, c, s);
-    if (ry == 4) return launch_t<double, 4>(kind, a, c, s);
+    if (a.N % 4 == 0) return launch_vw<float, 4>(kind, ry, a, c, s);
+    return launch_vw<float, 1>(kind, ry, a, c, s);
   }
-  return hipErrorInvalidValue;
+  if (a.N % 2 == 0) return launch_vw<double, 2>(kind, ry, a, c, s);
+  return launch_vw<double, 1>(kind, ry, a, c, s);
 }
 
 }  // namespace hode

@@ -131,7 +131,7 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
   }
   const hode::GSLaunch a = gs_args(c);
   static const int rk4[] = {hode::K_D1, hode::K_R2, hode::K_R3, hode::K_R4};
-  static const int dp5f[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6, hode::K_D7F};
+  static const int dp5f[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6F, hode::K_D7F};
   static const int dp5a[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6, hode::K_D7};
   const int* seq = mode == hode::MODE_FIXED_RK4 ? rk4 : (mode == hode::MODE_FIXED_DP5 ? dp5f : dp5a);
   const int ns = mode == hode::MODE_FIXED_RK4 ? 4 : 6;
@@ -581,7 +581,7 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
   int rc = check_ready(c);
   if (rc) return rc;
   if (reps < 1 || !avg_ms) return fail(c, HODE_EINVAL, "reps >= 1 and avg_ms required");
-  if (is_gs(c) && (kind < 0 || kind >= hode::K_COUNT)) return fail(c, HODE_EINVAL, "kernel kind");
+  if (is_gs(c) && (kind < 0 || kind > hode::K_D6F)) return fail(c, HODE_EINVAL, "kernel kind");
   if (!is_gs(c) && kind != HODE_RK4 && kind != HODE_DOPRI5) return fail(c, HODE_EINVAL, "kernel kind");
   HIPCHK(c, hipSetDevice(c->device));
   // a control block in timing mode: kernels run with the last step size but
@@ -611,6 +611,90 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
   if (e != hipSuccess) return fail(c, HODE_EHIP, std::string("timing: ") + hipGetErrorString(e));
   *avg_ms = (double)ms / reps;
   if (is_gs(c) && kind == hode::K_D1) c->k1_valid = true;
+  return HODE_OK;
+}
+
+// Stage sequence of one attempt of `method` (adaptive Dopri5 for HODE_DOPRI5).
+static int stage_seq(int method, int* seq) {
+  if (method == HODE_RK4) {
+    const int s[] = {hode::K_D1, hode::K_R2, hode::K_R3, hode::K_R4};
+    for (int i = 0; i < 4; ++i) seq[i] = s[i];
+    return 4;
+  }
+  const int s[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6, hode::K_D7};
+  for (int i = 0; i < 6; ++i) seq[i] = s[i];
+  return 6;
+}
+
+int hode_profile_attempt(hode_ctx* c, int method, int reps, double* ms) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!is_gs(c)) return fail(c, HODE_EINVAL, "stage profiling is for the Gray-Scott path");
+  if (reps < 1 || !ms || (method != HODE_RK4 && method != HODE_DOPRI5)) return fail(c, HODE_EINVAL, "arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  int seq[8];
+  const int ns = stage_seq(method, seq);
+  DevCtrl d = base_ctrl(c, 0);
+  d.h = c->last.dt_next > 0 ? c->last.dt_next : 0.01;
+  *c->h_ctrl = d;
+  HIPCHK(c, hipMemcpyAsync(c->d_ctrl, c->h_ctrl, sizeof(DevCtrl), hipMemcpyHostToDevice, c->stream));
+  const hode::GSLaunch a = gs_args(c);
+  if (method == HODE_DOPRI5 && !c->k1_valid) {
+    HIPCHK(c, hode::launch_gs(hode::K_D1, c->dtype, c->ry, a, c->d_ctrl, c->stream));
+    c->k1_valid = true;
+  }
+  hipEvent_t ev[9];
+  for (int i = 0; i <= ns; ++i) HIPCHK(c, hipEventCreate(&ev[i]));
+  double acc[8] = {0};
+  hipError_t e = hipSuccess;
+  for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // first round is warm-up
+    for (int i = 0; i < ns && e == hipSuccess; ++i) {
+      e = hipEventRecord(ev[i], c->stream);
+      if (e == hipSuccess) e = hode::launch_gs(seq[i], c->dtype, c->ry, a, c->d_ctrl, c->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[ns], c->stream);
+    if (e == hipSuccess) e = hode::launch_ctrl(c->d_ctrl, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[ns]);
+    for (int i = 0; i < ns && e == hipSuccess && r > 0; ++i) {
+      float t = 0;
+      e = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+      acc[i] += t;
+    }
+  }
+  for (int i = 0; i <= ns; ++i) hipEventDestroy(ev[i]);
+  HIPCHK(c, e);
+  for (int i = 0; i < ns; ++i) ms[i] = acc[i] / reps;
+  return HODE_OK;
+}
+
+int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc, double* best_ms) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!is_gs(c)) return fail(c, HODE_EINVAL, "autotuning is for the Gray-Scott path");
+  const int rys[] = {1, 2, 4};
+  const int zcs[] = {8, 16, 32, 64, 128, 256};
+  double best = 1e300;
+  int bry = c->ry, bzc = c->zc;
+  for (int ry : rys) {
+    for (int zc : zcs) {
+      if (zc > c->N && zc != zcs[0]) continue;
+      c->ry = ry;
+      c->zc = zc;
+      double ms[8];
+      rc = hode_profile_attempt(c, method, reps, ms);
+      if (rc) return rc;
+      const int ns = method == HODE_RK4 ? 4 : 6;
+      double tot = 0;
+      for (int i = 0; i < ns; ++i) tot += ms[i];
+      if (tot < best) { best = tot; bry = ry; bzc = zc; }
+    }
+  }
+  c->ry = bry;
+  c->zc = bzc;
+  clear_graphs(c);
+  if (best_ry) *best_ry = bry;
+  if (best_zc) *best_zc = bzc;
+  if (best_ms) *best_ms = best;
   return HODE_OK;
 }
 

@@ -10,11 +10,13 @@ namespace hode {
 
 // Stage kernels of the Gray-Scott path.  D1 computes k1 = f(y) (also the
 // first RK4 stage); R2..R4 are the remaining RK4 stages (R4 also forms the new
-// state); D2..D7 are the Dopri5 stages (D7 forms the new state, k7 and the
-// error norm; D7F is the fixed-step variant without the error norm).  The
-// control kernel follows the final stage of every attempt.
+// state); D2..D5 are Dopri5 stages 2..5; D6 forms k6 and from it the new state
+// and the partial error sum (D6F: new state only); D7 evaluates k7 = f(ynew)
+// and completes the error norm (D7F: k7 only).  The control kernel follows the
+// final stage of every attempt.
 enum GSKind : int {
-  K_D1 = 0, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_COUNT
+  K_D1 = 0, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_COUNT,
+  K_D6F = K_COUNT  // fixed-step stage 6: the new state only
 };
 
 struct GSLaunch {

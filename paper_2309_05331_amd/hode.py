@@ -24,7 +24,7 @@ TRACE_W = 8
 MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 
 # Gray-Scott stage kernels, as numbered by hode_time_kernel
-K_D1, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F = range(11)
+K_D1, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_D6F = range(12)
 
 
 class hode_stats(C.Structure):
@@ -72,6 +72,9 @@ def lib():
             "hode_set_tile": ([P, I, I], I),
             "hode_get_tile": ([P, C.POINTER(I), C.POINTER(I)], I),
             "hode_time_kernel": ([P, I, I, C.POINTER(D)], I),
+            "hode_profile_attempt": ([P, I, I, C.POINTER(D)], I),
+            "hode_autotune": ([P, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)], I),
+            "hode_stream_copy": ([P, P, S, I, C.POINTER(D)], I),
             "hode_last_error": ([P], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -80,6 +83,17 @@ def lib():
             f.restype = res
         _lib = L
     return _lib
+
+
+def stream_copy(dst, src, reps=20):
+    """Times the reference copy kernel between two equal-size device tensors;
+    returns (ms per copy, GB/s counting read + write)."""
+    ms = C.c_double()
+    nb = src.numel() * src.element_size()
+    rc = lib().hode_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nb, reps, C.byref(ms))
+    if rc != OK:
+        raise HodeError(rc, "stream copy")
+    return ms.value, 2 * nb / (ms.value * 1e-3) / 1e9
 
 
 def exported_symbols():
@@ -206,6 +220,16 @@ class Context:
         a, b = C.c_int(), C.c_int()
         self._check(self.L.hode_get_tile(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def profile_attempt(self, method, reps):
+        ms = (C.c_double * 8)()
+        self._check(self.L.hode_profile_attempt(self.h, method, reps, ms))
+        return list(ms)[: (4 if method == RK4 else 6)]
+
+    def autotune(self, method, reps=3):
+        ry, zc, ms = C.c_int(), C.c_int(), C.c_double()
+        self._check(self.L.hode_autotune(self.h, method, reps, C.byref(ry), C.byref(zc), C.byref(ms)))
+        return ry.value, zc.value, ms.value
 
     def time_kernel(self, kind, reps):
         ms = C.c_double()

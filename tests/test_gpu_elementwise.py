@@ -38,7 +38,7 @@ def test_adaptive_fp64_free_and_replay(orc, kind, n):
     ctx = ew_ctx(kind, x0)
     ctx.set_tolerances(1e-6, 1e-6)
     ctx.set_trace(10000)
-    st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01, max_steps=200000)
     g = read(ctx, np.float64, n)
     tr = ctx.read_trace()
     sysd = orc.ew_system(kind, n)
@@ -66,7 +66,7 @@ def test_adaptive_fp32_replay_maxabs(orc, kind):
     x32 = x0.astype(np.float32)
     ctx = ew_ctx(kind, x32)
     ctx.set_trace(10000)
-    st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01, max_steps=200000)
     assert st["status"] == 0 and st["t"] == 5.0
     g = read(ctx, np.float32, n)
     tr = ctx.read_trace()
@@ -87,7 +87,7 @@ def test_full_size_fp64_adaptive_exp(orc):
     x0 = inputs.exp_family_x0(n, seed=2)
     for kind in (hode.RHS_EXP, hode.RHS_LOGISTIC):
         ctx = ew_ctx(kind, x0)
-        st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+        st = ctx.integrate_adaptive(0.0, 5.0, 0.01, max_steps=200000)
         g = read(ctx, np.float64, n)
         o, ost, _ = orc.integrate_adaptive(orc.ew_system(kind, n), x0, 0.0, 5.0, 0.01, 1e-6, 1e-6)
         assert (st["accepted"], st["rejected"]) == (ost["accepted"], ost["rejected"])
@@ -103,27 +103,27 @@ def test_failure_modes_and_edges(orc):
     bad = x0.copy()
     bad[17] = np.nan
     ctx = ew_ctx(hode.RHS_EXP, bad)
-    st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01, max_steps=200000)
     assert st["status"] == hode.ENONFINITE and st["accepted"] == 0
     assert np.isnan(read(ctx, np.float64, 1000)[17])
     ctx = ew_ctx(hode.RHS_EXP, x0)
     ctx.set_tolerances(1e-300, 1e-300)
-    st = ctx.integrate_adaptive(0.0, 5.0, 0.01)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01, max_steps=200000)
     assert st["status"] == hode.EDT_UNDERFLOW and st["t"] < 5.0
     # t1 == t0: nothing happens
     ctx = ew_ctx(hode.RHS_EXP, x0)
-    st = ctx.integrate_adaptive(1.0, 1.0, 0.01)
+    st = ctx.integrate_adaptive(1.0, 1.0, 0.01, max_steps=200000)
     assert st["accepted"] == 0 and st["status"] == 0
     assert np.array_equal(read(ctx, np.float64, 1000), x0)
     # empty state
     ctx = ew_ctx(hode.RHS_EXP, np.zeros(0))
-    st = ctx.integrate_adaptive(0.0, 1.0, 0.1)
+    st = ctx.integrate_adaptive(0.0, 1.0, 0.1, max_steps=200000)
     assert st["status"] == 0 and st["t"] == 1.0
     # argument errors
     with pytest.raises(hode.HodeError):
         ctx.set_tolerances(0.0, 0.0)
     with pytest.raises(hode.HodeError):
-        ctx.integrate_adaptive(1.0, 0.0, 0.1)
+        ctx.integrate_adaptive(1.0, 0.0, 0.1, max_steps=200000)
     ctx = ew_ctx(hode.RHS_EXP, x0)
     with pytest.raises(hode.HodeError):
         ctx.read_state(np.empty(999))  # destination too small
