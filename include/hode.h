@@ -153,6 +153,10 @@ int hode_eval_rhs(hode_ctx *ctx, void *dst, size_t dst_bytes, int dst_on_device)
 int hode_set_tile(hode_ctx *ctx, int ry, int zc);
 int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);
 
+/* Gray-Scott cells per lane (1, 2 or 4; fp64 at most 2; must divide N), or 0
+ * for the widest that divides N (16-byte loads where possible). */
+int hode_set_vector_width(hode_ctx *ctx, int vw);
+
 /* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..10 as D1,
  * R2, R3, R4, D2..D7, D7F; element-wise: kind = method) on the context's
  * stream with HIP events and returns the mean duration in milliseconds.
@@ -178,6 +182,52 @@ int hode_autotune(hode_ctx *ctx, int method, int reps, int *best_ry, int *best_z
  * mean duration per copy in milliseconds.  Used as the achievable-bandwidth
  * ceiling and to calibrate HBM traffic counters. */
 int hode_stream_copy(void *dst, const void *src, size_t bytes, int reps, double *avg_ms);
+
+/* ---- batched ensemble ------------------------------------------------------
+ * n independent Gray-Scott instances (uneven grid edges and parameters), each
+ * with its own adaptive Dopri5 step control, stepped together by ONE
+ * persistent kernel launch (captured in a hipGraph): workgroups form gangs per
+ * instance (large grids get several workgroups splitting z-slabs, small ones
+ * one) following a static longest-processing-time schedule built on the host
+ * from per-instance work weights.  Every instance's arithmetic is the same as
+ * the single-grid path's, so results are bitwise those of running the
+ * instance alone. */
+
+/* Creates an ensemble context: instance i has grid edge edges[i] (1..1024) and
+ * params[5*i .. 5*i+4] = {Du, Dv, F, k, L}; dtype HODE_F32 or HODE_F64.  All
+ * instance buffers are allocated here (9 arrays of 2 N^3 elements each). */
+int hode_ensemble_create(hode_ctx **out, int device, void *stream, int n, const int64_t *edges,
+                         const double *params, int dtype);
+int hode_ensemble_size(const hode_ctx *ctx);
+
+/* Copies instance i's initial state in (layout as hode_init_state). */
+int hode_ensemble_init_state(hode_ctx *ctx, int i, const void *src, int src_on_device);
+int hode_ensemble_read_state(hode_ctx *ctx, int i, void *dst, size_t dst_bytes, int dst_on_device);
+
+/* Work weights (> 0) for the gang scheduler, one per instance (default:
+ * N^3 (1 + N/64)). */
+int hode_ensemble_set_weights(hode_ctx *ctx, const double *w);
+
+/* Cells per lane of instance i's tiles: 1, 2 or 4 (fp64: 1 or 2), dividing N. */
+int hode_ensemble_set_vector_width(hode_ctx *ctx, int i, int vw);
+
+/* Per-instance attempt traces (8 doubles per attempt, as hode_set_trace). */
+int hode_ensemble_set_trace(hode_ctx *ctx, int64_t capacity);
+int hode_ensemble_read_trace(hode_ctx *ctx, int i, double *dst, int64_t cap, int64_t *n);
+
+/* Tile autotuner of the ensemble: for every distinct grid edge, times one
+ * Dopri5 attempt (reps repetitions) of one of its instances for each vector
+ * width (cells per lane) and keeps the fastest; the scheduler's work weights
+ * become the measured attempt times.  vw_out/ms_out (n entries each, may be
+ * NULL) receive the choice and the attempt time per instance. */
+int hode_ensemble_autotune(hode_ctx *ctx, int reps, int *vw_out, double *ms_out);
+
+/* Integrates every instance from t0 to t1 (first trial step dt0, at most
+ * max_steps attempts each; tolerances and controller of the context).
+ * per_instance (may be NULL) receives n stats.  Returns HODE_OK, the first
+ * failing instance's status, or HODE_EHIP if a gang barrier timed out. */
+int hode_ensemble_integrate_adaptive(hode_ctx *ctx, double t0, double t1, double dt0, int64_t max_steps,
+                                     hode_stats *per_instance);
 
 /* Text of the last error on this context (valid until the next call). */
 const char *hode_last_error(const hode_ctx *ctx);

@@ -29,7 +29,12 @@ def hipcc() -> str:
 
 
 def flags():
-    return ["-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
+    # -ffp-contract=on: fused multiply-adds only where one source expression
+    # asks for them, so the rounding of every cell update is fixed by the
+    # source and does not depend on inlining or tiling (bitwise-equal results
+    # across tile shapes and between the ensemble and single-grid paths)
+    return ["-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
+            "-I" + INCLUDE, "-I" + CSRC,
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
 
 

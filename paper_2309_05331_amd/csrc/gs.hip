@@ -102,6 +102,8 @@ struct VecT;
 template <>
 struct VecT<float, 4> { using type = float4; };
 template <>
+struct VecT<float, 2> { using type = float2; };
+template <>
 struct VecT<float, 1> { using type = float; };
 template <>
 struct VecT<double, 2> { using type = double2; };
@@ -139,39 +141,35 @@ __device__ __forceinline__ T shfl_down1(T v) {
   return __shfl_down(v, 1, 64);
 }
 
+// Bytes of LDS one stage tile needs (the largest over all instantiations).
+constexpr int kTileSmem = 2 * 2 * 10 * 64 * 16 + 2 * 2 * 2 * 16 * 8;
+
+// One stage over one tile: columns x0 .. x0 + 64*VW - 1, rows ty*4*RY ..
+// (ty+1)*4*RY - 1, planes zbeg .. zend - 1 of the grid described by `a`, with
+// step h, parity and first-same-as-last slot taken from the control block.
+// Called by all 256 threads of a workgroup; smem is kTileSmem bytes of LDS.
 template <typename T, int KIND, int RY, int VW>
-__global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __restrict__ c) {
+__device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* smem, int tx, int ty, int zbeg,
+                           int zend) {
   constexpr KindDesc D = desc<KIND>();
   constexpr int TX = 64 * VW;
   constexpr int TY = 4 * RY;
   using P = Pk<T, VW>;
+  static_assert(2 * 2 * 10 * 64 * sizeof(P) + 2 * 2 * 2 * TY * sizeof(T) <= kTileSmem, "LDS budget");
   // LDS per buffer and field: 10 row slots (tile halo above, first and last
-  // row of each wave's strip, tile halo below) and the 2 x 16 x-halo cells
-  __shared__ P rows[2][2][10][64];
-  __shared__ T xh[2][2][2][TY];
+  // row of each wave's strip, tile halo below) and the x-halo cells
+  P(*rows)[2][10][64] = reinterpret_cast<P(*)[2][10][64]>(smem);
+  T(*xh)[2][2][TY] = reinterpret_cast<T(*)[2][2][TY]>(smem + 2 * 2 * 10 * 64 * sizeof(P));
+  __syncthreads();  // LDS may still be in use by the previous tile
 
-  if (c->done) return;
   const double h = c->h;
   const int p = c->parity, ksl = c->k1slot;
   const int N = a.N;
   const int64_t n3 = a.n3;
   const int64_t NN = (int64_t)N * N;
-
-  // ---- which tile: XCD-aware remap of the linear block id
-  const int nx = (N + TX - 1) / TX;
-  const int ny = (N + TY - 1) / TY;
-  const int nz = (N + a.zc - 1) / a.zc;
-  const int per = (gridDim.x + 7) / 8;
-  const int bb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (bb >= nx * ny * nz) return;  // padding block of the remap (whole block)
-  const int tx = bb % nx;
-  const int ty = (bb / nx) % ny;
-  const int tz = bb / (nx * ny);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x0 = tx * TX, yt = ty * TY;
   const int y0 = yt + wv * RY;  // first row of this wave's strip
-  const int zbeg = tz * a.zc;
-  const int zend = min(N, zbeg + a.zc);
 
   const T* src[6];
 #pragma unroll
@@ -414,6 +412,25 @@ __global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __res
   }
 }
 
+// One stage over a whole grid: one tile per workgroup.  The linear block id
+// is remapped XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so
+// each XCD gets a contiguous range of tiles and y/z-adjacent tiles (whose
+// halo rows overlap) share an L2.
+template <typename T, int KIND, int RY, int VW>
+__global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __restrict__ c) {
+  __shared__ __align__(16) char smem[kTileSmem];
+  if (c->done) return;
+  const int N = a.N;
+  const int nx = (N + 64 * VW - 1) / (64 * VW);
+  const int ny = (N + 4 * RY - 1) / (4 * RY);
+  const int nz = (N + a.zc - 1) / a.zc;
+  const int per = (gridDim.x + 7) / 8;
+  const int bb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (bb >= nx * ny * nz) return;  // padding block of the remap (whole block)
+  const int tz = bb / (nx * ny);
+  stage_tile<T, KIND, RY, VW>(a, c, smem, bb % nx, (bb / nx) % ny, tz * a.zc, min(N, (tz + 1) * a.zc));
+}
+
 template <typename T, int RY, int VW>
 hipError_t launch_t(int kind, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
   constexpr int TX = 64 * VW;
@@ -442,19 +459,146 @@ hipError_t launch_vw(int kind, int ry, const GSLaunch& a, DevCtrl* c, hipStream_
   return hipErrorInvalidValue;
 }
 
+// ---- the persistent ensemble kernel -------------------------------------------
+// Every workgroup walks its ordered list of gang memberships.  A gang steps
+// one instance: its members split the instance's z-planes into slabs, run
+// each stage over their slab, and meet at a gang barrier (an atomic arrival
+// counter per instance, agent-scope release/acquire) before the next stage,
+// because the next stage reads neighbour cells across slab boundaries.  The
+// rank-0 member runs the step controller of the instance after stage 7.
+// Memberships are listed in one global order on every workgroup, so a
+// workgroup only ever waits for members that are running or reach the gang
+// after finishing earlier gangs: no circular wait.  A barrier that waits
+// longer than spin_limit polls flags an error and every workgroup leaves.
+
+__device__ inline bool ens_error(const EnsSched& s) {
+  return __hip_atomic_load(s.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__device__ inline void gang_sync(EnsInst* I, uint32_t& gen, const EnsSched& s) {
+  __syncthreads();
+  const int g = I->gang;
+  if (g > 1) {
+    if (threadIdx.x == 0) {
+      __threadfence();  // release this workgroup's stage outputs
+      atomicAdd(&I->bar, 1u);
+      const uint32_t target = (gen + 1) * (uint32_t)g;
+      int64_t spins = 0;
+      while (__hip_atomic_load(&I->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > s.spin_limit) {
+          atomicExch(s.error, 1u);
+          break;
+        }
+        if ((spins & 255) == 0 && ens_error(s)) break;
+      }
+      __threadfence();  // acquire the other members' outputs
+    }
+    __syncthreads();
+  }
+  ++gen;
+}
+
+// Not inlined: each stage variant keeps its own register allocation, so the
+// persistent kernel's budget is the largest single stage, not their union.
+template <typename T, int KIND, int VW>
+__device__ __noinline__ void ens_slab_vw(EnsInst* I, char* smem, int z0, int z1) {
+  const int N = I->a.N;
+  const int nx = (N + 64 * VW - 1) / (64 * VW), ny = (N + 3) / 4;
+  for (int ty = 0; ty < ny; ++ty)
+    for (int tx = 0; tx < nx; ++tx) stage_tile<T, KIND, 1, VW>(I->a, &I->ctrl, smem, tx, ty, z0, z1);
+}
+
+template <typename T, int KIND>
+__device__ void ens_slab(EnsInst* I, char* smem, int z0, int z1) {
+  if constexpr (sizeof(T) == 4) {
+    if (I->vw == 4) return ens_slab_vw<T, KIND, 4>(I, smem, z0, z1);
+    if (I->vw == 2) return ens_slab_vw<T, KIND, 2>(I, smem, z0, z1);
+  } else {
+    if (I->vw == 2) return ens_slab_vw<T, KIND, 2>(I, smem, z0, z1);
+  }
+  ens_slab_vw<T, KIND, 1>(I, smem, z0, z1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 3) void ens_kernel(EnsInst* __restrict__ inst, const EnsSched s) {
+  __shared__ __align__(16) char smem[kTileSmem];
+  __shared__ int s_stop;
+  // block-uniform view of the error flag and of the instance's done flag
+  auto stop = [&](const EnsInst* I) -> bool {
+    __syncthreads();
+    if (threadIdx.x == 0)
+      s_stop = ens_error(s) ? 2 : (I && __hip_atomic_load(&I->ctrl.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    __syncthreads();
+    return s_stop != 0;
+  };
+  const int w = blockIdx.x;
+  for (int it = s.offs[w]; it < s.offs[w + 1]; ++it) {
+    const EnsWork wk = s.items[it];
+    EnsInst* I = &inst[wk.inst];
+    uint32_t gen = 0;
+    gang_sync(I, gen, s);  // all members present
+    ens_slab<T, K_D1>(I, smem, wk.z0, wk.z1);
+    gang_sync(I, gen, s);
+    while (!stop(I)) {
+      ens_slab<T, K_D2>(I, smem, wk.z0, wk.z1);
+      gang_sync(I, gen, s);
+      ens_slab<T, K_D3>(I, smem, wk.z0, wk.z1);
+      gang_sync(I, gen, s);
+      ens_slab<T, K_D4>(I, smem, wk.z0, wk.z1);
+      gang_sync(I, gen, s);
+      ens_slab<T, K_D5>(I, smem, wk.z0, wk.z1);
+      gang_sync(I, gen, s);
+      ens_slab<T, K_D6>(I, smem, wk.z0, wk.z1);
+      gang_sync(I, gen, s);
+      ens_slab<T, K_D7>(I, smem, wk.z0, wk.z1);
+      gang_sync(I, gen, s);
+      if (wk.rank == 0) {
+        __threadfence();
+        ctrl_step(&I->ctrl);
+        __threadfence();
+      }
+      gang_sync(I, gen, s);
+    }
+    if (s_stop == 2) return;  // error: every workgroup leaves
+  }
+}
+
 }  // namespace
 
 bool gs_ry_supported(int ry) { return ry == 1 || ry == 2 || ry == 4; }
 
-// kind K_COUNT is the fixed-step stage 6 (new state only).
-hipError_t launch_gs(int kind, int dtype, int ry, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
+// kind K_COUNT is the fixed-step stage 6 (new state only).  vw: cells per
+// lane (0 = widest that divides N: 16-byte loads when possible).
+hipError_t launch_gs(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
   if (a.N < 1 || a.zc < 1 || kind < 0 || kind > K_COUNT) return hipErrorInvalidValue;
   if (dtype == 1) {
-    if (a.N % 4 == 0) return launch_vw<float, 4>(kind, ry, a, c, s);
-    return launch_vw<float, 1>(kind, ry, a, c, s);
+    if (vw == 0) vw = a.N % 4 == 0 ? 4 : (a.N % 2 == 0 ? 2 : 1);
+    if (a.N % vw) return hipErrorInvalidValue;
+    if (vw == 4) return launch_vw<float, 4>(kind, ry, a, c, s);
+    if (vw == 2) return launch_vw<float, 2>(kind, ry, a, c, s);
+    if (vw == 1) return launch_vw<float, 1>(kind, ry, a, c, s);
+    return hipErrorInvalidValue;
   }
-  if (a.N % 2 == 0) return launch_vw<double, 2>(kind, ry, a, c, s);
-  return launch_vw<double, 1>(kind, ry, a, c, s);
+  if (vw == 0) vw = a.N % 2 == 0 ? 2 : 1;
+  if (a.N % vw) return hipErrorInvalidValue;
+  if (vw == 2) return launch_vw<double, 2>(kind, ry, a, c, s);
+  if (vw == 1) return launch_vw<double, 1>(kind, ry, a, c, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ensemble(int dtype, EnsInst* inst, EnsSched s, int nwg, hipStream_t st) {
+  if (nwg < 1) return hipErrorInvalidValue;
+  if (dtype == 1) ens_kernel<float><<<nwg, 256, 0, st>>>(inst, s);
+  else ens_kernel<double><<<nwg, 256, 0, st>>>(inst, s);
+  return hipGetLastError();
+}
+
+int ensemble_blocks_per_cu(int dtype) {
+  int n = 0;
+  hipError_t e = dtype == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<float>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<double>, 256, 0);
+  return e == hipSuccess ? n : 0;
 }
 
 }  // namespace hode

@@ -14,8 +14,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <new>
+#include <queue>
+#include <vector>
 #include <string>
 #include <utility>
 
@@ -23,6 +26,29 @@
 #include "hode_internal.h"
 
 using hode::DevCtrl;
+
+// ---- batched ensemble: host side -----------------------------------------------
+struct Ensemble {
+  int n = 0, dtype = 0;
+  std::vector<int> N;
+  std::vector<double> prm;  // n x {Du, Dv, F, k, L}
+  std::vector<hode::EnsInst> inst;
+  std::vector<int> parity, vw;
+  std::vector<double> weight;
+  std::vector<int64_t> attempts_last;
+  void* pool = nullptr;
+  hode::EnsInst* d_inst = nullptr;
+  hode::EnsWork* d_items = nullptr;
+  int32_t* d_offs = nullptr;
+  uint32_t* d_err = nullptr;
+  size_t items_cap = 0;
+  int nwg = 0;
+  double* d_trace = nullptr;
+  int64_t trace_cap = 0;
+  hipGraphExec_t graph = nullptr;
+  std::vector<int> gang;
+};
+
 
 struct hode_ctx {
   int device = 0;
@@ -45,7 +71,7 @@ struct hode_ctx {
   uint16_t* d_mlp = nullptr;
   int ctrl_kind = hode::CTRL_PI;
   double atol = 1e-6, rtol = 1e-6;
-  int ry = 0, zc = 0, ew_grid = 0;
+  int ry = 0, zc = 0, ew_grid = 0, vw = 0;
   bool k1_valid = false;
   int parity = 0, k1slot = 0;
   bool persist_valid = false;  // controller history carried between try_step calls
@@ -54,6 +80,7 @@ struct hode_ctx {
   int64_t last_attempts = 0;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   std::string err;
+  Ensemble* ens = nullptr;
 };
 
 namespace {
@@ -136,7 +163,7 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
   const int* seq = mode == hode::MODE_FIXED_RK4 ? rk4 : (mode == hode::MODE_FIXED_DP5 ? dp5f : dp5a);
   const int ns = mode == hode::MODE_FIXED_RK4 ? 4 : 6;
   for (int i = 0; i < ns; ++i) {
-    hipError_t e = hode::launch_gs(seq[i], c->dtype, c->ry, a, c->d_ctrl, c->stream);
+    hipError_t e = hode::launch_gs(seq[i], c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream);
     if (e != hipSuccess) return e;
   }
   return hode::launch_ctrl(c->d_ctrl, c->stream);
@@ -182,7 +209,7 @@ DevCtrl base_ctrl(const hode_ctx* c, int mode) {
 int launch_k1(hode_ctx* c) {
   if (!is_gs(c)) return HODE_OK;
   const hode::GSLaunch a = gs_args(c);
-  HIPCHK(c, hode::launch_gs(hode::K_D1, c->dtype, c->ry, a, c->d_ctrl, c->stream));
+  HIPCHK(c, hode::launch_gs(hode::K_D1, c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream));
   return HODE_OK;
 }
 
@@ -244,6 +271,61 @@ int check_ready(hode_ctx* c) {
   return HODE_OK;
 }
 
+void free_ensemble(hode_ctx* c) {
+  Ensemble* e = c ? c->ens : nullptr;
+  if (!e) return;
+  if (e->graph) hipGraphExecDestroy(e->graph);
+  if (e->pool) hipFree(e->pool);
+  if (e->d_inst) hipFree(e->d_inst);
+  if (e->d_items) hipFree(e->d_items);
+  if (e->d_offs) hipFree(e->d_offs);
+  if (e->d_err) hipFree(e->d_err);
+  if (e->d_trace) hipFree(e->d_trace);
+  delete e;
+  c->ens = nullptr;
+}
+
+// Static longest-processing-time gang schedule.  Instances are taken in
+// decreasing work; each gets g workgroups (its share of the total work, at
+// least 1, at most one per 8 z-planes) chosen among the earliest-free ones;
+// the gang starts when its last member is free.  Every workgroup's list is in
+// this one global order, which rules out circular waits between gangs.
+void build_schedule(const Ensemble& e, int G, std::vector<std::vector<hode::EnsWork>>& lists,
+                    std::vector<int>& gang) {
+  const int n = e.n;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return e.weight[a] > e.weight[b]; });
+  double total = 0;
+  for (double w : e.weight) total += w;
+  const double unit = total / G;
+  lists.assign(G, {});
+  gang.assign(n, 1);
+  using Slot = std::pair<double, int>;  // (free at, workgroup)
+  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> q;
+  for (int w = 0; w < G; ++w) q.push({0.0, w});
+  for (int i : order) {
+    const int maxg = std::max(1, std::min(G, e.N[i] / 8));
+    int g = (int)std::lround(e.weight[i] / (unit > 0 ? unit : 1.0));
+    g = std::max(1, std::min(g, maxg));
+    std::vector<Slot> pick;
+    for (int k = 0; k < g; ++k) {
+      pick.push_back(q.top());
+      q.pop();
+    }
+    double start = 0;
+    for (auto& sl : pick) start = std::max(start, sl.first);
+    std::sort(pick.begin(), pick.end(), [](const Slot& a, const Slot& b) { return a.second < b.second; });
+    const double end = start + e.weight[i] / g;
+    for (int r = 0; r < g; ++r) {
+      const int z0 = (int)((int64_t)e.N[i] * r / g), z1 = (int)((int64_t)e.N[i] * (r + 1) / g);
+      lists[pick[r].second].push_back({i, z0, z1, r});
+      q.push({end, pick[r].second});
+    }
+    gang[i] = g;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -287,6 +369,7 @@ void hode_destroy(hode_ctx* c) {
   if (c->h_ctrl) hipHostFree(c->h_ctrl);
   if (c->d_trace) hipFree(c->d_trace);
   if (c->d_mlp) hipFree(c->d_mlp);
+  free_ensemble(c);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -570,6 +653,16 @@ int hode_set_tile(hode_ctx* c, int ry, int zc) {
   return HODE_OK;
 }
 
+int hode_set_vector_width(hode_ctx* c, int vw) {
+  if (!c) return HODE_EINVAL;
+  if (vw != 0 && vw != 1 && vw != 2 && vw != 4) return fail(c, HODE_EINVAL, "vector width 0, 1, 2 or 4");
+  if (vw && c->dtype == HODE_F64 && vw > 2) return fail(c, HODE_EINVAL, "fp64 vector width at most 2");
+  if (vw && c->N && c->N % vw) return fail(c, HODE_EINVAL, "vector width must divide N");
+  c->vw = vw;
+  clear_graphs(c);
+  return HODE_OK;
+}
+
 int hode_get_tile(const hode_ctx* c, int* ry, int* zc) {
   if (!c || !ry || !zc) return HODE_EINVAL;
   *ry = c->ry;
@@ -595,7 +688,7 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
   HIPCHK(c, hipEventCreate(&e1));
   const hode::GSLaunch a = is_gs(c) ? gs_args(c) : hode::GSLaunch{};
   auto launch = [&]() -> hipError_t {
-    if (is_gs(c)) return hode::launch_gs(kind, c->dtype, c->ry, a, c->d_ctrl, c->stream);
+    if (is_gs(c)) return hode::launch_gs(kind, c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream);
     const int mode = kind == HODE_RK4 ? hode::MODE_FIXED_RK4 : hode::MODE_ADAPTIVE;
     return hode::launch_ew(c->dtype, c->rhs, mode, c->y[0], c->y[1], c->nelem, c->ew_grid, c->d_ctrl, c->stream);
   };
@@ -640,7 +733,7 @@ int hode_profile_attempt(hode_ctx* c, int method, int reps, double* ms) {
   HIPCHK(c, hipMemcpyAsync(c->d_ctrl, c->h_ctrl, sizeof(DevCtrl), hipMemcpyHostToDevice, c->stream));
   const hode::GSLaunch a = gs_args(c);
   if (method == HODE_DOPRI5 && !c->k1_valid) {
-    HIPCHK(c, hode::launch_gs(hode::K_D1, c->dtype, c->ry, a, c->d_ctrl, c->stream));
+    HIPCHK(c, hode::launch_gs(hode::K_D1, c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream));
     c->k1_valid = true;
   }
   hipEvent_t ev[9];
@@ -650,7 +743,7 @@ int hode_profile_attempt(hode_ctx* c, int method, int reps, double* ms) {
   for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // first round is warm-up
     for (int i = 0; i < ns && e == hipSuccess; ++i) {
       e = hipEventRecord(ev[i], c->stream);
-      if (e == hipSuccess) e = hode::launch_gs(seq[i], c->dtype, c->ry, a, c->d_ctrl, c->stream);
+      if (e == hipSuccess) e = hode::launch_gs(seq[i], c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream);
     }
     if (e == hipSuccess) e = hipEventRecord(ev[ns], c->stream);
     if (e == hipSuccess) e = hode::launch_ctrl(c->d_ctrl, c->stream);
@@ -695,6 +788,310 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   if (best_ry) *best_ry = bry;
   if (best_zc) *best_zc = bzc;
   if (best_ms) *best_ms = best;
+  return HODE_OK;
+}
+
+int hode_ensemble_create(hode_ctx** out, int device, void* stream, int n, const int64_t* edges,
+                         const double* params, int dtype) {
+  if (!out || n < 1 || !edges || !params || (dtype != HODE_F32 && dtype != HODE_F64)) return HODE_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (edges[i] < 1 || edges[i] > 1024) return HODE_EINVAL;
+    for (int j = 0; j < 5; ++j)
+      if (!std::isfinite(params[5 * i + j])) return HODE_EINVAL;
+    if (!(params[5 * i + 4] > 0)) return HODE_EINVAL;
+  }
+  int rc = hode_create(out, device, stream);
+  if (rc) return rc;
+  hode_ctx* c = *out;
+  Ensemble* e = new (std::nothrow) Ensemble();
+  if (!e) { hode_destroy(c); *out = nullptr; return HODE_ENOMEM; }
+  c->ens = e;
+  c->rhs = HODE_RHS_GRAYSCOTT3D;
+  c->dtype = dtype;
+  c->esize = dtype == HODE_F32 ? 4 : 8;
+  e->n = n;
+  e->dtype = dtype;
+  e->N.assign(edges, edges + n);
+  e->prm.assign(params, params + 5 * n);
+  e->parity.assign(n, 0);
+  e->vw.assign(n, 0);
+  e->attempts_last.assign(n, 0);
+  e->weight.resize(n);
+  e->inst.resize(n);
+  // default work weights: cells x an attempt count that grows like N^2 (the
+  // explicit stability limit of the 7-point Laplacian shrinks like 1/N^2)
+  for (int i = 0; i < n; ++i) {
+    const double Nd = (double)e->N[i];
+    e->weight[i] = Nd * Nd * Nd * (64.0 + Nd * Nd);
+  }
+  // one pool: 9 arrays of 2 N^3 elements per instance, 256-byte aligned
+  std::vector<size_t> off(n);
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    off[i] = tot;
+    const size_t ab = ((size_t)2 * e->N[i] * e->N[i] * e->N[i] * c->esize + 255) / 256 * 256;
+    tot += 9 * ab;
+  }
+  if (hipMalloc(&e->pool, tot) != hipSuccess) { hode_destroy(c); *out = nullptr; return HODE_ENOMEM; }
+  for (int i = 0; i < n; ++i) {
+    const int Ni = e->N[i];
+    const size_t ab = ((size_t)2 * Ni * Ni * Ni * c->esize + 255) / 256 * 256;
+    char* b = (char*)e->pool + off[i];
+    hode::EnsInst& I = e->inst[i];
+    std::memset(&I, 0, sizeof(I));
+    I.a.y[0] = b;
+    I.a.y[1] = b + ab;
+    I.a.ks[0] = b + 2 * ab;
+    I.a.ks[1] = b + 3 * ab;
+    for (int k = 2; k <= 6; ++k) I.a.k[k] = b + (2 + k) * ab;
+    I.a.N = Ni;
+    I.a.n3 = (int64_t)Ni * Ni * Ni;
+    I.a.zc = Ni;
+    const double hh = params[5 * i + 4] / Ni;
+    I.a.Du_h2 = params[5 * i + 0] / (hh * hh);
+    I.a.Dv_h2 = params[5 * i + 1] / (hh * hh);
+    I.a.F = params[5 * i + 2];
+    I.a.kk = params[5 * i + 3];
+    const int maxvw = dtype == HODE_F32 ? 4 : 2;
+    int v = 1;
+    while (v * 2 <= maxvw && Ni % (v * 2) == 0 && 64 * v < Ni) v *= 2;  // narrowest that still fills a row
+    e->vw[i] = v;
+  }
+  if (hipMalloc(&e->d_inst, sizeof(hode::EnsInst) * n) != hipSuccess ||
+      hipMalloc(&e->d_err, sizeof(uint32_t)) != hipSuccess) {
+    hode_destroy(c);
+    *out = nullptr;
+    return HODE_ENOMEM;
+  }
+  const int bpc = hode::ensemble_blocks_per_cu(dtype);
+  int cus = 0;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  e->nwg = std::max(1, bpc) * std::max(1, cus);
+  return HODE_OK;
+}
+
+static int ens_check(hode_ctx* c, int i) {
+  if (!c) return HODE_EINVAL;
+  if (!c->ens) return fail(c, HODE_ESTATE, "not an ensemble context");
+  if (i < 0 || i >= c->ens->n) return fail(c, HODE_EINVAL, "instance index out of range");
+  return HODE_OK;
+}
+
+int hode_ensemble_size(const hode_ctx* c) { return c && c->ens ? c->ens->n : 0; }
+
+int hode_ensemble_init_state(hode_ctx* c, int i, const void* src, int src_on_device) {
+  int rc = ens_check(c, i);
+  if (rc) return rc;
+  Ensemble* e = c->ens;
+  if (!src) return fail(c, HODE_EINVAL, "src is NULL");
+  const size_t bytes = (size_t)2 * e->N[i] * e->N[i] * e->N[i] * c->esize;
+  e->parity[i] = 0;
+  HIPCHK(c, hipMemcpy(e->inst[i].a.y[0], src, bytes, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+  return HODE_OK;
+}
+
+int hode_ensemble_read_state(hode_ctx* c, int i, void* dst, size_t dst_bytes, int dst_on_device) {
+  int rc = ens_check(c, i);
+  if (rc) return rc;
+  Ensemble* e = c->ens;
+  const size_t bytes = (size_t)2 * e->N[i] * e->N[i] * e->N[i] * c->esize;
+  if (dst_bytes < bytes) return fail(c, HODE_ESTATE, "destination too small");
+  if (!dst) return fail(c, HODE_EINVAL, "dst is NULL");
+  HIPCHK(c, hipMemcpy(dst, e->inst[i].a.y[e->parity[i]], bytes,
+                      dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return HODE_OK;
+}
+
+int hode_ensemble_set_weights(hode_ctx* c, const double* w) {
+  int rc = ens_check(c, 0);
+  if (rc) return rc;
+  if (!w) return fail(c, HODE_EINVAL, "weights are NULL");
+  for (int i = 0; i < c->ens->n; ++i)
+    if (!(w[i] > 0) || !std::isfinite(w[i])) return fail(c, HODE_EINVAL, "weights must be positive");
+  c->ens->weight.assign(w, w + c->ens->n);
+  return HODE_OK;
+}
+
+int hode_ensemble_set_vector_width(hode_ctx* c, int i, int vw) {
+  int rc = ens_check(c, i);
+  if (rc) return rc;
+  const int maxvw = c->dtype == HODE_F32 ? 4 : 2;
+  if (vw != 1 && vw != 2 && vw != 4) return fail(c, HODE_EINVAL, "vector width 1, 2 or 4");
+  if (vw > maxvw || c->ens->N[i] % vw) return fail(c, HODE_EINVAL, "vector width must divide N (fp64: at most 2)");
+  c->ens->vw[i] = vw;
+  return HODE_OK;
+}
+
+int hode_ensemble_set_trace(hode_ctx* c, int64_t capacity) {
+  int rc = ens_check(c, 0);
+  if (rc) return rc;
+  if (capacity < 0) return fail(c, HODE_EINVAL, "capacity");
+  Ensemble* e = c->ens;
+  if (e->d_trace) { hipFree(e->d_trace); e->d_trace = nullptr; }
+  e->trace_cap = 0;
+  if (capacity > 0) {
+    if (hipMalloc(&e->d_trace, sizeof(double) * hode::TRACE_W * (size_t)capacity * e->n) != hipSuccess)
+      return fail(c, HODE_ENOMEM, "trace allocation failed");
+    e->trace_cap = capacity;
+  }
+  return HODE_OK;
+}
+
+int hode_ensemble_read_trace(hode_ctx* c, int i, double* dst, int64_t cap, int64_t* n) {
+  int rc = ens_check(c, i);
+  if (rc) return rc;
+  Ensemble* e = c->ens;
+  const int64_t att = e->attempts_last[i];
+  const int64_t m = std::min(std::min(att, e->trace_cap), std::max<int64_t>(cap, 0));
+  if (n) *n = att;
+  if (m > 0) {
+    if (!dst) return fail(c, HODE_EINVAL, "dst is NULL");
+    HIPCHK(c, hipMemcpy(dst, e->d_trace + (size_t)hode::TRACE_W * e->trace_cap * i,
+                        sizeof(double) * hode::TRACE_W * (size_t)m, hipMemcpyDeviceToHost));
+  }
+  return HODE_OK;
+}
+
+int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double dt0, int64_t max_steps,
+                                     hode_stats* per_instance) {
+  int rc = ens_check(c, 0);
+  if (rc) return rc;
+  if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 > t0) || !(dt0 > 0) || max_steps < 1)
+    return fail(c, HODE_EINVAL, "bad integration arguments");
+  Ensemble* e = c->ens;
+  HIPCHK(c, hipSetDevice(c->device));
+  // schedule
+  std::vector<std::vector<hode::EnsWork>> lists;
+  build_schedule(*e, e->nwg, lists, e->gang);
+  std::vector<hode::EnsWork> items;
+  std::vector<int32_t> offs(e->nwg + 1, 0);
+  for (int w = 0; w < e->nwg; ++w) {
+    offs[w] = (int32_t)items.size();
+    items.insert(items.end(), lists[w].begin(), lists[w].end());
+  }
+  offs[e->nwg] = (int32_t)items.size();
+  if (items.size() > e->items_cap || !e->d_offs) {
+    if (e->d_items) hipFree(e->d_items);
+    if (e->d_offs) hipFree(e->d_offs);
+    e->d_items = nullptr;
+    e->d_offs = nullptr;
+    if (e->graph) { hipGraphExecDestroy(e->graph); e->graph = nullptr; }
+    e->items_cap = std::max<size_t>(items.size(), 2 * (size_t)e->n + e->nwg);
+    if (hipMalloc(&e->d_items, sizeof(hode::EnsWork) * e->items_cap) != hipSuccess ||
+        hipMalloc(&e->d_offs, sizeof(int32_t) * (e->nwg + 1)) != hipSuccess)
+      return fail(c, HODE_ENOMEM, "schedule allocation failed");
+  }
+  HIPCHK(c, hipMemcpy(e->d_items, items.data(), sizeof(hode::EnsWork) * items.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(e->d_offs, offs.data(), sizeof(int32_t) * offs.size(), hipMemcpyHostToDevice));
+  // per-instance control blocks
+  for (int i = 0; i < e->n; ++i) {
+    hode::EnsInst& I = e->inst[i];
+    DevCtrl d = base_ctrl(c, hode::MODE_ADAPTIVE);
+    d.parity = e->parity[i];
+    d.k1slot = 0;
+    d.t = d.t0 = t0;
+    d.t1 = t1;
+    d.dt = dt0;
+    const bool last = dt0 >= t1 - t0;
+    d.h = last ? t1 - t0 : dt0;
+    d.last_flag = last;
+    d.max_attempts = max_steps;
+    d.trace = e->trace_cap > 0 ? e->d_trace + (size_t)hode::TRACE_W * e->trace_cap * i : nullptr;
+    d.trace_cap = e->trace_cap;
+    I.ctrl = d;
+    I.bar = 0;
+    I.gang = e->gang[i];
+    I.vw = e->vw[i];
+  }
+  HIPCHK(c, hipMemcpy(e->d_inst, e->inst.data(), sizeof(hode::EnsInst) * e->n, hipMemcpyHostToDevice));
+  const uint32_t zero = 0;
+  HIPCHK(c, hipMemcpy(e->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  // the persistent kernel, captured once into a graph
+  if (!e->graph) {
+    hode::EnsSched sch{e->d_items, e->d_offs, e->d_err, (int64_t)1 << 30};
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hode::launch_ensemble(e->dtype, e->d_inst, sch, e->nwg, c->stream);
+    hipError_t ee = hipStreamEndCapture(c->stream, &g);
+    if (le != hipSuccess || ee != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return fail(c, HODE_EHIP, std::string("ensemble capture: ") + hipGetErrorString(le != hipSuccess ? le : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHK(c, ie);
+  }
+  HIPCHK(c, hipGraphLaunch(e->graph, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  uint32_t err = 0;
+  HIPCHK(c, hipMemcpy(&err, e->d_err, sizeof(err), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(e->inst.data(), e->d_inst, sizeof(hode::EnsInst) * e->n, hipMemcpyDeviceToHost));
+  int worst = HODE_OK;
+  for (int i = 0; i < e->n; ++i) {
+    const DevCtrl& d = e->inst[i].ctrl;
+    e->parity[i] = d.parity;
+    e->attempts_last[i] = d.attempts;
+    if (per_instance) {
+      hode_stats& st = per_instance[i];
+      st.accepted = d.accepted;
+      st.rejected = d.rejected;
+      st.rhs_evals = d.rhs_evals + 1;
+      st.t = d.t;
+      st.dt_next = d.dt;
+      st.last_err = d.last_err;
+      st.status = d.status;
+      st.pad = 0;
+    }
+    if (d.status != HODE_OK && worst == HODE_OK) worst = d.status;
+  }
+  if (err) return fail(c, HODE_EHIP, "ensemble gang barrier timed out (workgroups not co-resident?)");
+  return worst;
+}
+
+int hode_ensemble_autotune(hode_ctx* c, int reps, int* vw_out, double* ms_out) {
+  int rc = ens_check(c, 0);
+  if (rc) return rc;
+  if (reps < 1) return fail(c, HODE_EINVAL, "reps >= 1");
+  Ensemble* e = c->ens;
+  std::map<int, int> first;  // edge -> first instance with it
+  for (int i = 0; i < e->n; ++i) first.emplace(e->N[i], i);
+  std::map<int, std::pair<int, double>> best;  // edge -> (vw, ms per attempt)
+  for (auto& kv : first) {
+    const int N = kv.first, i = kv.second;
+    hode_ctx* t = nullptr;
+    rc = hode_create(&t, c->device, nullptr);
+    if (rc) return fail(c, rc, "autotune: context");
+    const int64_t shape[3] = {N, N, N};
+    rc = hode_set_rhs(t, HODE_RHS_GRAYSCOTT3D, &e->prm[5 * i], 5);
+    if (!rc) rc = hode_init_state(t, c->dtype, 2, 3, shape, e->inst[i].a.y[e->parity[i]], 1);
+    double bms = 1e300;
+    int bvw = e->vw[i];
+    const int maxvw = c->dtype == HODE_F32 ? 4 : 2;
+    for (int vw = 1; vw <= maxvw && !rc; vw *= 2) {
+      if (N % vw) continue;
+      rc = hode_set_vector_width(t, vw);
+      if (!rc) rc = hode_set_tile(t, 1, N);
+      double ms[8];
+      if (!rc) rc = hode_profile_attempt(t, HODE_DOPRI5, reps, ms);
+      if (rc) break;
+      double tot = 0;
+      for (int k = 0; k < 6; ++k) tot += ms[k];
+      if (tot < bms) { bms = tot; bvw = vw; }
+    }
+    const std::string msg = rc ? hode_last_error(t) : "";
+    hode_destroy(t);
+    if (rc) return fail(c, rc, "autotune: " + msg);
+    best[N] = {bvw, bms};
+  }
+  for (int i = 0; i < e->n; ++i) {
+    const auto& b = best[e->N[i]];
+    e->vw[i] = b.first;
+    // work weight: measured attempt time x attempts growing mildly with N
+    const double Nd = (double)e->N[i];
+    e->weight[i] = b.second * (1.0 + Nd / 64.0);
+    if (vw_out) vw_out[i] = b.first;
+    if (ms_out) ms_out[i] = b.second;
+  }
   return HODE_OK;
 }
 

@@ -291,7 +291,7 @@ __device__ inline void ctrl_step(DevCtrl* c) {
   }
   __syncthreads();
   if (!s_adaptive) return;
-  if (s.use_mlp) {
+  if (s.use_mlp && threadIdx.x < 64) {
     const float y = mlp_forward_wave(c->mlp_w, s.x, s.h);
     if (threadIdx.x == 0) s.y = y;
   }

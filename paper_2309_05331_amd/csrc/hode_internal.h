@@ -29,8 +29,9 @@ struct GSLaunch {
   double Du_h2, Dv_h2, F, kk;
 };
 
-// ry: rows of the x-y tile per wavefront (tile = 64 x 4*ry cells).
-hipError_t launch_gs(int kind, int dtype, int ry, const GSLaunch& a, DevCtrl* c, hipStream_t s);
+// ry: rows per wavefront strip (tile = 64*vw x 4*ry cells); vw: cells per
+// lane (1, 2 or 4 for fp32, 1 or 2 for fp64, dividing N; 0 picks the widest).
+hipError_t launch_gs(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s);
 bool gs_ry_supported(int ry);
 
 // Element-wise families: the whole step runs in registers (one kernel per
@@ -44,5 +45,35 @@ hipError_t launch_ctrl(DevCtrl* c, hipStream_t s);
 
 // out = f(y) for the element-wise systems (no control block involved).
 hipError_t launch_ew_rhs(int dtype, int rhs, const void* y, void* out, int64_t n, int grid, hipStream_t s);
+
+// ---- batched ensemble -------------------------------------------------------
+// One instance of the ensemble: its grid and arrays, its own control block
+// (time, step, controller state, counters) and the barrier counter of the
+// gang of workgroups that steps it.
+struct EnsInst {
+  GSLaunch a;
+  DevCtrl ctrl;
+  uint32_t bar;   // gang barrier arrivals (monotonic)
+  int32_t gang;   // workgroups in the gang
+  int32_t vw;     // cells per lane for this instance's tiles
+  int32_t pad;
+};
+
+// One gang membership of a workgroup: instance, z-slab [z0, z1), rank.
+struct EnsWork {
+  int32_t inst, z0, z1, rank;
+};
+
+struct EnsSched {
+  const EnsWork* items;  // memberships, grouped per workgroup
+  const int32_t* offs;   // workgroup w owns items[offs[w] .. offs[w+1])
+  uint32_t* error;       // set when a gang barrier waited past spin_limit
+  int64_t spin_limit;
+};
+
+// The persistent ensemble kernel: grid = nwg co-resident workgroups.
+hipError_t launch_ensemble(int dtype, EnsInst* inst, EnsSched s, int nwg, hipStream_t st);
+// Workgroups of the persistent kernel that fit on one CU at once.
+int ensemble_blocks_per_cu(int dtype);
 
 }  // namespace hode

@@ -75,6 +75,17 @@ def lib():
             "hode_profile_attempt": ([P, I, I, C.POINTER(D)], I),
             "hode_autotune": ([P, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)], I),
             "hode_stream_copy": ([P, P, S, I, C.POINTER(D)], I),
+            "hode_set_vector_width": ([P, I], I),
+            "hode_ensemble_create": ([C.POINTER(P), I, P, I, C.POINTER(I64), C.POINTER(D), I], I),
+            "hode_ensemble_size": ([P], I),
+            "hode_ensemble_init_state": ([P, I, P, I], I),
+            "hode_ensemble_read_state": ([P, I, P, S, I], I),
+            "hode_ensemble_set_weights": ([P, C.POINTER(D)], I),
+            "hode_ensemble_set_vector_width": ([P, I, I], I),
+            "hode_ensemble_set_trace": ([P, I64], I),
+            "hode_ensemble_read_trace": ([P, I, P, I64, C.POINTER(I64)], I),
+            "hode_ensemble_integrate_adaptive": ([P, D, D, D, I64, C.POINTER(hode_stats)], I),
+            "hode_ensemble_autotune": ([P, I, C.POINTER(I), C.POINTER(D)], I),
             "hode_last_error": ([P], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -231,7 +242,70 @@ class Context:
         self._check(self.L.hode_autotune(self.h, method, reps, C.byref(ry), C.byref(zc), C.byref(ms)))
         return ry.value, zc.value, ms.value
 
+    def set_vector_width(self, vw):
+        return self._check(self.L.hode_set_vector_width(self.h, vw))
+
     def time_kernel(self, kind, reps):
         ms = C.c_double()
         self._check(self.L.hode_time_kernel(self.h, kind, reps, C.byref(ms)))
         return ms.value
+
+
+class Ensemble(Context):
+    """An ensemble context (hode_ensemble_*): n Gray-Scott instances stepped by
+    one persistent kernel."""
+
+    def __init__(self, edges, params, dtype=F32, device=0, stream=None):
+        self.L = lib()
+        self.h = C.c_void_p()
+        self.edges = [int(e) for e in edges]
+        n = len(self.edges)
+        e = (C.c_int64 * n)(*self.edges)
+        flat = [float(v) for row in params for v in row]
+        assert len(flat) == 5 * n
+        p = (C.c_double * (5 * n))(*flat)
+        self.dtype = dtype
+        self._check(self.L.hode_ensemble_create(C.byref(self.h), device, C.c_void_p(stream) if stream else None,
+                                                n, e, p, dtype))
+
+    def __len__(self):
+        return self.L.hode_ensemble_size(self.h)
+
+    def init_instance(self, i, src):
+        p, _, on_dev = _ptr_of(src)
+        return self._check(self.L.hode_ensemble_init_state(self.h, i, p, on_dev))
+
+    def read_instance(self, i, dst):
+        p, nb, on_dev = _ptr_of(dst)
+        return self._check(self.L.hode_ensemble_read_state(self.h, i, p, nb, on_dev))
+
+    def set_weights(self, w):
+        arr = (C.c_double * len(w))(*[float(v) for v in w])
+        return self._check(self.L.hode_ensemble_set_weights(self.h, arr))
+
+    def set_instance_vector_width(self, i, vw):
+        return self._check(self.L.hode_ensemble_set_vector_width(self.h, i, vw))
+
+    def set_trace(self, capacity):
+        return self._check(self.L.hode_ensemble_set_trace(self.h, capacity))
+
+    def read_instance_trace(self, i, cap=None):
+        n = C.c_int64()
+        self._check(self.L.hode_ensemble_read_trace(self.h, i, None, 0, C.byref(n)))
+        m = n.value if cap is None else min(cap, n.value)
+        out = np.zeros((max(m, 1), TRACE_W))
+        self._check(self.L.hode_ensemble_read_trace(self.h, i, out.ctypes.data_as(C.c_void_p), m, C.byref(n)))
+        return out[:m]
+
+    def autotune(self, reps=3):
+        n = len(self)
+        vw = (C.c_int * n)()
+        ms = (C.c_double * n)()
+        self._check(self.L.hode_ensemble_autotune(self.h, reps, vw, ms))
+        return list(vw), list(ms)
+
+    def integrate_adaptive(self, t0, t1, dt0, max_steps=10 ** 9, allow=(EMAXSTEPS, EDT_UNDERFLOW, ENONFINITE)):
+        n = len(self)
+        st = (hode_stats * n)()
+        self._check(self.L.hode_ensemble_integrate_adaptive(self.h, t0, t1, dt0, max_steps, st), allow)
+        return [s.as_dict() for s in st]

@@ -1,0 +1,121 @@
+"""GPU: the batched ensemble (one persistent kernel stepping many Gray-Scott
+instances, each with its own adaptive Dopri5 control).  Every instance must
+equal, bitwise, the same instance integrated alone through the single-grid
+path; FP64 instances must match the oracle replaying their step sequence to
+1e-12 relative."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_05331_amd import hode, inputs
+from gpu_util import rel_err_fields
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(n, Du=2e-3, Dv=1e-3, seed=4):
+    edges, F, k = inputs.ensemble_draws(n, seed=seed)
+    return edges, [[Du, Dv, F[i], k[i], 2.5] for i in range(n)]
+
+
+def _single(y0, N, prm, vw, t1, dt0, tol):
+    ctx = hode.Context(0)
+    ctx.set_rhs(hode.RHS_GRAYSCOTT3D, prm)
+    ctx.init_state(np.ascontiguousarray(y0).ravel(), grid=N)
+    ctx.set_tile(1, max(1, N // 2))
+    ctx.set_vector_width(vw)
+    ctx.set_tolerances(tol, tol)
+    st = ctx.integrate_adaptive(0.0, t1, dt0, max_steps=100000)
+    out = np.empty(2 * N ** 3, dtype=y0.dtype)
+    ctx.read_state(out)
+    ctx.close()
+    return out, st
+
+
+def _run_ensemble(edges, prms, dtype, t1, tol, vws=None, weights=None, trace=0):
+    npd = np.float32 if dtype == hode.F32 else np.float64
+    ens = hode.Ensemble(edges, prms, dtype=dtype)
+    ys = []
+    for i, N in enumerate(edges):
+        y = inputs.ensemble_ic(i, N, dtype=npd)
+        ys.append(y)
+        ens.init_instance(i, np.ascontiguousarray(y).ravel())
+        if vws:
+            ens.set_instance_vector_width(i, vws[i])
+    if weights is not None:
+        ens.set_weights(weights)
+    if trace:
+        ens.set_trace(trace)
+    ens.set_tolerances(tol, tol)
+    stats = ens.integrate_adaptive(0.0, t1, 0.1, max_steps=100000)
+    outs = []
+    for i, N in enumerate(edges):
+        o = np.empty(2 * N ** 3, dtype=npd)
+        ens.read_instance(i, o)
+        outs.append(o)
+    return ens, ys, outs, stats
+
+
+@pytest.mark.parametrize("dtype", [hode.F32, hode.F64])
+def test_ensemble_matches_single_runs_bitwise(dtype):
+    edges = [8, 16, 24, 32, 12, 20, 40]
+    _, prms = _params(len(edges))
+    vws = [1, 2, 1, 2, 4 if dtype == hode.F32 else 2, 2, 1]
+    ens, ys, outs, stats = _run_ensemble(edges, prms, dtype, 30.0, 1e-5, vws=vws)
+    for i, N in enumerate(edges):
+        assert stats[i]["status"] == 0 and stats[i]["t"] == 30.0
+        ref, st = _single(ys[i], N, prms[i], vws[i], 30.0, 0.1, 1e-5)
+        assert (stats[i]["accepted"], stats[i]["rejected"]) == (st["accepted"], st["rejected"]), i
+        assert np.array_equal(outs[i], ref), i
+    ens.close()
+
+
+def test_ensemble_multi_workgroup_gangs_bitwise():
+    # weights that give the large instances gangs of several workgroups
+    edges = [48, 64, 16, 8]
+    _, prms = _params(len(edges))
+    ens, ys, outs, stats = _run_ensemble(edges, prms, hode.F32, 20.0, 1e-5, vws=[4, 4, 4, 4],
+                                         weights=[1e9, 1e9, 1.0, 1.0])
+    for i, N in enumerate(edges):
+        ref, st = _single(ys[i], N, prms[i], 4, 20.0, 0.1, 1e-5)
+        assert stats[i]["accepted"] == st["accepted"], i
+        assert np.array_equal(outs[i], ref), i
+    ens.close()
+
+
+def test_ensemble_fp64_oracle_replay(orc):
+    edges = [12, 16, 10]
+    _, prms = _params(len(edges))
+    ens, ys, outs, stats = _run_ensemble(edges, prms, hode.F64, 40.0, 1e-6, trace=100000)
+    for i, N in enumerate(edges):
+        tr = ens.read_instance_trace(i)
+        assert tr.shape[0] == stats[i]["accepted"] + stats[i]["rejected"]
+        sysd = orc.gs_system(N, *prms[i])
+        r, te, _ = orc.integrate_replay(sysd, ys[i].ravel(), 0.0, tr[:, 0], tr[:, 2].astype(np.int32), 1e-6, 1e-6)
+        assert abs(te - 40.0) < 1e-9
+        assert rel_err_fields(outs[i], r, 2) <= 1e-12, i
+    ens.close()
+
+
+def test_ensemble_full_draws_short_horizon():
+    # the 512-instance ensemble at its real sizes and parameters, over a short
+    # horizon; one instance of every edge is checked bitwise against a single run
+    n = 512
+    edges, F, k = inputs.ensemble_draws(n, seed=4)
+    prms = [[2e-5, 1e-5, F[i], k[i], 2.5] for i in range(n)]
+    ens = hode.Ensemble(edges, prms, dtype=hode.F32)
+    for i, N in enumerate(edges):
+        ens.init_instance(i, inputs.ensemble_ic(i, N).ravel())
+    ens.set_tolerances(1e-5, 1e-5)
+    stats = ens.integrate_adaptive(0.0, 4.0, 0.1, max_steps=100000)
+    assert all(s["status"] == 0 and s["t"] == 4.0 for s in stats)
+    seen = {}
+    for i, N in enumerate(edges):
+        seen.setdefault(N, i)
+    for N, i in sorted(seen.items()):
+        out = np.empty(2 * N ** 3, dtype=np.float32)
+        ens.read_instance(i, out)
+        vw = 2 if N > 64 else 1
+        ref, st = _single(inputs.ensemble_ic(i, N), N, prms[i], vw, 4.0, 0.1, 1e-5)
+        assert np.array_equal(out, ref), (i, N)
+    ens.close()
