@@ -107,7 +107,7 @@ int hode_set_tolerances(hode_ctx *ctx, double atol, double rtol);
 
 /* Step-size controller for adaptive runs: HODE_CTRL_PI (default,
  * Gustafsson PI), HODE_CTRL_I (elementary), or HODE_CTRL_MLP with `weights`
- * the packed bf16 parameters of the 16-64-64-1 network (nbytes = 2 * 5249:
+ * the packed bf16 parameters of the 16-64-64-1 network (nbytes = 2 * 5313:
  * W1[64][16], b1[64], W2[64][64], b2[64], w3[64], b3), copied in.  The PI
  * proposal remains the fallback and retry rule. */
 int hode_set_controller(hode_ctx *ctx, int kind, const void *weights, size_t nbytes);
@@ -134,9 +134,10 @@ int hode_integrate_adaptive(hode_ctx *ctx, double t0, double t1, double dt0, int
 /* Statistics of the last run. */
 int hode_get_stats(hode_ctx *ctx, hode_stats *out);
 
-/* Records one 8-double entry per adaptive attempt (h, err, accepted, t after,
- * dt proposed, PI log-ratio, learned log-ratio or NaN, landed-on-t1 flag) for
- * the next runs, up to `capacity` attempts (0 disables). */
+/* Records one 24-double entry per adaptive attempt (h, err, accepted, t
+ * after, dt proposed, PI log-ratio, learned log-ratio or NaN, landed-on-t1
+ * flag, then for accepted attempts the 16 learned-controller features, else
+ * NaN) for the next runs, up to `capacity` attempts (0 disables). */
 int hode_set_trace(hode_ctx *ctx, int64_t capacity);
 
 /* Copies up to `cap` recorded entries to host `dst`; *n receives the number
@@ -228,6 +229,30 @@ int hode_ensemble_autotune(hode_ctx *ctx, int reps, int *vw_out, double *ms_out)
  * failing instance's status, or HODE_EHIP if a gang barrier timed out. */
 int hode_ensemble_integrate_adaptive(hode_ctx *ctx, double t0, double t1, double dt0, int64_t max_steps,
                                      hode_stats *per_instance);
+
+/* ---- learned step-size controller: network kernels --------------------------
+ * The 16-64-64-1 tanh network of HODE_CTRL_MLP (packed parameters as in
+ * hode_set_controller, 5313 values).  All pointers are device memory owned by
+ * the caller; work runs on `stream` (a hipStream_t, NULL = default stream) and
+ * the calls return after it synchronised.  Arithmetic: bf16 weights, inputs
+ * and first-layer activations, fp32 accumulation on the matrix cores, as in
+ * the controller's own evaluation.
+ *   X: B x 16 features (fp32, row-major); T: B targets; Wt: B sample weights;
+ *   Wb: bf16 bits of the parameters; Wm: fp32 master parameters;
+ *   grad, m, v: 5313 fp32 each; acc: 2 doubles of scratch. */
+int hode_mlp_forward(const uint16_t *Wb, const float *X, float *Y, int64_t B, void *stream);
+/* Wb = bf16 rounding (to nearest, ties to even) of Wm. */
+int hode_mlp_quantize(const float *Wm, uint16_t *Wb, void *stream);
+/* grad = d/dparams of sum_b Wt_b (y_b - T_b)^2 / sum_b Wt_b (B >= 1);
+ * *loss_out (may be NULL) receives the loss. */
+int hode_mlp_loss_grad(const uint16_t *Wb, const float *X, const float *T, const float *Wt, int64_t B, float *grad,
+                       double *acc, double *loss_out, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step >= 1, learning rate
+ * lr) on Wm from the gradient at Wb; refreshes Wb; *loss_out receives the
+ * loss before the step. */
+int hode_mlp_train_step(const float *X, const float *T, const float *Wt, int64_t B, float *Wm, uint16_t *Wb,
+                        float *m, float *v, float *grad, double *acc, int64_t step, float lr, double *loss_out,
+                        void *stream);
 
 /* Text of the last error on this context (valid until the next call). */
 const char *hode_last_error(const hode_ctx *ctx);

@@ -415,7 +415,8 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 // One stage over a whole grid: one tile per workgroup.  The linear block id
 // is remapped XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so
 // each XCD gets a contiguous range of tiles and y/z-adjacent tiles (whose
-// halo rows overlap) share an L2.
+// halo rows overlap) share an L2.  Consecutive stages sweep those ranges in
+// opposite directions.
 template <typename T, int KIND, int RY, int VW>
 __global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __restrict__ c) {
   __shared__ __align__(16) char smem[kTileSmem];
@@ -425,7 +426,13 @@ __global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __res
   const int ny = (N + 4 * RY - 1) / (4 * RY);
   const int nz = (N + a.zc - 1) / a.zc;
   const int per = (gridDim.x + 7) / 8;
-  const int bb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  // Stages alternate their direction through each XCD's range, so a stage
+  // starts on the tiles the previous stage wrote last, which are still in the
+  // memory-side Infinity Cache.
+  constexpr bool rev = KIND == K_R2 || KIND == K_R4 || KIND == K_D3 || KIND == K_D5 || KIND == K_D7 ||
+                       KIND == K_D7F;
+  const int slot = rev ? per - 1 - (int)(blockIdx.x >> 3) : (int)(blockIdx.x >> 3);
+  const int bb = (blockIdx.x & 7) * per + slot;
   if (bb >= nx * ny * nz) return;  // padding block of the remap (whole block)
   const int tz = bb / (nx * ny);
   stage_tile<T, KIND, RY, VW>(a, c, smem, bb % nx, (bb / nx) % ny, tz * a.zc, min(N, (tz + 1) * a.zc));

@@ -489,7 +489,7 @@ int hode_set_controller(hode_ctx* c, int kind, const void* weights, size_t nbyte
     return HODE_OK;
   }
   if (kind != HODE_CTRL_MLP) return fail(c, HODE_EINVAL, "unknown controller");
-  if (!weights || nbytes != 2 * (size_t)hode::MLP_NPARAM) return fail(c, HODE_EINVAL, "MLP weights must be 10498 bytes");
+  if (!weights || nbytes != 2 * (size_t)hode::MLP_NPARAM) return fail(c, HODE_EINVAL, "MLP weights must be 10626 bytes");
   if (!c->d_mlp) {
     if (hipMalloc(&c->d_mlp, nbytes) != hipSuccess) return fail(c, HODE_ENOMEM, "allocation failed");
   }

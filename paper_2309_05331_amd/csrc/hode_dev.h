@@ -27,7 +27,7 @@ enum Status : int32_t {
   ST_ENONFINITE = -7,
 };
 
-constexpr int TRACE_W = 8;  // doubles per trace record
+constexpr int TRACE_W = 24;  // doubles per trace record (8 scalars + 16 controller features)
 constexpr int HIST = 4;     // attempts of history kept for the learned controller
 constexpr int MLP_IN = 16, MLP_H = 64;
 // packed bf16 weights: W1[64][16] b1[64] W2[64][64] b2[64] w3[64] b3[1]
@@ -129,10 +129,18 @@ __device__ inline void mlp_features(const DevCtrl* c, double h, double pi_lr, fl
   x[15] = 1.f;
 }
 
+__device__ inline float bf16_round(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return f;
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return __uint_as_float(u & 0xffff0000u);
+}
+
 // Forward pass of the 16-64-64-1 tanh network by one wavefront (lane j owns
-// hidden unit j): bf16 weights, fp32 accumulation.  W is the packed layout
-// W1[64][16] b1[64] W2[64][64] b2[64] w3[64] b3.  Returns the output in every
-// lane.  s_h is 64 floats of LDS.
+// hidden unit j), with the arithmetic of the training kernels: bf16 weights,
+// inputs and first-layer activations, fp32 accumulation.  W is the packed
+// layout W1[64][16] b1[64] W2[64][64] b2[64] w3[64] b3.  Returns the output in
+// every lane.  s_h is 64 floats of LDS.
 __device__ inline float mlp_forward_wave(const uint16_t* W, const float* x, float* s_h) {
   const int j = threadIdx.x & 63;
   const uint16_t* W1 = W;
@@ -141,15 +149,15 @@ __device__ inline float mlp_forward_wave(const uint16_t* W, const float* x, floa
   const uint16_t* b2 = W2 + MLP_H * MLP_H;
   const uint16_t* w3 = b2 + MLP_H;
   const uint16_t* b3 = w3 + MLP_H;
-  float s = bf16_to_f32(b1[j]);
+  float s = 0.f;
 #pragma unroll
-  for (int i = 0; i < MLP_IN; ++i) s += bf16_to_f32(W1[j * MLP_IN + i]) * x[i];
-  s_h[j] = tanhf(s);
+  for (int i = 0; i < MLP_IN; ++i) s += bf16_to_f32(W1[j * MLP_IN + i]) * bf16_round(x[i]);
+  s_h[j] = bf16_round(tanhf(s + bf16_to_f32(b1[j])));
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  float s2 = bf16_to_f32(b2[j]);
+  float s2 = 0.f;
   for (int i = 0; i < MLP_H; ++i) s2 += bf16_to_f32(W2[j * MLP_H + i]) * s_h[i];
-  float o = bf16_to_f32(w3[j]) * tanhf(s2);
+  float o = bf16_to_f32(w3[j]) * tanhf(s2 + bf16_to_f32(b2[j]));
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) o += __shfl_xor(o, off, 64);
   return o + bf16_to_f32(b3[0]);
@@ -222,7 +230,7 @@ __device__ inline void decide_a(DevCtrl* c, double err, CtrlScratch* s) {
   s->pi_lr = log(fac);
   s->ok = ok;
   s->use_mlp = ok && c->ctrl_kind == CTRL_MLP && c->mlp_w != nullptr && c->t < c->t1;
-  if (s->use_mlp) mlp_features(c, h, s->pi_lr, s->x);
+  if (ok) mlp_features(c, h, s->pi_lr, s->x);  // also recorded in the trace (training data)
 }
 
 // Phase C (one thread): apply the proposal, trace, prepare the next attempt.
@@ -253,6 +261,7 @@ __device__ inline void decide_c(DevCtrl* c, CtrlScratch* s) {
     r[5] = s->pi_lr;
     r[6] = mlp_lr;
     r[7] = c->last_flag ? 1.0 : 0.0;
+    for (int i = 0; i < MLP_IN; ++i) r[8 + i] = s->ok ? (double)s->x[i] : __longlong_as_double(0x7ff8000000000000LL);
   }
   if (c->t >= c->t1) {
     c->done = 1;

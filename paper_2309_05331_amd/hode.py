@@ -20,7 +20,7 @@ RHS_EXP, RHS_LOGISTIC, RHS_GRAYSCOTT3D = 1, 2, 3
 RK4, DOPRI5 = 1, 2
 CTRL_PI, CTRL_I, CTRL_MLP = 1, 2, 3
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EDT_UNDERFLOW, EMAXSTEPS, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
-TRACE_W = 8
+TRACE_W = 24  # h, err, accepted, t after, dt next, PI log-ratio, learned log-ratio, landed, 16 features
 MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 
 # Gray-Scott stage kernels, as numbered by hode_time_kernel
@@ -86,6 +86,10 @@ def lib():
             "hode_ensemble_read_trace": ([P, I, P, I64, C.POINTER(I64)], I),
             "hode_ensemble_integrate_adaptive": ([P, D, D, D, I64, C.POINTER(hode_stats)], I),
             "hode_ensemble_autotune": ([P, I, C.POINTER(I), C.POINTER(D)], I),
+            "hode_mlp_forward": ([P, P, P, I64, P], I),
+            "hode_mlp_quantize": ([P, P, P], I),
+            "hode_mlp_loss_grad": ([P, P, P, P, I64, P, P, C.POINTER(D), P], I),
+            "hode_mlp_train_step": ([P, P, P, I64, P, P, P, P, P, P, I64, C.c_float, C.POINTER(D), P], I),
             "hode_last_error": ([P], C.c_char_p),
         }
         for name, (args, res) in sig.items():
