@@ -198,6 +198,35 @@ def run_ew(wl, steps, warmup):
                 dom_bytes=2 * n * 8, stage_gbs=None, attempt_gbs=2 * n * 8 / (ms * 1e-3) / 1e9, tile=None)
 
 
+def run_ab(N, t1, weights_path, dtype="f32"):
+    """Wall time to integrate the whole horizon with PI and with the learned
+    controller (same grid, tolerances and start)."""
+    import torch
+    from paper_2309_05331_amd import hode, inputs
+    np_dt = np.float32 if dtype == "f32" else np.float64
+    y0 = torch.from_numpy(inputs.gray_scott_ic(N, seed=5, dtype=np_dt).ravel()).to("cuda:0")
+    wb = np.load(weights_path)
+    res = {}
+    for name, kind, w in (("pi", hode.CTRL_PI, None), ("learned", hode.CTRL_MLP, wb)):
+        ctx = hode.Context(0)
+        ctx.set_rhs(hode.RHS_GRAYSCOTT3D, GS_PRM)
+        ctx.init_state(y0, grid=N)
+        ctx.set_tolerances(1e-6, 1e-6)
+        ctx.set_controller(kind, w)
+        ctx.set_tile(1, 256 if N >= 256 else N)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.integrate_adaptive(0.0, t1, 0.1, max_steps=10 ** 7)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"wall_s": el, "accepted": st["accepted"], "rejected": st["rejected"], "status": st["status"],
+                     "cell_updates_per_s": N ** 3 * st["accepted"] / el}
+        print(json.dumps({name: res[name]}), file=sys.stderr, flush=True)
+        ctx.close()
+    res["wall_ratio_learned_over_pi"] = res["learned"]["wall_s"] / res["pi"]["wall_s"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +236,9 @@ def main():
     ap.add_argument("--controller", default="pi", choices=["pi", "i"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="auto", help="auto (autotune) or RY,ZC")
+    ap.add_argument("--ab", type=float, default=0.0, metavar="T1",
+                    help="also integrate the workload grid from 0 to T1 with PI and with the learned controller")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2309_05331_amd", "controller_weights.npy"))
     ap.add_argument("--copy-reference", action="store_true",
                     help="time only the plain 16-byte streaming copy of 1 GiB (bandwidth ceiling, counter calibration)")
     args = ap.parse_args()
@@ -252,6 +284,8 @@ def main():
                      "traffic": traffic_from_profiles(tag)},
         "stage_gbs": r["stage_gbs"], "attempt_gbs": round(r["attempt_gbs"], 1),
     }
+    if args.ab > 0 and wl["kind"] == "gs":
+        out["controller_ab"] = dict(run_ab(wl["N"], args.ab, args.weights, wl["dtype"]), t1=args.ab, rtol=1e-6)
     if not args.no_cpu_baseline:
         cb = cpu_baseline_leg(wl)
         out["cpu_baseline"] = cb

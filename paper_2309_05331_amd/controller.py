@@ -11,7 +11,8 @@ Training target (hindsight): for an accepted attempt n followed by attempt
 n+1, the step that would have produced the error level rho under the local
 model err ~ h^5 is h* = h_{n+1} (rho / err_{n+1})^(1/5); the target is
 log(h* / h_n), clamped like the proposal.  Pairs whose next attempt was
-rejected weigh twice (a reject costs a whole attempt).  The 16 input features
+rejected weigh more (a reject costs a whole attempt); rho and that weight are
+chosen on held-out runs.  The 16 input features
 are the ones the device computed at decision n and stored in the trace.
 """
 from __future__ import annotations
@@ -27,7 +28,7 @@ RHO = 0.8
 LOG_LO, LOG_HI = math.log(0.2), math.log(5.0)
 
 
-def dataset_from_trace(tr, rho=RHO):
+def dataset_from_trace(tr, rho=RHO, reject_weight=2.0):
     """(X, T, W) training triples from one run's trace (rows in attempt order)."""
     tr = np.asarray(tr, dtype=np.float64)
     if tr.shape[0] < 2:
@@ -39,7 +40,7 @@ def dataset_from_trace(tr, rho=RHO):
     e1 = np.maximum(err[n + 1], 1e-10)
     target = np.log(h[n + 1] / h[n]) + 0.2 * np.log(rho / e1)
     target = np.clip(target, LOG_LO, LOG_HI)
-    weight = np.where(err[n + 1] > 1.0, 2.0, 1.0)
+    weight = np.where(err[n + 1] > 1.0, reject_weight, 1.0)
     return tr[n, 8:24].copy(), target, weight
 
 

@@ -124,12 +124,30 @@ __device__ __forceinline__ Pk<T, VW> ldv(const T* __restrict__ p, int64_t g) {
   return r;
 }
 
+#ifndef HODE_NT_STORES
+#define HODE_NT_STORES 1
+#endif
+
+// Stage outputs are streamed out with non-temporal stores: each array is
+// written once and read by later stage kernels, far beyond what L2 holds.
 template <typename T, int VW>
 __device__ __forceinline__ void stv(T* __restrict__ p, int64_t g, const Pk<T, VW>& r) {
-  using V = typename VecT<T, VW>::type;
-  V x;
-  __builtin_memcpy(&x, &r, sizeof(r));
-  *reinterpret_cast<V*>(p + g) = x;
+  if constexpr (HODE_NT_STORES) {
+    if constexpr (VW == 1) {
+      __builtin_nontemporal_store(r.v[0], p + g);
+    } else {
+      typedef T V __attribute__((ext_vector_type(VW)));
+      V x;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) x[e] = r.v[e];
+      __builtin_nontemporal_store(x, reinterpret_cast<V*>(p + g));
+    }
+  } else {
+    using V = typename VecT<T, VW>::type;
+    V x;
+    __builtin_memcpy(&x, &r, sizeof(r));
+    *reinterpret_cast<V*>(p + g) = x;
+  }
 }
 
 template <typename T>

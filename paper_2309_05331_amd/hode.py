@@ -50,6 +50,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIBPATH):
             raise RuntimeError("libhode.so is not built: run python -m paper_2309_05331_amd.build")
+        # torch bundles its own HIP runtime under the same soname; load it
+        # first so the process holds one runtime that both torch (device
+        # memory, streams) and this library use
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIBPATH)
         P, I, I64, D, S = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_size_t
         sig = {

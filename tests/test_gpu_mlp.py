@@ -112,3 +112,23 @@ def test_nonfinite_network_falls_back_to_pi_exactly():
     assert (st_ml["accepted"], st_ml["rejected"]) == (st_pi["accepted"], st_pi["rejected"])
     assert np.array_equal(y_ml, y_pi)
     assert np.all(np.isnan(tr_ml[:, 6]))
+
+
+def test_trained_controller_beats_pi_on_held_out_instances():
+    # the committed network (trained on the integrator's own traces of the
+    # 512-instance workload) against PI on instances it has not seen: new
+    # initial conditions, rtol 1e-6, horizon 0..400
+    import os
+    from paper_2309_05331_amd import train_controller as tc
+    wb = np.load(os.path.join(os.path.dirname(hode.__file__), "controller_weights.npy"))
+    edges, prms = tc.c4_params()
+    m = 24
+    he, hp = edges[:m], prms[:m]
+    seeds = list(range(9500, 9500 + m))
+    res = {}
+    for name, kind, w in (("pi", hode.CTRL_PI, None), ("mlp", hode.CTRL_MLP, wb)):
+        stats, el, _ = tc.run_ensemble(he, hp, seeds, 400.0, 1e-6, kind, weights=w)
+        assert all(s["status"] == 0 and s["t"] == 400.0 for s in stats)
+        res[name] = sum(s["accepted"] + s["rejected"] for s in stats)
+    print("attempts PI %d learned %d" % (res["pi"], res["mlp"]))
+    assert res["mlp"] < res["pi"]
