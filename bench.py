@@ -243,7 +243,7 @@ def main():
                     help="time only the plain 16-byte streaming copy of 1 GiB (bandwidth ceiling, counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path; the sharding plan is documented with the design.",
               file=sys.stderr)
         sys.exit(2)
     from paper_2309_05331_amd import hode

@@ -189,6 +189,14 @@ int get_graph(hode_ctx* c, int mode, int M, hipGraphExec_t* out) {
   return HODE_OK;
 }
 
+// Scale of the largest Jacobian eigenvalue of Gray-Scott on an N^3 grid: the
+// 7-point Laplacian's spectral radius 12/dx^2 times the larger diffusivity,
+// plus 1 for the reaction terms.
+double gs_stiffness(const double* prm, int N) {
+  const double dx = prm[4] / N;
+  return 12.0 * std::max(std::fabs(prm[0]), std::fabs(prm[1])) / (dx * dx) + 1.0;
+}
+
 DevCtrl base_ctrl(const hode_ctx* c, int mode) {
   DevCtrl d;
   std::memset(&d, 0, sizeof(d));
@@ -203,6 +211,8 @@ DevCtrl base_ctrl(const hode_ctx* c, int mode) {
   d.trace_cap = c->trace_cap;
   d.mlp_w = c->d_mlp;
   d.max_attempts = INT64_MAX;
+  d.stiff = 1.0;
+  if (c->rhs == HODE_RHS_GRAYSCOTT3D && c->N > 0) d.stiff = gs_stiffness(c->prm, c->N);
   return d;
 }
 
@@ -998,6 +1008,7 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     d.max_attempts = max_steps;
     d.trace = e->trace_cap > 0 ? e->d_trace + (size_t)hode::TRACE_W * e->trace_cap * i : nullptr;
     d.trace_cap = e->trace_cap;
+    d.stiff = gs_stiffness(&e->prm[5 * i], e->N[i]);
     I.ctrl = d;
     I.bar = 0;
     I.gang = e->gang[i];

@@ -53,7 +53,8 @@ struct DevCtrl {
   int64_t trace_cap;
   const uint16_t* mlp_w;  // bf16 weights in device memory (CTRL_MLP)
   int64_t mlp_used, mlp_fallback;
-  double pad[4];
+  double stiff;  // spectral-radius scale of the System's Jacobian (feature of the learned controller)
+  double pad[3];
 };
 
 // ---- tableaux (Dormand & Prince 1980; classical RK4) ------------------------
@@ -114,7 +115,10 @@ __device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint3
 // attempt has been pushed into the history (newest first) and t advanced:
 // for each of the last 4 attempts log(err) clamped to [-23, 23], log(h_i/h)
 // and the accept flag (zeros where the history is shorter); the PI proposal's
-// log-ratio; log(rtol); log(max(t1 - t, h)/h); a constant 1.
+// log-ratio; log(rtol); log(max(t1 - t, h)/h); log(h * stiff), where stiff
+// scales the System's largest Jacobian eigenvalue (for the 7-point diffusion,
+// 12 max(Du, Dv)/dx^2 + 1), so h*stiff measures the step against the
+// explicit stability limit.
 __device__ inline void mlp_features(const DevCtrl* c, double h, double pi_lr, float* x) {
   const double lh = log(h);
   for (int i = 0; i < HIST; ++i) {
@@ -126,7 +130,7 @@ __device__ inline void mlp_features(const DevCtrl* c, double h, double pi_lr, fl
   x[12] = (float)pi_lr;
   x[13] = (float)log(c->rtol > 0 ? c->rtol : c->atol);
   x[14] = (float)log(fmax(c->t1 - c->t, h) / h);
-  x[15] = 1.f;
+  x[15] = (float)log(h * (c->stiff > 0 ? c->stiff : 1.0));
 }
 
 __device__ inline float bf16_round(float f) {

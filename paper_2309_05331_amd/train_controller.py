@@ -3,15 +3,23 @@
     python -m paper_2309_05331_amd.train_controller [--t1 2000] [--out FILE]
 
 1. Collects accept/reject traces with the PI controller from batched-ensemble
-   runs of the 512-instance Gray-Scott workload (grid edges 16..96, F and k
-   drawn per instance, FP32) at rtol = atol = 1e-5 and 1e-6 (so the
-   tolerance feature covers both values the controller meets).
+   runs at rtol = atol = 1e-5 and 1e-6 (so the tolerance feature covers both
+   values the controller meets), FP32, on two instance sets:
+   - smooth: the 512-instance Gray-Scott workload (grid edges 16..96, F and k
+     drawn per instance, domain length 2.5), whose steps are accuracy-limited;
+   - stiff: instances whose domain is a window of a finer grid (edge M drawn
+     log-uniformly in [128, 640], domain length 2.5 N/M), so the diffusion
+     eigenvalue 12 D/dx^2 is that of an M^3 grid and the step is held by the
+     explicit stability limit, as on the 512^3 workload.
 2. Builds hindsight targets (see controller.py) for each candidate target
-   level rho and reject weight, and trains the network with the library's
-   MFMA forward/backward kernels and Adam on the GPU.
-3. Evaluates every candidate on held-out instances (other initial-condition
-   seeds) against PI: attempts, rejects, wall time; keeps the candidate with
-   the lowest mean wall-time ratio.
+   level rho and reject weight, trains the network with the library's MFMA
+   forward/backward kernels and Adam on the GPU, then aggregates data from
+   its own runs: the trained controller integrates the training instances,
+   its traces (with the rejects it causes, whose targets shrink the step) join
+   the data set and the network is retrained; repeated --rounds times.
+3. Evaluates every candidate on held-out instances of both sets (other
+   initial-condition seeds) against PI: attempts, rejects, wall time; keeps
+   the candidate with the lowest mean wall-time ratio.
 4. Writes the chosen bf16 weights (uint16 bit patterns, .npy) and a JSON
    summary of every run.
 """
@@ -33,6 +41,19 @@ DEFAULT_OUT = os.path.join(HERE, "controller_weights.npy")
 def c4_params(n=512, seed=4):
     edges, F, k = inputs.ensemble_draws(n, seed=seed)
     return edges, [[2e-5, 1e-5, F[i], k[i], 2.5] for i in range(n)]
+
+
+def stiff_params(n=256, seed=6):
+    """Instances whose diffusion stiffness is that of a finer grid: edges as
+    in the ensemble workload, F ~ U[0.02, 0.06], k ~ U[0.01, 0.065] (covering
+    the 512^3 workload's k = 0.014), domain length 2.5 N / M with M
+    log-uniform in [128, 640]."""
+    edges, _, _ = inputs.ensemble_draws(n, seed=seed)
+    rng = np.random.default_rng(seed)
+    M = np.exp(rng.uniform(np.log(128.0), np.log(640.0), size=n))
+    F = rng.uniform(0.02, 0.06, size=n)
+    k = rng.uniform(0.01, 0.065, size=n)
+    return edges, [[2e-5, 1e-5, F[i], k[i], 2.5 * edges[i] / M[i]] for i in range(n)]
 
 
 def run_ensemble(edges, prms, seeds, t1, rtol, ctrl, weights=None, trace_cap=0, dtype=hode.F32):
@@ -62,55 +83,84 @@ def summarize(stats, el, edges):
             "status_ok": bool(all(s["status"] == 0 for s in stats))}
 
 
+RTOLS = (1e-5, 1e-6)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--t1", type=float, default=2000.0)
+    ap.add_argument("--t1", type=float, default=2000.0, help="horizon of the smooth set")
+    ap.add_argument("--t1-stiff", type=float, default=400.0, help="horizon of the stiff set")
+    ap.add_argument("--n-stiff", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--rounds", type=int, default=2, help="data-aggregation rounds after the PI-trace fit")
+    ap.add_argument("--agg-smooth", type=int, default=128, help="smooth instances rerun in each aggregation round")
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--holdout", type=int, default=64)
-    ap.add_argument("--rhos", default="0.3,0.5,0.8")
+    ap.add_argument("--rhos", default="0.3,0.5")
     ap.add_argument("--reject-weights", default="2,5")
     args = ap.parse_args()
-    edges, prms = c4_params()
-    n = len(edges)
-    traces = []
-    summary = {"train": {}, "eval": {}, "candidates": {}}
-    for rtol in (1e-5, 1e-6):
-        stats, el, tr = run_ensemble(edges, prms, list(range(4000, 4000 + n)), args.t1, rtol, hode.CTRL_PI,
-                                     trace_cap=4000)
-        traces += tr
-        summary["train"]["rtol=%g" % rtol] = summarize(stats, el, edges)
-        print("traces rtol=%g: %s" % (rtol, summary["train"]["rtol=%g" % rtol]), flush=True)
+    sets = {"smooth": c4_params() + (4000, args.t1), "stiff": stiff_params(args.n_stiff) + (6000, args.t1_stiff)}
+    summary = {"train": {}, "eval": {}, "candidates": {}, "args": vars(args)}
+    pi_traces = []
+    for name, (edges, prms, s0, t1) in sets.items():
+        seeds = list(range(s0, s0 + len(edges)))
+        for rtol in RTOLS:
+            stats, el, tr = run_ensemble(edges, prms, seeds, t1, rtol, hode.CTRL_PI, trace_cap=4000)
+            pi_traces += tr
+            key = "%s pi rtol=%g" % (name, rtol)
+            summary["train"][key] = summarize(stats, el, edges)
+            print(key, summary["train"][key], flush=True)
     # held-out: the first instances' parameter draws with new initial conditions
     m = args.holdout
-    he, hp = edges[:m], prms[:m]
-    seeds = list(range(9000, 9000 + m))
+    held = {name: (e[:m], p[:m], list(range(s0 + 5000, s0 + 5000 + m)), t1) for name, (e, p, s0, t1) in sets.items()}
     base = {}
-    for rtol in (1e-5, 1e-6):
-        stats, el, _ = run_ensemble(he, hp, seeds, args.t1, rtol, hode.CTRL_PI)
-        base[rtol] = summarize(stats, el, he)
-        summary["eval"]["pi rtol=%g" % rtol] = base[rtol]
-        print("pi", rtol, base[rtol], flush=True)
+    for name, (he, hp, seeds, t1) in held.items():
+        for rtol in RTOLS:
+            stats, el, _ = run_ensemble(he, hp, seeds, t1, rtol, hode.CTRL_PI)
+            base[name, rtol] = summarize(stats, el, he)
+            summary["eval"]["%s pi rtol=%g" % (name, rtol)] = base[name, rtol]
+            print("held-out", name, rtol, base[name, rtol], flush=True)
+
+    def fit(traces, rho, rw):
+        parts = [controller.dataset_from_trace(tr, rho=rho, reject_weight=rw) for tr in traces]
+        X = np.concatenate([p[0] for p in parts])
+        T = np.concatenate([p[1] for p in parts])
+        W = np.concatenate([p[2] for p in parts])
+        trn = controller.Trainer(seed=0)
+        hist = trn.fit(X, T, W, epochs=args.epochs, batch=4096, lr=2e-3)
+        return trn.weights_bf16(), int(X.shape[0]), [hist[0], hist[-1]]
+
     best = None
     for rho in (float(v) for v in args.rhos.split(",")):
         for rw in (float(v) for v in args.reject_weights.split(",")):
-            parts = [controller.dataset_from_trace(tr, rho=rho, reject_weight=rw) for tr in traces]
-            X = np.concatenate([p[0] for p in parts])
-            T = np.concatenate([p[1] for p in parts])
-            W = np.concatenate([p[2] for p in parts])
-            trn = controller.Trainer(seed=0)
-            t0 = time.perf_counter()
-            hist = trn.fit(X, T, W, epochs=args.epochs, batch=4096, lr=2e-3)
-            wb = trn.weights_bf16()
-            res = {"samples": int(X.shape[0]), "train_seconds": time.perf_counter() - t0,
-                   "loss_first_last": [hist[0], hist[-1]]}
-            tot = 0.0
-            for rtol in (1e-5, 1e-6):
-                stats, el, _ = run_ensemble(he, hp, seeds, args.t1, rtol, hode.CTRL_MLP, weights=wb)
-                res["rtol=%g" % rtol] = summarize(stats, el, he)
-                tot += el / base[rtol]["wall_s"]
-            res["mean_wall_ratio_vs_pi"] = tot / 2
             key = "rho=%g,reject_weight=%g" % (rho, rw)
+            t0 = time.perf_counter()
+            traces = list(pi_traces)
+            wb, ns, loss = fit(traces, rho, rw)
+            res = {"rounds": []}
+            for r in range(args.rounds):
+                rr = {}
+                for name, (edges, prms, s0, t1) in sets.items():
+                    k = len(edges) if name == "stiff" else min(args.agg_smooth, len(edges))
+                    for rtol in RTOLS:
+                        stats, el, tr = run_ensemble(edges[:k], prms[:k], list(range(s0, s0 + k)), t1, rtol,
+                                                     hode.CTRL_MLP, weights=wb, trace_cap=4000)
+                        traces += tr
+                        rr["%s rtol=%g" % (name, rtol)] = summarize(stats, el, edges[:k])
+                wb, ns, loss = fit(traces, rho, rw)
+                rr["samples"], rr["loss_first_last"] = ns, loss
+                res["rounds"].append(rr)
+                print(key, "round", r, json.dumps(rr), flush=True)
+            res["train_seconds"] = time.perf_counter() - t0
+            res["samples"], res["loss_first_last"] = ns, loss
+            ratios = []
+            for name, (he, hp, seeds, t1) in held.items():
+                for rtol in RTOLS:
+                    stats, el, _ = run_ensemble(he, hp, seeds, t1, rtol, hode.CTRL_MLP, weights=wb)
+                    res["%s rtol=%g" % (name, rtol)] = summarize(stats, el, he)
+                    ratios.append(el / base[name, rtol]["wall_s"])
+            res["wall_ratios_vs_pi"] = ratios
+            res["mean_wall_ratio_vs_pi"] = float(np.mean(ratios))
             summary["candidates"][key] = res
             print(key, json.dumps(res), flush=True)
             if best is None or res["mean_wall_ratio_vs_pi"] < best[0]:
