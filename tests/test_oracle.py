@@ -441,3 +441,40 @@ def test_parallel_and_serial_runs_identical(orc, tmp_path):
         subprocess.check_call([sys.executable, "-c", code % p], env=env, cwd=root)
         outs.append(np.load(p))
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_periodic_window_reproduces_full_grid_centre(orc):
+    # The full-size GPU tests check sampled cells against the oracle run on a
+    # periodic window of edge 2R + 1 around each sample (grid spacing kept):
+    # after E <= R right-hand-side evaluations the window centre equals the
+    # full grid's cell.  Pinned here against the full-grid oracle, including
+    # a window that wraps across the domain boundary.
+    # two attempts: the second ynew needs 12 evaluations (k1..k6 twice)
+    N, R = 40, 12
+    W = 2 * R + 1
+    y = inputs.gray_scott_ic(N, seed=21).reshape(2, N, N, N)
+    prm = dict(Du=2e-3, Dv=1e-3, F=0.053, k=0.014)
+    full = orc.gs_system(N, L=2.5, **prm)
+    win = orc.gs_system(W, L=2.5 * W / N, **prm)
+    ctr = np.array([0, 1]) * W ** 3 + (R * W + R) * W + R
+    yn_full, _, e_full = orc.dopri5_attempt(full, y.ravel(), 0.3)
+    yn_full2, _, _ = orc.dopri5_attempt(full, yn_full, 0.3)
+    for c in [(20, 20, 20), (0, 39, 5), (15, 15, 15)]:
+        idx = [np.arange(ci - R, ci + R + 1) % N for ci in c]
+        yw = y[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]].ravel()
+        ynw, _, ew = orc.dopri5_attempt(win, yw, 0.3)
+        ynw2, _, _ = orc.dopri5_attempt(win, ynw, 0.3)
+        got = ynw2[ctr]
+        want = yn_full2.reshape(2, N, N, N)[:, c[0], c[1], c[2]]
+        assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+        assert np.max(np.abs(ew[ctr] - e_full.reshape(2, N, N, N)[:, c[0], c[1], c[2]])) <= 1e-15
+    # a window one cell too small is wrong at the centre (the bound is tight)
+    Rs = 11
+    Ws = 2 * Rs + 1
+    small = orc.gs_system(Ws, L=2.5 * Ws / N, **prm)
+    c = (20, 20, 20)
+    idx = [np.arange(ci - Rs, ci + Rs + 1) % N for ci in c]
+    yw = y[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]].ravel()
+    ynw2, _, _ = orc.dopri5_attempt(small, orc.dopri5_attempt(small, yw, 0.3)[0], 0.3)
+    cs = np.array([0, 1]) * Ws ** 3 + (Rs * Ws + Rs) * Ws + Rs
+    assert np.max(np.abs(ynw2[cs] - yn_full2.reshape(2, N, N, N)[:, 20, 20, 20])) > 0
