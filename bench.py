@@ -9,7 +9,9 @@ noise +-0.01 (seed 5).  One benchmark step integrates one window of `--window`
 time units along the same trajectory (the next window starts where the last
 ended, with the last proposed step); the value is cells x accepted steps /
 wall time over the timed windows.  Other workloads: --workload
-gs256-rk4 | gs256-dp5 | ew24-dp5 | gs32-rk4-fp64.
+gs256-rk4 | gs256-dp5 | ew24-dp5 | gs32-rk4-fp64 | ens512-dp5 (the
+512-instance batched ensemble, edges 16..96, rtol 1e-5, t 0 -> 2000; one
+step integrates the whole horizon from the initial conditions).
 
 Prints ONE JSON line.  Inputs are resident in HBM before timing starts.
 """
@@ -45,9 +47,12 @@ WORKLOADS = {
     "gs512-dp5": dict(kind="gs", N=512, dtype="f32", method="dp5", window=10.0, seed=5, dt0=0.1),
     "gs256-dp5": dict(kind="gs", N=256, dtype="f32", method="dp5", window=10.0, seed=3, dt0=0.1),
     "gs256-rk4": dict(kind="gs", N=256, dtype="f32", method="rk4", steps_per=100, dt=0.1, seed=3),
-    "gs32-rk4-fp64": dict(kind="gs", N=32, dtype="f64", method="rk4", steps_per=500, dt=0.1, seed=1),
+    "gs32-rk4-fp64": dict(kind="gs", N=32, dtype="f64", method="rk4", steps_per=500, dt=0.1, seed=1,
+                          compare_graphs=True),
     "ew24-dp5": dict(kind="ew", n=1 << 24, dtype="f64", method="dp5", t1=5.0, seed=2, dt0=0.01),
+    "ens512-dp5": dict(kind="ens", n=512, dtype="f32", method="dp5", t1=2000.0, seed=4, dt0=0.1, rtol=1e-5),
 }
+DP5_ARRAYS = 30  # arrays of 2 N^3 elements one Dopri5 attempt reads or writes
 
 
 def traffic_from_profiles(kernel_tag: str):
@@ -89,6 +94,20 @@ def cpu_baseline_leg(wl, budget_s=10.0):
         sample = "%s on a %d^3 grid (same parameters), %d calls, %.1f s" % (
             "RK4 steps" if wl["method"] == "rk4" else "adaptive Dopri5 accepted steps", Ns, done, el)
         unit = "cell-updates/s"
+    elif wl["kind"] == "ens":
+        edges, F, k = inputs.ensemble_draws(wl["n"], seed=wl["seed"])
+        t0, units, i, t = time.perf_counter(), 0, 0, 0.0
+        while time.perf_counter() - t0 < budget_s and i < wl["n"]:
+            N = edges[i]
+            y = inputs.ensemble_ic(4000 + i, N).astype(np.float64).ravel()
+            sysd = oracle.gs_system(N, GS_PRM[0], GS_PRM[1], F[i], k[i], GS_PRM[4])
+            _, st, _ = oracle.integrate_adaptive(sysd, y, 0.0, wl["t1"], wl["dt0"], wl["rtol"], wl["rtol"],
+                                                 max_steps=20)
+            units += st["accepted"] * N ** 3
+            i += 1
+        el = time.perf_counter() - t0
+        sample = "the first %d ensemble instances, their first 20 adaptive Dopri5 attempts each, %.1f s" % (i, el)
+        unit = "cell-updates/s"
     else:
         n = 1 << 20
         x0 = inputs.exp_family_x0(n, seed=wl["seed"])
@@ -102,6 +121,69 @@ def cpu_baseline_leg(wl, budget_s=10.0):
         sample = "%d adaptive Dopri5 runs t 0->5 on 2^20 components, %.1f s" % (reps, el)
         unit = "component-updates/s"
     return {"value": units / el, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle", "sample": sample}
+
+
+def timed_steps(one_step, steps):
+    """Runs the timed steps between device synchronisations; returns the
+    total seconds and the per-step seconds."""
+    import torch
+    per = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        one_step()
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - ts)
+    return time.perf_counter() - t0, per
+
+
+def run_ens(wl, steps, warmup):
+    """The batched ensemble: 512 Gray-Scott instances (edges uniform over
+    16..96, F and k drawn per instance), each integrated adaptively over the
+    whole horizon; one step restarts every instance from its initial
+    condition (device-resident, copied in inside the step)."""
+    import torch
+    from paper_2309_05331_amd import hode, inputs
+    n = wl["n"]
+    edges, F, k = inputs.ensemble_draws(n, seed=wl["seed"])
+    prms = [[GS_PRM[0], GS_PRM[1], F[i], k[i], GS_PRM[4]] for i in range(n)]
+    ics = [torch.from_numpy(inputs.ensemble_ic(4000 + i, N).ravel()).to("cuda:0") for i, N in enumerate(edges)]
+    ens = hode.Ensemble(edges, prms, dtype=hode.F32)
+    ens.set_tolerances(wl["rtol"], wl["rtol"])
+    ens.set_controller(hode.CTRL_PI)
+    ens.autotune(3)
+    cells = np.array(edges, dtype=np.float64) ** 3
+    tot = {"acc": 0, "rej": 0, "cell_att": 0.0, "kernel_ms": 0.0, "launches": 0}
+
+    def one_step():
+        for i in range(n):
+            ens.init_instance(i, ics[i])
+        st = ens.integrate_adaptive(0.0, wl["t1"], wl["dt0"], max_steps=10 ** 6)
+        assert all(x["status"] == 0 for x in st)
+        acc = np.array([x["accepted"] for x in st])
+        rej = np.array([x["rejected"] for x in st])
+        kms, nl = ens.timing()
+        tot["acc"] += float((cells * acc).sum())
+        tot["rej"] += int(rej.sum())
+        tot["cell_att"] += float((cells * (acc + rej)).sum())
+        tot["kernel_ms"] += kms
+        tot["launches"] += nl
+        tot["instance_attempts"] = int((acc + rej).sum())
+
+    for _ in range(warmup):
+        one_step()
+    for key in ("acc", "rej", "cell_att", "kernel_ms", "launches"):
+        tot[key] = 0
+    el, per = timed_steps(one_step, steps)
+    ens.close()
+    # algorithmic bytes: 30 arrays per attempt plus the first k1 (2 arrays) per
+    # instance and step
+    abytes = (DP5_ARRAYS * tot["cell_att"] + 2 * steps * cells.sum()) * 2 * 4
+    return dict(elapsed=el, per_step=per, cells=1, accepted=tot["acc"], rejected=tot["rej"], dom="ens_kernel",
+                dom_ms=tot["kernel_ms"], dom_bytes=abytes, stage_gbs=None,
+                attempt_gbs=abytes / el / 1e9, tile=None, launches=tot["launches"],
+                instance_attempts=tot["instance_attempts"])
 
 
 def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
@@ -141,12 +223,17 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     for _ in range(warmup):
         one_step()
     state["acc"] = state["rej"] = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        one_step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el, per = timed_steps(one_step, steps)
+    no_graph = None
+    if wl.get("compare_graphs"):
+        # the same steps with every kernel enqueued on the stream instead of
+        # replayed from captured graphs (launch overhead of a small grid)
+        acc0 = state["acc"]
+        ctx.set_graphs(False)
+        el_ng, _ = timed_steps(one_step, steps)
+        ctx.set_graphs(True)
+        no_graph = {"value": N ** 3 * (state["acc"] - acc0) / el_ng, "ms_per_step": el_ng / steps * 1e3}
+        state["acc"] = acc0  # the value counts the timed (graph) steps only
     # per-stage durations: HIP events around every stage kernel of attempts
     # replayed in the same order on the library's stream, right after the
     # timed region
@@ -162,7 +249,8 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     attempt_ms = sum(ms.values())
     ry, zc = ctx.get_tile()
     ctx.close()
-    return dict(elapsed=el, cells=N ** 3, accepted=state["acc"], rejected=state["rej"], t_end=state["t"],
+    return dict(elapsed=el, per_step=per, no_graph=no_graph, cells=N ** 3, accepted=state["acc"], rejected=state["rej"],
+                t_end=state["t"],
                 dom=GS_NAMES[dom], dom_ms=ms[dom], dom_bytes=bytes_dom, stage_gbs=stage_gbs,
                 attempt_gbs=step_bytes / (attempt_ms * 1e-3) / 1e9, tile=[ry, zc])
 
@@ -186,15 +274,10 @@ def run_ew(wl, steps, warmup):
     for _ in range(warmup):
         one_step()
     acc[0] = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        one_step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el, per = timed_steps(one_step, steps)
     ms = ctx.time_kernel(hode.DOPRI5, 20)
     ctx.close()
-    return dict(elapsed=el, cells=n, accepted=acc[0], rejected=0, dom="ew_step_dp5", dom_ms=ms,
+    return dict(elapsed=el, per_step=per, cells=n, accepted=acc[0], rejected=0, dom="ew_step_dp5", dom_ms=ms,
                 dom_bytes=2 * n * 8, stage_gbs=None, attempt_gbs=2 * n * 8 / (ms * 1e-3) / 1e9, tile=None)
 
 
@@ -235,6 +318,8 @@ def main():
     ap.add_argument("--workload", default="gs512-dp5", choices=sorted(WORKLOADS))
     ap.add_argument("--controller", default="pi", choices=["pi", "i"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-ceiling", action="store_true",
+                    help="skip timing the plain streaming copy beside the workload")
     ap.add_argument("--tile", default="auto", help="auto (autotune) or RY,ZC")
     ap.add_argument("--ab", type=float, default=0.0, metavar="T1",
                     help="also integrate the workload grid from 0 to T1 with PI and with the learned controller")
@@ -266,6 +351,13 @@ def main():
                "rtol": 1e-6 if wl["method"] == "dp5" else None, "controller": args.controller,
                "window_time_units": wl.get("window"), "dt": wl.get("dt"), "tile_ry_zc": r["tile"],
                "params": {"Du": GS_PRM[0], "Dv": GS_PRM[1], "F": GS_PRM[2], "k": GS_PRM[3], "L": GS_PRM[4]}}
+    elif wl["kind"] == "ens":
+        r = run_ens(wl, args.steps, args.warmup)
+        unit = "cell-updates/s"
+        cfg = {"workload": args.workload, "instances": wl["n"], "edges": "uniform over 16..96 step 8", "fields": 2,
+               "method": "dopri5-adaptive", "rtol": wl["rtol"], "controller": "pi", "t": [0.0, wl["t1"]],
+               "launch": "persistent gang kernel in a hipGraph, relaunched per epoch of attempts",
+               "launches_per_step": r["launches"] / max(args.steps, 1)}
     else:
         r = run_ew(wl, args.steps, args.warmup)
         unit = "component-updates/s"
@@ -274,9 +366,12 @@ def main():
     value = r["cells"] * r["accepted"] / r["elapsed"]
     achieved = r["dom_bytes"] / (r["dom_ms"] * 1e-3) / 1e9
     tag = "%s_%s" % (r["dom"], args.workload)
+    per = np.array(r["per_step"]) * 1e3
     out = {
         "metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": r["elapsed"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": r["elapsed"] / args.steps * 1e3,
+        "ms_per_step_sd": round(float(per.std(ddof=1)), 3) if per.size > 1 else None,
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": wl["dtype"], "data": "synthetic", "config": cfg,
         "accepted_steps": r["accepted"], "rejected_steps": r["rejected"],
         "roofline": {"bound": "hbm", "kernel": r["dom"], "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
@@ -284,6 +379,17 @@ def main():
                      "traffic": traffic_from_profiles(tag)},
         "stage_gbs": r["stage_gbs"], "attempt_gbs": round(r["attempt_gbs"], 1),
     }
+    if r.get("no_graph"):
+        out["without_graphs"] = r["no_graph"]
+    if not args.no_copy_ceiling:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        cms, cgbs = hode.stream_copy(dst, src, reps=10)
+        del src, dst
+        out["copy_ceiling"] = {"kernel": "hode_stream_copy", "bytes": 2 << 30, "GBps": round(cgbs, 1),
+                               "frac_of_peak": round(cgbs / PEAK_HBM_GBS, 4),
+                               "dominant_kernel_frac_of_copy": round(achieved / cgbs, 4)}
     if args.ab > 0 and wl["kind"] == "gs":
         out["controller_ab"] = dict(run_ab(wl["N"], args.ab, args.weights, wl["dtype"]), t1=args.ab, rtol=1e-6)
     if not args.no_cpu_baseline:

@@ -148,6 +148,12 @@ int hode_read_trace(hode_ctx *ctx, double *dst, int64_t cap, int64_t *n);
  * the state). */
 int hode_eval_rhs(hode_ctx *ctx, void *dst, size_t dst_bytes, int dst_on_device);
 
+/* Launch mode of the integration loop: enable != 0 (default) replays
+ * captured hipGraph chunks of attempts; 0 enqueues every stage and control
+ * kernel on the stream instead (same kernels and results; for comparing
+ * launch overhead on small, launch-bound grids). */
+int hode_set_graphs(hode_ctx *ctx, int enable);
+
 /* Gray-Scott tile configuration: ry in {1, 2, 4} (tile of 64 x 4*ry cells per
  * workgroup), zc >= 1 z-planes per workgroup.  Element-wise: `ry` is ignored
  * and zc is the workgroup count cap. */
@@ -186,13 +192,17 @@ int hode_stream_copy(void *dst, const void *src, size_t bytes, int reps, double 
 
 /* ---- batched ensemble ------------------------------------------------------
  * n independent Gray-Scott instances (uneven grid edges and parameters), each
- * with its own adaptive Dopri5 step control, stepped together by ONE
- * persistent kernel launch (captured in a hipGraph): workgroups form gangs per
- * instance (large grids get several workgroups splitting z-slabs, small ones
- * one) following a static longest-processing-time schedule built on the host
- * from per-instance work weights.  Every instance's arithmetic is the same as
- * the single-grid path's, so results are bitwise those of running the
- * instance alone. */
+ * with its own adaptive Dopri5 step control, stepped together by a
+ * persistent kernel (captured once in a hipGraph).  One launch advances every
+ * unfinished instance by up to a fixed number of attempts (64 by default) in
+ * lock step: per attempt, six stage phases and one control phase separated by
+ * grid-wide barriers; in a stage phase the workgroups claim tiles (rows and
+ * planes of one instance) from eight per-XCD queues, their own XCD's first,
+ * so every phase is balanced dynamically.  The host relaunches with the
+ * instances still running until all are done.  Pausing changes no result:
+ * every instance's arithmetic and step decisions are those of the
+ * single-grid path, so results are bitwise those of running the instance
+ * alone. */
 
 /* Creates an ensemble context: instance i has grid edge edges[i] (1..1024) and
  * params[5*i .. 5*i+4] = {Du, Dv, F, k, L}; dtype HODE_F32 or HODE_F64.  All
@@ -205,9 +215,19 @@ int hode_ensemble_size(const hode_ctx *ctx);
 int hode_ensemble_init_state(hode_ctx *ctx, int i, const void *src, int src_on_device);
 int hode_ensemble_read_state(hode_ctx *ctx, int i, void *dst, size_t dst_bytes, int dst_on_device);
 
-/* Work weights (> 0) for the gang scheduler, one per instance (default:
- * N^3 (1 + N/64)). */
+/* Per-attempt work estimates (> 0, any common unit), one per instance, used
+ * to deal the instances to the per-XCD tile queues (default: the cells the
+ * instance's tiles cover, rows padded to the 64-lane tile width). */
 int hode_ensemble_set_weights(hode_ctx *ctx, const double *w);
+
+/* Attempts per instance in the first launch and in every later one (1 ..
+ * 4096; defaults 64 and 64).  Shorter launches drop finished instances'
+ * tiles sooner and relaunch more often. */
+int hode_ensemble_set_epoch(hode_ctx *ctx, int first, int rest);
+
+/* The last integration's summed kernel durations (HIP events around every
+ * launch, in ms) and its number of launches; either pointer may be NULL. */
+int hode_ensemble_timing(hode_ctx *ctx, double *kernel_ms, int *launches);
 
 /* Cells per lane of instance i's tiles: 1, 2 or 4 (fp64: 1 or 2), dividing N. */
 int hode_ensemble_set_vector_width(hode_ctx *ctx, int i, int vw);
@@ -218,8 +238,8 @@ int hode_ensemble_read_trace(hode_ctx *ctx, int i, double *dst, int64_t cap, int
 
 /* Tile autotuner of the ensemble: for every distinct grid edge, times one
  * Dopri5 attempt (reps repetitions) of one of its instances for each vector
- * width (cells per lane) and keeps the fastest; the scheduler's work weights
- * become the measured attempt times.  vw_out/ms_out (n entries each, may be
+ * width (cells per lane) and keeps the fastest; the work estimates become
+ * the measured attempt times.  vw_out/ms_out (n entries each, may be
  * NULL) receive the choice and the attempt time per instance. */
 int hode_ensemble_autotune(hode_ctx *ctx, int reps, int *vw_out, double *ms_out);
 

@@ -34,21 +34,24 @@ struct Ensemble {
   std::vector<double> prm;  // n x {Du, Dv, F, k, L}
   std::vector<hode::EnsInst> inst;
   std::vector<int> parity, vw;
-  std::vector<double> weight;
+  std::vector<double> weight;  // per-attempt work estimates (dealing instances to queues)
   std::vector<int64_t> attempts_last;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  double kernel_ms_last = 0;  // summed launch durations of the last integration
+  int launches_last = 0;
+  int epoch_first = 64, epoch_len = 64;  // attempts per instance per launch
   void* pool = nullptr;
   hode::EnsInst* d_inst = nullptr;
-  hode::EnsWork* d_items = nullptr;
-  int32_t* d_offs = nullptr;
-  uint32_t* d_err = nullptr;
-  size_t items_cap = 0;
+  hode::EnsTile* d_tiles = nullptr;
+  size_t tiles_cap = 0;
+  // one device block: qoff[9] | params | bar | error | live[max_rounds] | qctr[8 (1 + 6 max_rounds)]
+  void* d_sync = nullptr;
+  int sync_rounds = 0;
   int nwg = 0;
   double* d_trace = nullptr;
   int64_t trace_cap = 0;
   hipGraphExec_t graph = nullptr;
-  std::vector<int> gang;
 };
-
 
 struct hode_ctx {
   int device = 0;
@@ -74,6 +77,7 @@ struct hode_ctx {
   int ry = 0, zc = 0, ew_grid = 0, vw = 0;
   bool k1_valid = false;
   int parity = 0, k1slot = 0;
+  bool use_graphs = true;      // replay captured chunks (else enqueue every kernel)
   bool persist_valid = false;  // controller history carried between try_step calls
   DevCtrl persist;
   hode_stats last{};
@@ -250,10 +254,14 @@ int run_loop(hode_ctx* c, const DevCtrl& init, bool need_k1) {
     } else {
       M = pow2_floor(cur.nsteps - cur.accepted);
     }
-    hipGraphExec_t ex;
-    int rc = get_graph(c, init.mode, M, &ex);
-    if (rc) return rc;
-    HIPCHK(c, hipGraphLaunch(ex, c->stream));
+    if (c->use_graphs) {
+      hipGraphExec_t ex;
+      int rc = get_graph(c, init.mode, M, &ex);
+      if (rc) return rc;
+      HIPCHK(c, hipGraphLaunch(ex, c->stream));
+    } else {
+      for (int i = 0; i < M; ++i) HIPCHK(c, enqueue_attempt(c, init.mode));
+    }
     HIPCHK(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, sizeof(DevCtrl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     cur = *c->h_ctrl;
@@ -287,53 +295,53 @@ void free_ensemble(hode_ctx* c) {
   if (e->graph) hipGraphExecDestroy(e->graph);
   if (e->pool) hipFree(e->pool);
   if (e->d_inst) hipFree(e->d_inst);
-  if (e->d_items) hipFree(e->d_items);
-  if (e->d_offs) hipFree(e->d_offs);
-  if (e->d_err) hipFree(e->d_err);
+  if (e->d_tiles) hipFree(e->d_tiles);
+  if (e->d_sync) hipFree(e->d_sync);
   if (e->d_trace) hipFree(e->d_trace);
+  for (hipEvent_t& v : e->ev)
+    if (v) hipEventDestroy(v);
   delete e;
   c->ens = nullptr;
 }
 
-// Static longest-processing-time gang schedule.  Instances are taken in
-// decreasing work; each gets g workgroups (its share of the total work, at
-// least 1, at most one per 8 z-planes) chosen among the earliest-free ones;
-// the gang starts when its last member is free.  Every workgroup's list is in
-// this one global order, which rules out circular waits between gangs.
-void build_schedule(const Ensemble& e, int G, std::vector<std::vector<hode::EnsWork>>& lists,
-                    std::vector<int>& gang) {
-  const int n = e.n;
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
+// The tiles of one launch: every active instance cut into row chunks of 16
+// (the last one ends at N) and plane chunks sized so a phase has about four
+// tiles per workgroup (at least 4096 cells per tile, at least 4 planes), in
+// plane-chunk-major, row-chunk-minor order (tiles that share halo rows are
+// claimed close together).  Instances are dealt to eight queues, one per
+// XCD, largest work first onto the least loaded queue.
+void build_tiles(const Ensemble& e, int G, const std::vector<int>& active, std::vector<hode::EnsTile>& tiles,
+                 std::vector<int32_t>& qoff) {
+  double cells = 0;
+  for (int i : active) cells += (double)e.N[i] * e.N[i] * e.N[i];
+  const double target = std::max(4096.0, cells / (4.0 * G));
+  std::vector<int> order(active);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return e.weight[a] > e.weight[b]; });
-  double total = 0;
-  for (double w : e.weight) total += w;
-  const double unit = total / G;
-  lists.assign(G, {});
-  gang.assign(n, 1);
-  using Slot = std::pair<double, int>;  // (free at, workgroup)
-  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> q;
-  for (int w = 0; w < G; ++w) q.push({0.0, w});
+  std::vector<std::vector<int>> q(8);
+  std::vector<double> load(8, 0.0);
   for (int i : order) {
-    const int maxg = std::max(1, std::min(G, e.N[i] / 8));
-    int g = (int)std::lround(e.weight[i] / (unit > 0 ? unit : 1.0));
-    g = std::max(1, std::min(g, maxg));
-    std::vector<Slot> pick;
-    for (int k = 0; k < g; ++k) {
-      pick.push_back(q.top());
-      q.pop();
-    }
-    double start = 0;
-    for (auto& sl : pick) start = std::max(start, sl.first);
-    std::sort(pick.begin(), pick.end(), [](const Slot& a, const Slot& b) { return a.second < b.second; });
-    const double end = start + e.weight[i] / g;
-    for (int r = 0; r < g; ++r) {
-      const int z0 = (int)((int64_t)e.N[i] * r / g), z1 = (int)((int64_t)e.N[i] * (r + 1) / g);
-      lists[pick[r].second].push_back({i, z0, z1, r});
-      q.push({end, pick[r].second});
-    }
-    gang[i] = g;
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    q[x].push_back(i);
+    load[x] += e.weight[i];
   }
+  tiles.clear();
+  qoff.assign(9, 0);
+  for (int x = 0; x < 8; ++x) {
+    qoff[x] = (int32_t)tiles.size();
+    for (int i : q[x]) {
+      const int N = e.N[i];
+      const int ny = (N + 15) / 16;
+      int zc = (int)std::lround(target / ((double)N * 16.0));
+      zc = std::max(4, std::min(N, zc));
+      const int nz = (N + zc - 1) / zc;
+      for (int kz = 0; kz < nz; ++kz) {
+        const int z0 = (int)((int64_t)N * kz / nz), z1 = (int)((int64_t)N * (kz + 1) / nz);
+        for (int ky = 0; ky < ny; ++ky)
+          tiles.push_back({i, 16 * ky, std::min(N, 16 * (ky + 1)), z0, z1, 0});
+      }
+    }
+  }
+  qoff[8] = (int32_t)tiles.size();
 }
 
 }  // namespace
@@ -801,6 +809,12 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   return HODE_OK;
 }
 
+int hode_set_graphs(hode_ctx* c, int enable) {
+  if (!c) return HODE_EINVAL;
+  c->use_graphs = enable != 0;
+  return HODE_OK;
+}
+
 int hode_ensemble_create(hode_ctx** out, int device, void* stream, int n, const int64_t* edges,
                          const double* params, int dtype) {
   if (!out || n < 1 || !edges || !params || (dtype != HODE_F32 && dtype != HODE_F64)) return HODE_EINVAL;
@@ -828,11 +842,11 @@ int hode_ensemble_create(hode_ctx** out, int device, void* stream, int n, const 
   e->attempts_last.assign(n, 0);
   e->weight.resize(n);
   e->inst.resize(n);
-  // default work weights: cells x an attempt count that grows like N^2 (the
-  // explicit stability limit of the 7-point Laplacian shrinks like 1/N^2)
+  // default per-attempt work estimates: the cells the instance's tiles cover
+  // (rows padded to the 64-lane tile width)
   for (int i = 0; i < n; ++i) {
     const double Nd = (double)e->N[i];
-    e->weight[i] = Nd * Nd * Nd * (64.0 + Nd * Nd);
+    e->weight[i] = std::ceil(Nd / 64.0) * 64.0 * Nd * Nd;
   }
   // one pool: 9 arrays of 2 N^3 elements per instance, 256-byte aligned
   std::vector<size_t> off(n);
@@ -867,8 +881,7 @@ int hode_ensemble_create(hode_ctx** out, int device, void* stream, int n, const 
     while (v * 2 <= maxvw && Ni % (v * 2) == 0 && 64 * v < Ni) v *= 2;  // narrowest that still fills a row
     e->vw[i] = v;
   }
-  if (hipMalloc(&e->d_inst, sizeof(hode::EnsInst) * n) != hipSuccess ||
-      hipMalloc(&e->d_err, sizeof(uint32_t)) != hipSuccess) {
+  if (hipMalloc(&e->d_inst, sizeof(hode::EnsInst) * n) != hipSuccess) {
     hode_destroy(c);
     *out = nullptr;
     return HODE_ENOMEM;
@@ -877,6 +890,11 @@ int hode_ensemble_create(hode_ctx** out, int device, void* stream, int n, const 
   int cus = 0;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   e->nwg = std::max(1, bpc) * std::max(1, cus);
+  if (hipEventCreate(&e->ev[0]) != hipSuccess || hipEventCreate(&e->ev[1]) != hipSuccess) {
+    hode_destroy(c);
+    *out = nullptr;
+    return HODE_EHIP;
+  }
   return HODE_OK;
 }
 
@@ -962,6 +980,38 @@ int hode_ensemble_read_trace(hode_ctx* c, int i, double* dst, int64_t cap, int64
   return HODE_OK;
 }
 
+int hode_ensemble_set_epoch(hode_ctx* c, int first, int rest) {
+  int rc = ens_check(c, 0);
+  if (rc) return rc;
+  if (first < 1 || rest < 1 || first > 4096 || rest > 4096)
+    return fail(c, HODE_EINVAL, "attempts per launch must be in 1 .. 4096");
+  c->ens->epoch_first = first;
+  c->ens->epoch_len = rest;
+  return HODE_OK;
+}
+
+int hode_ensemble_timing(hode_ctx* c, double* kernel_ms, int* launches) {
+  int rc = ens_check(c, 0);
+  if (rc) return rc;
+  if (kernel_ms) *kernel_ms = c->ens->kernel_ms_last;
+  if (launches) *launches = c->ens->launches_last;
+  return HODE_OK;
+}
+
+// Device block of the launch bookkeeping, sized for `rounds` rounds.
+struct SyncLayout {
+  size_t qoff, params, bar, error, live, qctr, bytes;
+  explicit SyncLayout(int rounds) {
+    qoff = 0;
+    params = 64;
+    bar = params + sizeof(hode::EnsParams);
+    error = bar + 4;
+    live = error + 4;
+    qctr = live + 4 * (size_t)rounds;
+    bytes = qctr + 4 * 8 * (1 + 6 * (size_t)rounds);
+  }
+};
+
 int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double dt0, int64_t max_steps,
                                      hode_stats* per_instance) {
   int rc = ens_check(c, 0);
@@ -970,29 +1020,6 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     return fail(c, HODE_EINVAL, "bad integration arguments");
   Ensemble* e = c->ens;
   HIPCHK(c, hipSetDevice(c->device));
-  // schedule
-  std::vector<std::vector<hode::EnsWork>> lists;
-  build_schedule(*e, e->nwg, lists, e->gang);
-  std::vector<hode::EnsWork> items;
-  std::vector<int32_t> offs(e->nwg + 1, 0);
-  for (int w = 0; w < e->nwg; ++w) {
-    offs[w] = (int32_t)items.size();
-    items.insert(items.end(), lists[w].begin(), lists[w].end());
-  }
-  offs[e->nwg] = (int32_t)items.size();
-  if (items.size() > e->items_cap || !e->d_offs) {
-    if (e->d_items) hipFree(e->d_items);
-    if (e->d_offs) hipFree(e->d_offs);
-    e->d_items = nullptr;
-    e->d_offs = nullptr;
-    if (e->graph) { hipGraphExecDestroy(e->graph); e->graph = nullptr; }
-    e->items_cap = std::max<size_t>(items.size(), 2 * (size_t)e->n + e->nwg);
-    if (hipMalloc(&e->d_items, sizeof(hode::EnsWork) * e->items_cap) != hipSuccess ||
-        hipMalloc(&e->d_offs, sizeof(int32_t) * (e->nwg + 1)) != hipSuccess)
-      return fail(c, HODE_ENOMEM, "schedule allocation failed");
-  }
-  HIPCHK(c, hipMemcpy(e->d_items, items.data(), sizeof(hode::EnsWork) * items.size(), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(e->d_offs, offs.data(), sizeof(int32_t) * offs.size(), hipMemcpyHostToDevice));
   // per-instance control blocks
   for (int i = 0; i < e->n; ++i) {
     hode::EnsInst& I = e->inst[i];
@@ -1010,33 +1037,98 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     d.trace_cap = e->trace_cap;
     d.stiff = gs_stiffness(&e->prm[5 * i], e->N[i]);
     I.ctrl = d;
-    I.bar = 0;
-    I.gang = e->gang[i];
     I.vw = e->vw[i];
+    I.k1_valid = 0;
   }
-  HIPCHK(c, hipMemcpy(e->d_inst, e->inst.data(), sizeof(hode::EnsInst) * e->n, hipMemcpyHostToDevice));
-  const uint32_t zero = 0;
-  HIPCHK(c, hipMemcpy(e->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice));
-  // the persistent kernel, captured once into a graph
-  if (!e->graph) {
-    hode::EnsSched sch{e->d_items, e->d_offs, e->d_err, (int64_t)1 << 30};
-    hipGraph_t g = nullptr;
-    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = hode::launch_ensemble(e->dtype, e->d_inst, sch, e->nwg, c->stream);
-    hipError_t ee = hipStreamEndCapture(c->stream, &g);
-    if (le != hipSuccess || ee != hipSuccess) {
-      if (g) hipGraphDestroy(g);
-      return fail(c, HODE_EHIP, std::string("ensemble capture: ") + hipGetErrorString(le != hipSuccess ? le : ee));
+  // bookkeeping block and tile buffer (the captured graph holds their addresses)
+  const int max_rounds = std::max(e->epoch_first, e->epoch_len);
+  if (!e->d_sync || e->sync_rounds < max_rounds) {
+    if (e->graph) { hipGraphExecDestroy(e->graph); e->graph = nullptr; }
+    if (e->d_sync) hipFree(e->d_sync);
+    e->d_sync = nullptr;
+    if (hipMalloc(&e->d_sync, SyncLayout(max_rounds).bytes) != hipSuccess)
+      return fail(c, HODE_ENOMEM, "ensemble bookkeeping allocation failed");
+    e->sync_rounds = max_rounds;
+  }
+  const SyncLayout L(e->sync_rounds);
+  char* sb = (char*)e->d_sync;
+  e->kernel_ms_last = 0;
+  e->launches_last = 0;
+  std::vector<int> active;
+  std::vector<hode::EnsTile> tiles;
+  std::vector<int32_t> qoff;
+  for (int launch = 0;; ++launch) {
+    active.clear();
+    for (int i = 0; i < e->n; ++i)
+      if (!e->inst[i].ctrl.done) active.push_back(i);
+    if (active.empty()) break;
+    const int rounds = launch == 0 ? e->epoch_first : e->epoch_len;
+    build_tiles(*e, e->nwg, active, tiles, qoff);
+    if (tiles.size() > e->tiles_cap) {
+      if (e->graph) { hipGraphExecDestroy(e->graph); e->graph = nullptr; }
+      if (e->d_tiles) hipFree(e->d_tiles);
+      e->d_tiles = nullptr;
+      e->tiles_cap = std::max(tiles.size(), (size_t)1024);
+      if (hipMalloc(&e->d_tiles, sizeof(hode::EnsTile) * e->tiles_cap) != hipSuccess)
+        return fail(c, HODE_ENOMEM, "tile allocation failed");
     }
-    hipError_t ie = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    HIPCHK(c, ie);
+    bool need_d1 = false;
+    for (int i : active) {
+      hode::EnsInst& I = e->inst[i];
+      I.pause_at = I.ctrl.attempts + rounds;
+      need_d1 = need_d1 || !I.k1_valid;
+    }
+    const hode::EnsParams prm{rounds, need_d1 ? 1 : 0, e->n, 0};
+    HIPCHK(c, hipMemcpy(e->d_tiles, tiles.data(), sizeof(hode::EnsTile) * tiles.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemsetAsync(sb + L.bar, 0, L.bytes - L.bar, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sb + L.qoff, qoff.data(), sizeof(int32_t) * 9, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sb + L.params, &prm, sizeof(prm), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(e->d_inst, e->inst.data(), sizeof(hode::EnsInst) * e->n, hipMemcpyHostToDevice,
+                             c->stream));
+    // the persistent kernel, captured once into a graph: its arguments are
+    // the fixed buffers above, refilled before every launch
+    if (!e->graph) {
+      hode::EnsSched sch{e->d_tiles,
+                         (const int32_t*)(sb + L.qoff),
+                         (uint32_t*)(sb + L.qctr),
+                         (uint32_t*)(sb + L.bar),
+                         (uint32_t*)(sb + L.live),
+                         (uint32_t*)(sb + L.error),
+                         (const hode::EnsParams*)(sb + L.params),
+                         (int64_t)1 << 30};
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      hipGraph_t g = nullptr;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      hipError_t le = hode::launch_ensemble(e->dtype, e->d_inst, sch, e->nwg, c->stream);
+      hipError_t ee = hipStreamEndCapture(c->stream, &g);
+      if (le != hipSuccess || ee != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return fail(c, HODE_EHIP, std::string("ensemble capture: ") + hipGetErrorString(le != hipSuccess ? le : ee));
+      }
+      hipError_t ie = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIPCHK(c, ie);
+    }
+    HIPCHK(c, hipEventRecord(e->ev[0], c->stream));
+    HIPCHK(c, hipGraphLaunch(e->graph, c->stream));
+    HIPCHK(c, hipEventRecord(e->ev[1], c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float kms = 0;
+    HIPCHK(c, hipEventElapsedTime(&kms, e->ev[0], e->ev[1]));
+    e->kernel_ms_last += kms;
+    ++e->launches_last;
+    uint32_t err = 0;
+    HIPCHK(c, hipMemcpy(&err, sb + L.error, sizeof(err), hipMemcpyDeviceToHost));
+    if (err) return fail(c, HODE_EHIP, "ensemble grid barrier timed out (workgroups not co-resident?)");
+    std::vector<int64_t> before(e->n);
+    for (int i = 0; i < e->n; ++i) before[i] = e->inst[i].ctrl.attempts;
+    HIPCHK(c, hipMemcpy(e->inst.data(), e->d_inst, sizeof(hode::EnsInst) * e->n, hipMemcpyDeviceToHost));
+    for (int i : active) {
+      hode::EnsInst& I = e->inst[i];
+      if (I.ctrl.attempts == before[i] && !I.ctrl.done) return fail(c, HODE_EHIP, "ensemble launch made no progress");
+      I.k1_valid = 1;
+    }
   }
-  HIPCHK(c, hipGraphLaunch(e->graph, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  uint32_t err = 0;
-  HIPCHK(c, hipMemcpy(&err, e->d_err, sizeof(err), hipMemcpyDeviceToHost));
-  HIPCHK(c, hipMemcpy(e->inst.data(), e->d_inst, sizeof(hode::EnsInst) * e->n, hipMemcpyDeviceToHost));
   int worst = HODE_OK;
   for (int i = 0; i < e->n; ++i) {
     const DevCtrl& d = e->inst[i].ctrl;
@@ -1055,7 +1147,6 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     }
     if (d.status != HODE_OK && worst == HODE_OK) worst = d.status;
   }
-  if (err) return fail(c, HODE_EHIP, "ensemble gang barrier timed out (workgroups not co-resident?)");
   return worst;
 }
 
@@ -1081,7 +1172,8 @@ int hode_ensemble_autotune(hode_ctx* c, int reps, int* vw_out, double* ms_out) {
     for (int vw = 1; vw <= maxvw && !rc; vw *= 2) {
       if (N % vw) continue;
       rc = hode_set_vector_width(t, vw);
-      if (!rc) rc = hode_set_tile(t, 1, N);
+      // the ensemble's tiles: 16 bytes of state per lane and field per row set
+      if (!rc) rc = hode_set_tile(t, (int)(16 / c->esize) / vw, N);
       double ms[8];
       if (!rc) rc = hode_profile_attempt(t, HODE_DOPRI5, reps, ms);
       if (rc) break;
@@ -1098,8 +1190,7 @@ int hode_ensemble_autotune(hode_ctx* c, int reps, int* vw_out, double* ms_out) {
     const auto& b = best[e->N[i]];
     e->vw[i] = b.first;
     // work weight: measured attempt time x attempts growing mildly with N
-    const double Nd = (double)e->N[i];
-    e->weight[i] = b.second * (1.0 + Nd / 64.0);
+    e->weight[i] = b.second;
     if (vw_out) vw_out[i] = b.first;
     if (ms_out) ms_out[i] = b.second;
   }

@@ -296,8 +296,10 @@ __device__ inline void ctrl_step(DevCtrl* c) {
   __shared__ CtrlScratch s;
   __shared__ int s_adaptive;
   if (threadIdx.x == 0) {
-    const uint64_t bits = c->errmax_bits;
-    c->errmax_bits = 0;
+    // read and clear with one atomic: the stage kernels' contributions are
+    // atomics too, so this stays coherent with them when the controller
+    // runs inside the same workgroup that produced them
+    const uint64_t bits = atomicExch((unsigned long long*)&c->errmax_bits, 0ull);
     s_adaptive = c->mode == MODE_ADAPTIVE;
     if (s_adaptive) decide_a(c, __longlong_as_double((long long)bits), &s);
     else if (c->mode != 0) fixed_step_done(c);  // mode 0: timing runs change nothing

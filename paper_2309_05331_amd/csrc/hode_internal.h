@@ -48,26 +48,38 @@ hipError_t launch_ew_rhs(int dtype, int rhs, const void* y, void* out, int64_t n
 
 // ---- batched ensemble -------------------------------------------------------
 // One instance of the ensemble: its grid and arrays, its own control block
-// (time, step, controller state, counters) and the barrier counter of the
-// gang of workgroups that steps it.
+// (time, step, controller state, counters).
 struct EnsInst {
   GSLaunch a;
   DevCtrl ctrl;
-  uint32_t bar;   // gang barrier arrivals (monotonic)
-  int32_t gang;   // workgroups in the gang
-  int32_t vw;     // cells per lane for this instance's tiles
+  int64_t pause_at;  // the instance sits out the rest of a launch once ctrl.attempts reaches this
+  int32_t vw;        // cells per lane for this instance's tiles
+  int32_t k1_valid;  // k1 = f(y) is already in the first-same-as-last slot (resumed instance)
+};
+
+// One tile of a stage phase: rows [y0, y1) (y0 a multiple of 16) and planes
+// [z0, z1) of one instance, all columns.
+struct EnsTile {
+  int32_t inst, y0, y1, z0, z1, pad;
+};
+
+// Launch parameters the kernel reads from device memory (so one captured
+// graph serves every launch).
+struct EnsParams {
+  int32_t rounds;    // attempts per instance in this launch (at most)
+  int32_t first_d1;  // run a stage-1 phase first (some instance has no k1 yet)
+  int32_t n_inst;
   int32_t pad;
 };
 
-// One gang membership of a workgroup: instance, z-slab [z0, z1), rank.
-struct EnsWork {
-  int32_t inst, z0, z1, rank;
-};
-
 struct EnsSched {
-  const EnsWork* items;  // memberships, grouped per workgroup
-  const int32_t* offs;   // workgroup w owns items[offs[w] .. offs[w+1])
-  uint32_t* error;       // set when a gang barrier waited past spin_limit
+  const EnsTile* tiles;     // tiles, grouped in eight queues (one per XCD)
+  const int32_t* qoff;      // queue x holds tiles[qoff[x] .. qoff[x+1])
+  uint32_t* qctr;           // claim counters, 8 per tile phase (zero at launch)
+  uint32_t* bar;            // grid barrier arrivals (zero at launch)
+  uint32_t* live;           // per round: instances still running after it (zero at launch)
+  uint32_t* error;          // set when a barrier waited past spin_limit
+  const EnsParams* params;
   int64_t spin_limit;
 };
 

@@ -76,6 +76,7 @@ def lib():
             "hode_set_trace": ([P, I64], I),
             "hode_read_trace": ([P, P, I64, C.POINTER(I64)], I),
             "hode_eval_rhs": ([P, P, S, I], I),
+            "hode_set_graphs": ([P, I], I),
             "hode_set_tile": ([P, I, I], I),
             "hode_get_tile": ([P, C.POINTER(I), C.POINTER(I)], I),
             "hode_time_kernel": ([P, I, I, C.POINTER(D)], I),
@@ -88,6 +89,8 @@ def lib():
             "hode_ensemble_init_state": ([P, I, P, I], I),
             "hode_ensemble_read_state": ([P, I, P, S, I], I),
             "hode_ensemble_set_weights": ([P, C.POINTER(D)], I),
+            "hode_ensemble_set_epoch": ([P, I, I], I),
+            "hode_ensemble_timing": ([P, C.POINTER(D), C.POINTER(I)], I),
             "hode_ensemble_set_vector_width": ([P, I, I], I),
             "hode_ensemble_set_trace": ([P, I64], I),
             "hode_ensemble_read_trace": ([P, I, P, I64, C.POINTER(I64)], I),
@@ -235,6 +238,9 @@ class Context:
         p, nb, on_dev = _ptr_of(dst)
         return self._check(self.L.hode_eval_rhs(self.h, p, nb, on_dev))
 
+    def set_graphs(self, enable):
+        return self._check(self.L.hode_set_graphs(self.h, 1 if enable else 0))
+
     def set_tile(self, ry, zc):
         return self._check(self.L.hode_set_tile(self.h, ry, zc))
 
@@ -293,6 +299,15 @@ class Ensemble(Context):
     def set_weights(self, w):
         arr = (C.c_double * len(w))(*[float(v) for v in w])
         return self._check(self.L.hode_ensemble_set_weights(self.h, arr))
+
+    def set_epoch(self, first, rest):
+        return self._check(self.L.hode_ensemble_set_epoch(self.h, first, rest))
+
+    def timing(self):
+        """(summed kernel ms, launches) of the last integration."""
+        ms, n = C.c_double(), C.c_int()
+        self._check(self.L.hode_ensemble_timing(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def set_instance_vector_width(self, i, vw):
         return self._check(self.L.hode_ensemble_set_vector_width(self.h, i, vw))
