@@ -63,10 +63,12 @@ def traffic_from_profiles(kernel_tag: str):
         return None
     try:
         rec = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_2309_05331_amd", "csrc", rec["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        h = hashlib.sha256()
+        for nm in rec["sources"]:
+            h.update(open(os.path.join(ROOT, "paper_2309_05331_amd", "csrc", nm), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
             return None
-        return rec["hbm_bytes_per_launch"]
+        return rec.get("hbm_bytes_per_launch", rec.get("hbm_bytes_per_run"))
     except Exception:
         return None
 

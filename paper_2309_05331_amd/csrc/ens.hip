@@ -1,0 +1,206 @@
+// The batched-ensemble kernel: many Gray-Scott instances stepped by one
+// persistent kernel with the same stage tiles (stage.h) as the single-grid
+// path.
+#include "stage.h"
+
+#include <type_traits>
+
+namespace hode {
+
+namespace {
+
+// ---- the persistent ensemble kernel -------------------------------------------
+// One launch steps every unfinished instance for up to `rounds` attempts in
+// lock step: each round runs the six stage phases of a Dopri5 attempt and a
+// control phase, with a grid-wide barrier after each.  A stage phase is a
+// pool of tiles (instance, rows, planes) covering every instance; the host
+// deals the instances to eight queues, one per XCD, and a workgroup claims
+// tiles from its own XCD's queue first (neighbouring tiles, whose halo rows
+// overlap, then share an L2) and from the others once it is empty, so each
+// phase is balanced dynamically.  The control phase runs each instance's
+// step controller on one workgroup.  Instances that are done, or reached
+// the launch's pause point, skip their tiles and control; the host then
+// relaunches with the instances still running, and a resumed instance skips
+// stage 1 (its k1 is in the first-same-as-last slot), so pausing changes no
+// result.  The grid barrier is an arrival counter with device-scope
+// release/acquire; the grid is sized from the occupancy so every workgroup
+// is resident at once, and a barrier that waits longer than spin_limit polls
+// flags an error on which every workgroup leaves.
+
+__device__ inline bool ens_error(const EnsSched& s) {
+  return __hip_atomic_load(s.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__device__ inline void grid_sync(const EnsSched& s, uint32_t& gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();  // release this workgroup's outputs
+    atomicAdd(s.bar, 1u);
+    const uint32_t target = (gen + 1) * gridDim.x;
+    int64_t spins = 0;
+    while (__hip_atomic_load(s.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > s.spin_limit) {
+        atomicExch(s.error, 1u);
+        break;
+      }
+      if ((spins & 255) == 0 && ens_error(s)) break;
+    }
+    __threadfence();  // acquire everyone's outputs
+  }
+  __syncthreads();
+  ++gen;
+}
+
+// The arguments of a device function arrive in vector registers; the launch
+// description is the same for every lane, so it is copied word by word
+// through the first lane into scalar registers (as a kernel argument would
+// be), which keeps the array pointers and grid constants out of the vector
+// register budget of the stage loop.
+template <typename S>
+__device__ inline S uniform_copy(const S& src) {
+  static_assert(sizeof(S) % 4 == 0, "word copy");
+  uint32_t w[sizeof(S) / 4];
+  __builtin_memcpy(w, &src, sizeof(S));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  S out;
+  __builtin_memcpy(&out, w, sizeof(S));
+  return out;
+}
+
+// Rows per wave of the ensemble's tiles: narrow rows (few cells per lane)
+// take more rows per wave, so each plane step still has about 16 bytes of
+// state per lane and field in flight, except where that would exceed the
+// persistent kernel's register budget (stage 6, the widest, keeps half).
+// Every choice divides 16, the row granularity of the tiles.
+template <typename T, int KIND, int VW>
+constexpr int ens_rows() {
+  constexpr int full = (int)(16 / sizeof(T)) / VW;
+  constexpr int r = KIND == K_D6 ? full / 2 : full;
+  return r < 1 ? 1 : r;
+}
+
+// Not inlined: each stage variant keeps its own register allocation, so the
+// persistent kernel's budget is the largest single stage, not their union.
+template <typename T, int KIND, int VW>
+__device__ __noinline__ void ens_tile_vw(EnsInst* I, char* smem, int y0, int y1, int z0, int z1) {
+  constexpr int RY = ens_rows<T, KIND, VW>();
+  constexpr int TY = 4 * RY;
+  const GSLaunch a = uniform_copy(I->a);
+  DevCtrl* c = uniform_copy(&I->ctrl);
+  y0 = __builtin_amdgcn_readfirstlane(y0);
+  y1 = __builtin_amdgcn_readfirstlane(y1);
+  z0 = __builtin_amdgcn_readfirstlane(z0);
+  z1 = __builtin_amdgcn_readfirstlane(z1);
+  const int nx = (a.N + 64 * VW - 1) / (64 * VW);
+  for (int ty = y0 / TY; ty * TY < y1; ++ty)
+    for (int tx = 0; tx < nx; ++tx) stage_tile<T, KIND, RY, VW>(a, c, smem, tx, ty, z0, z1);
+}
+
+template <typename T, int KIND>
+__device__ void ens_tile(EnsInst* I, char* smem, const EnsTile& t) {
+  if constexpr (sizeof(T) == 4) {
+    if (I->vw == 4) return ens_tile_vw<T, KIND, 4>(I, smem, t.y0, t.y1, t.z0, t.z1);
+    if (I->vw == 2) return ens_tile_vw<T, KIND, 2>(I, smem, t.y0, t.y1, t.z0, t.z1);
+  } else {
+    if (I->vw == 2) return ens_tile_vw<T, KIND, 2>(I, smem, t.y0, t.y1, t.z0, t.z1);
+  }
+  ens_tile_vw<T, KIND, 1>(I, smem, t.y0, t.y1, t.z0, t.z1);
+}
+
+// An instance takes part in a round's phases while it is not done and below
+// its pause point (both change only in the control phase).
+__device__ inline bool ens_running(const EnsInst* I) {
+  return !__hip_atomic_load(&I->ctrl.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+         __hip_atomic_load(&I->ctrl.attempts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < I->pause_at;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 3) void ens_kernel(EnsInst* __restrict__ inst, const EnsSched s) {
+  __shared__ __align__(16) char smem[kTileSmem];
+  __shared__ int s_claim, s_run;
+  const EnsParams prm = *s.params;
+  const int xcd = blockIdx.x & 7;  // workgroups are dealt round-robin to the 8 XCDs
+  uint32_t gen = 0;
+  int phase = 0;
+
+  // one stage phase over every queue's tiles; false once an error is flagged
+  auto stage_phase = [&](auto kind) -> bool {
+    constexpr int K = decltype(kind)::value;
+    for (int q = 0; q < 8; ++q) {
+      const int x = (xcd + q) & 7;
+      const int base = s.qoff[x], cnt = s.qoff[x + 1] - base;
+      uint32_t* ctr = s.qctr + phase * 8 + x;
+      for (;;) {
+        if (threadIdx.x == 0) {
+          int t = cnt;
+          if ((int)__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < cnt) t = (int)atomicAdd(ctr, 1u);
+          int run = 0;
+          if (t < cnt) {
+            const EnsInst* I = &inst[s.tiles[base + t].inst];
+            run = K == K_D1 ? (!I->k1_valid && ens_running(I)) : ens_running(I);
+          }
+          s_claim = t;
+          s_run = run;
+        }
+        __syncthreads();
+        const int t = s_claim, run = s_run;
+        __syncthreads();
+        if (t >= cnt) break;
+        if (run) {
+          const EnsTile tl = s.tiles[base + t];
+          ens_tile<T, K>(&inst[tl.inst], smem, tl);
+        }
+      }
+    }
+    ++phase;
+    grid_sync(s, gen);
+    return !ens_error(s);
+  };
+
+  if (prm.first_d1 && !stage_phase(std::integral_constant<int, K_D1>())) return;
+  for (int r = 0; r < prm.rounds; ++r) {
+    if (!stage_phase(std::integral_constant<int, K_D2>())) return;
+    if (!stage_phase(std::integral_constant<int, K_D3>())) return;
+    if (!stage_phase(std::integral_constant<int, K_D4>())) return;
+    if (!stage_phase(std::integral_constant<int, K_D5>())) return;
+    if (!stage_phase(std::integral_constant<int, K_D6>())) return;
+    if (!stage_phase(std::integral_constant<int, K_D7>())) return;
+    // control phase: the members' error maxima are device-scope atomics made
+    // before the barrier above; the controller reads them with an atomic
+    for (int i = blockIdx.x; i < prm.n_inst; i += gridDim.x) {
+      EnsInst* I = &inst[i];
+      if (threadIdx.x == 0) s_run = ens_running(I);
+      __syncthreads();
+      const int run = s_run;
+      __syncthreads();
+      if (run) {
+        ctrl_step(&I->ctrl);
+        if (threadIdx.x == 0 && ens_running(I)) atomicAdd(&s.live[r], 1u);
+      }
+    }
+    grid_sync(s, gen);
+    if (ens_error(s)) return;
+    // every instance finished or paused: leave early (uniform: all read after the barrier)
+    if (__hip_atomic_load(&s.live[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_ensemble(int dtype, EnsInst* inst, EnsSched s, int nwg, hipStream_t st) {
+  if (nwg < 1) return hipErrorInvalidValue;
+  if (dtype == 1) ens_kernel<float><<<nwg, 256, 0, st>>>(inst, s);
+  else ens_kernel<double><<<nwg, 256, 0, st>>>(inst, s);
+  return hipGetLastError();
+}
+
+int ensemble_blocks_per_cu(int dtype) {
+  int n = 0;
+  hipError_t e = dtype == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<float>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<double>, 256, 0);
+  return e == hipSuccess ? n : 0;
+}
+
+}  // namespace hode

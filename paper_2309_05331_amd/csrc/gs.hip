@@ -1,436 +1,14 @@
-// Fused Runge-Kutta stage kernels for the periodic 3D Gray-Scott system.
-//
-// System (the paper's Gray-Scott equation and its System functor listing):
-//   du/dt = Du Lap(u) - u v^2 + F (1 - u)
-//   dv/dt = Dv Lap(v) + u v^2 - (F + k) v
-// with Lap the 7-point finite-difference Laplacian on an N^3 periodic grid of
-// spacing L/N.  One kernel per Runge-Kutta stage fuses the Algebra (the stage
-// input y + h sum_j a_sj k_j, formed on the fly, neighbour cells included),
-// the System (stencil + reaction) and the stage's outputs.
-//
-// Layout: field-major SoA, u then v, each N^3 with x fastest.
-//
-// Work decomposition (2.5D blocking): a workgroup of 4 wavefronts owns a tile
-// of 64*VW x 4*RY cells of an x-y plane and marches a chunk of zc planes in z.
-// Each wavefront owns a strip of RY consecutive x-rows, VW cells per lane (one
-// 16-byte load per lane per row).  Per plane, every row is loaded from memory
-// once: the stage input is formed in registers, the z neighbours stay in
-// registers (planes z-1, z, z+1), x neighbours come across lanes by shuffle,
-// y neighbours inside a strip are the wave's own rows, and only the strips'
-// first and last rows plus the tile halo (the rows above and below the tile,
-// the two x-halo columns) pass through a small double-buffered LDS area: one
-// barrier per plane.  Periodic wrap is folded into precomputed offsets; lanes
-// and rows beyond a ragged edge load wrapped cells, which are exactly the
-// neighbours the edge cells need, and write nothing.
+// Single-grid launches of the fused Runge-Kutta stage kernels: one tile
+// (stage_tile, in stage.h) per workgroup over the whole grid.
 //
 // Block order is XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so
 // the linear block id is remapped to give each XCD a contiguous range of
 // tiles, keeping y- and z-adjacent tiles (whose halo rows overlap) on one L2.
-//
-// Dopri5 stages 6 and 7 are restructured so stage 7 reads 3 arrays instead of
-// 6: stage 6 forms the new state y + h sum b_j k_j (= the stage-7 input, first
-// same as last) and the partial error h sum_{j<=6} (b_j - bhat_j) k_j at the
-// own cell and stores both instead of k6; stage 7 evaluates k7 = f(ynew) and
-// completes the error with h (b_7 - bhat_7) k7.
-#include "hode_internal.h"
-
-#include <type_traits>
+#include "stage.h"
 
 namespace hode {
 
 namespace {
-
-// array ids
-enum : int { A_Y = 0, A_K1 = 1, A_K2, A_K3, A_K4, A_K5, A_E6 = 6, A_K7 = 7, A_YN = 8 };
-
-struct KindDesc {
-  int ns;          // source arrays forming the stage input (first has coefficient 1)
-  int src[6];
-  double a[6];     // stage-input coefficients (times h); a[0] unused
-  int nx;          // extra arrays needed at the own cell only
-  int extra[2];
-  int out;         // array receiving f(stage input), -1 none
-  int fin;         // own-cell finish: 0 none, 1 RK4 new state, 2 Dopri5 new state (+ partial error),
-                   // 3 Dopri5 error completion
-  bool err;        // error norm computed
-};
-
-constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0, B5 = -2187.0 / 6784.0,
-                 B6 = 11.0 / 84.0;
-constexpr double D1 = 35.0 / 384.0 - 5179.0 / 57600.0, D3 = 500.0 / 1113.0 - 7571.0 / 16695.0,
-                 D4 = 125.0 / 192.0 - 393.0 / 640.0, D5 = -2187.0 / 6784.0 + 92097.0 / 339200.0,
-                 D6 = 11.0 / 84.0 - 187.0 / 2100.0, D7 = -1.0 / 40.0;
-
-constexpr KindDesc kDesc[K_COUNT] = {
-    /* D1  */ {1, {A_Y}, {0}, 0, {0, 0}, A_K1, 0, false},
-    /* R2  */ {2, {A_Y, A_K1}, {0, 0.5}, 0, {0, 0}, A_K2, 0, false},
-    /* R3  */ {2, {A_Y, A_K2}, {0, 0.5}, 0, {0, 0}, A_K3, 0, false},
-    /* R4  */ {2, {A_Y, A_K3}, {0, 1.0}, 2, {A_K1, A_K2}, -1, 1, false},
-    /* D2  */ {2, {A_Y, A_K1}, {0, 1.0 / 5.0}, 0, {0, 0}, A_K2, 0, false},
-    /* D3  */ {3, {A_Y, A_K1, A_K2}, {0, 3.0 / 40.0, 9.0 / 40.0}, 0, {0, 0}, A_K3, 0, false},
-    /* D4  */ {4, {A_Y, A_K1, A_K2, A_K3}, {0, 44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0}, 0, {0, 0}, A_K4, 0, false},
-    /* D5  */ {5, {A_Y, A_K1, A_K2, A_K3, A_K4},
-               {0, 19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0}, 0, {0, 0}, A_K5, 0,
-               false},
-    /* D6  */ {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
-               {0, 9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0}, 0, {0, 0},
-               -1, 2, true},
-    /* D7  */ {1, {A_YN}, {0}, 2, {A_E6, A_Y}, A_K7, 3, true},
-    /* D7F */ {1, {A_YN}, {0}, 0, {0, 0}, A_K7, 0, false},
-};
-// D6 in fixed-step mode: the new state only (no partial error).
-constexpr KindDesc kD6F = {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
-                           {0, 9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0},
-                           0, {0, 0}, -1, 2, false};
-
-template <int KIND>
-__host__ __device__ constexpr KindDesc desc() {
-  return KIND == K_COUNT ? kD6F : kDesc[KIND];
-}
-
-template <typename T>
-__device__ inline T* array_ptr(const GSLaunch& a, int id, int p, int ks) {
-  switch (id) {
-    case A_Y: return (T*)a.y[p];
-    case A_YN: return (T*)a.y[p ^ 1];
-    case A_K1: return (T*)a.ks[ks];
-    case A_K7: return (T*)a.ks[ks ^ 1];
-    default: return (T*)a.k[id];
-  }
-}
-
-template <typename T, int VW>
-struct VecT;
-template <>
-struct VecT<float, 4> { using type = float4; };
-template <>
-struct VecT<float, 2> { using type = float2; };
-template <>
-struct VecT<float, 1> { using type = float; };
-template <>
-struct VecT<double, 2> { using type = double2; };
-template <>
-struct VecT<double, 1> { using type = double; };
-
-template <typename T, int VW>
-struct Pk {
-  T v[VW];
-};
-
-template <typename T, int VW>
-__device__ __forceinline__ Pk<T, VW> ldv(const T* __restrict__ p, int64_t g) {
-  using V = typename VecT<T, VW>::type;
-  const V x = *reinterpret_cast<const V*>(p + g);
-  Pk<T, VW> r;
-  __builtin_memcpy(&r, &x, sizeof(r));
-  return r;
-}
-
-#ifndef HODE_NT_STORES
-#define HODE_NT_STORES 1
-#endif
-
-// Stage outputs are streamed out with non-temporal stores: each array is
-// written once and read by later stage kernels, far beyond what L2 holds.
-template <typename T, int VW>
-__device__ __forceinline__ void stv(T* __restrict__ p, int64_t g, const Pk<T, VW>& r) {
-  if constexpr (HODE_NT_STORES) {
-    if constexpr (VW == 1) {
-      __builtin_nontemporal_store(r.v[0], p + g);
-    } else {
-      typedef T V __attribute__((ext_vector_type(VW)));
-      V x;
-#pragma unroll
-      for (int e = 0; e < VW; ++e) x[e] = r.v[e];
-      __builtin_nontemporal_store(x, reinterpret_cast<V*>(p + g));
-    }
-  } else {
-    using V = typename VecT<T, VW>::type;
-    V x;
-    __builtin_memcpy(&x, &r, sizeof(r));
-    *reinterpret_cast<V*>(p + g) = x;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ T shfl_up1(T v) {
-  return __shfl_up(v, 1, 64);
-}
-template <typename T>
-__device__ __forceinline__ T shfl_down1(T v) {
-  return __shfl_down(v, 1, 64);
-}
-
-// Bytes of LDS one stage tile needs (the largest over all instantiations).
-constexpr int kTileSmem = 2 * 2 * 10 * 64 * 16 + 2 * 2 * 2 * 16 * 8;
-
-// One stage over one tile: columns x0 .. x0 + 64*VW - 1, rows ty*4*RY ..
-// (ty+1)*4*RY - 1, planes zbeg .. zend - 1 of the grid described by `a`, with
-// step h, parity and first-same-as-last slot taken from the control block.
-// Called by all 256 threads of a workgroup; smem is kTileSmem bytes of LDS.
-template <typename T, int KIND, int RY, int VW>
-__device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* smem, int tx, int ty, int zbeg,
-                           int zend) {
-  constexpr KindDesc D = desc<KIND>();
-  constexpr int TX = 64 * VW;
-  constexpr int TY = 4 * RY;
-  using P = Pk<T, VW>;
-  static_assert(2 * 2 * 10 * 64 * sizeof(P) + 2 * 2 * 2 * TY * sizeof(T) <= kTileSmem, "LDS budget");
-  // LDS per buffer and field: 10 row slots (tile halo above, first and last
-  // row of each wave's strip, tile halo below) and the x-halo cells
-  P(*rows)[2][10][64] = reinterpret_cast<P(*)[2][10][64]>(smem);
-  T(*xh)[2][2][TY] = reinterpret_cast<T(*)[2][2][TY]>(smem + 2 * 2 * 10 * 64 * sizeof(P));
-  __syncthreads();  // LDS may still be in use by the previous tile
-
-  const double h = c->h;
-  const int p = c->parity, ksl = c->k1slot;
-  const int N = a.N;
-  const int64_t n3 = a.n3;
-  const int64_t NN = (int64_t)N * N;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int x0 = tx * TX, yt = ty * TY;
-  const int y0 = yt + wv * RY;  // first row of this wave's strip
-
-  const T* src[6];
-#pragma unroll
-  for (int i = 0; i < D.ns; ++i) src[i] = array_ptr<T>(a, D.src[i], p, ksl);
-  const T* ext[2];
-#pragma unroll
-  for (int i = 0; i < D.nx; ++i) ext[i] = array_ptr<T>(a, D.extra[i], p, ksl);
-  T* out = D.out >= 0 ? array_ptr<T>(a, D.out, p, ksl) : nullptr;
-  T* ynew = (D.fin == 1 || D.fin == 2) ? (T*)a.y[p ^ 1] : nullptr;
-  T* e6 = (D.fin == 2 && D.err) ? (T*)a.k[A_E6] : nullptr;
-
-  T cf[6];
-#pragma unroll
-  for (int i = 1; i < D.ns; ++i) cf[i] = (T)(h * D.a[i]);
-  const T Du = (T)a.Du_h2, Dv = (T)a.Dv_h2, F = (T)a.F, Fk = (T)(a.F + a.kk);
-  const double atol = c->atol, rtol = c->rtol;
-  (void)atol;
-  (void)rtol;
-  const T b16 = (T)(h * (1.0 / 6.0)), b13 = (T)(h * (1.0 / 3.0));
-  const T q1 = (T)(h * B1), q3 = (T)(h * B3), q4 = (T)(h * B4), q5 = (T)(h * B5), q6 = (T)(h * B6);
-  const double h1 = h * D1, h3 = h * D3, h4 = h * D4, h5 = h * D5, h6 = h * D6, h7 = h * D7;
-
-  // ---- offsets (periodic wrap folded in)
-  const int xl = x0 + VW * lane;
-  const int gx = xl % N;  // N % VW == 0, so gx .. gx+VW-1 are one aligned run
-  const bool xval = xl < N;
-  int rowoff[RY];
-#pragma unroll
-  for (int r = 0; r < RY; ++r) rowoff[r] = N * ((y0 + r) % N);
-  // halo role of this wave: 0 the row above the tile, 1 the row below,
-  // 2 the x-halo cells (lanes < TY left column, TY .. 2TY-1 right column)
-  int hoff = 0;
-  bool hact = false;
-  if (wv == 0) { hoff = N * ((yt - 1 + N) % N) + gx; hact = true; }
-  else if (wv == 1) { hoff = N * ((yt + TY) % N) + gx; hact = true; }
-  else if (wv == 2 && lane < 2 * TY) {
-    const int side = lane >= TY, rr = lane - side * TY;
-    hoff = N * ((yt + rr) % N) + (side ? (x0 + TX) % N : (x0 - 1 + N) % N);
-    hact = true;
-  }
-
-  // Partial own-cell finish of one row-field, formed at load time so the raw
-  // sources need not stay live: RK4 y + h/6 k1 + h/3 k2 + h/3 k3; Dopri5
-  // stage 6 y + h sum_{j<6} b_j k_j and (fp64) h sum_{j<6} (b_j - bhat_j) k_j;
-  // stage 7 the stored partial error and y.
-  struct Fin {
-    T a[VW];
-    double e[(D.fin == 2 && D.err) ? VW : 1];
-    T b[D.fin == 3 ? VW : 1];
-  };
-
-  auto stage_in = [&](int64_t g, Fin* fin) -> P {
-    P s[6];
-#pragma unroll
-    for (int i = 0; i < D.ns; ++i) s[i] = ldv<T, VW>(src[i], g);
-    P w = s[0];
-#pragma unroll
-    for (int i = 1; i < D.ns; ++i)
-#pragma unroll
-      for (int e = 0; e < VW; ++e) w.v[e] += cf[i] * s[i].v[e];
-    if constexpr (D.fin != 0) {
-      if (fin == nullptr) return w;  // halo cells need no finish
-      P x[2];
-#pragma unroll
-      for (int i = 0; i < D.nx; ++i) x[i] = ldv<T, VW>(ext[i], g);
-#pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        if constexpr (D.fin == 1) {
-          // sources y, k3; extras k1, k2
-          fin->a[e] = s[0].v[e] + b16 * x[0].v[e] + b13 * x[1].v[e] + b13 * s[1].v[e];
-        } else if constexpr (D.fin == 2) {
-          // sources y, k1 .. k5
-          fin->a[e] = s[0].v[e] + q1 * s[1].v[e] + q3 * s[3].v[e] + q4 * s[4].v[e] + q5 * s[5].v[e];
-          if constexpr (D.err)
-            fin->e[e] = h1 * (double)s[1].v[e] + h3 * (double)s[3].v[e] + h4 * (double)s[4].v[e] +
-                        h5 * (double)s[5].v[e];
-        } else {
-          // source ynew; extras partial error, y
-          fin->a[e] = x[0].v[e];
-          fin->b[e] = x[1].v[e];
-        }
-      }
-    }
-    return w;
-  };
-  auto stage_in1 = [&](int64_t g) -> T {
-    T w = src[0][g];
-#pragma unroll
-    for (int i = 1; i < D.ns; ++i) w += cf[i] * src[i][g];
-    return w;
-  };
-
-  P wp[2][RY], wc[2][RY], wn[2][RY];
-  Fin fc[2][RY], fn[2][RY];
-  P hv[2];  // halo data of this wave's role (scalar in .v[0] for the x-halo role)
-  uint64_t emax = 0;
-
-  auto load_plane = [&](int z, P (&w)[2][RY], Fin (&fin)[2][RY], bool halo) {
-    const int64_t zb = (int64_t)z * NN;
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      const int64_t fb = f * n3 + zb;
-#pragma unroll
-      for (int r = 0; r < RY; ++r) w[f][r] = stage_in(fb + rowoff[r] + gx, &fin[f][r]);
-      if (halo && hact) {
-        if (wv < 2) hv[f] = stage_in(fb + hoff, nullptr);
-        else hv[f].v[0] = stage_in1(fb + hoff);
-      }
-    }
-  };
-  // boundary rows of the strip and the halo role's data go to LDS buffer b
-  auto publish = [&](int b, const P (&w)[2][RY]) {
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      rows[b][f][1 + 2 * wv][lane] = w[f][0];
-      rows[b][f][2 + 2 * wv][lane] = w[f][RY - 1];
-      if (hact) {
-        if (wv == 0) rows[b][f][0][lane] = hv[f];
-        else if (wv == 1) rows[b][f][9][lane] = hv[f];
-        else xh[b][f][lane >= TY][lane - (lane >= TY) * TY] = hv[f].v[0];
-      }
-    }
-  };
-
-  // prologue: own rows of plane zbeg-1 (z neighbours), plane zbeg in full
-  {
-    Fin tmpf[2][RY];
-    load_plane((zbeg - 1 + N) % N, wp, tmpf, false);
-  }
-  load_plane(zbeg, wc, fc, true);
-  publish(0, wc);
-
-  for (int z = zbeg; z < zend; ++z) {
-    const int b = (z - zbeg) & 1;
-    load_plane(z + 1 == N ? 0 : z + 1, wn, fn, true);
-    __syncthreads();
-    const int64_t zb = (int64_t)z * NN;
-    // neighbours across strip boundaries and the x-halo of the strip rows
-    P above[2], below[2];
-    T xlft[2][RY], xrgt[2][RY];
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      above[f] = rows[b][f][2 * wv][lane];
-      below[f] = rows[b][f][2 * wv + 3][lane];
-#pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        xlft[f][r] = xh[b][f][0][wv * RY + r];
-        xrgt[f][r] = xh[b][f][1][wv * RY + r];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      P fo[2];
-#pragma unroll
-      for (int f = 0; f < 2; ++f) {
-        const P& cc = wc[f][r];
-        const P& up = r == 0 ? above[f] : wc[f][r - 1];
-        const P& dn = r == RY - 1 ? below[f] : wc[f][r + 1];
-        const T left = shfl_up1(cc.v[VW - 1]);
-        const T right = shfl_down1(cc.v[0]);
-        const T xm0 = lane == 0 ? xlft[f][r] : left;
-        const T xpN = lane == 63 ? xrgt[f][r] : right;
-#pragma unroll
-        for (int e = 0; e < VW; ++e) {
-          const T xm = e == 0 ? xm0 : cc.v[e - 1];
-          const T xp = e == VW - 1 ? xpN : cc.v[e + 1];
-          const T s = (xm + xp + up.v[e] + dn.v[e]);
-          fo[f].v[e] = (s + wp[f][r].v[e] + wn[f][r].v[e]) - (T)6 * cc.v[e];
-        }
-      }
-      // reaction terms
-#pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        const T u = wc[0][r].v[e], v = wc[1][r].v[e];
-        const T uvv = u * v * v;
-        const T lu = fo[0].v[e], lv = fo[1].v[e];
-        fo[0].v[e] = Du * lu - uvv + F * ((T)1 - u);
-        fo[1].v[e] = Dv * lv + uvv - Fk * v;
-      }
-      const bool valid = xval && (y0 + r < N);
-      if (valid) {
-        const int64_t g = zb + rowoff[r] + gx;
-        if (D.out >= 0) {
-          stv<T, VW>(out, g, fo[0]);
-          stv<T, VW>(out, n3 + g, fo[1]);
-        }
-        if constexpr (D.fin == 1) {
-          // RK4 new state
-#pragma unroll
-          for (int f = 0; f < 2; ++f) {
-            P yn;
-#pragma unroll
-            for (int e = 0; e < VW; ++e) yn.v[e] = fc[f][r].a[e] + b16 * fo[f].v[e];
-            stv<T, VW>(ynew, f * n3 + g, yn);
-          }
-        } else if constexpr (D.fin == 2) {
-          // Dopri5 new state (and partial error)
-#pragma unroll
-          for (int f = 0; f < 2; ++f) {
-            P yn, ep;
-#pragma unroll
-            for (int e = 0; e < VW; ++e) {
-              yn.v[e] = fc[f][r].a[e] + q6 * fo[f].v[e];
-              if constexpr (D.err) ep.v[e] = (T)(fc[f][r].e[e] + h6 * (double)fo[f].v[e]);
-            }
-            stv<T, VW>(ynew, f * n3 + g, yn);
-            if constexpr (D.err) stv<T, VW>(e6, f * n3 + g, ep);
-          }
-        } else if constexpr (D.fin == 3) {
-          // Dopri5 error completion: |E6 + h d7 k7| / (atol + rtol max(|y|, |ynew|))
-#pragma unroll
-          for (int f = 0; f < 2; ++f) {
-#pragma unroll
-            for (int e = 0; e < VW; ++e) {
-              const double err = (double)fc[f][r].a[e] + h7 * (double)fo[f].v[e];
-              const double sc = atol + rtol * fmax(fabs((double)fc[f][r].b[e]), fabs((double)wc[f][r].v[e]));
-              const uint64_t bits = (uint64_t)__double_as_longlong(fabs(err) / sc);
-              emax = bits > emax ? bits : emax;
-            }
-          }
-        }
-      }
-    }
-    publish(b ^ 1, wn);
-    // rotate planes
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-#pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        wp[f][r] = wc[f][r];
-        wc[f][r] = wn[f][r];
-        if constexpr (D.fin != 0) fc[f][r] = fn[f][r];
-      }
-    }
-  }
-
-  if constexpr (D.err && D.fin == 3) {
-    emax = wave_max_u64(emax);
-    if (lane == 0 && emax) atomicMax((unsigned long long*)&c->errmax_bits, (unsigned long long)emax);
-  }
-}
 
 // One stage over a whole grid: one tile per workgroup.  The linear block id
 // is remapped XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so
@@ -486,184 +64,6 @@ hipError_t launch_vw(int kind, int ry, const GSLaunch& a, DevCtrl* c, hipStream_
   return hipErrorInvalidValue;
 }
 
-// ---- the persistent ensemble kernel -------------------------------------------
-// One launch steps every unfinished instance for up to `rounds` attempts in
-// lock step: each round runs the six stage phases of a Dopri5 attempt and a
-// control phase, with a grid-wide barrier after each.  A stage phase is a
-// pool of tiles (instance, rows, planes) covering every instance; the host
-// deals the instances to eight queues, one per XCD, and a workgroup claims
-// tiles from its own XCD's queue first (neighbouring tiles, whose halo rows
-// overlap, then share an L2) and from the others once it is empty, so each
-// phase is balanced dynamically.  The control phase runs each instance's
-// step controller on one workgroup.  Instances that are done, or reached
-// the launch's pause point, skip their tiles and control; the host then
-// relaunches with the instances still running, and a resumed instance skips
-// stage 1 (its k1 is in the first-same-as-last slot), so pausing changes no
-// result.  The grid barrier is an arrival counter with device-scope
-// release/acquire; the grid is sized from the occupancy so every workgroup
-// is resident at once, and a barrier that waits longer than spin_limit polls
-// flags an error on which every workgroup leaves.
-
-__device__ inline bool ens_error(const EnsSched& s) {
-  return __hip_atomic_load(s.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-}
-
-__device__ inline void grid_sync(const EnsSched& s, uint32_t& gen) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();  // release this workgroup's outputs
-    atomicAdd(s.bar, 1u);
-    const uint32_t target = (gen + 1) * gridDim.x;
-    int64_t spins = 0;
-    while (__hip_atomic_load(s.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > s.spin_limit) {
-        atomicExch(s.error, 1u);
-        break;
-      }
-      if ((spins & 255) == 0 && ens_error(s)) break;
-    }
-    __threadfence();  // acquire everyone's outputs
-  }
-  __syncthreads();
-  ++gen;
-}
-
-// The arguments of a device function arrive in vector registers; the launch
-// description is the same for every lane, so it is copied word by word
-// through the first lane into scalar registers (as a kernel argument would
-// be), which keeps the array pointers and grid constants out of the vector
-// register budget of the stage loop.
-template <typename S>
-__device__ inline S uniform_copy(const S& src) {
-  static_assert(sizeof(S) % 4 == 0, "word copy");
-  uint32_t w[sizeof(S) / 4];
-  __builtin_memcpy(w, &src, sizeof(S));
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
-  S out;
-  __builtin_memcpy(&out, w, sizeof(S));
-  return out;
-}
-
-// Rows per wave of the ensemble's tiles: narrow rows (few cells per lane)
-// take more rows per wave, so each plane step still has about 16 bytes of
-// state per lane and field in flight, except where that would exceed the
-// persistent kernel's register budget (stage 6, the widest, keeps half).
-// Every choice divides 16, the row granularity of the tiles.
-template <typename T, int KIND, int VW>
-constexpr int ens_rows() {
-  constexpr int full = (int)(16 / sizeof(T)) / VW;
-  constexpr int r = KIND == K_D6 ? full / 2 : full;
-  return r < 1 ? 1 : r;
-}
-
-// Not inlined: each stage variant keeps its own register allocation, so the
-// persistent kernel's budget is the largest single stage, not their union.
-template <typename T, int KIND, int VW>
-__device__ __noinline__ void ens_tile_vw(EnsInst* I, char* smem, int y0, int y1, int z0, int z1) {
-  constexpr int RY = ens_rows<T, KIND, VW>();
-  constexpr int TY = 4 * RY;
-  const GSLaunch a = uniform_copy(I->a);
-  DevCtrl* c = uniform_copy(&I->ctrl);
-  y0 = __builtin_amdgcn_readfirstlane(y0);
-  y1 = __builtin_amdgcn_readfirstlane(y1);
-  z0 = __builtin_amdgcn_readfirstlane(z0);
-  z1 = __builtin_amdgcn_readfirstlane(z1);
-  const int nx = (a.N + 64 * VW - 1) / (64 * VW);
-  for (int ty = y0 / TY; ty * TY < y1; ++ty)
-    for (int tx = 0; tx < nx; ++tx) stage_tile<T, KIND, RY, VW>(a, c, smem, tx, ty, z0, z1);
-}
-
-template <typename T, int KIND>
-__device__ void ens_tile(EnsInst* I, char* smem, const EnsTile& t) {
-  if constexpr (sizeof(T) == 4) {
-    if (I->vw == 4) return ens_tile_vw<T, KIND, 4>(I, smem, t.y0, t.y1, t.z0, t.z1);
-    if (I->vw == 2) return ens_tile_vw<T, KIND, 2>(I, smem, t.y0, t.y1, t.z0, t.z1);
-  } else {
-    if (I->vw == 2) return ens_tile_vw<T, KIND, 2>(I, smem, t.y0, t.y1, t.z0, t.z1);
-  }
-  ens_tile_vw<T, KIND, 1>(I, smem, t.y0, t.y1, t.z0, t.z1);
-}
-
-// An instance takes part in a round's phases while it is not done and below
-// its pause point (both change only in the control phase).
-__device__ inline bool ens_running(const EnsInst* I) {
-  return !__hip_atomic_load(&I->ctrl.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
-         __hip_atomic_load(&I->ctrl.attempts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < I->pause_at;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256, 3) void ens_kernel(EnsInst* __restrict__ inst, const EnsSched s) {
-  __shared__ __align__(16) char smem[kTileSmem];
-  __shared__ int s_claim, s_run;
-  const EnsParams prm = *s.params;
-  const int xcd = blockIdx.x & 7;  // workgroups are dealt round-robin to the 8 XCDs
-  uint32_t gen = 0;
-  int phase = 0;
-
-  // one stage phase over every queue's tiles; false once an error is flagged
-  auto stage_phase = [&](auto kind) -> bool {
-    constexpr int K = decltype(kind)::value;
-    for (int q = 0; q < 8; ++q) {
-      const int x = (xcd + q) & 7;
-      const int base = s.qoff[x], cnt = s.qoff[x + 1] - base;
-      uint32_t* ctr = s.qctr + phase * 8 + x;
-      for (;;) {
-        if (threadIdx.x == 0) {
-          int t = cnt;
-          if ((int)__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < cnt) t = (int)atomicAdd(ctr, 1u);
-          int run = 0;
-          if (t < cnt) {
-            const EnsInst* I = &inst[s.tiles[base + t].inst];
-            run = K == K_D1 ? (!I->k1_valid && ens_running(I)) : ens_running(I);
-          }
-          s_claim = t;
-          s_run = run;
-        }
-        __syncthreads();
-        const int t = s_claim, run = s_run;
-        __syncthreads();
-        if (t >= cnt) break;
-        if (run) {
-          const EnsTile tl = s.tiles[base + t];
-          ens_tile<T, K>(&inst[tl.inst], smem, tl);
-        }
-      }
-    }
-    ++phase;
-    grid_sync(s, gen);
-    return !ens_error(s);
-  };
-
-  if (prm.first_d1 && !stage_phase(std::integral_constant<int, K_D1>())) return;
-  for (int r = 0; r < prm.rounds; ++r) {
-    if (!stage_phase(std::integral_constant<int, K_D2>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D3>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D4>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D5>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D6>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D7>())) return;
-    // control phase: the members' error maxima are device-scope atomics made
-    // before the barrier above; the controller reads them with an atomic
-    for (int i = blockIdx.x; i < prm.n_inst; i += gridDim.x) {
-      EnsInst* I = &inst[i];
-      if (threadIdx.x == 0) s_run = ens_running(I);
-      __syncthreads();
-      const int run = s_run;
-      __syncthreads();
-      if (run) {
-        ctrl_step(&I->ctrl);
-        if (threadIdx.x == 0 && ens_running(I)) atomicAdd(&s.live[r], 1u);
-      }
-    }
-    grid_sync(s, gen);
-    if (ens_error(s)) return;
-    // every instance finished or paused: leave early (uniform: all read after the barrier)
-    if (__hip_atomic_load(&s.live[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
-  }
-}
-
 }  // namespace
 
 bool gs_ry_supported(int ry) { return ry == 1 || ry == 2 || ry == 4; }
@@ -685,20 +85,6 @@ hipError_t launch_gs(int kind, int dtype, int ry, int vw, const GSLaunch& a, Dev
   if (vw == 2) return launch_vw<double, 2>(kind, ry, a, c, s);
   if (vw == 1) return launch_vw<double, 1>(kind, ry, a, c, s);
   return hipErrorInvalidValue;
-}
-
-hipError_t launch_ensemble(int dtype, EnsInst* inst, EnsSched s, int nwg, hipStream_t st) {
-  if (nwg < 1) return hipErrorInvalidValue;
-  if (dtype == 1) ens_kernel<float><<<nwg, 256, 0, st>>>(inst, s);
-  else ens_kernel<double><<<nwg, 256, 0, st>>>(inst, s);
-  return hipGetLastError();
-}
-
-int ensemble_blocks_per_cu(int dtype) {
-  int n = 0;
-  hipError_t e = dtype == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<float>, 256, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<double>, 256, 0);
-  return e == hipSuccess ? n : 0;
 }
 
 }  // namespace hode

@@ -2,6 +2,7 @@
 
     python -m paper_2309_05331_amd.prof_summary kernel-trace RESULTS.db [--min-us 20]
     python -m paper_2309_05331_amd.prof_summary counters FETCH.csv WRITE.csv [--fetch-scale 2] [--write-scale 1]
+    python -m paper_2309_05331_amd.prof_summary counters-json FETCH.csv WRITE.csv --kernel NAME --tag TAG --workload W
 
 kernel-trace: per-kernel dispatch count, mean/min/max duration over real
 dispatches only.  The integration loop launches graph chunks whose kernels
@@ -27,6 +28,9 @@ def short(name: str) -> str:
     if m:
         kinds = ["D1", "R2", "R3", "R4", "D2", "D3", "D4", "D5", "D6", "D7", "D7F", "D6F"]
         return "gs_stage %s %s ry=%s vw=%s" % (kinds[int(m.group(2))], m.group(1), m.group(3), m.group(4))
+    m = re.search(r"ens_kernel<(\w+)>", name)
+    if m:
+        return "ens_kernel %s" % m.group(1)
     m = re.search(r"(\w+)\(", name)
     return (m.group(1) if m else name)[:60]
 
@@ -51,15 +55,41 @@ def kernel_trace(db: str, min_us: float):
     return "\n".join(lines)
 
 
+def _load(path, cname):
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == cname:
+            agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return agg
+
+
+def counters_record(fetch_csv, write_csv, fs, ws, kernel, tag, workload, source, per="launch"):
+    """JSON record of one kernel's mean scaled HBM bytes per dispatch (or the
+    sum over all its dispatches with per="run"), stamped with the SHA-256 of
+    the kernel's source files (concatenated in the order given) so a reader
+    can tell whether it still applies."""
+    import hashlib
+    import os
+    f = _load(fetch_csv, "FETCH_SIZE")[kernel]
+    w = _load(write_csv, "WRITE_SIZE")[kernel]
+    if not f or not w:
+        raise SystemExit("kernel %r not in the counter files" % kernel)
+    agg = (lambda v: sum(v)) if per == "run" else (lambda v: sum(v) / len(v))
+    fk, wk = agg(f), agg(w)
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    names = [x for x in source.split(",") if x]
+    h = hashlib.sha256()
+    for nm in names:
+        h.update(open(os.path.join(here, nm), "rb").read())
+    return {"kernel": tag, "workload": workload, "sources": names, "sources_sha256": h.hexdigest(),
+            "fetch_kib": round(fk, 1), "write_kib": round(wk, 1), "fetch_scale": fs, "write_scale": ws,
+            "dispatches": len(f), "per": per,
+            "hbm_bytes_per_launch" if per == "launch" else "hbm_bytes_per_run": int(round((fk * fs + wk * ws) * 1024))}
+
+
 def counters(fetch_csv: str, write_csv: str, fs: float, ws: float):
-    def load(path, cname):
-        agg = collections.defaultdict(list)
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] == cname:
-                agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
-        return agg
-    f = load(fetch_csv, "FETCH_SIZE")
-    w = load(write_csv, "WRITE_SIZE")
+    f = _load(fetch_csv, "FETCH_SIZE")
+    w = _load(write_csv, "WRITE_SIZE")
     lines = ["%-40s %6s %14s %14s %16s" % ("kernel", "n", "FETCH_KiB", "WRITE_KiB", "HBM_bytes_scaled")]
     for k in sorted(set(f) | set(w)):
         fm = sum(f[k]) / len(f[k]) if f.get(k) else 0.0
@@ -80,11 +110,25 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("--fetch-scale", type=float, default=2.0)
     b.add_argument("--write-scale", type=float, default=1.0)
+    j = sub.add_parser("counters-json")
+    j.add_argument("fetch_csv")
+    j.add_argument("write_csv")
+    j.add_argument("--kernel", required=True, help="summary name of the kernel, e.g. 'gs_stage D6 float ry=1 vw=4'")
+    j.add_argument("--tag", required=True, help="short kernel tag used by bench.py, e.g. D6")
+    j.add_argument("--workload", required=True)
+    j.add_argument("--source", default="stage.h,gs.hip", help="comma-separated kernel sources under csrc/")
+    j.add_argument("--per", choices=["launch", "run"], default="launch")
+    j.add_argument("--fetch-scale", type=float, default=2.0)
+    j.add_argument("--write-scale", type=float, default=1.0)
     args = ap.parse_args()
     if args.cmd == "kernel-trace":
         print(kernel_trace(args.db, args.min_us))
-    else:
+    elif args.cmd == "counters":
         print(counters(args.fetch_csv, args.write_csv, args.fetch_scale, args.write_scale))
+    else:
+        import json
+        print(json.dumps(counters_record(args.fetch_csv, args.write_csv, args.fetch_scale, args.write_scale,
+                                         args.kernel, args.tag, args.workload, args.source, args.per), indent=1))
 
 
 if __name__ == "__main__":
