@@ -73,7 +73,8 @@ __device__ inline S uniform_copy(const S& src) {
 // take more rows per wave, so each plane step still has about 16 bytes of
 // state per lane and field in flight, except where that would exceed the
 // persistent kernel's register budget (stage 6, the widest, keeps half).
-// Every choice divides 16, the row granularity of the tiles.
+// The host cuts tiles into row chunks of the non-stage-6 pass height, which
+// the stage-6 height divides.
 template <typename T, int KIND, int VW>
 constexpr int ens_rows() {
   constexpr int full = (int)(16 / sizeof(T)) / VW;

@@ -304,17 +304,29 @@ void free_ensemble(hode_ctx* c) {
   c->ens = nullptr;
 }
 
-// The tiles of one launch: every active instance cut into row chunks of 16
-// (the last one ends at N) and plane chunks sized so a phase has about four
-// tiles per workgroup (at least 4096 cells per tile, at least 4 planes), in
-// plane-chunk-major, row-chunk-minor order (tiles that share halo rows are
-// claimed close together).  Instances are dealt to eight queues, one per
-// XCD, largest work first onto the least loaded queue.
+// Rows one pass of the ensemble's stage tiles covers for instance i (four
+// waves of 16 bytes of state per lane and field, stage 6 excepted): a tile
+// of exactly this many rows needs one pass, so no halo row of it is read
+// twice.
+int ens_tile_rows(const Ensemble& e, int i) {
+  const int per_lane = (e.dtype == HODE_F32 ? 4 : 2) / e.vw[i];
+  return 4 * std::max(1, per_lane);
+}
+
+// Tiles per workgroup and phase that the plane ranges are sized for.
+constexpr double kTilesPerWorkgroup = 1.0;
+
+// The tiles of one launch: every active instance cut into row chunks of one
+// tile pass (the last one ends at N) and plane chunks sized so a phase has
+// about kTilesPerWorkgroup tiles per workgroup (at least 4096 cells, at least
+// 4 planes), in plane-chunk-major, row-chunk-minor order (tiles that share
+// halo rows are claimed close together).  Instances are dealt to eight
+// queues, one per XCD, largest work first onto the least loaded queue.
 void build_tiles(const Ensemble& e, int G, const std::vector<int>& active, std::vector<hode::EnsTile>& tiles,
                  std::vector<int32_t>& qoff) {
   double cells = 0;
   for (int i : active) cells += (double)e.N[i] * e.N[i] * e.N[i];
-  const double target = std::max(4096.0, cells / (4.0 * G));
+  const double target = std::max(4096.0, cells / (kTilesPerWorkgroup * G));
   std::vector<int> order(active);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return e.weight[a] > e.weight[b]; });
   std::vector<std::vector<int>> q(8);
@@ -330,14 +342,15 @@ void build_tiles(const Ensemble& e, int G, const std::vector<int>& active, std::
     qoff[x] = (int32_t)tiles.size();
     for (int i : q[x]) {
       const int N = e.N[i];
-      const int ny = (N + 15) / 16;
-      int zc = (int)std::lround(target / ((double)N * 16.0));
+      const int rows = ens_tile_rows(e, i);
+      const int ny = (N + rows - 1) / rows;
+      int zc = (int)std::lround(target / ((double)N * rows));
       zc = std::max(4, std::min(N, zc));
       const int nz = (N + zc - 1) / zc;
       for (int kz = 0; kz < nz; ++kz) {
         const int z0 = (int)((int64_t)N * kz / nz), z1 = (int)((int64_t)N * (kz + 1) / nz);
         for (int ky = 0; ky < ny; ++ky)
-          tiles.push_back({i, 16 * ky, std::min(N, 16 * (ky + 1)), z0, z1, 0});
+          tiles.push_back({i, rows * ky, std::min(N, rows * (ky + 1)), z0, z1, 0});
       }
     }
   }

@@ -57,8 +57,9 @@ struct EnsInst {
   int32_t k1_valid;  // k1 = f(y) is already in the first-same-as-last slot (resumed instance)
 };
 
-// One tile of a stage phase: rows [y0, y1) (y0 a multiple of 16) and planes
-// [z0, z1) of one instance, all columns.
+// One tile of a stage phase: rows [y0, y1) (y0 a multiple of the tile pass
+// height of every stage kind) and planes [z0, z1) of one instance, all
+// columns.
 struct EnsTile {
   int32_t inst, y0, y1, z0, z1, pad;
 };
