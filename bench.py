@@ -358,7 +358,7 @@ def main():
         unit = "cell-updates/s"
         cfg = {"workload": args.workload, "instances": wl["n"], "edges": "uniform over 16..96 step 8", "fields": 2,
                "method": "dopri5-adaptive", "rtol": wl["rtol"], "controller": "pi", "t": [0.0, wl["t1"]],
-               "launch": "persistent gang kernel in a hipGraph, relaunched per epoch of attempts",
+               "launch": "persistent kernel in a hipGraph (stage phases over per-XCD tile queues, grid barriers), relaunched per 64 attempts",
                "launches_per_step": r["launches"] / max(args.steps, 1)}
     else:
         r = run_ew(wl, args.steps, args.warmup)

@@ -178,7 +178,8 @@ int hode_time_kernel(hode_ctx *ctx, int kind, int reps, double *avg_ms);
 int hode_profile_attempt(hode_ctx *ctx, int method, int reps, double *ms);
 
 /* Gray-Scott: times one attempt of `method` for every tile configuration
- * (ry in {1,2,4}, zc in {8..256}) with hode_profile_attempt and keeps the
+ * (ry in {1,2,4}; zc the powers of two 8 .. 256 and ceil(N / k) for k = 1 ..
+ * 12, at least 8) with hode_profile_attempt and keeps the
  * fastest; the choice and its attempt time (ms) are returned (any output
  * pointer may be NULL).  Results are bitwise identical for every tile. */
 int hode_autotune(hode_ctx *ctx, int method, int reps, int *best_ry, int *best_zc, double *best_ms);

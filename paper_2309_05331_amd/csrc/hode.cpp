@@ -796,12 +796,18 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   if (rc) return rc;
   if (!is_gs(c)) return fail(c, HODE_EINVAL, "autotuning is for the Gray-Scott path");
   const int rys[] = {1, 2, 4};
-  const int zcs[] = {8, 16, 32, 64, 128, 256};
+  // plane chunks: powers of two, and the even splits of the grid into 1 .. 12
+  // chunks (block counts that fill whole rounds of resident workgroups)
+  std::vector<int> zcs;
+  for (int zc = 8; zc <= 256; zc *= 2) zcs.push_back(zc);
+  for (int nz = 1; nz <= 12; ++nz) zcs.push_back((c->N + nz - 1) / nz);
+  std::sort(zcs.begin(), zcs.end());
+  zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
   double best = 1e300;
   int bry = c->ry, bzc = c->zc;
   for (int ry : rys) {
     for (int zc : zcs) {
-      if (zc > c->N && zc != zcs[0]) continue;
+      if ((zc > c->N || zc < 8) && zc != 8) continue;
       c->ry = ry;
       c->zc = zc;
       double ms[8];

@@ -70,16 +70,42 @@ def test_ensemble_matches_single_runs_bitwise(dtype):
     ens.close()
 
 
-def test_ensemble_multi_workgroup_gangs_bitwise():
-    # weights that give the large instances gangs of several workgroups
-    edges = [48, 64, 16, 8]
+def test_ensemble_paused_launches_bitwise():
+    # a few attempts per launch, so every instance is paused and resumed many
+    # times (resumed instances skip stage 1: k1 is in the first-same-as-last
+    # slot); work estimates that put the big instances in one queue
+    edges = [48, 64, 16, 8, 33]
     _, prms = _params(len(edges))
-    ens, ys, outs, stats = _run_ensemble(edges, prms, hode.F32, 20.0, 1e-5, vws=[4, 4, 4, 4],
-                                         weights=[1e9, 1e9, 1.0, 1.0])
+    vws = [4, 4, 4, 4, 1]
+    npd = np.float32
+    ens = hode.Ensemble(edges, prms, dtype=hode.F32)
+    ys = [inputs.ensemble_ic(i, N, dtype=npd) for i, N in enumerate(edges)]
     for i, N in enumerate(edges):
-        ref, st = _single(ys[i], N, prms[i], 4, 20.0, 0.1, 1e-5)
-        assert stats[i]["accepted"] == st["accepted"], i
-        assert np.array_equal(outs[i], ref), i
+        ens.init_instance(i, np.ascontiguousarray(ys[i]).ravel())
+        ens.set_instance_vector_width(i, vws[i])
+    ens.set_weights([1e9, 1e9, 1.0, 1.0, 1.0])
+    ens.set_epoch(3, 5)
+    ens.set_tolerances(1e-5, 1e-5)
+    stats = ens.integrate_adaptive(0.0, 20.0, 0.1, max_steps=100000)
+    ms, launches = ens.timing()
+    most = max(s["accepted"] + s["rejected"] for s in stats)
+    assert launches == 1 + -(-(most - 3) // 5) and ms > 0
+    for i, N in enumerate(edges):
+        out = np.empty(2 * N ** 3, dtype=npd)
+        ens.read_instance(i, out)
+        ref, st = _single(ys[i], N, prms[i], vws[i], 20.0, 0.1, 1e-5)
+        assert (stats[i]["accepted"], stats[i]["rejected"]) == (st["accepted"], st["rejected"]), i
+        assert stats[i]["rhs_evals"] == st["rhs_evals"], i
+        assert np.array_equal(out, ref), i
+    ens.close()
+
+
+def test_ensemble_rejects_bad_epoch():
+    ens = hode.Ensemble([8], [[2e-3, 1e-3, 0.04, 0.06, 2.5]])
+    with pytest.raises(hode.HodeError):
+        ens.set_epoch(0, 5)
+    with pytest.raises(hode.HodeError):
+        ens.set_epoch(3, 5000)
     ens.close()
 
 

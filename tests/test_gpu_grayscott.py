@@ -174,3 +174,21 @@ def test_full_size_256_fp32_one_step(orc):
     t, dt, acc = ctx.try_step(0.0, 0.5)
     err = orc.err_norm(y64, yn, e, 1e-6, 1e-6)
     assert acc == (err <= 1.0)
+
+
+def test_graph_and_plain_launches_bitwise():
+    # the same integration replayed from captured graph chunks and enqueued
+    # kernel by kernel
+    N = 24
+    y0 = inputs.gray_scott_ic(N, seed=38)
+    outs = []
+    for graphs in (True, False):
+        ctx = gs_ctx(y0, N, PRM_D)
+        ctx.set_graphs(graphs)
+        ctx.set_tolerances(1e-8, 1e-8)
+        st = ctx.integrate_adaptive(0.0, 5.0, 0.1, max_steps=100000)
+        ctx.integrate_n_steps(hode.RK4, st["t"], 0.05, 7)
+        outs.append((read(ctx, np.float64, 2 * N ** 3), st["accepted"], st["rejected"]))
+        ctx.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
+
