@@ -230,7 +230,9 @@ int hode_ensemble_set_epoch(hode_ctx *ctx, int first, int rest);
  * launch, in ms) and its number of launches; either pointer may be NULL. */
 int hode_ensemble_timing(hode_ctx *ctx, double *kernel_ms, int *launches);
 
-/* Cells per lane of instance i's tiles: 1, 2 or 4 (fp64: 1 or 2), dividing N. */
+/* Cells per lane of instance i's tiles: 1, 2 or 4 (fp64: 1 or 2), dividing N.
+ * With 16-byte lanes (4, fp64 2) and rows of at most 32 lanes, the tiles
+ * pack one row per segment of a wavefront (the default for such grids). */
 int hode_ensemble_set_vector_width(hode_ctx *ctx, int i, int vw);
 
 /* Per-instance attempt traces (8 doubles per attempt, as hode_set_trace). */
@@ -239,7 +241,8 @@ int hode_ensemble_read_trace(hode_ctx *ctx, int i, double *dst, int64_t cap, int
 
 /* Tile autotuner of the ensemble: for every distinct grid edge, times one
  * Dopri5 attempt (reps repetitions) of one of its instances for each vector
- * width (cells per lane) and keeps the fastest; the work estimates become
+ * width (cells per lane) and keeps the fastest (grids with segmented rows keep
+ * 16-byte lanes and are only timed); the work estimates become
  * the measured attempt times.  vw_out/ms_out (n entries each, may be
  * NULL) receive the choice and the attempt time per instance. */
 int hode_ensemble_autotune(hode_ctx *ctx, int reps, int *vw_out, double *ms_out);

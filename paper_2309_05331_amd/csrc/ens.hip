@@ -84,10 +84,13 @@ constexpr int ens_rows() {
 
 // Not inlined: each stage variant keeps its own register allocation, so the
 // persistent kernel's budget is the largest single stage, not their union.
-template <typename T, int KIND, int VW>
+// SEG > 1: segmented rows (16-byte lanes, one whole row per segment of
+// 64/SEG lanes; see stage_tile).
+template <typename T, int KIND, int VW, int SEG = 1>
 __device__ __noinline__ void ens_tile_vw(EnsInst* I, char* smem, int y0, int y1, int z0, int z1) {
-  constexpr int RY = ens_rows<T, KIND, VW>();
-  constexpr int TY = 4 * RY;
+  // segmented rows: two register rows of SEG rows each (stage 6, the widest, one)
+  constexpr int RY = SEG == 1 ? ens_rows<T, KIND, VW>() : (KIND == K_D6 ? 1 : 2);
+  constexpr int TY = 4 * RY * SEG;
   const GSLaunch a = uniform_copy(I->a);
   DevCtrl* c = uniform_copy(&I->ctrl);
   y0 = __builtin_amdgcn_readfirstlane(y0);
@@ -96,11 +99,19 @@ __device__ __noinline__ void ens_tile_vw(EnsInst* I, char* smem, int y0, int y1,
   z1 = __builtin_amdgcn_readfirstlane(z1);
   const int nx = (a.N + 64 * VW - 1) / (64 * VW);
   for (int ty = y0 / TY; ty * TY < y1; ++ty)
-    for (int tx = 0; tx < nx; ++tx) stage_tile<T, KIND, RY, VW>(a, c, smem, tx, ty, z0, z1);
+    for (int tx = 0; tx < nx; ++tx) stage_tile<T, KIND, RY, VW, SEG>(a, c, smem, tx, ty, z0, z1);
 }
 
 template <typename T, int KIND>
 __device__ void ens_tile(EnsInst* I, char* smem, const EnsTile& t) {
+  constexpr int VF = (int)(16 / sizeof(T));  // cells per 16-byte lane
+  switch (I->seg) {
+    case 2: return ens_tile_vw<T, KIND, VF, 2>(I, smem, t.y0, t.y1, t.z0, t.z1);
+    case 4: return ens_tile_vw<T, KIND, VF, 4>(I, smem, t.y0, t.y1, t.z0, t.z1);
+    case 8: return ens_tile_vw<T, KIND, VF, 8>(I, smem, t.y0, t.y1, t.z0, t.z1);
+    case 16: return ens_tile_vw<T, KIND, VF, 16>(I, smem, t.y0, t.y1, t.z0, t.z1);
+    default: break;
+  }
   if constexpr (sizeof(T) == 4) {
     if (I->vw == 4) return ens_tile_vw<T, KIND, 4>(I, smem, t.y0, t.y1, t.z0, t.z1);
     if (I->vw == 2) return ens_tile_vw<T, KIND, 2>(I, smem, t.y0, t.y1, t.z0, t.z1);
@@ -118,7 +129,7 @@ __device__ inline bool ens_running(const EnsInst* I) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, 3) void ens_kernel(EnsInst* __restrict__ inst, const EnsSched s) {
+__global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst, const EnsSched s) {
   __shared__ __align__(16) char smem[kTileSmem];
   __shared__ int s_claim, s_run;
   const EnsParams prm = *s.params;

@@ -304,11 +304,26 @@ void free_ensemble(hode_ctx* c) {
   c->ens = nullptr;
 }
 
+// Segments per wavefront of an ensemble instance's tiles: rows of at most
+// 32 16-byte lanes are packed one per segment of 64/seg lanes (seg 2 .. 16,
+// at least 4 lanes a segment); 1 = ordinary tiles.
+int ens_seg_for(int dtype, int N, int vw) {
+  const int vf = dtype == HODE_F32 ? 4 : 2;
+  if (vw != vf || N % vw) return 1;
+  const int nl = N / vw;
+  if (nl > 32) return 1;
+  int sl = 4;
+  while (sl < nl) sl *= 2;
+  return 64 / sl;
+}
+
 // Rows one pass of the ensemble's stage tiles covers for instance i (four
-// waves of 16 bytes of state per lane and field, stage 6 excepted): a tile
-// of exactly this many rows needs one pass, so no halo row of it is read
-// twice.
+// waves of 16 bytes of state per lane and field, or of two register rows of
+// seg rows each; stage 6 excepted): a tile of exactly this many rows needs
+// one pass, so no halo row of it is read twice.
 int ens_tile_rows(const Ensemble& e, int i) {
+  const int seg = ens_seg_for(e.dtype, e.N[i], e.vw[i]);
+  if (seg > 1) return 8 * seg;
   const int per_lane = (e.dtype == HODE_F32 ? 4 : 2) / e.vw[i];
   return 4 * std::max(1, per_lane);
 }
@@ -898,6 +913,7 @@ int hode_ensemble_create(hode_ctx** out, int device, void* stream, int n, const 
     const int maxvw = dtype == HODE_F32 ? 4 : 2;
     int v = 1;
     while (v * 2 <= maxvw && Ni % (v * 2) == 0 && 64 * v < Ni) v *= 2;  // narrowest that still fills a row
+    if (ens_seg_for(dtype, Ni, maxvw) > 1) v = maxvw;                   // short rows: segmented 16-byte lanes
     e->vw[i] = v;
   }
   if (hipMalloc(&e->d_inst, sizeof(hode::EnsInst) * n) != hipSuccess) {
@@ -1057,6 +1073,7 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     d.stiff = gs_stiffness(&e->prm[5 * i], e->N[i]);
     I.ctrl = d;
     I.vw = e->vw[i];
+    I.seg = ens_seg_for(e->dtype, e->N[i], e->vw[i]);
     I.k1_valid = 0;
   }
   // bookkeeping block and tile buffer (the captured graph holds their addresses)
@@ -1188,7 +1205,10 @@ int hode_ensemble_autotune(hode_ctx* c, int reps, int* vw_out, double* ms_out) {
     double bms = 1e300;
     int bvw = e->vw[i];
     const int maxvw = c->dtype == HODE_F32 ? 4 : 2;
-    for (int vw = 1; vw <= maxvw && !rc; vw *= 2) {
+    // rows short enough for segmented 16-byte lanes keep them (the
+    // single-grid path the timing runs on has no segmented tiles)
+    const bool seg = ens_seg_for(c->dtype, N, maxvw) > 1;
+    for (int vw = seg ? maxvw : 1; vw <= maxvw && !rc; vw *= 2) {
       if (N % vw) continue;
       rc = hode_set_vector_width(t, vw);
       // the ensemble's tiles: 16 bytes of state per lane and field per row set

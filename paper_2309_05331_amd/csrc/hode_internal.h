@@ -55,6 +55,8 @@ struct EnsInst {
   int64_t pause_at;  // the instance sits out the rest of a launch once ctrl.attempts reaches this
   int32_t vw;        // cells per lane for this instance's tiles
   int32_t k1_valid;  // k1 = f(y) is already in the first-same-as-last slot (resumed instance)
+  int32_t seg;       // > 1: segmented rows (vw = 16 bytes / element, one row per 64/seg lanes)
+  int32_t pad;
 };
 
 // One tile of a stage phase: rows [y0, y1) (y0 a multiple of the tile pass

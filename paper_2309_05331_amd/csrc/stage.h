@@ -164,18 +164,33 @@ constexpr int kTileSmem = 2 * 2 * 10 * 64 * 16 + 2 * 2 * 2 * 16 * 8;
 // (ty+1)*4*RY - 1, planes zbeg .. zend - 1 of the grid described by `a`, with
 // step h, parity and first-same-as-last slot taken from the control block.
 // Called by all 256 threads of a workgroup; smem is kTileSmem bytes of LDS.
-template <typename T, int KIND, int RY, int VW>
+//
+// Segmented rows (SEG > 1, for grids whose rows are at most 64*VW/SEG cells):
+// each wavefront is cut into SEG segments of 64/SEG lanes and every segment
+// of a register row holds one whole x-row, so register row r of a wave holds
+// rows r*SEG .. r*SEG + SEG - 1 of its strip of RY*SEG rows, and the tile is
+// the full width of the grid (tx = 0).  x neighbours wrap inside the
+// segment; the rows above and below come from the neighbouring segment, or
+// the last/first segment of the neighbouring register row, by cross-lane
+// permutes, and across strips from the LDS row slots as for the ordinary
+// tiles; no x-halo is needed.  The arithmetic of every cell is the same
+// expression in the same order, so the results are bitwise those of the
+// ordinary tiles.
+template <typename T, int KIND, int RY, int VW, int SEG = 1>
 __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* smem, int tx, int ty, int zbeg,
                            int zend) {
   constexpr KindDesc D = desc<KIND>();
+  static_assert(SEG == 1 || 64 % SEG == 0, "segments split the wavefront evenly");
+  constexpr int SL = 64 / SEG;  // lanes per segment
   constexpr int TX = 64 * VW;
-  constexpr int TY = 4 * RY;
+  constexpr int TY = 4 * RY * SEG;
+  constexpr int TYX = SEG == 1 ? TY : 1;  // x-halo cells per column (ordinary tiles only)
   using P = Pk<T, VW>;
-  static_assert(2 * 2 * 10 * 64 * sizeof(P) + 2 * 2 * 2 * TY * sizeof(T) <= kTileSmem, "LDS budget");
+  static_assert(2 * 2 * 10 * 64 * sizeof(P) + 2 * 2 * 2 * TYX * sizeof(T) <= kTileSmem, "LDS budget");
   // LDS per buffer and field: 10 row slots (tile halo above, first and last
   // row of each wave's strip, tile halo below) and the x-halo cells
   P(*rows)[2][10][64] = reinterpret_cast<P(*)[2][10][64]>(smem);
-  T(*xh)[2][2][TY] = reinterpret_cast<T(*)[2][2][TY]>(smem + 2 * 2 * 10 * 64 * sizeof(P));
+  T(*xh)[2][2][TYX] = reinterpret_cast<T(*)[2][2][TYX]>(smem + 2 * 2 * 10 * 64 * sizeof(P));
   __syncthreads();  // LDS may still be in use by the previous tile
 
   const double h = c->h;
@@ -184,8 +199,10 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   const int64_t n3 = a.n3;
   const int64_t NN = (int64_t)N * N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int seg = SEG == 1 ? 0 : lane / SL;  // segment of this lane
+  const int jl = SEG == 1 ? lane : lane % SL;  // lane within the segment
   const int x0 = tx * TX, yt = ty * TY;
-  const int y0 = yt + wv * RY;  // first row of this wave's strip
+  const int y0 = yt + wv * RY * SEG + seg;  // first row of this lane's strip
 
   const T* src[6];
 #pragma unroll
@@ -209,19 +226,23 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   const double h1 = h * D1, h3 = h * D3, h4 = h * D4, h5 = h * D5, h6 = h * D6, h7 = h * D7;
 
   // ---- offsets (periodic wrap folded in)
-  const int xl = x0 + VW * lane;
+  const int xl = x0 + VW * jl;
   const int gx = xl % N;  // N % VW == 0, so gx .. gx+VW-1 are one aligned run
   const bool xval = xl < N;
+  const int nl = N / VW;  // lanes holding a row (segmented rows)
+  (void)nl;
   int rowoff[RY];
 #pragma unroll
-  for (int r = 0; r < RY; ++r) rowoff[r] = N * ((y0 + r) % N);
+  for (int r = 0; r < RY; ++r) rowoff[r] = N * ((y0 + r * SEG) % N);
   // halo role of this wave: 0 the row above the tile, 1 the row below,
   // 2 the x-halo cells (lanes < TY left column, TY .. 2TY-1 right column)
+  // (segmented rows: the row above is kept in the last segment's lanes and
+  // the row below in the first segment's, where the strips' edge rows are)
   int hoff = 0;
   bool hact = false;
-  if (wv == 0) { hoff = N * ((yt - 1 + N) % N) + gx; hact = true; }
-  else if (wv == 1) { hoff = N * ((yt + TY) % N) + gx; hact = true; }
-  else if (wv == 2 && lane < 2 * TY) {
+  if (wv == 0) { hoff = N * ((yt - 1 + N) % N) + gx; hact = SEG == 1 || seg == SEG - 1; }
+  else if (wv == 1) { hoff = N * ((yt + TY) % N) + gx; hact = SEG == 1 || seg == 0; }
+  else if (SEG == 1 && wv == 2 && lane < 2 * TY) {
     const int side = lane >= TY, rr = lane - side * TY;
     hoff = N * ((yt + rr) % N) + (side ? (x0 + TX) % N : (x0 - 1 + N) % N);
     hact = true;
@@ -305,7 +326,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
       if (hact) {
         if (wv == 0) rows[b][f][0][lane] = hv[f];
         else if (wv == 1) rows[b][f][9][lane] = hv[f];
-        else xh[b][f][lane >= TY][lane - (lane >= TY) * TY] = hv[f].v[0];
+        else if constexpr (SEG == 1) xh[b][f][lane >= TY][lane - (lane >= TY) * TY] = hv[f].v[0];
       }
     }
   };
@@ -328,12 +349,19 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
     T xlft[2][RY], xrgt[2][RY];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-      above[f] = rows[b][f][2 * wv][lane];
-      below[f] = rows[b][f][2 * wv + 3][lane];
+      if constexpr (SEG == 1) {
+        above[f] = rows[b][f][2 * wv][lane];
+        below[f] = rows[b][f][2 * wv + 3][lane];
 #pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        xlft[f][r] = xh[b][f][0][wv * RY + r];
-        xrgt[f][r] = xh[b][f][1][wv * RY + r];
+        for (int r = 0; r < RY; ++r) {
+          xlft[f][r] = xh[b][f][0][wv * RY + r];
+          xrgt[f][r] = xh[b][f][1][wv * RY + r];
+        }
+      } else {
+        // the strip above ends with its last segment, the strip below starts
+        // with its first
+        above[f] = rows[b][f][2 * wv][(SEG - 1) * SL + jl];
+        below[f] = rows[b][f][2 * wv + 3][jl];
       }
     }
 #pragma unroll
@@ -342,12 +370,34 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
         const P& cc = wc[f][r];
-        const P& up = r == 0 ? above[f] : wc[f][r - 1];
-        const P& dn = r == RY - 1 ? below[f] : wc[f][r + 1];
-        const T left = shfl_up1(cc.v[VW - 1]);
-        const T right = shfl_down1(cc.v[0]);
-        const T xm0 = lane == 0 ? xlft[f][r] : left;
-        const T xpN = lane == 63 ? xrgt[f][r] : right;
+        P up, dn;
+        T xm0, xpN;
+        if constexpr (SEG == 1) {
+          up = r == 0 ? above[f] : wc[f][r - 1];
+          dn = r == RY - 1 ? below[f] : wc[f][r + 1];
+          const T left = shfl_up1(cc.v[VW - 1]);
+          const T right = shfl_down1(cc.v[0]);
+          xm0 = lane == 0 ? xlft[f][r] : left;
+          xpN = lane == 63 ? xrgt[f][r] : right;
+        } else {
+          // rows of the neighbouring segments (the first segment's upper
+          // neighbour is the previous register row's last segment, the last
+          // segment's lower one the next register row's first); x wraps
+          // inside the segment
+          const int lu = (lane - SL) & 63, ld = (lane + SL) & 63;
+          const int lu2 = (lane + (SEG - 1) * SL) & 63, ld2 = (lane - (SEG - 1) * SL) & 63;
+#pragma unroll
+          for (int e = 0; e < VW; ++e) {
+            const T vu = __shfl(cc.v[e], lu, 64), vd = __shfl(cc.v[e], ld, 64);
+            const T vu2 = r == 0 ? above[f].v[e] : __shfl(wc[f][r > 0 ? r - 1 : 0].v[e], lu2, 64);
+            const T vd2 = r == RY - 1 ? below[f].v[e] : __shfl(wc[f][r < RY - 1 ? r + 1 : 0].v[e], ld2, 64);
+            up.v[e] = seg == 0 ? vu2 : vu;
+            dn.v[e] = seg == SEG - 1 ? vd2 : vd;
+          }
+          const int base = lane - jl;
+          xm0 = __shfl(cc.v[VW - 1], base + (jl == 0 ? nl - 1 : jl - 1), 64);
+          xpN = __shfl(cc.v[0], base + (jl >= nl - 1 ? 0 : jl + 1), 64);
+        }
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
           const T xm = e == 0 ? xm0 : cc.v[e - 1];
@@ -365,7 +415,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
         fo[0].v[e] = Du * lu - uvv + F * ((T)1 - u);
         fo[1].v[e] = Dv * lv + uvv - Fk * v;
       }
-      const bool valid = xval && (y0 + r < N);
+      const bool valid = xval && (y0 + r * SEG < N);
       if (valid) {
         const int64_t g = zb + rowoff[r] + gx;
         if (D.out >= 0) {

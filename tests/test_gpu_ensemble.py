@@ -145,3 +145,33 @@ def test_ensemble_full_draws_short_horizon():
         ref, st = _single(inputs.ensemble_ic(i, N), N, prms[i], vw, 4.0, 0.1, 1e-5)
         assert np.array_equal(out, ref), (i, N)
     ens.close()
+
+
+def test_ensemble_instance_failure_is_contained():
+    # one instance exhausts its attempts; the others still reach t1 with the
+    # same results as alone, and the call reports the failing status
+    edges = [16, 12, 20]
+    _, prms = _params(len(edges))
+    ens = hode.Ensemble(edges, prms, dtype=hode.F64)
+    ys = [inputs.ensemble_ic(i, N, dtype=np.float64) for i, N in enumerate(edges)]
+    for i, N in enumerate(edges):
+        ens.init_instance(i, np.ascontiguousarray(ys[i]).ravel())
+    ens.set_tolerances(1e-9, 1e-9)
+    ens.set_epoch(4, 4)
+    # a budget between the smallest and the largest attempt count of the three
+    alone = [_single(ys[i], N, prms[i], 1, 10.0, 0.1, 1e-9)[1] for i, N in enumerate(edges)]
+    att = [a["accepted"] + a["rejected"] for a in alone]
+    budget = (min(att) + max(att)) // 2
+    assert min(att) < budget < max(att)
+    stats = ens.integrate_adaptive(0.0, 10.0, 0.1, max_steps=budget, allow=(hode.EMAXSTEPS,))
+    for i, N in enumerate(edges):
+        if att[i] <= budget:
+            assert stats[i]["status"] == 0 and stats[i]["t"] == 10.0, i
+            out = np.empty(2 * N ** 3)
+            ens.read_instance(i, out)
+            ref, _ = _single(ys[i], N, prms[i], 1, 10.0, 0.1, 1e-9)
+            assert np.array_equal(out, ref), i
+        else:
+            assert stats[i]["status"] == hode.EMAXSTEPS and stats[i]["t"] < 10.0, i
+            assert stats[i]["accepted"] + stats[i]["rejected"] == budget, i
+    ens.close()
