@@ -158,7 +158,7 @@ int hode_set_graphs(hode_ctx *ctx, int enable);
  * workgroup), zc >= 1 z-planes per workgroup.  Element-wise: `ry` is ignored
  * and zc is the workgroup count cap. */
 int hode_set_tile(hode_ctx *ctx, int ry, int zc);
-int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);
+int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);  /* the widest stage's tile */
 
 /* Gray-Scott cells per lane (1, 2 or 4; fp64 at most 2; must divide N), or 0
  * for the widest that divides N (16-byte loads where possible). */
@@ -179,9 +179,12 @@ int hode_profile_attempt(hode_ctx *ctx, int method, int reps, double *ms);
 
 /* Gray-Scott: times one attempt of `method` for every tile configuration
  * (ry in {1,2,4}; zc the powers of two 8 .. 256 and ceil(N / k) for k = 1 ..
- * 12, at least 8) with hode_profile_attempt and keeps the
- * fastest; the choice and its attempt time (ms) are returned (any output
- * pointer may be NULL).  Results are bitwise identical for every tile. */
+ * 12, at least 8) with hode_profile_attempt and keeps, for every stage kernel
+ * of the attempt, its fastest configuration (the first k1 and the fixed-step
+ * stage variants take those of their shape twins); returned are the widest
+ * stage's (stage 6 of Dopri5, stage 4 of RK4) and the sum of the stages'
+ * best times (ms); any output pointer may be NULL.  Results are bitwise
+ * identical for every tile.  hode_set_tile sets one tile for all stages. */
 int hode_autotune(hode_ctx *ctx, int method, int reps, int *best_ry, int *best_zc, double *best_ms);
 
 /* Measurement reference: copies `bytes` (a multiple of 16) from device

@@ -74,7 +74,8 @@ struct hode_ctx {
   uint16_t* d_mlp = nullptr;
   int ctrl_kind = hode::CTRL_PI;
   double atol = 1e-6, rtol = 1e-6;
-  int ry = 0, zc = 0, ew_grid = 0, vw = 0;
+  int ry = 0, zc = 0, ew_grid = 0, vw = 0;  // ry, zc: the tile of the widest stage kind
+  int kry[hode::K_COUNT + 1] = {0}, kzc[hode::K_COUNT + 1] = {0};  // tile of every stage kind
   bool k1_valid = false;
   int parity = 0, k1slot = 0;
   bool use_graphs = true;      // replay captured chunks (else enqueue every kernel)
@@ -135,6 +136,21 @@ hode::GSLaunch gs_args(const hode_ctx* c) {
   return a;
 }
 
+// One stage kernel of `kind` with that kind's tile.
+hipError_t launch_stage(const hode_ctx* c, int kind, hode::GSLaunch a) {
+  a.zc = c->kzc[kind];
+  return hode::launch_gs(kind, c->dtype, c->kry[kind], c->vw, a, c->d_ctrl, c->stream);
+}
+
+void set_all_tiles(hode_ctx* c, int ry, int zc) {
+  c->ry = ry;
+  c->zc = zc;
+  for (int k = 0; k <= hode::K_COUNT; ++k) {
+    c->kry[k] = ry;
+    c->kzc[k] = zc;
+  }
+}
+
 int default_zc(int N, int ry) {
   const int nx = (N + 63) / 64, ny = (N + 4 * ry - 1) / (4 * ry);
   const int want = 2048;
@@ -167,7 +183,7 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
   const int* seq = mode == hode::MODE_FIXED_RK4 ? rk4 : (mode == hode::MODE_FIXED_DP5 ? dp5f : dp5a);
   const int ns = mode == hode::MODE_FIXED_RK4 ? 4 : 6;
   for (int i = 0; i < ns; ++i) {
-    hipError_t e = hode::launch_gs(seq[i], c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream);
+    hipError_t e = launch_stage(c, seq[i], a);
     if (e != hipSuccess) return e;
   }
   return hode::launch_ctrl(c->d_ctrl, c->stream);
@@ -223,7 +239,7 @@ DevCtrl base_ctrl(const hode_ctx* c, int mode) {
 int launch_k1(hode_ctx* c) {
   if (!is_gs(c)) return HODE_OK;
   const hode::GSLaunch a = gs_args(c);
-  HIPCHK(c, hode::launch_gs(hode::K_D1, c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream));
+  HIPCHK(c, launch_stage(c, hode::K_D1, a));
   return HODE_OK;
 }
 
@@ -329,7 +345,7 @@ int ens_tile_rows(const Ensemble& e, int i) {
 }
 
 // Tiles per workgroup and phase that the plane ranges are sized for.
-constexpr double kTilesPerWorkgroup = 1.0;
+constexpr double kTilesPerWorkgroup = 0.5;
 
 // The tiles of one launch: every active instance cut into row chunks of one
 // tile pass (the last one ends at N) and plane chunks sized so a phase has
@@ -495,8 +511,8 @@ int hode_init_state(hode_ctx* c, int dtype, int nfields, int ndim, const int64_t
   c->persist_valid = false;
   if (!reuse) {
     if (is_gs(c)) {
-      if (!c->ry) c->ry = dtype == HODE_F32 ? 4 : 2;
-      c->zc = default_zc(N, c->ry);
+      const int ry = c->ry ? c->ry : (dtype == HODE_F32 ? 4 : 2);
+      set_all_tiles(c, ry, default_zc(N, ry));
     } else {
       c->ew_grid = default_ew_grid(nelem, dtype);
     }
@@ -692,8 +708,7 @@ int hode_set_tile(hode_ctx* c, int ry, int zc) {
     c->ew_grid = zc;
   } else {
     if (!hode::gs_ry_supported(ry) || zc < 1) return fail(c, HODE_EINVAL, "ry must be 1, 2 or 4 and zc >= 1");
-    c->ry = ry;
-    c->zc = zc;
+    set_all_tiles(c, ry, zc);
   }
   clear_graphs(c);
   return HODE_OK;
@@ -734,7 +749,7 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
   HIPCHK(c, hipEventCreate(&e1));
   const hode::GSLaunch a = is_gs(c) ? gs_args(c) : hode::GSLaunch{};
   auto launch = [&]() -> hipError_t {
-    if (is_gs(c)) return hode::launch_gs(kind, c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream);
+    if (is_gs(c)) return launch_stage(c, kind, a);
     const int mode = kind == HODE_RK4 ? hode::MODE_FIXED_RK4 : hode::MODE_ADAPTIVE;
     return hode::launch_ew(c->dtype, c->rhs, mode, c->y[0], c->y[1], c->nelem, c->ew_grid, c->d_ctrl, c->stream);
   };
@@ -779,7 +794,7 @@ int hode_profile_attempt(hode_ctx* c, int method, int reps, double* ms) {
   HIPCHK(c, hipMemcpyAsync(c->d_ctrl, c->h_ctrl, sizeof(DevCtrl), hipMemcpyHostToDevice, c->stream));
   const hode::GSLaunch a = gs_args(c);
   if (method == HODE_DOPRI5 && !c->k1_valid) {
-    HIPCHK(c, hode::launch_gs(hode::K_D1, c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream));
+    HIPCHK(c, launch_stage(c, hode::K_D1, a));
     c->k1_valid = true;
   }
   hipEvent_t ev[9];
@@ -789,7 +804,7 @@ int hode_profile_attempt(hode_ctx* c, int method, int reps, double* ms) {
   for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // first round is warm-up
     for (int i = 0; i < ns && e == hipSuccess; ++i) {
       e = hipEventRecord(ev[i], c->stream);
-      if (e == hipSuccess) e = hode::launch_gs(seq[i], c->dtype, c->ry, c->vw, a, c->d_ctrl, c->stream);
+      if (e == hipSuccess) e = launch_stage(c, seq[i], a);
     }
     if (e == hipSuccess) e = hipEventRecord(ev[ns], c->stream);
     if (e == hipSuccess) e = hode::launch_ctrl(c->d_ctrl, c->stream);
@@ -810,6 +825,7 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   int rc = check_ready(c);
   if (rc) return rc;
   if (!is_gs(c)) return fail(c, HODE_EINVAL, "autotuning is for the Gray-Scott path");
+  if (method != HODE_RK4 && method != HODE_DOPRI5) return fail(c, HODE_EINVAL, "method");
   const int rys[] = {1, 2, 4};
   // plane chunks: powers of two, and the even splits of the grid into 1 .. 12
   // chunks (block counts that fill whole rounds of resident workgroups)
@@ -818,28 +834,46 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   for (int nz = 1; nz <= 12; ++nz) zcs.push_back((c->N + nz - 1) / nz);
   std::sort(zcs.begin(), zcs.end());
   zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
-  double best = 1e300;
-  int bry = c->ry, bzc = c->zc;
+  int seq[8];
+  const int ns = stage_seq(method, seq);
+  // every stage kind keeps its own fastest tile
+  double best[8];
+  int bry[8], bzc[8];
+  for (int i = 0; i < ns; ++i) { best[i] = 1e300; bry[i] = c->kry[seq[i]]; bzc[i] = c->kzc[seq[i]]; }
   for (int ry : rys) {
     for (int zc : zcs) {
       if ((zc > c->N || zc < 8) && zc != 8) continue;
-      c->ry = ry;
-      c->zc = zc;
+      set_all_tiles(c, ry, zc);
       double ms[8];
       rc = hode_profile_attempt(c, method, reps, ms);
       if (rc) return rc;
-      const int ns = method == HODE_RK4 ? 4 : 6;
-      double tot = 0;
-      for (int i = 0; i < ns; ++i) tot += ms[i];
-      if (tot < best) { best = tot; bry = ry; bzc = zc; }
+      for (int i = 0; i < ns; ++i)
+        if (ms[i] < best[i]) { best[i] = ms[i]; bry[i] = ry; bzc[i] = zc; }
     }
   }
-  c->ry = bry;
-  c->zc = bzc;
+  double tot = 0;
+  for (int i = 0; i < ns; ++i) {
+    c->kry[seq[i]] = bry[i];
+    c->kzc[seq[i]] = bzc[i];
+    tot += best[i];
+  }
+  if (method == HODE_DOPRI5) {
+    // kinds of the same shape outside the timed attempt: the first k1, and
+    // the fixed-step variants of stages 6 and 7
+    c->kry[hode::K_D1] = c->kry[hode::K_D2];
+    c->kzc[hode::K_D1] = c->kzc[hode::K_D2];
+    c->kry[hode::K_D6F] = c->kry[hode::K_D6];
+    c->kzc[hode::K_D6F] = c->kzc[hode::K_D6];
+    c->kry[hode::K_D7F] = c->kry[hode::K_D7];
+    c->kzc[hode::K_D7F] = c->kzc[hode::K_D7];
+  }
+  const int widest = method == HODE_RK4 ? hode::K_R4 : hode::K_D6;
+  c->ry = c->kry[widest];
+  c->zc = c->kzc[widest];
   clear_graphs(c);
-  if (best_ry) *best_ry = bry;
-  if (best_zc) *best_zc = bzc;
-  if (best_ms) *best_ms = best;
+  if (best_ry) *best_ry = c->ry;
+  if (best_zc) *best_zc = c->zc;
+  if (best_ms) *best_ms = tot;
   return HODE_OK;
 }
 
