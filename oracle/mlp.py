@@ -129,3 +129,43 @@ def adam_step(flat, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return flat - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def features(hs, errs, accs, t_after, t1, rtol, stiff, ctrl_decide):
+    """The 16 inputs of the learned controller for every accepted attempt of
+    one integration (rows of NaN for rejected ones), from the attempt
+    sequence: h_n, its error norm, accept flag and the time after it.
+
+    For an accepted attempt n, with the attempts n, n-1, n-2, n-3 as the
+    history (newest first, zeros where there are fewer):
+      3i+0: log of the error norm clamped to [-23, 23] (NaN counts as 23),
+      3i+1: log(h_{n-i} / h_n), 3i+2: accept flag;
+      12: log of the PI factor taken after attempt n (``ctrl_decide`` is the
+          oracle's PI controller), 13: log(rtol),
+      14: log(max(t1 - t, h_n) / h_n) with t the time after the attempt,
+      15: log(h_n * stiff), stiff the scale of the System's largest Jacobian
+          eigenvalue.
+    """
+    n = len(hs)
+    X = np.full((n, NIN), np.nan)
+    err_prev, last_rej = 1.0, False
+    for k in range(n):
+        acc, fac, err_prev, last_rej = ctrl_decide(errs[k], err_prev, last_rej)
+        assert bool(acc) == bool(accs[k])
+        if not acc:
+            continue
+        x = np.zeros(NIN)
+        for i in range(4):
+            j = k - i
+            if j < 0:
+                break
+            e = errs[j]
+            x[3 * i] = 23.0 if np.isnan(e) else min(23.0, max(-23.0, np.log(max(e, 1e-300))))
+            x[3 * i + 1] = np.log(hs[j]) - np.log(hs[k])
+            x[3 * i + 2] = 1.0 if accs[j] else 0.0
+        x[12] = np.log(fac)
+        x[13] = np.log(rtol)
+        x[14] = np.log(max(t1 - t_after[k], hs[k]) / hs[k])
+        x[15] = np.log(hs[k] * stiff)
+        X[k] = x
+    return X

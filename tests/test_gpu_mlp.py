@@ -105,6 +105,22 @@ def test_fused_proposal_matches_oracle_network():
     assert np.all(trace[trace[:, 2] == 1, 1] <= 1.0) and np.all(trace[trace[:, 2] == 0, 1] > 1.0)
 
 
+def test_recorded_features_match_oracle_definition(orc):
+    # the features the device computes for the network (and records for
+    # training) against the oracle's definition from the attempt sequence
+    st, _, trace = _gs_run(hode.CTRL_PI)
+    N, prm = 24, [2e-3, 1e-3, 0.04, 0.06, 2.5]
+    stiff = 12.0 * max(prm[0], prm[1]) / (prm[4] / N) ** 2 + 1.0
+    X = omlp.features(trace[:, 0], trace[:, 1], trace[:, 2] == 1, trace[:, 3], 40.0, 1e-5, stiff,
+                      lambda e, ep, lr: orc.ctrl_decide(orc.CTRL_PI, e, ep, lr))
+    acc = trace[:, 2] == 1
+    assert acc.sum() > 5
+    assert np.all(np.isnan(trace[~acc, 8:24]))
+    got, want = trace[acc, 8:24], X[acc]
+    # the device rounds each feature to fp32 once
+    assert np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want))) <= 1e-6, np.max(np.abs(got - want))
+
+
 def test_nonfinite_network_falls_back_to_pi_exactly():
     bad = np.full(hode.MLP_NPARAM, 0x7FC0, dtype=np.uint16)  # bf16 NaN everywhere
     st_pi, y_pi, tr_pi = _gs_run(hode.CTRL_PI)

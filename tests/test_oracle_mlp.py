@@ -76,3 +76,41 @@ def test_bf16_forward_close_to_exact():
     y, _ = mlp.forward(p, X)
     yq, _ = mlp.forward(p, X, bf16=True)
     assert np.max(np.abs(y - yq)) < 0.05 * (1 + np.max(np.abs(y)))
+
+
+def test_features_history_shifts_and_special_values(orc):
+    # invariants of the feature definition on a synthetic attempt sequence
+    # with a reject and a NaN error: the history of attempt k is that of
+    # attempt k-1 shifted by one slot (step ratios rebased to h_k), the PI
+    # entry is the oracle controller's factor, and rejected rows are NaN
+    hs = np.array([0.1, 0.3, 0.5, 0.2, 0.25, 0.4, 0.35])
+    errs = np.array([0.2, 0.5, 3.0, float("nan"), 0.8, 0.1, 1e-40])
+    accs = np.array([e <= 1.0 for e in errs])
+    t_after = np.cumsum(np.where(accs, hs, 0.0))
+    X = mlp.features(hs, errs, accs, t_after, 1.5, 1e-6, 7.0,
+                      lambda e, ep, lr: orc.ctrl_decide(orc.CTRL_PI, e, ep, lr))
+    assert np.all(np.isnan(X[~accs]))
+    k_acc = np.nonzero(accs)[0]
+    for k in k_acc:
+        x = X[k]
+        assert x[1] == 0.0 and x[2] == 1.0                       # the attempt itself
+        assert x[13] == np.log(1e-6) and abs(x[15] - np.log(hs[k] * 7.0)) < 1e-15
+        assert abs(x[14] - np.log(max(1.5 - t_after[k], hs[k]) / hs[k])) < 1e-15
+        for i in range(1, 4):
+            j = k - i
+            if j < 0:
+                assert np.all(x[3 * i:3 * i + 3] == 0.0)
+                continue
+            assert x[3 * i + 2] == (1.0 if accs[j] else 0.0)
+            assert abs(x[3 * i + 1] - np.log(hs[j] / hs[k])) < 1e-14
+    # NaN error counts as the upper clamp, tiny errors hit the lower clamp
+    assert X[4][3] == 23.0 and X[6][0] == -23.0
+    # consecutive accepted attempts: slots shift by one
+    for k in (1, 5, 6):
+        assert np.allclose(X[k][3:12:3], X[k - 1][0:9:3])
+    # PI entry: the oracle controller's factor after attempt k
+    ep, lr = 1.0, False
+    for k in range(len(hs)):
+        acc, fac, ep, lr = orc.ctrl_decide(orc.CTRL_PI, errs[k], ep, lr)
+        if acc:
+            assert X[k][12] == np.log(fac)
