@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "hode_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 EXP, LOGISTIC, GRAYSCOTT = 1, 2, 3
-RK4, DOPRI5 = 1, 2
+RK4, DOPRI5, CASHKARP = 1, 2, 3
 CTRL_PI, CTRL_I = 1, 2
 OK, EINVAL, EDT_UNDERFLOW, EMAXSTEPS, ENONFINITE = 0, -1, -5, -6, -7
 
@@ -73,6 +73,12 @@ def lib():
                                              C.POINTER(Stats), P, C.c_int64]
         L.orc_integrate_replay.argtypes = [C.POINTER(System), P, C.c_double, P, P, C.c_int64,
                                            C.c_double, C.c_double, C.POINTER(C.c_double), P]
+        L.orc_cashkarp_attempt.argtypes = [C.POINTER(System), P, C.c_double, P, P]
+        L.orc_integrate_adaptive_m.argtypes = [C.POINTER(System), C.c_int, P, C.c_double, C.c_double, C.c_double,
+                                               C.c_double, C.c_double, C.c_int, C.c_int64,
+                                               C.POINTER(Stats), P, C.c_int64]
+        L.orc_integrate_replay_m.argtypes = [C.POINTER(System), C.c_int, P, C.c_double, P, P, C.c_int64,
+                                             C.c_double, C.c_double, C.POINTER(C.c_double), P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -103,7 +109,7 @@ def rhs(sysd: System, y) -> np.ndarray:
 
 
 def tableau(method: int):
-    s = 4 if method == RK4 else 7
+    s = {RK4: 4, DOPRI5: 7, CASHKARP: 6}[method]
     a = np.zeros(s * s)
     b = np.zeros(s)
     bh = np.zeros(s)
@@ -139,6 +145,14 @@ def dopri5_attempt(sysd: System, y, h: float):
     return yn, k7, e
 
 
+def cashkarp_attempt(sysd: System, y, h: float):
+    """One Cash-Karp 5(4) attempt from y: returns (ynew, e)."""
+    y = _f64(y).ravel()
+    yn, e = np.empty_like(y), np.empty_like(y)
+    assert lib().orc_cashkarp_attempt(C.byref(sysd), _ptr(y), h, _ptr(yn), _ptr(e)) == OK
+    return yn, e
+
+
 def integrate_n_steps(sysd: System, method: int, y, t0: float, dt: float, n: int):
     y = _f64(y).ravel().copy()
     te = C.c_double(0)
@@ -148,27 +162,30 @@ def integrate_n_steps(sysd: System, method: int, y, t0: float, dt: float, n: int
 
 
 def integrate_adaptive(sysd: System, y, t0, t1, dt0, atol, rtol, ctrl=CTRL_PI, max_steps=10 ** 7,
-                       trace_cap=0):
-    """Returns (y, stats dict, trace array of shape (attempts, 4) or None)."""
+                       trace_cap=0, method=None):
+    """Returns (y, stats dict, trace array of shape (attempts, 4) or None).
+    method: DOPRI5 (default) or CASHKARP."""
     y = _f64(y).ravel().copy()
     st = Stats()
     tr = np.zeros((max(trace_cap, 1), 4))
-    lib().orc_integrate_adaptive(C.byref(sysd), _ptr(y), t0, t1, dt0, atol, rtol, ctrl, max_steps,
-                                 C.byref(st), _ptr(tr) if trace_cap else None, trace_cap)
+    lib().orc_integrate_adaptive_m(C.byref(sysd), DOPRI5 if method is None else method, _ptr(y), t0, t1, dt0,
+                                   atol, rtol, ctrl, max_steps, C.byref(st), _ptr(tr) if trace_cap else None,
+                                   trace_cap)
     stats = {f: getattr(st, f) for f, _ in Stats._fields_ if f != "pad"}
     n_att = stats["accepted"] + stats["rejected"]
     return y, stats, (tr[:min(n_att, trace_cap)] if trace_cap else None)
 
 
-def integrate_replay(sysd: System, y, t0, hs, accepted, atol=1e-6, rtol=1e-6):
-    """Replays (h, accepted) pairs; returns (y, t_end, per-attempt error norms)."""
+def integrate_replay(sysd: System, y, t0, hs, accepted, atol=1e-6, rtol=1e-6, method=None):
+    """Replays (h, accepted) pairs; returns (y, t_end, per-attempt error norms).
+    method: DOPRI5 (default) or CASHKARP."""
     y = _f64(y).ravel().copy()
     hs = _f64(hs).ravel()
     acc = np.ascontiguousarray(np.asarray(accepted, dtype=np.int32).ravel())
     errs = np.zeros(max(hs.size, 1))
     te = C.c_double(0)
-    rc = lib().orc_integrate_replay(C.byref(sysd), _ptr(y), t0, _ptr(hs), _ptr(acc), hs.size, atol, rtol,
-                                    C.byref(te), _ptr(errs))
+    rc = lib().orc_integrate_replay_m(C.byref(sysd), DOPRI5 if method is None else method, _ptr(y), t0, _ptr(hs),
+                                      _ptr(acc), hs.size, atol, rtol, C.byref(te), _ptr(errs))
     assert rc == OK, rc
     return y, te.value, errs[:hs.size]
 

@@ -11,11 +11,12 @@
 // combined by an *Algebra* (linear combinations of states); adaptive steppers
 // bound the error with the L-infinity norm of the embedded error estimate.
 //
-//  * Steppers: classical Runge-Kutta 4 and Runge-Kutta-Dopri 5 (the paper's
-//    Table 1, fixed and dynamic step size).  Tableaux: Kutta 1901 and
-//    Dormand & Prince 1980 (Hairer, Norsett & Wanner, Solving ODEs I, Table
-//    II.5.2).  Dopri 5 is first-same-as-last: k7 of an accepted step is k1 of
-//    the next.
+//  * Steppers: classical Runge-Kutta 4, Runge-Kutta-Dopri 5 and Runge-Kutta
+//    Cash-Karp 5(4) (the paper's Table 1, fixed and dynamic step size).
+//    Tableaux: Kutta 1901, Dormand & Prince 1980 (Hairer, Norsett & Wanner,
+//    Solving ODEs I, Table II.5.2) and Cash & Karp 1990 (ACM TOMS 16, 201).
+//    Dopri 5 is first-same-as-last: k7 of an accepted step is k1 of the next;
+//    Cash-Karp evaluates its 6 stages afresh every attempt.
 //  * Systems: exponential dx/dt = x and sigmoidal (logistic) dx/dt = x(1-x),
 //    the two families of the accuracy benchmark read as autonomous ODEs whose
 //    solutions are x0 e^t and the logistic curve; and the 3D Gray-Scott
@@ -44,7 +45,7 @@
 extern "C" {
 
 enum { ORC_EXP = 1, ORC_LOGISTIC = 2, ORC_GRAYSCOTT = 3 };
-enum { ORC_RK4 = 1, ORC_DOPRI5 = 2 };
+enum { ORC_RK4 = 1, ORC_DOPRI5 = 2, ORC_CASHKARP = 3 };
 enum { ORC_CTRL_PI = 1, ORC_CTRL_I = 2 };
 enum {
   ORC_OK = 0,
@@ -100,6 +101,20 @@ const double DP_A[7][7] = {
 const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
 const double DP_BHAT[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
                            -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
+
+// Cash-Karp 5(4), 6 stages: 5th-order weights b (the solution carried on) and
+// 4th-order embedded weights bhat.
+const double CK_C[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
+const double CK_A[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0},
+    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0, 0},
+    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0, 0},
+    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0, 0},
+};
+const double CK_B[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
+const double CK_BHAT[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0, 277.0 / 14336.0, 1.0 / 4.0};
 
 // ---- the System: right-hand sides -----------------------------------------
 
@@ -235,6 +250,31 @@ void dopri5_attempt(const orc_system& s, const double* y, const double* k1, doub
   }
 }
 
+// One Cash-Karp attempt from y: k1 = f(y) and five more stages; writes ynew
+// (5th order) and (if e != null) e = h * sum_j (b_j - bhat_j) k_j.
+void cashkarp_attempt(const orc_system& s, const double* y, double h, double* ynew, double* e, Work& W) {
+  const int64_t n = s.n;
+  double* kp[6];
+  for (int j = 0; j < 6; ++j) kp[j] = W.k[j].data();
+  rhs(s, y, kp[0]);
+  for (int st = 1; st < 6; ++st) {
+    stage_input(n, y, h, st, CK_A[st], kp, W.w.data());
+    rhs(s, W.w.data(), kp[st]);
+  }
+  stage_input(n, y, h, 6, CK_B, kp, ynew);
+  if (e) {
+    double d[6];
+    for (int j = 0; j < 6; ++j) d[j] = CK_B[j] - CK_BHAT[j];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < 6; ++j)
+        if (d[j] != 0.0) acc += d[j] * kp[j][i];
+      e[i] = h * acc;
+    }
+  }
+}
+
 // ---- step-size controller -------------------------------------------------------
 
 struct Ctrl {
@@ -281,6 +321,13 @@ void orc_tableau(int method, double* a, double* b, double* bhat, double* c) {
       c[i] = RK4_C[i];
       if (bhat) bhat[i] = 0.0;
     }
+  } else if (method == ORC_CASHKARP) {
+    for (int i = 0; i < 6; ++i) {
+      for (int j = 0; j < 6; ++j) a[i * 6 + j] = CK_A[i][j];
+      b[i] = CK_B[i];
+      bhat[i] = CK_BHAT[i];
+      c[i] = CK_C[i];
+    }
   } else {
     for (int i = 0; i < 7; ++i) {
       for (int j = 0; j < 7; ++j) a[i * 7 + j] = DP_A[i][j];
@@ -324,14 +371,29 @@ int orc_dopri5_attempt(const orc_system* s, const double* y, double h, double* y
   return ORC_OK;
 }
 
+int orc_cashkarp_attempt(const orc_system* s, const double* y, double h, double* ynew, double* e) {
+  if (!valid(s)) return ORC_EINVAL;
+  Work W(s->n, 6);
+  cashkarp_attempt(*s, y, h, ynew, e, W);
+  return ORC_OK;
+}
+
 // Fixed steps: t_n = t0 + n dt (Odeint integrate_const / do_step).
 int orc_integrate_n_steps(const orc_system* s, int method, double* y, double t0, double dt, int64_t nsteps,
                           double* t_end) {
-  if (!valid(s) || nsteps < 0 || !(method == ORC_RK4 || method == ORC_DOPRI5)) return ORC_EINVAL;
+  if (!valid(s) || nsteps < 0 || !(method == ORC_RK4 || method == ORC_DOPRI5 || method == ORC_CASHKARP))
+    return ORC_EINVAL;
   const int64_t n = s->n;
   if (method == ORC_RK4) {
     Work W(n, 4);
     for (int64_t i = 0; i < nsteps; ++i) rk4_step(*s, y, dt, W);
+  } else if (method == ORC_CASHKARP) {
+    Work W(n, 6);
+    std::vector<double> ynew(n);
+    for (int64_t i = 0; i < nsteps; ++i) {
+      cashkarp_attempt(*s, y, dt, ynew.data(), nullptr, W);
+      std::swap_ranges(ynew.begin(), ynew.end(), y);
+    }
   } else {
     Work W(n, 7);
     std::vector<double> k1(n), k7(n), ynew(n);
@@ -346,20 +408,23 @@ int orc_integrate_n_steps(const orc_system* s, int method, double* y, double t0,
   return ORC_OK;
 }
 
-// Error-controlled Dopri5 from t0 to t1 (Odeint integrate_adaptive).  The trace,
-// if given, receives 4 doubles per attempt: h, err, accepted (0/1), t after.
-int orc_integrate_adaptive(const orc_system* s, double* y, double t0, double t1, double dt0, double atol,
-                           double rtol, int ctrl_kind, int64_t max_steps, orc_stats* st, double* trace,
-                           int64_t trace_cap) {
-  if (!valid(s) || !(t1 >= t0) || !(dt0 > 0) || !(atol >= 0) || !(rtol >= 0) || (atol == 0 && rtol == 0))
+// Error-controlled integration from t0 to t1 with an embedded pair (Dopri5 or
+// Cash-Karp; Odeint integrate_adaptive).  The trace, if given, receives 4
+// doubles per attempt: h, err, accepted (0/1), t after.
+int orc_integrate_adaptive_m(const orc_system* s, int method, double* y, double t0, double t1, double dt0,
+                             double atol, double rtol, int ctrl_kind, int64_t max_steps, orc_stats* st,
+                             double* trace, int64_t trace_cap) {
+  if (!valid(s) || !(t1 >= t0) || !(dt0 > 0) || !(atol >= 0) || !(rtol >= 0) || (atol == 0 && rtol == 0) ||
+      !(method == ORC_DOPRI5 || method == ORC_CASHKARP))
     return ORC_EINVAL;
+  const bool dp = method == ORC_DOPRI5;
   const int64_t n = s->n;
   Work W(n, 7);
   std::vector<double> k1(n), k7(n), ynew(n), e(n);
-  rhs(*s, y, k1.data());
+  if (dp) rhs(*s, y, k1.data());
   Ctrl c(ctrl_kind);
   double t = t0, dt = dt0, last_err = 0.0;
-  int64_t acc = 0, rej = 0, evals = 1, att = 0;
+  int64_t acc = 0, rej = 0, evals = dp ? 1 : 0, att = 0;
   int status = ORC_OK;
   while (t < t1) {
     if (att >= max_steps) { status = ORC_EMAXSTEPS; break; }
@@ -369,7 +434,8 @@ int orc_integrate_adaptive(const orc_system* s, double* y, double t0, double t1,
       status = std::isfinite(last_err) ? ORC_EDT_UNDERFLOW : ORC_ENONFINITE;
       break;
     }
-    dopri5_attempt(*s, y, k1.data(), h, ynew.data(), k7.data(), e.data(), W);
+    if (dp) dopri5_attempt(*s, y, k1.data(), h, ynew.data(), k7.data(), e.data(), W);
+    else cashkarp_attempt(*s, y, h, ynew.data(), e.data(), W);
     evals += 6;
     ++att;
     const double err = err_norm(n, y, ynew.data(), e.data(), atol, rtol);
@@ -378,7 +444,7 @@ int orc_integrate_adaptive(const orc_system* s, double* y, double t0, double t1,
     const bool ok = c.decide(err, &fac);
     if (ok) {
       std::swap_ranges(ynew.begin(), ynew.end(), y);
-      k1.swap(k7);
+      if (dp) k1.swap(k7);
       t = last ? t1 : t + h;
       ++acc;
     } else {
@@ -397,28 +463,43 @@ int orc_integrate_adaptive(const orc_system* s, double* y, double t0, double t1,
   return status;
 }
 
+int orc_integrate_adaptive(const orc_system* s, double* y, double t0, double t1, double dt0, double atol,
+                           double rtol, int ctrl_kind, int64_t max_steps, orc_stats* st, double* trace,
+                           int64_t trace_cap) {
+  return orc_integrate_adaptive_m(s, ORC_DOPRI5, y, t0, t1, dt0, atol, rtol, ctrl_kind, max_steps, st, trace,
+                                  trace_cap);
+}
+
 // Replays a recorded step sequence: attempt i uses step h[i] and is accepted iff
 // accepted[i] != 0 (the controller is bypassed).  errs (optional) receives the
 // error norm of every attempt.
-int orc_integrate_replay(const orc_system* s, double* y, double t0, const double* hs, const int32_t* accepted,
-                         int64_t n_att, double atol, double rtol, double* t_end, double* errs) {
-  if (!valid(s) || n_att < 0) return ORC_EINVAL;
+int orc_integrate_replay_m(const orc_system* s, int method, double* y, double t0, const double* hs,
+                           const int32_t* accepted, int64_t n_att, double atol, double rtol, double* t_end,
+                           double* errs) {
+  if (!valid(s) || n_att < 0 || !(method == ORC_DOPRI5 || method == ORC_CASHKARP)) return ORC_EINVAL;
+  const bool dp = method == ORC_DOPRI5;
   const int64_t n = s->n;
   Work W(n, 7);
   std::vector<double> k1(n), k7(n), ynew(n), e(n);
-  rhs(*s, y, k1.data());
+  if (dp) rhs(*s, y, k1.data());
   double t = t0;
   for (int64_t i = 0; i < n_att; ++i) {
-    dopri5_attempt(*s, y, k1.data(), hs[i], ynew.data(), k7.data(), e.data(), W);
+    if (dp) dopri5_attempt(*s, y, k1.data(), hs[i], ynew.data(), k7.data(), e.data(), W);
+    else cashkarp_attempt(*s, y, hs[i], ynew.data(), e.data(), W);
     if (errs) errs[i] = err_norm(n, y, ynew.data(), e.data(), atol, rtol);
     if (accepted[i]) {
       std::swap_ranges(ynew.begin(), ynew.end(), y);
-      k1.swap(k7);
+      if (dp) k1.swap(k7);
       t += hs[i];
     }
   }
   if (t_end) *t_end = t;
   return ORC_OK;
+}
+
+int orc_integrate_replay(const orc_system* s, double* y, double t0, const double* hs, const int32_t* accepted,
+                         int64_t n_att, double atol, double rtol, double* t_end, double* errs) {
+  return orc_integrate_replay_m(s, ORC_DOPRI5, y, t0, hs, accepted, n_att, atol, rtol, t_end, errs);
 }
 
 int orc_num_threads(void);
