@@ -39,13 +39,16 @@ GS_PRM = [2e-5, 1e-5, 0.053, 0.014, 2.5]
 #   R4: y,k3,k1,k2 -> ynew           D2: y,k1 -> k2     D3: y,k1,k2 -> k3
 #   D4: y,k1..k3 -> k4               D5: y,k1..k4 -> k5
 #   D6: y,k1..k5 -> ynew, partial error                D7: ynew,partial error,y -> k7
-GS_ARRAYS = {0: 2, 1: 3, 2: 3, 3: 5, 4: 3, 5: 4, 6: 5, 7: 6, 8: 8, 9: 4, 10: 2, 11: 7}
+#   Cash-Karp: D1 D2 D3 (shared), C4: y,k1..k3 -> k4   C5: y,k1..k4 -> k5   C6: y,k1..k5 -> ynew (+ error norm)
+GS_ARRAYS = {0: 2, 1: 3, 2: 3, 3: 5, 4: 3, 5: 4, 6: 5, 7: 6, 8: 8, 9: 4, 10: 2, 11: 5, 12: 6, 13: 7, 14: 7, 15: 7}
 GS_NAMES = {0: "D1", 1: "R2", 2: "R3", 3: "R4", 4: "D2", 5: "D3", 6: "D4", 7: "D5", 8: "D6", 9: "D7", 10: "D7F",
-            11: "D6F"}
+            11: "C4", 12: "C5", 13: "C6", 14: "C6F", 15: "D6F"}
+STAGES = {"rk4": [0, 1, 2, 3], "dp5": [4, 5, 6, 7, 8, 9], "ck54": [0, 4, 5, 11, 12, 13]}
 
 WORKLOADS = {
     "gs512-dp5": dict(kind="gs", N=512, dtype="f32", method="dp5", window=10.0, seed=5, dt0=0.1),
     "gs256-dp5": dict(kind="gs", N=256, dtype="f32", method="dp5", window=10.0, seed=3, dt0=0.1),
+    "gs512-ck54": dict(kind="gs", N=512, dtype="f32", method="ck54", window=10.0, seed=5, dt0=0.1),
     "gs256-rk4": dict(kind="gs", N=256, dtype="f32", method="rk4", steps_per=100, dt=0.1, seed=3),
     "gs32-rk4-fp64": dict(kind="gs", N=32, dtype="f64", method="rk4", steps_per=500, dt=0.1, seed=1,
                           compare_graphs=True),
@@ -88,13 +91,15 @@ def cpu_baseline_leg(wl, budget_s=10.0):
                 y, t = oracle.integrate_n_steps(sysd, oracle.RK4, y, t, 0.1, 5)
                 units += 5 * Ns ** 3
             else:
-                y, st, _ = oracle.integrate_adaptive(sysd, y, t, 1e9, 0.3, 1e-6, 1e-6, max_steps=4)
+                om = oracle.CASHKARP if wl["method"] == "ck54" else oracle.DOPRI5
+                y, st, _ = oracle.integrate_adaptive(sysd, y, t, 1e9, 0.3, 1e-6, 1e-6, max_steps=4, method=om)
                 t = st["t"]
                 units += st["accepted"] * Ns ** 3
             done += 1
         el = time.perf_counter() - t0
-        sample = "%s on a %d^3 grid (same parameters), %d calls, %.1f s" % (
-            "RK4 steps" if wl["method"] == "rk4" else "adaptive Dopri5 accepted steps", Ns, done, el)
+        what = {"rk4": "RK4 steps", "dp5": "adaptive Dopri5 accepted steps",
+                "ck54": "adaptive Cash-Karp accepted steps"}[wl["method"]]
+        sample = "%s on a %d^3 grid (same parameters), %d calls, %.1f s" % (what, Ns, done, el)
         unit = "cell-updates/s"
     elif wl["kind"] == "ens":
         edges, F, k = inputs.ensemble_draws(wl["n"], seed=wl["seed"])
@@ -202,7 +207,9 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     torch.cuda.synchronize()
     ctx.set_tolerances(1e-6, 1e-6)
     ctx.set_controller(ctrl_kind, weights)
-    method = hode.RK4 if wl["method"] == "rk4" else hode.DOPRI5
+    method = {"rk4": hode.RK4, "dp5": hode.DOPRI5, "ck54": hode.CASHKARP54}[wl["method"]]
+    if method == hode.CASHKARP54:
+        ctx.set_stepper(hode.CASHKARP54)
     if tile is None:
         ctx.autotune(method, 3)  # project autotuner: fastest (ry, zc) for this grid
     else:
@@ -239,7 +246,7 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     # per-stage durations: HIP events around every stage kernel of attempts
     # replayed in the same order on the library's stream, right after the
     # timed region
-    kinds = [0, 1, 2, 3] if wl["method"] == "rk4" else [4, 5, 6, 7, 8, 9]
+    kinds = STAGES[wl["method"]]
     prof = ctx.profile_attempt(method, 10)
     ms = dict(zip(kinds, prof))
     dom = max(kinds, key=lambda k: ms[k])
@@ -349,8 +356,8 @@ def main():
         r = run_gs(wl, args.steps, args.warmup, ctrl, tile=tile)
         unit = "cell-updates/s"
         cfg = {"workload": args.workload, "grid": [wl["N"]] * 3, "fields": 2,
-               "method": "dopri5-adaptive" if wl["method"] == "dp5" else "rk4-fixed",
-               "rtol": 1e-6 if wl["method"] == "dp5" else None, "controller": args.controller,
+               "method": {"dp5": "dopri5-adaptive", "ck54": "cashkarp54-adaptive", "rk4": "rk4-fixed"}[wl["method"]],
+               "rtol": None if wl["method"] == "rk4" else 1e-6, "controller": args.controller,
                "window_time_units": wl.get("window"), "dt": wl.get("dt"), "tile_ry_zc": r["tile"],
                "params": {"Du": GS_PRM[0], "Dv": GS_PRM[1], "F": GS_PRM[2], "k": GS_PRM[3], "L": GS_PRM[4]}}
     elif wl["kind"] == "ens":

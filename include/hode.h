@@ -46,7 +46,10 @@ typedef struct hode_ctx hode_ctx;
 
 enum { HODE_F32 = 1, HODE_F64 = 2 };
 enum { HODE_RHS_EXP = 1, HODE_RHS_LOGISTIC = 2, HODE_RHS_GRAYSCOTT3D = 3 };
-enum { HODE_RK4 = 1, HODE_DOPRI5 = 2 };
+/* Steppers (the paper's Table 1): classical Runge-Kutta 4; Dormand-Prince
+ * 5(4) ("Dopri5", 7 stages, first same as last); Cash-Karp 5(4) (6 stages,
+ * Cash & Karp 1990).  The embedded pairs carry the 5th-order solution. */
+enum { HODE_RK4 = 1, HODE_DOPRI5 = 2, HODE_CASHKARP54 = 3 };
 enum { HODE_CTRL_PI = 1, HODE_CTRL_I = 2, HODE_CTRL_MLP = 3 };
 enum {
   HODE_OK = 0,
@@ -112,20 +115,28 @@ int hode_set_tolerances(hode_ctx *ctx, double atol, double rtol);
  * proposal remains the fallback and retry rule. */
 int hode_set_controller(hode_ctx *ctx, int kind, const void *weights, size_t nbytes);
 
-/* One fixed step of size dt from time t, in place (Odeint do_step). */
+/* One fixed step of size dt from time t, in place (Odeint do_step); any
+ * stepper. */
 int hode_do_step(hode_ctx *ctx, int method, double t, double dt);
 
 /* n fixed steps (Odeint integrate_const with n = (tf - t0)/dt):
  * t_n = t0 + n dt.  *t_end (may be NULL) receives t_n. */
 int hode_integrate_n_steps(hode_ctx *ctx, int method, double t0, double dt, int64_t n, double *t_end);
 
-/* One error-controlled Dopri5 attempt of size *dt from *t.  On acceptance *t
+/* Embedded pair of the adaptive calls (hode_try_step,
+ * hode_integrate_adaptive): HODE_DOPRI5 (default) or HODE_CASHKARP54.  Both
+ * use the same error norm and controller (embedded order 4).  Not for
+ * ensemble contexts (they step with Dopri5). */
+int hode_set_stepper(hode_ctx *ctx, int method);
+
+/* One error-controlled attempt of size *dt from *t.  On acceptance *t
  * advances and the state is updated; either way *dt receives the proposed
  * next step and *accepted 0/1.  Controller history carries over between
  * calls until the next integrate call. */
 int hode_try_step(hode_ctx *ctx, double *t, double *dt, int *accepted);
 
-/* Error-controlled Dopri5 from t0 to t1 (Odeint integrate_adaptive), first
+/* Error-controlled integration from t0 to t1 with the adaptive stepper
+ * (Odeint integrate_adaptive), first
  * trial step dt0, at most max_steps attempts.  The last step is clipped to
  * land on t1 exactly.  Returns HODE_OK or the status that ended the run; the
  * state holds the last accepted step either way.  `out` may be NULL. */
@@ -164,17 +175,19 @@ int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);  /* the widest stage's
  * for the widest that divides N (16-byte loads where possible). */
 int hode_set_vector_width(hode_ctx *ctx, int vw);
 
-/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..10 as D1,
- * R2, R3, R4, D2..D7, D7F; element-wise: kind = method) on the context's
+/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..15 as D1,
+ * R2, R3, R4, D2..D7, D7F, C4, C5, C6, C6F, D6F; element-wise: kind =
+ * method) on the context's
  * stream with HIP events and returns the mean duration in milliseconds.
  * The state is left unchanged for Gray-Scott non-final kinds only. */
 int hode_time_kernel(hode_ctx *ctx, int kind, int reps, double *avg_ms);
 
 /* Gray-Scott: runs `reps` attempts of `method` (RK4: stages D1 R2 R3 R4;
- * DOPRI5: stages D2..D7 of an adaptive attempt) with the control kernel in a
+ * DOPRI5: stages D2..D7 of an adaptive attempt; CASHKARP54: D1 D2 D3 C4 C5
+ * C6) with the control kernel in a
  * no-op timing mode, HIP events around every stage kernel on the context's
  * stream, and writes the mean duration of each stage in milliseconds to
- * ms[0..3] or ms[0..5].  The current state and k1 are left unchanged. */
+ * ms[0..3] or ms[0..5].  The current state is left unchanged (and k1 = f(y)). */
 int hode_profile_attempt(hode_ctx *ctx, int method, int reps, double *ms);
 
 /* Gray-Scott: times one attempt of `method` for every tile configuration

@@ -1,8 +1,9 @@
 // Whole-step kernel for the element-wise families of the accuracy benchmark:
 // exponential dx/dt = x and sigmoidal (logistic) dx/dt = x (1 - x), one
 // independent ODE per component.  With no spatial coupling every stage of a
-// step needs only the component itself, so the entire RK4 step or Dopri5
-// attempt (7 stages, first same as last) runs in registers: each component is
+// step needs only the component itself, so the entire RK4 step, Dopri5
+// attempt (7 stages, first same as last) or Cash-Karp 5(4) attempt (6
+// stages) runs in registers: each component is
 // read once and written once per attempt, and the embedded error's L-infinity
 // norm is reduced on the fly (wavefront shuffle, LDS, one atomic per
 // workgroup).  The one-wavefront control kernel then takes the decision.
@@ -56,10 +57,64 @@ __device__ inline DPCoef<T> dp_coef(double h) {
   return q;
 }
 
+// Cash-Karp 5(4) (Cash & Karp 1990), times h: stage coefficients, the
+// 5th-order weights (b2 = b5 = 0) and b - bhat of the embedded estimate.
+template <typename T>
+struct CKCoef {
+  T a21, a31, a32, a41, a42, a43, a51, a52, a53, a54, a61, a62, a63, a64, a65, b1, b3, b4, b6;
+  double e1, e3, e4, e5, e6;
+};
+
+template <typename T>
+__device__ inline CKCoef<T> ck_coef(double h) {
+  CKCoef<T> q;
+  q.a21 = (T)(h * (1.0 / 5.0));
+  q.a31 = (T)(h * (3.0 / 40.0));
+  q.a32 = (T)(h * (9.0 / 40.0));
+  q.a41 = (T)(h * (3.0 / 10.0));
+  q.a42 = (T)(h * (-9.0 / 10.0));
+  q.a43 = (T)(h * (6.0 / 5.0));
+  q.a51 = (T)(h * (-11.0 / 54.0));
+  q.a52 = (T)(h * (5.0 / 2.0));
+  q.a53 = (T)(h * (-70.0 / 27.0));
+  q.a54 = (T)(h * (35.0 / 27.0));
+  q.a61 = (T)(h * (1631.0 / 55296.0));
+  q.a62 = (T)(h * (175.0 / 512.0));
+  q.a63 = (T)(h * (575.0 / 13824.0));
+  q.a64 = (T)(h * (44275.0 / 110592.0));
+  q.a65 = (T)(h * (253.0 / 4096.0));
+  q.b1 = (T)(h * (37.0 / 378.0));
+  q.b3 = (T)(h * (250.0 / 621.0));
+  q.b4 = (T)(h * (125.0 / 594.0));
+  q.b6 = (T)(h * (512.0 / 1771.0));
+  q.e1 = h * (37.0 / 378.0 - 2825.0 / 27648.0);
+  q.e3 = h * (250.0 / 621.0 - 18575.0 / 48384.0);
+  q.e4 = h * (125.0 / 594.0 - 13525.0 / 55296.0);
+  q.e5 = h * (-277.0 / 14336.0);
+  q.e6 = h * (512.0 / 1771.0 - 1.0 / 4.0);
+  return q;
+}
+
 template <typename T, int RHS, int MODE>
-__device__ __forceinline__ T step_one(T x, const DPCoef<T>& q, T r2, T r1, T r16, T r13, double atol, double rtol,
-                                      uint64_t& emax) {
-  if constexpr (MODE == MODE_FIXED_RK4) {
+__device__ __forceinline__ T step_one(T x, const DPCoef<T>& q, const CKCoef<T>& ck, T r2, T r1, T r16, T r13,
+                                      double atol, double rtol, uint64_t& emax) {
+  if constexpr (MODE == MODE_FIXED_CK || MODE == MODE_ADAPTIVE_CK) {
+    const T k1 = frhs<T, RHS>(x);
+    const T k2 = frhs<T, RHS>(x + ck.a21 * k1);
+    const T k3 = frhs<T, RHS>(x + ck.a31 * k1 + ck.a32 * k2);
+    const T k4 = frhs<T, RHS>(x + ck.a41 * k1 + ck.a42 * k2 + ck.a43 * k3);
+    const T k5 = frhs<T, RHS>(x + ck.a51 * k1 + ck.a52 * k2 + ck.a53 * k3 + ck.a54 * k4);
+    const T k6 = frhs<T, RHS>(x + ck.a61 * k1 + ck.a62 * k2 + ck.a63 * k3 + ck.a64 * k4 + ck.a65 * k5);
+    const T xn = x + ck.b1 * k1 + ck.b3 * k3 + ck.b4 * k4 + ck.b6 * k6;
+    if constexpr (MODE == MODE_ADAPTIVE_CK) {
+      const double e = ck.e1 * (double)k1 + ck.e3 * (double)k3 + ck.e4 * (double)k4 + ck.e5 * (double)k5 +
+                       ck.e6 * (double)k6;
+      const double ratio = fabs(e) / (atol + rtol * fmax(fabs((double)x), fabs((double)xn)));
+      const uint64_t bits = (uint64_t)__double_as_longlong(ratio);
+      emax = bits > emax ? bits : emax;
+    }
+    return xn;
+  } else if constexpr (MODE == MODE_FIXED_RK4) {
     const T k1 = frhs<T, RHS>(x);
     const T k2 = frhs<T, RHS>(x + r2 * k1);
     const T k3 = frhs<T, RHS>(x + r2 * k2);
@@ -107,6 +162,7 @@ __global__ __launch_bounds__(256) void ew_step(DevCtrl* __restrict__ c, T* __res
   T* __restrict__ yn = c->parity ? b0 : b1;
   const double atol = c->atol, rtol = c->rtol;
   DPCoef<T> q = dp_coef<T>(h);
+  CKCoef<T> ck = ck_coef<T>(h);
   const T r2 = (T)(h * 0.5), r1 = (T)h, r16 = (T)(h * (1.0 / 6.0)), r13 = (T)(h * (1.0 / 3.0));
   uint64_t emax = 0;
 
@@ -118,16 +174,16 @@ __global__ __launch_bounds__(256) void ew_step(DevCtrl* __restrict__ c, T* __res
     V v = reinterpret_cast<const V*>(y)[i];
     T* e = reinterpret_cast<T*>(&v);
 #pragma unroll
-    for (int j = 0; j < W; ++j) e[j] = step_one<T, RHS, MODE>(e[j], q, r2, r1, r16, r13, atol, rtol, emax);
+    for (int j = 0; j < W; ++j) e[j] = step_one<T, RHS, MODE>(e[j], q, ck, r2, r1, r16, r13, atol, rtol, emax);
     reinterpret_cast<V*>(yn)[i] = v;
   }
   // ragged tail
   const int64_t tail = nv * W;
   if (blockIdx.x == gridDim.x - 1 && tail + threadIdx.x < n) {
     const int64_t i = tail + threadIdx.x;
-    yn[i] = step_one<T, RHS, MODE>(y[i], q, r2, r1, r16, r13, atol, rtol, emax);
+    yn[i] = step_one<T, RHS, MODE>(y[i], q, ck, r2, r1, r16, r13, atol, rtol, emax);
   }
-  if constexpr (MODE == MODE_ADAPTIVE) block_max_to<256>(emax, &c->errmax_bits);
+  if constexpr (mode_adaptive(MODE)) block_max_to<256>(emax, &c->errmax_bits);
 }
 
 __global__ __launch_bounds__(64) void ctrl_kernel(DevCtrl* c) {
@@ -145,6 +201,8 @@ template <typename T, int RHS>
 hipError_t launch_rhs(int mode, T* y0, T* y1, int64_t n, int grid, DevCtrl* c, hipStream_t s) {
   if (mode == MODE_FIXED_RK4) ew_step<T, RHS, MODE_FIXED_RK4><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else if (mode == MODE_FIXED_DP5) ew_step<T, RHS, MODE_FIXED_DP5><<<grid, 256, 0, s>>>(c, y0, y1, n);
+  else if (mode == MODE_FIXED_CK) ew_step<T, RHS, MODE_FIXED_CK><<<grid, 256, 0, s>>>(c, y0, y1, n);
+  else if (mode == MODE_ADAPTIVE_CK) ew_step<T, RHS, MODE_ADAPTIVE_CK><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else ew_step<T, RHS, MODE_ADAPTIVE><<<grid, 256, 0, s>>>(c, y0, y1, n);
   return hipGetLastError();
 }

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __res
   // starts on the tiles the previous stage wrote last, which are still in the
   // memory-side Infinity Cache.
   constexpr bool rev = KIND == K_R2 || KIND == K_R4 || KIND == K_D3 || KIND == K_D5 || KIND == K_D7 ||
-                       KIND == K_D7F;
+                       KIND == K_D7F || KIND == K_C5;
   const int slot = rev ? per - 1 - (int)(blockIdx.x >> 3) : (int)(blockIdx.x >> 3);
   const int bb = (blockIdx.x & 7) * per + slot;
   if (bb >= nx * ny * nz) return;  // padding block of the remap (whole block)
@@ -49,7 +49,8 @@ hipError_t launch_t(int kind, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
 #define HODE_CASE(K) \
   case K: gs_stage<T, K, RY, VW><<<dim3((unsigned)grid), dim3(256), 0, s>>>(a, c); break;
     HODE_CASE(K_D1) HODE_CASE(K_R2) HODE_CASE(K_R3) HODE_CASE(K_R4) HODE_CASE(K_D2) HODE_CASE(K_D3)
-    HODE_CASE(K_D4) HODE_CASE(K_D5) HODE_CASE(K_D6) HODE_CASE(K_D7) HODE_CASE(K_D7F) HODE_CASE(K_COUNT)
+    HODE_CASE(K_D4) HODE_CASE(K_D5) HODE_CASE(K_D6) HODE_CASE(K_D7) HODE_CASE(K_D7F) HODE_CASE(K_C4)
+    HODE_CASE(K_C5) HODE_CASE(K_C6) HODE_CASE(K_C6F) HODE_CASE(K_COUNT)
 #undef HODE_CASE
     default: return hipErrorInvalidValue;
   }

@@ -79,6 +79,7 @@ struct hode_ctx {
   bool k1_valid = false;
   int parity = 0, k1slot = 0;
   bool use_graphs = true;      // replay captured chunks (else enqueue every kernel)
+  int stepper = HODE_DOPRI5;   // embedded pair of the adaptive calls
   bool persist_valid = false;  // controller history carried between try_step calls
   DevCtrl persist;
   hode_stats last{};
@@ -180,7 +181,14 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
   static const int rk4[] = {hode::K_D1, hode::K_R2, hode::K_R3, hode::K_R4};
   static const int dp5f[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6F, hode::K_D7F};
   static const int dp5a[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6, hode::K_D7};
-  const int* seq = mode == hode::MODE_FIXED_RK4 ? rk4 : (mode == hode::MODE_FIXED_DP5 ? dp5f : dp5a);
+  // Cash-Karp: stages 1-3 have the Dopri5 shapes and coefficients
+  static const int ckf[] = {hode::K_D1, hode::K_D2, hode::K_D3, hode::K_C4, hode::K_C5, hode::K_C6F};
+  static const int cka[] = {hode::K_D1, hode::K_D2, hode::K_D3, hode::K_C4, hode::K_C5, hode::K_C6};
+  const int* seq = mode == hode::MODE_FIXED_RK4   ? rk4
+                   : mode == hode::MODE_FIXED_DP5 ? dp5f
+                   : mode == hode::MODE_FIXED_CK  ? ckf
+                   : mode == hode::MODE_ADAPTIVE_CK ? cka
+                                                    : dp5a;
   const int ns = mode == hode::MODE_FIXED_RK4 ? 4 : 6;
   for (int i = 0; i < ns; ++i) {
     hipError_t e = launch_stage(c, seq[i], a);
@@ -215,6 +223,10 @@ int get_graph(hode_ctx* c, int mode, int M, hipGraphExec_t* out) {
 double gs_stiffness(const double* prm, int N) {
   const double dx = prm[4] / N;
   return 12.0 * std::max(std::fabs(prm[0]), std::fabs(prm[1])) / (dx * dx) + 1.0;
+}
+
+int adaptive_mode(const hode_ctx* c) {
+  return c->stepper == HODE_CASHKARP54 ? hode::MODE_ADAPTIVE_CK : hode::MODE_ADAPTIVE;
 }
 
 DevCtrl base_ctrl(const hode_ctx* c, int mode) {
@@ -264,7 +276,7 @@ int run_loop(hode_ctx* c, const DevCtrl& init, bool need_k1) {
   int64_t chunks = 0;
   while (!cur.done) {
     int M;
-    if (init.mode == hode::MODE_ADAPTIVE) {
+    if (hode::mode_adaptive(init.mode)) {
       const double est = std::ceil((cur.t1 - cur.t) / (cur.dt > 0 ? cur.dt : 1.0)) + 1.0;
       M = pow2_floor(est > 64 ? 64 : (int64_t)est);
     } else {
@@ -285,12 +297,14 @@ int run_loop(hode_ctx* c, const DevCtrl& init, bool need_k1) {
   }
   c->parity = cur.parity;
   c->k1slot = cur.k1slot;
-  if (init.mode != hode::MODE_FIXED_RK4) c->k1_valid = true;
+  // k1 = f(y) of the current state is in the first-same-as-last slot only
+  // after the Dopri5 modes
+  c->k1_valid = init.mode == hode::MODE_FIXED_DP5 || init.mode == hode::MODE_ADAPTIVE;
   c->last.accepted = cur.accepted;
   c->last.rejected = cur.rejected;
   c->last.rhs_evals = cur.rhs_evals + extra_evals;
   c->last.t = cur.t;
-  c->last.dt_next = init.mode == hode::MODE_ADAPTIVE ? cur.dt : cur.h;
+  c->last.dt_next = hode::mode_adaptive(init.mode) ? cur.dt : cur.h;
   c->last.last_err = cur.last_err;
   c->last.status = cur.status;
   c->last_attempts = cur.attempts;
@@ -563,10 +577,13 @@ int hode_set_controller(hode_ctx* c, int kind, const void* weights, size_t nbyte
 int hode_integrate_n_steps(hode_ctx* c, int method, double t0, double dt, int64_t n, double* t_end) {
   int rc = check_ready(c);
   if (rc) return rc;
-  if (method != HODE_RK4 && method != HODE_DOPRI5) return fail(c, HODE_EINVAL, "method");
+  if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54)
+    return fail(c, HODE_EINVAL, "method");
   if (n < 0 || !std::isfinite(t0) || !std::isfinite(dt)) return fail(c, HODE_EINVAL, "bad step arguments");
   HIPCHK(c, hipSetDevice(c->device));
-  const int mode = method == HODE_RK4 ? hode::MODE_FIXED_RK4 : hode::MODE_FIXED_DP5;
+  const int mode = method == HODE_RK4    ? hode::MODE_FIXED_RK4
+                   : method == HODE_DOPRI5 ? hode::MODE_FIXED_DP5
+                                           : hode::MODE_FIXED_CK;
   DevCtrl d = base_ctrl(c, mode);
   d.t = d.t0 = t0;
   d.h = d.dt = dt;
@@ -589,7 +606,7 @@ int hode_integrate_adaptive(hode_ctx* c, double t0, double t1, double dt0, int64
   if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0) || !(dt0 > 0) || !std::isfinite(dt0) || max_steps < 0)
     return fail(c, HODE_EINVAL, "bad integration arguments");
   HIPCHK(c, hipSetDevice(c->device));
-  DevCtrl d = base_ctrl(c, hode::MODE_ADAPTIVE);
+  DevCtrl d = base_ctrl(c, adaptive_mode(c));
   d.t = d.t0 = t0;
   d.t1 = t1;
   d.dt = dt0;
@@ -606,7 +623,7 @@ int hode_integrate_adaptive(hode_ctx* c, double t0, double t1, double dt0, int64
     d.done = 1;
     d.status = hode::ST_EDT_UNDERFLOW;
   }
-  rc = run_loop(c, d, !c->k1_valid);
+  rc = run_loop(c, d, c->stepper == HODE_DOPRI5 && !c->k1_valid);
   if (rc) return rc;
   c->persist_valid = false;
   if (out) *out = c->last;
@@ -619,7 +636,7 @@ int hode_try_step(hode_ctx* c, double* t, double* dt, int* accepted) {
   if (!t || !dt || !accepted || !std::isfinite(*t) || !(*dt > 0) || !std::isfinite(*dt))
     return fail(c, HODE_EINVAL, "bad try_step arguments");
   HIPCHK(c, hipSetDevice(c->device));
-  DevCtrl d = base_ctrl(c, hode::MODE_ADAPTIVE);
+  DevCtrl d = base_ctrl(c, adaptive_mode(c));
   if (c->persist_valid) {
     d.err_prev = c->persist.err_prev;
     d.last_rejected = c->persist.last_rejected;
@@ -636,7 +653,7 @@ int hode_try_step(hode_ctx* c, double* t, double* dt, int* accepted) {
   d.dt = *dt;
   d.last_flag = 1;
   d.max_attempts = 1;
-  rc = run_loop(c, d, !c->k1_valid);
+  rc = run_loop(c, d, c->stepper == HODE_DOPRI5 && !c->k1_valid);
   if (rc) return rc;
   c->persist_valid = true;
   *accepted = c->last.accepted > 0;
@@ -768,12 +785,17 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
   return HODE_OK;
 }
 
-// Stage sequence of one attempt of `method` (adaptive Dopri5 for HODE_DOPRI5).
+// Stage sequence of one attempt of `method` (adaptive for the embedded pairs).
 static int stage_seq(int method, int* seq) {
   if (method == HODE_RK4) {
     const int s[] = {hode::K_D1, hode::K_R2, hode::K_R3, hode::K_R4};
     for (int i = 0; i < 4; ++i) seq[i] = s[i];
     return 4;
+  }
+  if (method == HODE_CASHKARP54) {
+    const int s[] = {hode::K_D1, hode::K_D2, hode::K_D3, hode::K_C4, hode::K_C5, hode::K_C6};
+    for (int i = 0; i < 6; ++i) seq[i] = s[i];
+    return 6;
   }
   const int s[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6, hode::K_D7};
   for (int i = 0; i < 6; ++i) seq[i] = s[i];
@@ -784,7 +806,8 @@ int hode_profile_attempt(hode_ctx* c, int method, int reps, double* ms) {
   int rc = check_ready(c);
   if (rc) return rc;
   if (!is_gs(c)) return fail(c, HODE_EINVAL, "stage profiling is for the Gray-Scott path");
-  if (reps < 1 || !ms || (method != HODE_RK4 && method != HODE_DOPRI5)) return fail(c, HODE_EINVAL, "arguments");
+  if (reps < 1 || !ms || (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54))
+    return fail(c, HODE_EINVAL, "arguments");
   HIPCHK(c, hipSetDevice(c->device));
   int seq[8];
   const int ns = stage_seq(method, seq);
@@ -825,7 +848,7 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   int rc = check_ready(c);
   if (rc) return rc;
   if (!is_gs(c)) return fail(c, HODE_EINVAL, "autotuning is for the Gray-Scott path");
-  if (method != HODE_RK4 && method != HODE_DOPRI5) return fail(c, HODE_EINVAL, "method");
+  if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54) return fail(c, HODE_EINVAL, "method");
   const int rys[] = {1, 2, 4};
   // plane chunks: powers of two, and the even splits of the grid into 1 .. 12
   // chunks (block counts that fill whole rounds of resident workgroups)
@@ -867,13 +890,26 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
     c->kry[hode::K_D7F] = c->kry[hode::K_D7];
     c->kzc[hode::K_D7F] = c->kzc[hode::K_D7];
   }
-  const int widest = method == HODE_RK4 ? hode::K_R4 : hode::K_D6;
+  if (method == HODE_CASHKARP54) {
+    c->kry[hode::K_C6F] = c->kry[hode::K_C6];
+    c->kzc[hode::K_C6F] = c->kzc[hode::K_C6];
+  }
+  const int widest = method == HODE_RK4 ? hode::K_R4 : (method == HODE_CASHKARP54 ? hode::K_C6 : hode::K_D6);
   c->ry = c->kry[widest];
   c->zc = c->kzc[widest];
   clear_graphs(c);
   if (best_ry) *best_ry = c->ry;
   if (best_zc) *best_zc = c->zc;
   if (best_ms) *best_ms = tot;
+  return HODE_OK;
+}
+
+int hode_set_stepper(hode_ctx* c, int method) {
+  if (!c) return HODE_EINVAL;
+  if (method != HODE_DOPRI5 && method != HODE_CASHKARP54) return fail(c, HODE_EINVAL, "adaptive stepper: Dopri5 or Cash-Karp");
+  if (c->ens) return fail(c, HODE_EINVAL, "the ensemble steps with Dopri5");
+  c->stepper = method;
+  c->persist_valid = false;
   return HODE_OK;
 }
 

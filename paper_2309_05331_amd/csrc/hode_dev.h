@@ -18,7 +18,12 @@
 
 namespace hode {
 
-enum Mode : int32_t { MODE_FIXED_RK4 = 1, MODE_FIXED_DP5 = 2, MODE_ADAPTIVE = 3 };
+enum Mode : int32_t {
+  MODE_FIXED_RK4 = 1, MODE_FIXED_DP5 = 2, MODE_ADAPTIVE = 3,  // RK4, Dopri5 fixed, Dopri5 adaptive
+  MODE_FIXED_CK = 4, MODE_ADAPTIVE_CK = 5                     // Cash-Karp 5(4) fixed, adaptive
+};
+
+__host__ __device__ constexpr bool mode_adaptive(int m) { return m == MODE_ADAPTIVE || m == MODE_ADAPTIVE_CK; }
 enum CtrlKind : int32_t { CTRL_PI = 1, CTRL_I = 2, CTRL_MLP = 3 };
 enum Status : int32_t {
   ST_OK = 0,
@@ -300,7 +305,7 @@ __device__ inline void ctrl_step(DevCtrl* c) {
     // atomics too, so this stays coherent with them when the controller
     // runs inside the same workgroup that produced them
     const uint64_t bits = atomicExch((unsigned long long*)&c->errmax_bits, 0ull);
-    s_adaptive = c->mode == MODE_ADAPTIVE;
+    s_adaptive = mode_adaptive(c->mode);
     if (s_adaptive) decide_a(c, __longlong_as_double((long long)bits), &s);
     else if (c->mode != 0) fixed_step_done(c);  // mode 0: timing runs change nothing
   }

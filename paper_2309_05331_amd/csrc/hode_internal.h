@@ -14,8 +14,12 @@ namespace hode {
 // and the partial error sum (D6F: new state only); D7 evaluates k7 = f(ynew)
 // and completes the error norm (D7F: k7 only).  The control kernel follows the
 // final stage of every attempt.
+// Stage kernels: RK4 (D1 R2 R3 R4), Dopri5 (D1 D2 .. D7; D7F, D6F fixed
+// step) and Cash-Karp 5(4) (D1 D2 D3 share the Dopri5 stage shapes and
+// coefficients; C4 C5, then C6 = stage 6 with new state and error norm, C6F
+// its fixed-step form).
 enum GSKind : int {
-  K_D1 = 0, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_COUNT,
+  K_D1 = 0, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_C4, K_C5, K_C6, K_C6F, K_COUNT,
   K_D6F = K_COUNT  // fixed-step stage 6: the new state only
 };
 
@@ -35,7 +39,7 @@ hipError_t launch_gs(int kind, int dtype, int ry, int vw, const GSLaunch& a, Dev
 bool gs_ry_supported(int ry);
 
 // Element-wise families: the whole step runs in registers (one kernel per
-// attempt).  mode: MODE_FIXED_RK4, MODE_FIXED_DP5 or MODE_ADAPTIVE.
+// attempt).  mode: one of the Mode values (RK4, Dopri5 or Cash-Karp; fixed or adaptive).
 hipError_t launch_ew(int dtype, int rhs, int mode, void* y0, void* y1, int64_t n, int grid, DevCtrl* c,
                      hipStream_t s);
 

@@ -47,7 +47,7 @@ struct KindDesc {
   int extra[2];
   int out;         // array receiving f(stage input), -1 none
   int fin;         // own-cell finish: 0 none, 1 RK4 new state, 2 Dopri5 new state (+ partial error),
-                   // 3 Dopri5 error completion
+                   // 3 Dopri5 error completion, 4 Cash-Karp new state (+ error norm)
   bool err;        // error norm computed
 };
 
@@ -56,6 +56,13 @@ constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0, B5 
 constexpr double D1 = 35.0 / 384.0 - 5179.0 / 57600.0, D3 = 500.0 / 1113.0 - 7571.0 / 16695.0,
                  D4 = 125.0 / 192.0 - 393.0 / 640.0, D5 = -2187.0 / 6784.0 + 92097.0 / 339200.0,
                  D6 = 11.0 / 84.0 - 187.0 / 2100.0, D7 = -1.0 / 40.0;
+
+// Cash-Karp 5(4) (Cash & Karp 1990): 5th-order weights CB (b2 = b5 = 0) and
+// CE = b - bhat (the embedded estimate's weights; CE2 = 0).
+constexpr double CB1 = 37.0 / 378.0, CB3 = 250.0 / 621.0, CB4 = 125.0 / 594.0, CB6 = 512.0 / 1771.0;
+constexpr double CE1 = 37.0 / 378.0 - 2825.0 / 27648.0, CE3 = 250.0 / 621.0 - 18575.0 / 48384.0,
+                 CE4 = 125.0 / 594.0 - 13525.0 / 55296.0, CE5 = -277.0 / 14336.0,
+                 CE6 = 512.0 / 1771.0 - 1.0 / 4.0;
 
 constexpr KindDesc kDesc[K_COUNT] = {
     /* D1  */ {1, {A_Y}, {0}, 0, {0, 0}, A_K1, 0, false},
@@ -73,6 +80,15 @@ constexpr KindDesc kDesc[K_COUNT] = {
                -1, 2, true},
     /* D7  */ {1, {A_YN}, {0}, 2, {A_E6, A_Y}, A_K7, 3, true},
     /* D7F */ {1, {A_YN}, {0}, 0, {0, 0}, A_K7, 0, false},
+    /* C4  */ {4, {A_Y, A_K1, A_K2, A_K3}, {0, 3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0}, 0, {0, 0}, A_K4, 0, false},
+    /* C5  */ {5, {A_Y, A_K1, A_K2, A_K3, A_K4}, {0, -11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0}, 0, {0, 0},
+               A_K5, 0, false},
+    /* C6  */ {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
+               {0, 1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}, 0, {0, 0},
+               -1, 4, true},
+    /* C6F */ {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
+               {0, 1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}, 0, {0, 0},
+               -1, 4, false},
 };
 // D6 in fixed-step mode: the new state only (no partial error).
 constexpr KindDesc kD6F = {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
@@ -211,7 +227,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 #pragma unroll
   for (int i = 0; i < D.nx; ++i) ext[i] = array_ptr<T>(a, D.extra[i], p, ksl);
   T* out = D.out >= 0 ? array_ptr<T>(a, D.out, p, ksl) : nullptr;
-  T* ynew = (D.fin == 1 || D.fin == 2) ? (T*)a.y[p ^ 1] : nullptr;
+  T* ynew = (D.fin == 1 || D.fin == 2 || D.fin == 4) ? (T*)a.y[p ^ 1] : nullptr;
   T* e6 = (D.fin == 2 && D.err) ? (T*)a.k[A_E6] : nullptr;
 
   T cf[6];
@@ -224,6 +240,8 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   const T b16 = (T)(h * (1.0 / 6.0)), b13 = (T)(h * (1.0 / 3.0));
   const T q1 = (T)(h * B1), q3 = (T)(h * B3), q4 = (T)(h * B4), q5 = (T)(h * B5), q6 = (T)(h * B6);
   const double h1 = h * D1, h3 = h * D3, h4 = h * D4, h5 = h * D5, h6 = h * D6, h7 = h * D7;
+  const T cq1 = (T)(h * CB1), cq3 = (T)(h * CB3), cq4 = (T)(h * CB4), cq6 = (T)(h * CB6);
+  const double ce1 = h * CE1, ce3 = h * CE3, ce4 = h * CE4, ce5 = h * CE5, ce6 = h * CE6;
 
   // ---- offsets (periodic wrap folded in)
   const int xl = x0 + VW * jl;
@@ -254,8 +272,8 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   // stage 7 the stored partial error and y.
   struct Fin {
     T a[VW];
-    double e[(D.fin == 2 && D.err) ? VW : 1];
-    T b[D.fin == 3 ? VW : 1];
+    double e[((D.fin == 2 || D.fin == 4) && D.err) ? VW : 1];
+    T b[(D.fin == 3 || (D.fin == 4 && D.err)) ? VW : 1];
   };
 
   auto stage_in = [&](int64_t g, Fin* fin) -> P {
@@ -283,6 +301,14 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
           if constexpr (D.err)
             fin->e[e] = h1 * (double)s[1].v[e] + h3 * (double)s[3].v[e] + h4 * (double)s[4].v[e] +
                         h5 * (double)s[5].v[e];
+        } else if constexpr (D.fin == 4) {
+          // sources y, k1 .. k5: Cash-Karp new state and error without k6
+          fin->a[e] = s[0].v[e] + cq1 * s[1].v[e] + cq3 * s[3].v[e] + cq4 * s[4].v[e];
+          if constexpr (D.err) {
+            fin->e[e] = ce1 * (double)s[1].v[e] + ce3 * (double)s[3].v[e] + ce4 * (double)s[4].v[e] +
+                        ce5 * (double)s[5].v[e];
+            fin->b[e] = s[0].v[e];
+          }
         } else {
           // source ynew; extras partial error, y
           fin->a[e] = x[0].v[e];
@@ -444,6 +470,25 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
             stv<T, VW>(ynew, f * n3 + g, yn);
             if constexpr (D.err) stv<T, VW>(e6, f * n3 + g, ep);
           }
+        } else if constexpr (D.fin == 4) {
+          // Cash-Karp new state y + h sum b_j k_j and, adaptive, the error
+          // |h sum (b_j - bhat_j) k_j| / (atol + rtol max(|y|, |ynew|))
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            P yn;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) yn.v[e] = fc[f][r].a[e] + cq6 * fo[f].v[e];
+            stv<T, VW>(ynew, f * n3 + g, yn);
+            if constexpr (D.err) {
+#pragma unroll
+              for (int e = 0; e < VW; ++e) {
+                const double err = fc[f][r].e[e] + ce6 * (double)fo[f].v[e];
+                const double sc = atol + rtol * fmax(fabs((double)fc[f][r].b[e]), fabs((double)yn.v[e]));
+                const uint64_t bits = (uint64_t)__double_as_longlong(fabs(err) / sc);
+                emax = bits > emax ? bits : emax;
+              }
+            }
+          }
         } else if constexpr (D.fin == 3) {
           // Dopri5 error completion: |E6 + h d7 k7| / (atol + rtol max(|y|, |ynew|))
 #pragma unroll
@@ -472,7 +517,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
     }
   }
 
-  if constexpr (D.err && D.fin == 3) {
+  if constexpr (D.err && (D.fin == 3 || D.fin == 4)) {
     emax = wave_max_u64(emax);
     if (lane == 0 && emax) atomicMax((unsigned long long*)&c->errmax_bits, (unsigned long long)emax);
   }
