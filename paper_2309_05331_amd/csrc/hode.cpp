@@ -106,15 +106,15 @@ int fail(hode_ctx* c, int code, const std::string& msg) {
 bool is_gs(const hode_ctx* c) { return c->rhs == HODE_RHS_GRAYSCOTT3D; }
 
 void clear_graphs(hode_ctx* c) {
-  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
 }
 
 void free_state(hode_ctx* c) {
   clear_graphs(c);
-  for (void*& p : c->y) { if (p) hipFree(p); p = nullptr; }
-  for (void*& p : c->ks) { if (p) hipFree(p); p = nullptr; }
-  for (void*& p : c->k) { if (p) hipFree(p); p = nullptr; }
+  for (void*& p : c->y) { if (p) (void)hipFree(p); p = nullptr; }
+  for (void*& p : c->ks) { if (p) (void)hipFree(p); p = nullptr; }
+  for (void*& p : c->k) { if (p) (void)hipFree(p); p = nullptr; }
   c->nelem = 0;
   c->N = 0;
   c->dtype = 0;
@@ -206,11 +206,11 @@ int get_graph(hode_ctx* c, int mode, int M, hipGraphExec_t* out) {
   hipError_t le = hipSuccess;
   for (int i = 0; i < M && le == hipSuccess; ++i) le = enqueue_attempt(c, mode);
   hipError_t ee = hipStreamEndCapture(c->stream, &g);
-  if (le != hipSuccess) { if (g) hipGraphDestroy(g); return fail(c, HODE_EHIP, std::string("capture: ") + hipGetErrorString(le)); }
+  if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return fail(c, HODE_EHIP, std::string("capture: ") + hipGetErrorString(le)); }
   if (ee != hipSuccess) return fail(c, HODE_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
   hipGraphExec_t ex = nullptr;
   hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (ie != hipSuccess) return fail(c, HODE_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
   c->graphs[key] = ex;
   *out = ex;
@@ -322,14 +322,14 @@ int check_ready(hode_ctx* c) {
 void free_ensemble(hode_ctx* c) {
   Ensemble* e = c ? c->ens : nullptr;
   if (!e) return;
-  if (e->graph) hipGraphExecDestroy(e->graph);
-  if (e->pool) hipFree(e->pool);
-  if (e->d_inst) hipFree(e->d_inst);
-  if (e->d_tiles) hipFree(e->d_tiles);
-  if (e->d_sync) hipFree(e->d_sync);
-  if (e->d_trace) hipFree(e->d_trace);
+  if (e->graph) (void)hipGraphExecDestroy(e->graph);
+  if (e->pool) (void)hipFree(e->pool);
+  if (e->d_inst) (void)hipFree(e->d_inst);
+  if (e->d_tiles) (void)hipFree(e->d_tiles);
+  if (e->d_sync) (void)hipFree(e->d_sync);
+  if (e->d_trace) (void)hipFree(e->d_trace);
   for (hipEvent_t& v : e->ev)
-    if (v) hipEventDestroy(v);
+    if (v) (void)hipEventDestroy(v);
   delete e;
   c->ens = nullptr;
 }
@@ -437,16 +437,16 @@ int hode_create(hode_ctx** out, int device, void* stream) {
 
 void hode_destroy(hode_ctx* c) {
   if (!c) return;
-  hipSetDevice(c->device);
-  if (c->stream) hipStreamSynchronize(c->stream);
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_state(c);
-  if (c->d_ctrl) hipFree(c->d_ctrl);
-  if (c->d_ctrl_save) hipFree(c->d_ctrl_save);
-  if (c->h_ctrl) hipHostFree(c->h_ctrl);
-  if (c->d_trace) hipFree(c->d_trace);
-  if (c->d_mlp) hipFree(c->d_mlp);
+  if (c->d_ctrl) (void)hipFree(c->d_ctrl);
+  if (c->d_ctrl_save) (void)hipFree(c->d_ctrl_save);
+  if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+  if (c->d_trace) (void)hipFree(c->d_trace);
+  if (c->d_mlp) (void)hipFree(c->d_mlp);
   free_ensemble(c);
-  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -670,7 +670,7 @@ int hode_get_stats(hode_ctx* c, hode_stats* out) {
 
 int hode_set_trace(hode_ctx* c, int64_t capacity) {
   if (!c || capacity < 0) return HODE_EINVAL;
-  if (c->d_trace) { hipFree(c->d_trace); c->d_trace = nullptr; }
+  if (c->d_trace) { (void)hipFree(c->d_trace); c->d_trace = nullptr; }
   c->trace_cap = 0;
   if (capacity > 0) {
     if (hipMalloc(&c->d_trace, sizeof(double) * hode::TRACE_W * (size_t)capacity) != hipSuccess)
@@ -777,8 +777,8 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(c, HODE_EHIP, std::string("timing: ") + hipGetErrorString(e));
   *avg_ms = (double)ms / reps;
   if (is_gs(c) && kind == hode::K_D1) c->k1_valid = true;
@@ -838,7 +838,7 @@ int hode_profile_attempt(hode_ctx* c, int method, int reps, double* ms) {
       acc[i] += t;
     }
   }
-  for (int i = 0; i <= ns; ++i) hipEventDestroy(ev[i]);
+  for (int i = 0; i <= ns; ++i) (void)hipEventDestroy(ev[i]);
   HIPCHK(c, e);
   for (int i = 0; i < ns; ++i) ms[i] = acc[i] / reps;
   return HODE_OK;
@@ -991,10 +991,15 @@ int hode_ensemble_create(hode_ctx** out, int device, void* stream, int n, const 
     *out = nullptr;
     return HODE_ENOMEM;
   }
+  // the persistent grid: every workgroup resident at once (grid barriers)
   const int bpc = hode::ensemble_blocks_per_cu(dtype);
   int cus = 0;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-  e->nwg = std::max(1, bpc) * std::max(1, cus);
+  if (bpc < 1 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) {
+    hode_destroy(c);
+    *out = nullptr;
+    return HODE_EHIP;
+  }
+  e->nwg = bpc * cus;
   if (hipEventCreate(&e->ev[0]) != hipSuccess || hipEventCreate(&e->ev[1]) != hipSuccess) {
     hode_destroy(c);
     *out = nullptr;
@@ -1060,7 +1065,7 @@ int hode_ensemble_set_trace(hode_ctx* c, int64_t capacity) {
   if (rc) return rc;
   if (capacity < 0) return fail(c, HODE_EINVAL, "capacity");
   Ensemble* e = c->ens;
-  if (e->d_trace) { hipFree(e->d_trace); e->d_trace = nullptr; }
+  if (e->d_trace) { (void)hipFree(e->d_trace); e->d_trace = nullptr; }
   e->trace_cap = 0;
   if (capacity > 0) {
     if (hipMalloc(&e->d_trace, sizeof(double) * hode::TRACE_W * (size_t)capacity * e->n) != hipSuccess)
@@ -1149,8 +1154,8 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
   // bookkeeping block and tile buffer (the captured graph holds their addresses)
   const int max_rounds = std::max(e->epoch_first, e->epoch_len);
   if (!e->d_sync || e->sync_rounds < max_rounds) {
-    if (e->graph) { hipGraphExecDestroy(e->graph); e->graph = nullptr; }
-    if (e->d_sync) hipFree(e->d_sync);
+    if (e->graph) { (void)hipGraphExecDestroy(e->graph); e->graph = nullptr; }
+    if (e->d_sync) (void)hipFree(e->d_sync);
     e->d_sync = nullptr;
     if (hipMalloc(&e->d_sync, SyncLayout(max_rounds).bytes) != hipSuccess)
       return fail(c, HODE_ENOMEM, "ensemble bookkeeping allocation failed");
@@ -1171,8 +1176,8 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     const int rounds = launch == 0 ? e->epoch_first : e->epoch_len;
     build_tiles(*e, e->nwg, active, tiles, qoff);
     if (tiles.size() > e->tiles_cap) {
-      if (e->graph) { hipGraphExecDestroy(e->graph); e->graph = nullptr; }
-      if (e->d_tiles) hipFree(e->d_tiles);
+      if (e->graph) { (void)hipGraphExecDestroy(e->graph); e->graph = nullptr; }
+      if (e->d_tiles) (void)hipFree(e->d_tiles);
       e->d_tiles = nullptr;
       e->tiles_cap = std::max(tiles.size(), (size_t)1024);
       if (hipMalloc(&e->d_tiles, sizeof(hode::EnsTile) * e->tiles_cap) != hipSuccess)
@@ -1208,11 +1213,11 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
       hipError_t le = hode::launch_ensemble(e->dtype, e->d_inst, sch, e->nwg, c->stream);
       hipError_t ee = hipStreamEndCapture(c->stream, &g);
       if (le != hipSuccess || ee != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return fail(c, HODE_EHIP, std::string("ensemble capture: ") + hipGetErrorString(le != hipSuccess ? le : ee));
       }
       hipError_t ie = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       HIPCHK(c, ie);
     }
     HIPCHK(c, hipEventRecord(e->ev[0], c->stream));
