@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "hode_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 EXP, LOGISTIC, GRAYSCOTT = 1, 2, 3
-RK4, DOPRI5, CASHKARP = 1, 2, 3
+RK4, DOPRI5, CASHKARP, EULER = 1, 2, 3, 4
 CTRL_PI, CTRL_I = 1, 2
 OK, EINVAL, EDT_UNDERFLOW, EMAXSTEPS, ENONFINITE = 0, -1, -5, -6, -7
 

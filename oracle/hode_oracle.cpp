@@ -11,8 +11,9 @@
 // combined by an *Algebra* (linear combinations of states); adaptive steppers
 // bound the error with the L-infinity norm of the embedded error estimate.
 //
-//  * Steppers: classical Runge-Kutta 4, Runge-Kutta-Dopri 5 and Runge-Kutta
-//    Cash-Karp 5(4) (the paper's Table 1, fixed and dynamic step size).
+//  * Steppers: explicit Euler, classical Runge-Kutta 4, Runge-Kutta-Dopri 5
+//    and Runge-Kutta Cash-Karp 5(4) (the paper's Table 1, fixed and dynamic
+//    step size).
 //    Tableaux: Kutta 1901, Dormand & Prince 1980 (Hairer, Norsett & Wanner,
 //    Solving ODEs I, Table II.5.2) and Cash & Karp 1990 (ACM TOMS 16, 201).
 //    Dopri 5 is first-same-as-last: k7 of an accepted step is k1 of the next;
@@ -45,7 +46,7 @@
 extern "C" {
 
 enum { ORC_EXP = 1, ORC_LOGISTIC = 2, ORC_GRAYSCOTT = 3 };
-enum { ORC_RK4 = 1, ORC_DOPRI5 = 2, ORC_CASHKARP = 3 };
+enum { ORC_RK4 = 1, ORC_DOPRI5 = 2, ORC_CASHKARP = 3, ORC_EULER = 4 };
 enum { ORC_CTRL_PI = 1, ORC_CTRL_I = 2 };
 enum {
   ORC_OK = 0,
@@ -208,6 +209,15 @@ struct Work {
   std::vector<double> w;
   explicit Work(int64_t n, int nk) : k(nk, std::vector<double>(n)), w(n) {}
 };
+
+// One explicit Euler step in place: y += h f(y).
+void euler_step(const orc_system& s, double* y, double h, Work& W) {
+  const int64_t n = s.n;
+  rhs(s, y, W.k[0].data());
+  const double* k = W.k[0].data();
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) y[i] = y[i] + h * k[i];
+}
 
 // One classical RK4 step in place.
 void rk4_step(const orc_system& s, double* y, double h, Work& W) {
@@ -381,10 +391,14 @@ int orc_cashkarp_attempt(const orc_system* s, const double* y, double h, double*
 // Fixed steps: t_n = t0 + n dt (Odeint integrate_const / do_step).
 int orc_integrate_n_steps(const orc_system* s, int method, double* y, double t0, double dt, int64_t nsteps,
                           double* t_end) {
-  if (!valid(s) || nsteps < 0 || !(method == ORC_RK4 || method == ORC_DOPRI5 || method == ORC_CASHKARP))
+  if (!valid(s) || nsteps < 0 ||
+      !(method == ORC_RK4 || method == ORC_DOPRI5 || method == ORC_CASHKARP || method == ORC_EULER))
     return ORC_EINVAL;
   const int64_t n = s->n;
-  if (method == ORC_RK4) {
+  if (method == ORC_EULER) {
+    Work W(n, 1);
+    for (int64_t i = 0; i < nsteps; ++i) euler_step(*s, y, dt, W);
+  } else if (method == ORC_RK4) {
     Work W(n, 4);
     for (int64_t i = 0; i < nsteps; ++i) rk4_step(*s, y, dt, W);
   } else if (method == ORC_CASHKARP) {

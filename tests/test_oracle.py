@@ -195,6 +195,19 @@ def test_cashkarp_one_step_amplification_and_error(orc, h):
     assert np.all(np.abs(e - E * x0) <= tol)
 
 
+@pytest.mark.parametrize("h", [0.05, 0.3, -0.7])
+def test_euler_amplification_and_logistic_step(orc, h):
+    # explicit Euler multiplies x' = x by exactly 1 + h per step (one
+    # rounding); on the logistic family one step is x + h x (1 - x)
+    x0 = inputs.exp_family_x0(257, seed=14)
+    y, _ = orc.integrate_n_steps(orc.ew_system(orc.EXP, x0.size), orc.EULER, x0, 0.0, h, 1)
+    assert np.array_equal(y, x0 + h * x0)
+    y, _ = orc.integrate_n_steps(orc.ew_system(orc.LOGISTIC, x0.size), orc.EULER, x0, 0.0, h, 1)
+    assert np.array_equal(y, x0 + h * (x0 * (1.0 - x0)))
+    y3, _ = orc.integrate_n_steps(orc.ew_system(orc.EXP, x0.size), orc.EULER, x0, 0.0, h, 3)
+    assert np.allclose(y3, (1 + h) ** 3 * x0, rtol=1e-15, atol=0)
+
+
 # -------------------------------------------------- closed forms, order
 
 def _closed(kind, x0, t):
@@ -204,7 +217,7 @@ def _closed(kind, x0, t):
 
 
 @pytest.mark.parametrize("kind", [1, 2])
-@pytest.mark.parametrize("method,order", [(1, 4), (2, 5), (3, 5)])
+@pytest.mark.parametrize("method,order", [(1, 4), (2, 5), (3, 5), (4, 1)])
 def test_fixed_step_convergence_order(orc, kind, method, order):
     x0 = inputs.exp_family_x0(4096, seed=2)
     sysd = orc.ew_system(kind, x0.size)
