@@ -40,9 +40,10 @@ GS_PRM = [2e-5, 1e-5, 0.053, 0.014, 2.5]
 #   D4: y,k1..k3 -> k4               D5: y,k1..k4 -> k5
 #   D6: y,k1..k5 -> ynew, partial error                D7: ynew,partial error,y -> k7
 #   Cash-Karp: D1 D2 D3 (shared), C4: y,k1..k3 -> k4   C5: y,k1..k4 -> k5   C6: y,k1..k5 -> ynew (+ error norm)
-GS_ARRAYS = {0: 2, 1: 3, 2: 3, 3: 5, 4: 3, 5: 4, 6: 5, 7: 6, 8: 8, 9: 4, 10: 2, 11: 5, 12: 6, 13: 7, 14: 7, 15: 7}
+GS_ARRAYS = {0: 2, 1: 3, 2: 3, 3: 5, 4: 3, 5: 4, 6: 5, 7: 6, 8: 8, 9: 4, 10: 2, 11: 5, 12: 6, 13: 7, 14: 7, 15: 2,
+             16: 7}
 GS_NAMES = {0: "D1", 1: "R2", 2: "R3", 3: "R4", 4: "D2", 5: "D3", 6: "D4", 7: "D5", 8: "D6", 9: "D7", 10: "D7F",
-            11: "C4", 12: "C5", 13: "C6", 14: "C6F", 15: "D6F"}
+            11: "C4", 12: "C5", 13: "C6", 14: "C6F", 15: "E1", 16: "D6F"}
 STAGES = {"rk4": [0, 1, 2, 3], "dp5": [4, 5, 6, 7, 8, 9], "ck54": [0, 4, 5, 11, 12, 13]}
 
 WORKLOADS = {

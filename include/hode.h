@@ -48,8 +48,9 @@ enum { HODE_F32 = 1, HODE_F64 = 2 };
 enum { HODE_RHS_EXP = 1, HODE_RHS_LOGISTIC = 2, HODE_RHS_GRAYSCOTT3D = 3 };
 /* Steppers (the paper's Table 1): classical Runge-Kutta 4; Dormand-Prince
  * 5(4) ("Dopri5", 7 stages, first same as last); Cash-Karp 5(4) (6 stages,
- * Cash & Karp 1990).  The embedded pairs carry the 5th-order solution. */
-enum { HODE_RK4 = 1, HODE_DOPRI5 = 2, HODE_CASHKARP54 = 3 };
+ * Cash & Karp 1990); explicit Euler (fixed steps only).  The embedded pairs
+ * carry the 5th-order solution. */
+enum { HODE_RK4 = 1, HODE_DOPRI5 = 2, HODE_CASHKARP54 = 3, HODE_EULER = 4 };
 enum { HODE_CTRL_PI = 1, HODE_CTRL_I = 2, HODE_CTRL_MLP = 3 };
 enum {
   HODE_OK = 0,
@@ -175,8 +176,8 @@ int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);  /* the widest stage's
  * for the widest that divides N (16-byte loads where possible). */
 int hode_set_vector_width(hode_ctx *ctx, int vw);
 
-/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..15 as D1,
- * R2, R3, R4, D2..D7, D7F, C4, C5, C6, C6F, D6F; element-wise: kind =
+/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..16 as D1,
+ * R2, R3, R4, D2..D7, D7F, C4, C5, C6, C6F, E1, D6F; element-wise: kind =
  * method) on the context's
  * stream with HIP events and returns the mean duration in milliseconds.
  * The state is left unchanged for Gray-Scott non-final kinds only. */

@@ -1,7 +1,7 @@
 // Whole-step kernel for the element-wise families of the accuracy benchmark:
 // exponential dx/dt = x and sigmoidal (logistic) dx/dt = x (1 - x), one
 // independent ODE per component.  With no spatial coupling every stage of a
-// step needs only the component itself, so the entire RK4 step, Dopri5
+// step needs only the component itself, so the entire Euler or RK4 step, Dopri5
 // attempt (7 stages, first same as last) or Cash-Karp 5(4) attempt (6
 // stages) runs in registers: each component is
 // read once and written once per attempt, and the embedded error's L-infinity
@@ -98,7 +98,9 @@ __device__ inline CKCoef<T> ck_coef(double h) {
 template <typename T, int RHS, int MODE>
 __device__ __forceinline__ T step_one(T x, const DPCoef<T>& q, const CKCoef<T>& ck, T r2, T r1, T r16, T r13,
                                       double atol, double rtol, uint64_t& emax) {
-  if constexpr (MODE == MODE_FIXED_CK || MODE == MODE_ADAPTIVE_CK) {
+  if constexpr (MODE == MODE_FIXED_EULER) {
+    return x + r1 * frhs<T, RHS>(x);
+  } else if constexpr (MODE == MODE_FIXED_CK || MODE == MODE_ADAPTIVE_CK) {
     const T k1 = frhs<T, RHS>(x);
     const T k2 = frhs<T, RHS>(x + ck.a21 * k1);
     const T k3 = frhs<T, RHS>(x + ck.a31 * k1 + ck.a32 * k2);
@@ -202,6 +204,7 @@ hipError_t launch_rhs(int mode, T* y0, T* y1, int64_t n, int grid, DevCtrl* c, h
   if (mode == MODE_FIXED_RK4) ew_step<T, RHS, MODE_FIXED_RK4><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else if (mode == MODE_FIXED_DP5) ew_step<T, RHS, MODE_FIXED_DP5><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else if (mode == MODE_FIXED_CK) ew_step<T, RHS, MODE_FIXED_CK><<<grid, 256, 0, s>>>(c, y0, y1, n);
+  else if (mode == MODE_FIXED_EULER) ew_step<T, RHS, MODE_FIXED_EULER><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else if (mode == MODE_ADAPTIVE_CK) ew_step<T, RHS, MODE_ADAPTIVE_CK><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else ew_step<T, RHS, MODE_ADAPTIVE><<<grid, 256, 0, s>>>(c, y0, y1, n);
   return hipGetLastError();

@@ -50,7 +50,7 @@ hipError_t launch_t(int kind, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
   case K: gs_stage<T, K, RY, VW><<<dim3((unsigned)grid), dim3(256), 0, s>>>(a, c); break;
     HODE_CASE(K_D1) HODE_CASE(K_R2) HODE_CASE(K_R3) HODE_CASE(K_R4) HODE_CASE(K_D2) HODE_CASE(K_D3)
     HODE_CASE(K_D4) HODE_CASE(K_D5) HODE_CASE(K_D6) HODE_CASE(K_D7) HODE_CASE(K_D7F) HODE_CASE(K_C4)
-    HODE_CASE(K_C5) HODE_CASE(K_C6) HODE_CASE(K_C6F) HODE_CASE(K_COUNT)
+    HODE_CASE(K_C5) HODE_CASE(K_C6) HODE_CASE(K_C6F) HODE_CASE(K_E1) HODE_CASE(K_COUNT)
 #undef HODE_CASE
     default: return hipErrorInvalidValue;
   }

@@ -184,12 +184,14 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
   // Cash-Karp: stages 1-3 have the Dopri5 shapes and coefficients
   static const int ckf[] = {hode::K_D1, hode::K_D2, hode::K_D3, hode::K_C4, hode::K_C5, hode::K_C6F};
   static const int cka[] = {hode::K_D1, hode::K_D2, hode::K_D3, hode::K_C4, hode::K_C5, hode::K_C6};
+  static const int eul[] = {hode::K_E1};
   const int* seq = mode == hode::MODE_FIXED_RK4   ? rk4
                    : mode == hode::MODE_FIXED_DP5 ? dp5f
                    : mode == hode::MODE_FIXED_CK  ? ckf
                    : mode == hode::MODE_ADAPTIVE_CK ? cka
+                   : mode == hode::MODE_FIXED_EULER ? eul
                                                     : dp5a;
-  const int ns = mode == hode::MODE_FIXED_RK4 ? 4 : 6;
+  const int ns = mode == hode::MODE_FIXED_RK4 ? 4 : (mode == hode::MODE_FIXED_EULER ? 1 : 6);
   for (int i = 0; i < ns; ++i) {
     hipError_t e = launch_stage(c, seq[i], a);
     if (e != hipSuccess) return e;
@@ -577,13 +579,14 @@ int hode_set_controller(hode_ctx* c, int kind, const void* weights, size_t nbyte
 int hode_integrate_n_steps(hode_ctx* c, int method, double t0, double dt, int64_t n, double* t_end) {
   int rc = check_ready(c);
   if (rc) return rc;
-  if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54)
+  if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54 && method != HODE_EULER)
     return fail(c, HODE_EINVAL, "method");
   if (n < 0 || !std::isfinite(t0) || !std::isfinite(dt)) return fail(c, HODE_EINVAL, "bad step arguments");
   HIPCHK(c, hipSetDevice(c->device));
-  const int mode = method == HODE_RK4    ? hode::MODE_FIXED_RK4
-                   : method == HODE_DOPRI5 ? hode::MODE_FIXED_DP5
-                                           : hode::MODE_FIXED_CK;
+  const int mode = method == HODE_RK4      ? hode::MODE_FIXED_RK4
+                   : method == HODE_DOPRI5   ? hode::MODE_FIXED_DP5
+                   : method == HODE_CASHKARP54 ? hode::MODE_FIXED_CK
+                                               : hode::MODE_FIXED_EULER;
   DevCtrl d = base_ctrl(c, mode);
   d.t = d.t0 = t0;
   d.h = d.dt = dt;

@@ -20,7 +20,8 @@ namespace hode {
 
 enum Mode : int32_t {
   MODE_FIXED_RK4 = 1, MODE_FIXED_DP5 = 2, MODE_ADAPTIVE = 3,  // RK4, Dopri5 fixed, Dopri5 adaptive
-  MODE_FIXED_CK = 4, MODE_ADAPTIVE_CK = 5                     // Cash-Karp 5(4) fixed, adaptive
+  MODE_FIXED_CK = 4, MODE_ADAPTIVE_CK = 5,                    // Cash-Karp 5(4) fixed, adaptive
+  MODE_FIXED_EULER = 6                                        // explicit Euler
 };
 
 __host__ __device__ constexpr bool mode_adaptive(int m) { return m == MODE_ADAPTIVE || m == MODE_ADAPTIVE_CK; }
@@ -195,7 +196,7 @@ __device__ inline void fixed_step_done(DevCtrl* c) {
   c->t = c->t0 + (double)c->accepted * c->h;
   c->parity ^= 1;
   c->k1slot ^= 1;
-  c->rhs_evals += (c->mode == MODE_FIXED_RK4) ? 4 : 6;
+  c->rhs_evals += c->mode == MODE_FIXED_RK4 ? 4 : (c->mode == MODE_FIXED_EULER ? 1 : 6);
   if (c->accepted >= c->nsteps) c->done = 1;
 }
 

@@ -15,11 +15,11 @@ namespace hode {
 // and completes the error norm (D7F: k7 only).  The control kernel follows the
 // final stage of every attempt.
 // Stage kernels: RK4 (D1 R2 R3 R4), Dopri5 (D1 D2 .. D7; D7F, D6F fixed
-// step) and Cash-Karp 5(4) (D1 D2 D3 share the Dopri5 stage shapes and
+// step), Cash-Karp 5(4) (D1 D2 D3 share the Dopri5 stage shapes and
 // coefficients; C4 C5, then C6 = stage 6 with new state and error norm, C6F
-// its fixed-step form).
+// its fixed-step form) and explicit Euler (E1: the new state y + h f(y)).
 enum GSKind : int {
-  K_D1 = 0, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_C4, K_C5, K_C6, K_C6F, K_COUNT,
+  K_D1 = 0, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_C4, K_C5, K_C6, K_C6F, K_E1, K_COUNT,
   K_D6F = K_COUNT  // fixed-step stage 6: the new state only
 };
 

@@ -47,7 +47,8 @@ struct KindDesc {
   int extra[2];
   int out;         // array receiving f(stage input), -1 none
   int fin;         // own-cell finish: 0 none, 1 RK4 new state, 2 Dopri5 new state (+ partial error),
-                   // 3 Dopri5 error completion, 4 Cash-Karp new state (+ error norm)
+                   // 3 Dopri5 error completion, 4 Cash-Karp new state (+ error norm),
+                   // 5 Euler new state
   bool err;        // error norm computed
 };
 
@@ -89,6 +90,7 @@ constexpr KindDesc kDesc[K_COUNT] = {
     /* C6F */ {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
                {0, 1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}, 0, {0, 0},
                -1, 4, false},
+    /* E1  */ {1, {A_Y}, {0}, 0, {0, 0}, -1, 5, false},
 };
 // D6 in fixed-step mode: the new state only (no partial error).
 constexpr KindDesc kD6F = {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
@@ -227,7 +229,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 #pragma unroll
   for (int i = 0; i < D.nx; ++i) ext[i] = array_ptr<T>(a, D.extra[i], p, ksl);
   T* out = D.out >= 0 ? array_ptr<T>(a, D.out, p, ksl) : nullptr;
-  T* ynew = (D.fin == 1 || D.fin == 2 || D.fin == 4) ? (T*)a.y[p ^ 1] : nullptr;
+  T* ynew = (D.fin == 1 || D.fin == 2 || D.fin == 4 || D.fin == 5) ? (T*)a.y[p ^ 1] : nullptr;
   T* e6 = (D.fin == 2 && D.err) ? (T*)a.k[A_E6] : nullptr;
 
   T cf[6];
@@ -241,6 +243,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   const T q1 = (T)(h * B1), q3 = (T)(h * B3), q4 = (T)(h * B4), q5 = (T)(h * B5), q6 = (T)(h * B6);
   const double h1 = h * D1, h3 = h * D3, h4 = h * D4, h5 = h * D5, h6 = h * D6, h7 = h * D7;
   const T cq1 = (T)(h * CB1), cq3 = (T)(h * CB3), cq4 = (T)(h * CB4), cq6 = (T)(h * CB6);
+  const T hT = (T)h;
   const double ce1 = h * CE1, ce3 = h * CE3, ce4 = h * CE4, ce5 = h * CE5, ce6 = h * CE6;
 
   // ---- offsets (periodic wrap folded in)
@@ -301,6 +304,9 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
           if constexpr (D.err)
             fin->e[e] = h1 * (double)s[1].v[e] + h3 * (double)s[3].v[e] + h4 * (double)s[4].v[e] +
                         h5 * (double)s[5].v[e];
+        } else if constexpr (D.fin == 5) {
+          // source y: Euler keeps the own cell's state for the new state
+          fin->a[e] = s[0].v[e];
         } else if constexpr (D.fin == 4) {
           // sources y, k1 .. k5: Cash-Karp new state and error without k6
           fin->a[e] = s[0].v[e] + cq1 * s[1].v[e] + cq3 * s[3].v[e] + cq4 * s[4].v[e];
@@ -469,6 +475,15 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
             }
             stv<T, VW>(ynew, f * n3 + g, yn);
             if constexpr (D.err) stv<T, VW>(e6, f * n3 + g, ep);
+          }
+        } else if constexpr (D.fin == 5) {
+          // Euler new state y + h f(y)
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            P yn;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) yn.v[e] = fc[f][r].a[e] + hT * fo[f].v[e];
+            stv<T, VW>(ynew, f * n3 + g, yn);
           }
         } else if constexpr (D.fin == 4) {
           // Cash-Karp new state y + h sum b_j k_j and, adaptive, the error

@@ -17,14 +17,14 @@ LIBPATH = os.path.join(HERE, "libhode.so")
 
 F32, F64 = 1, 2
 RHS_EXP, RHS_LOGISTIC, RHS_GRAYSCOTT3D = 1, 2, 3
-RK4, DOPRI5, CASHKARP54 = 1, 2, 3
+RK4, DOPRI5, CASHKARP54, EULER = 1, 2, 3, 4
 CTRL_PI, CTRL_I, CTRL_MLP = 1, 2, 3
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EDT_UNDERFLOW, EMAXSTEPS, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 TRACE_W = 24  # h, err, accepted, t after, dt next, PI log-ratio, learned log-ratio, landed, 16 features
 MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 
 # Gray-Scott stage kernels, as numbered by hode_time_kernel
-K_D1, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_C4, K_C5, K_C6, K_C6F, K_D6F = range(16)
+K_D1, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_C4, K_C5, K_C6, K_C6F, K_E1, K_D6F = range(17)
 
 
 class hode_stats(C.Structure):
