@@ -74,6 +74,8 @@ def lib():
         L.orc_integrate_replay.argtypes = [C.POINTER(System), P, C.c_double, P, P, C.c_int64,
                                            C.c_double, C.c_double, C.POINTER(C.c_double), P]
         L.orc_cashkarp_attempt.argtypes = [C.POINTER(System), P, C.c_double, P, P]
+        L.orc_integrate_times.argtypes = [C.POINTER(System), C.c_int, P, P, C.c_int64, C.c_double, C.c_double,
+                                          C.c_double, C.c_int, C.c_int64, P, C.POINTER(Stats)]
         L.orc_integrate_adaptive_m.argtypes = [C.POINTER(System), C.c_int, P, C.c_double, C.c_double, C.c_double,
                                                C.c_double, C.c_double, C.c_int, C.c_int64,
                                                C.POINTER(Stats), P, C.c_int64]
@@ -174,6 +176,20 @@ def integrate_adaptive(sysd: System, y, t0, t1, dt0, atol, rtol, ctrl=CTRL_PI, m
     stats = {f: getattr(st, f) for f, _ in Stats._fields_ if f != "pad"}
     n_att = stats["accepted"] + stats["rejected"]
     return y, stats, (tr[:min(n_att, trace_cap)] if trace_cap else None)
+
+
+def integrate_times(sysd: System, y, times, dt0, atol, rtol, ctrl=CTRL_PI, max_steps=10 ** 7, method=None):
+    """States at times[0], times[1], ... (rows of the returned array; rows
+    after a failing status stay zero) and the stats dict."""
+    y = _f64(y).ravel().copy()
+    times = _f64(times).ravel()
+    out = np.zeros((times.size, y.size))
+    st = Stats()
+    rc = lib().orc_integrate_times(C.byref(sysd), DOPRI5 if method is None else method, _ptr(y), _ptr(times),
+                                   times.size, dt0, atol, rtol, ctrl, max_steps, _ptr(out), C.byref(st))
+    if rc == EINVAL:
+        raise ValueError("integrate_times: invalid arguments (times must increase)")
+    return out, {f: getattr(st, f) for f, _ in Stats._fields_ if f != "pad"}
 
 
 def integrate_replay(sysd: System, y, t0, hs, accepted, atol=1e-6, rtol=1e-6, method=None):

@@ -425,55 +425,101 @@ int orc_integrate_n_steps(const orc_system* s, int method, double* y, double t0,
 // Error-controlled integration from t0 to t1 with an embedded pair (Dopri5 or
 // Cash-Karp; Odeint integrate_adaptive).  The trace, if given, receives 4
 // doubles per attempt: h, err, accepted (0/1), t after.
+// The state of an error-controlled integration that a run carries from one
+// end time to the next: the embedded pair's k1 (first same as last), the
+// proposed step, the controller and the counters.
+struct Adaptive {
+  const orc_system& s;
+  bool dp;
+  double atol, rtol;
+  Work W;
+  std::vector<double> k1, k7, ynew, e;
+  Ctrl c;
+  double dt, last_err = 0.0;
+  int64_t acc = 0, rej = 0, evals = 0, att = 0;
+  Adaptive(const orc_system& sys, int method, const double* y, double dt0, double a, double r, int ctrl_kind)
+      : s(sys), dp(method == ORC_DOPRI5), atol(a), rtol(r), W(sys.n, 7), k1(sys.n), k7(sys.n), ynew(sys.n),
+        e(sys.n), c(ctrl_kind), dt(dt0) {
+    if (dp) {
+      rhs(s, y, k1.data());
+      evals = 1;
+    }
+  }
+  // Advances y from *t to t1 (the last step clipped to land on t1); returns
+  // the status.  max_steps bounds the attempts of the whole run.
+  int advance(double* y, double* t, double t1, int64_t max_steps, double* trace, int64_t trace_cap) {
+    const int64_t n = s.n;
+    while (*t < t1) {
+      if (att >= max_steps) return ORC_EMAXSTEPS;
+      const bool last = dt >= t1 - *t;
+      const double h = last ? t1 - *t : dt;
+      if (h < 1e-12 * std::max(1.0, std::fabs(*t))) return std::isfinite(last_err) ? ORC_EDT_UNDERFLOW : ORC_ENONFINITE;
+      if (dp) dopri5_attempt(s, y, k1.data(), h, ynew.data(), k7.data(), e.data(), W);
+      else cashkarp_attempt(s, y, h, ynew.data(), e.data(), W);
+      evals += 6;
+      ++att;
+      const double err = err_norm(n, y, ynew.data(), e.data(), atol, rtol);
+      last_err = err;
+      double fac;
+      const bool ok = c.decide(err, &fac);
+      if (ok) {
+        std::swap_ranges(ynew.begin(), ynew.end(), y);
+        if (dp) k1.swap(k7);
+        *t = last ? t1 : *t + h;
+        ++acc;
+      } else {
+        ++rej;
+      }
+      dt = h * fac;
+      if (trace && att <= trace_cap) {
+        double* r = trace + 4 * (att - 1);
+        r[0] = h; r[1] = err; r[2] = ok ? 1.0 : 0.0; r[3] = *t;
+      }
+    }
+    return ORC_OK;
+  }
+  void stats(orc_stats* st, double t, int status) const {
+    if (!st) return;
+    st->accepted = acc; st->rejected = rej; st->rhs_evals = evals;
+    st->t = t; st->dt_next = dt; st->last_err = last_err; st->status = status;
+  }
+};
+
 int orc_integrate_adaptive_m(const orc_system* s, int method, double* y, double t0, double t1, double dt0,
                              double atol, double rtol, int ctrl_kind, int64_t max_steps, orc_stats* st,
                              double* trace, int64_t trace_cap) {
   if (!valid(s) || !(t1 >= t0) || !(dt0 > 0) || !(atol >= 0) || !(rtol >= 0) || (atol == 0 && rtol == 0) ||
       !(method == ORC_DOPRI5 || method == ORC_CASHKARP))
     return ORC_EINVAL;
-  const bool dp = method == ORC_DOPRI5;
+  Adaptive A(*s, method, y, dt0, atol, rtol, ctrl_kind);
+  double t = t0;
+  const int status = A.advance(y, &t, t1, max_steps, trace, trace_cap);
+  A.stats(st, t, status);
+  return status;
+}
+
+// Odeint integrate_times: the state at times[0] is the current one; the run
+// then advances to times[1], times[2], ... in turn, every step clipped to
+// land on them, carrying the proposed step, the controller and (Dopri5) k1
+// from one to the next, and out[i * n ..] receives the state at times[i].
+// Stops at the first failing status (max_steps bounds the whole run).
+int orc_integrate_times(const orc_system* s, int method, double* y, const double* times, int64_t nt, double dt0,
+                        double atol, double rtol, int ctrl_kind, int64_t max_steps, double* out, orc_stats* st) {
+  if (!valid(s) || nt < 1 || !(dt0 > 0) || !(atol >= 0) || !(rtol >= 0) || (atol == 0 && rtol == 0) ||
+      !(method == ORC_DOPRI5 || method == ORC_CASHKARP) || !out)
+    return ORC_EINVAL;
+  for (int64_t i = 1; i < nt; ++i)
+    if (!(times[i] > times[i - 1])) return ORC_EINVAL;
   const int64_t n = s->n;
-  Work W(n, 7);
-  std::vector<double> k1(n), k7(n), ynew(n), e(n);
-  if (dp) rhs(*s, y, k1.data());
-  Ctrl c(ctrl_kind);
-  double t = t0, dt = dt0, last_err = 0.0;
-  int64_t acc = 0, rej = 0, evals = dp ? 1 : 0, att = 0;
+  Adaptive A(*s, method, y, dt0, atol, rtol, ctrl_kind);
+  std::memcpy(out, y, sizeof(double) * n);
+  double t = times[0];
   int status = ORC_OK;
-  while (t < t1) {
-    if (att >= max_steps) { status = ORC_EMAXSTEPS; break; }
-    const bool last = dt >= t1 - t;
-    const double h = last ? t1 - t : dt;
-    if (h < 1e-12 * std::max(1.0, std::fabs(t))) {
-      status = std::isfinite(last_err) ? ORC_EDT_UNDERFLOW : ORC_ENONFINITE;
-      break;
-    }
-    if (dp) dopri5_attempt(*s, y, k1.data(), h, ynew.data(), k7.data(), e.data(), W);
-    else cashkarp_attempt(*s, y, h, ynew.data(), e.data(), W);
-    evals += 6;
-    ++att;
-    const double err = err_norm(n, y, ynew.data(), e.data(), atol, rtol);
-    last_err = err;
-    double fac;
-    const bool ok = c.decide(err, &fac);
-    if (ok) {
-      std::swap_ranges(ynew.begin(), ynew.end(), y);
-      if (dp) k1.swap(k7);
-      t = last ? t1 : t + h;
-      ++acc;
-    } else {
-      ++rej;
-    }
-    dt = h * fac;
-    if (trace && att <= trace_cap) {
-      double* r = trace + 4 * (att - 1);
-      r[0] = h; r[1] = err; r[2] = ok ? 1.0 : 0.0; r[3] = t;
-    }
+  for (int64_t i = 1; i < nt && status == ORC_OK; ++i) {
+    status = A.advance(y, &t, times[i], max_steps, nullptr, 0);
+    if (status == ORC_OK) std::memcpy(out + i * n, y, sizeof(double) * n);
   }
-  if (st) {
-    st->accepted = acc; st->rejected = rej; st->rhs_evals = evals;
-    st->t = t; st->dt_next = dt; st->last_err = last_err; st->status = status;
-  }
+  A.stats(st, t, status);
   return status;
 }
 

@@ -550,3 +550,24 @@ def test_periodic_window_reproduces_full_grid_centre(orc):
     ynw2, _, _ = orc.dopri5_attempt(small, orc.dopri5_attempt(small, yw, 0.3)[0], 0.3)
     cs = np.array([0, 1]) * Ws ** 3 + (Rs * Ws + Rs) * Ws + Rs
     assert np.max(np.abs(ynw2[cs] - yn_full2.reshape(2, N, N, N)[:, 20, 20, 20])) > 0
+
+
+@pytest.mark.parametrize("method", [2, 3])
+def test_integrate_times_closed_form_and_single_interval(orc, method):
+    # the states at the requested times follow the closed forms to the
+    # tolerance; with only [t0, t1] requested it is integrate_adaptive itself
+    x0 = inputs.exp_family_x0(512, seed=15)
+    times = [0.0, 0.37, 1.0, 2.5, 2.51, 5.0]
+    for kind in (1, 2):
+        sysd = orc.ew_system(kind, x0.size)
+        out, st = orc.integrate_times(sysd, x0, times, 0.01, 1e-8, 1e-8, method=method)
+        assert st["status"] == 0 and st["t"] == 5.0
+        assert np.array_equal(out[0], x0)
+        for i, t in enumerate(times):
+            exact = _closed(kind, x0, t)
+            assert np.max(np.abs(out[i] - exact) / (1 + np.abs(exact))) < 30e-8, (kind, t)
+        y1, st1, _ = orc.integrate_adaptive(sysd, x0, 0.0, 5.0, 0.01, 1e-8, 1e-8, method=method)
+        out1, st2 = orc.integrate_times(sysd, x0, [0.0, 5.0], 0.01, 1e-8, 1e-8, method=method)
+        assert np.array_equal(out1[1], y1) and st2["accepted"] == st1["accepted"]
+    with pytest.raises(ValueError):
+        orc.integrate_times(orc.ew_system(1, 4), x0[:4], [0.0, 1.0, 1.0], 0.01, 1e-6, 1e-6)
