@@ -143,6 +143,19 @@ int hode_try_step(hode_ctx *ctx, double *t, double *dt, int *accepted);
  * state holds the last accepted step either way.  `out` may be NULL. */
 int hode_integrate_adaptive(hode_ctx *ctx, double t0, double t1, double dt0, int64_t max_steps, hode_stats *out);
 
+/* Odeint integrate_times with a recording observer: the state at times[0]
+ * is the current one; the adaptive stepper then advances to times[1],
+ * times[2], ... (strictly increasing) in turn, each step clipped to land on
+ * them exactly, carrying the proposed step and the controller's memory from
+ * one to the next.  dst receives n_times states back to back (layout as
+ * hode_read_state; host or device memory, dst_bytes >= n_times * state
+ * bytes).  max_steps bounds the attempts of the whole call; at the first
+ * failing status the call stops (later slots are not written) and returns
+ * it.  `out` (may be NULL) receives the summed stats; traces keep the last
+ * interval's attempts. */
+int hode_integrate_times(hode_ctx *ctx, const double *times, int64_t n_times, double dt0, int64_t max_steps,
+                         void *dst, size_t dst_bytes, int dst_on_device, hode_stats *out);
+
 /* Statistics of the last run. */
 int hode_get_stats(hode_ctx *ctx, hode_stats *out);
 

@@ -633,6 +633,81 @@ int hode_integrate_adaptive(hode_ctx* c, double t0, double t1, double dt0, int64
   return c->last.status;
 }
 
+int hode_integrate_times(hode_ctx* c, const double* times, int64_t n_times, double dt0, int64_t max_steps,
+                         void* dst, size_t dst_bytes, int dst_on_device, hode_stats* out) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!times || n_times < 1 || !(dt0 > 0) || !std::isfinite(dt0) || max_steps < 0)
+    return fail(c, HODE_EINVAL, "bad integrate_times arguments");
+  for (int64_t i = 0; i < n_times; ++i)
+    if (!std::isfinite(times[i]) || (i > 0 && !(times[i] > times[i - 1])))
+      return fail(c, HODE_EINVAL, "times must be finite and increasing");
+  const size_t bytes = (size_t)c->nelem * c->esize;
+  if (!dst || dst_bytes / (size_t)n_times < bytes) return fail(c, HODE_ESTATE, "destination too small");
+  HIPCHK(c, hipSetDevice(c->device));
+  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  // the observation at times[0]: the current state
+  HIPCHK(c, hipMemcpyAsync(dst, c->y[c->parity], bytes, kind, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  hode_stats tot{};
+  tot.t = times[0];
+  tot.dt_next = dt0;
+  double dt = dt0;
+  int64_t left = max_steps;
+  bool carry = false;
+  DevCtrl prev{};
+  for (int64_t i = 1; i < n_times; ++i) {
+    // one segment times[i-1] -> times[i], landing on it; the proposed step,
+    // the controller's memory and (Dopri5) k1 carry over from the last one
+    DevCtrl d = base_ctrl(c, adaptive_mode(c));
+    d.t = d.t0 = times[i - 1];
+    d.t1 = times[i];
+    d.dt = dt;
+    d.max_attempts = left;
+    const bool last = dt >= d.t1 - d.t0;
+    d.h = last ? d.t1 - d.t0 : dt;
+    d.last_flag = last;
+    if (carry) {
+      d.err_prev = prev.err_prev;
+      d.last_rejected = prev.last_rejected;
+      d.hist_n = prev.hist_n;
+      for (int k = 0; k < hode::HIST; ++k) {
+        d.hist_lerr[k] = prev.hist_lerr[k];
+        d.hist_lh[k] = prev.hist_lh[k];
+        d.hist_acc[k] = prev.hist_acc[k];
+      }
+    }
+    if (left == 0) {
+      d.done = 1;
+      d.status = hode::ST_EMAXSTEPS;
+    } else if (d.h < 1e-12 * std::fmax(1.0, std::fabs(d.t0))) {
+      d.done = 1;
+      d.status = hode::ST_EDT_UNDERFLOW;
+    }
+    rc = run_loop(c, d, c->stepper == HODE_DOPRI5 && !c->k1_valid);
+    if (rc) return rc;
+    const hode_stats& st = c->last;
+    tot.accepted += st.accepted;
+    tot.rejected += st.rejected;
+    tot.rhs_evals += st.rhs_evals;
+    tot.t = st.t;
+    tot.dt_next = st.dt_next;
+    tot.last_err = st.last_err;
+    tot.status = st.status;
+    left -= c->last_attempts;
+    dt = st.dt_next;
+    prev = c->persist;
+    carry = true;
+    if (st.status != HODE_OK) break;
+    HIPCHK(c, hipMemcpyAsync((char*)dst + (size_t)i * bytes, c->y[c->parity], bytes, kind, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  c->persist_valid = false;
+  c->last = tot;
+  if (out) *out = tot;
+  return tot.status;
+}
+
 int hode_try_step(hode_ctx* c, double* t, double* dt, int* accepted) {
   int rc = check_ready(c);
   if (rc) return rc;

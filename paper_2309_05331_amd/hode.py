@@ -70,6 +70,7 @@ def lib():
             "hode_set_controller": ([P, I, P, S], I),
             "hode_do_step": ([P, I, D, D], I),
             "hode_integrate_n_steps": ([P, I, D, D, I64, C.POINTER(D)], I),
+            "hode_integrate_times": ([P, C.POINTER(D), I64, D, I64, P, S, I, C.POINTER(hode_stats)], I),
             "hode_try_step": ([P, C.POINTER(D), C.POINTER(D), C.POINTER(I)], I),
             "hode_integrate_adaptive": ([P, D, D, D, I64, C.POINTER(hode_stats)], I),
             "hode_get_stats": ([P, C.POINTER(hode_stats)], I),
@@ -217,6 +218,16 @@ class Context:
     def integrate_adaptive(self, t0, t1, dt0, max_steps=10 ** 9, allow=(EMAXSTEPS, EDT_UNDERFLOW, ENONFINITE)):
         st = hode_stats()
         self._check(self.L.hode_integrate_adaptive(self.h, t0, t1, dt0, max_steps, C.byref(st)), allow)
+        return st.as_dict()
+
+    def integrate_times(self, times, dt0, dst, max_steps=10 ** 9, allow=(EMAXSTEPS, EDT_UNDERFLOW, ENONFINITE)):
+        """States at the given times into dst (numpy array or device tensor of
+        len(times) * state elements); returns the summed stats."""
+        arr = (C.c_double * len(times))(*[float(t) for t in times])
+        p, nb, on_dev = _ptr_of(dst)
+        st = hode_stats()
+        self._check(self.L.hode_integrate_times(self.h, arr, len(times), dt0, max_steps, p, nb, on_dev, C.byref(st)),
+                    allow)
         return st.as_dict()
 
     def get_stats(self):
