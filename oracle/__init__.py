@@ -21,7 +21,15 @@ _SRC = os.path.join(_HERE, "hode_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 EXP, LOGISTIC, GRAYSCOTT = 1, 2, 3
-RK4, DOPRI5, CASHKARP, EULER = 1, 2, 3, 4
+RK4, DOPRI5, CASHKARP, EULER, FEHLBERG78 = 1, 2, 3, 4, 5
+
+
+def AB(steps: int) -> int:
+    """Method code of Adams-Bashforth with `steps` steps (1 .. 8)."""
+    assert 1 <= steps <= 8
+    return 10 + steps
+
+
 CTRL_PI, CTRL_I = 1, 2
 OK, EINVAL, EDT_UNDERFLOW, EMAXSTEPS, ENONFINITE = 0, -1, -5, -6, -7
 
@@ -74,6 +82,13 @@ def lib():
         L.orc_integrate_replay.argtypes = [C.POINTER(System), P, C.c_double, P, P, C.c_int64,
                                            C.c_double, C.c_double, C.POINTER(C.c_double), P]
         L.orc_cashkarp_attempt.argtypes = [C.POINTER(System), P, C.c_double, P, P]
+        L.orc_fehlberg78_attempt.argtypes = [C.POINTER(System), P, C.c_double, P, P]
+        L.orc_ab_weights.argtypes = [C.c_int, P]
+        L.orc_ab_weights.restype = None
+        L.orc_ctrl_decide_k.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.orc_integrate_n_steps_e.argtypes = [C.POINTER(System), C.c_int, P, C.c_double, C.c_double,
+                                              C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.orc_integrate_times.argtypes = [C.POINTER(System), C.c_int, P, P, C.c_int64, C.c_double, C.c_double,
                                           C.c_double, C.c_int, C.c_int64, P, C.POINTER(Stats)]
         L.orc_integrate_adaptive_m.argtypes = [C.POINTER(System), C.c_int, P, C.c_double, C.c_double, C.c_double,
@@ -111,7 +126,7 @@ def rhs(sysd: System, y) -> np.ndarray:
 
 
 def tableau(method: int):
-    s = {RK4: 4, DOPRI5: 7, CASHKARP: 6}[method]
+    s = {RK4: 4, DOPRI5: 7, CASHKARP: 6, FEHLBERG78: 13}[method]
     a = np.zeros(s * s)
     b = np.zeros(s)
     bh = np.zeros(s)
@@ -125,12 +140,23 @@ def err_norm(y, ynew, e, atol, rtol) -> float:
     return lib().orc_err_norm(y.size, _ptr(y), _ptr(ynew), _ptr(e), atol, rtol)
 
 
-def ctrl_decide(kind: int, err: float, err_prev: float, last_rejected: bool):
+def ctrl_decide(kind: int, err: float, err_prev: float, last_rejected: bool, order_k=None):
+    """One controller decision; order_k = 1 + the embedded order (default 5)."""
     ep = C.c_double(err_prev)
     lr = C.c_int(1 if last_rejected else 0)
     fac = C.c_double(0)
-    acc = lib().orc_ctrl_decide(kind, err, C.byref(ep), C.byref(lr), C.byref(fac))
+    if order_k is None:
+        acc = lib().orc_ctrl_decide(kind, err, C.byref(ep), C.byref(lr), C.byref(fac))
+    else:
+        acc = lib().orc_ctrl_decide_k(kind, order_k, err, C.byref(ep), C.byref(lr), C.byref(fac))
     return bool(acc), fac.value, ep.value, bool(lr.value)
+
+
+def ab_weights(steps: int) -> np.ndarray:
+    """Adams-Bashforth weights beta_0 .. beta_{steps-1} (beta_j multiplies f_{n-j})."""
+    b = np.zeros(8)
+    lib().orc_ab_weights(steps, _ptr(b))
+    return b[:steps]
 
 
 def rk4_step(sysd: System, y, h: float) -> np.ndarray:
@@ -155,18 +181,29 @@ def cashkarp_attempt(sysd: System, y, h: float):
     return yn, e
 
 
-def integrate_n_steps(sysd: System, method: int, y, t0: float, dt: float, n: int):
+def fehlberg78_attempt(sysd: System, y, h: float):
+    """One Fehlberg 7(8) attempt from y: returns (ynew, e)."""
+    y = _f64(y).ravel()
+    yn, e = np.empty_like(y), np.empty_like(y)
+    assert lib().orc_fehlberg78_attempt(C.byref(sysd), _ptr(y), h, _ptr(yn), _ptr(e)) == OK
+    return yn, e
+
+
+def integrate_n_steps(sysd: System, method: int, y, t0: float, dt: float, n: int, evals: bool = False):
+    """n fixed steps (an Adams-Bashforth method, AB(s), starts afresh);
+    returns (y, t_end) or, with evals, (y, t_end, right-hand side evaluations)."""
     y = _f64(y).ravel().copy()
     te = C.c_double(0)
-    rc = lib().orc_integrate_n_steps(C.byref(sysd), method, _ptr(y), t0, dt, n, C.byref(te))
+    ne = C.c_int64(0)
+    rc = lib().orc_integrate_n_steps_e(C.byref(sysd), method, _ptr(y), t0, dt, n, C.byref(te), C.byref(ne))
     assert rc == OK, rc
-    return y, te.value
+    return (y, te.value, ne.value) if evals else (y, te.value)
 
 
 def integrate_adaptive(sysd: System, y, t0, t1, dt0, atol, rtol, ctrl=CTRL_PI, max_steps=10 ** 7,
                        trace_cap=0, method=None):
     """Returns (y, stats dict, trace array of shape (attempts, 4) or None).
-    method: DOPRI5 (default) or CASHKARP."""
+    method: DOPRI5 (default), CASHKARP or FEHLBERG78."""
     y = _f64(y).ravel().copy()
     st = Stats()
     tr = np.zeros((max(trace_cap, 1), 4))
@@ -194,7 +231,7 @@ def integrate_times(sysd: System, y, times, dt0, atol, rtol, ctrl=CTRL_PI, max_s
 
 def integrate_replay(sysd: System, y, t0, hs, accepted, atol=1e-6, rtol=1e-6, method=None):
     """Replays (h, accepted) pairs; returns (y, t_end, per-attempt error norms).
-    method: DOPRI5 (default) or CASHKARP."""
+    method: DOPRI5 (default), CASHKARP or FEHLBERG78."""
     y = _f64(y).ravel().copy()
     hs = _f64(hs).ravel()
     acc = np.ascontiguousarray(np.asarray(accepted, dtype=np.int32).ravel())

@@ -11,13 +11,20 @@
 // combined by an *Algebra* (linear combinations of states); adaptive steppers
 // bound the error with the L-infinity norm of the embedded error estimate.
 //
-//  * Steppers: explicit Euler, classical Runge-Kutta 4, Runge-Kutta-Dopri 5
-//    and Runge-Kutta Cash-Karp 5(4) (the paper's Table 1, fixed and dynamic
-//    step size).
+//  * Steppers: explicit Euler, classical Runge-Kutta 4, Runge-Kutta-Dopri 5,
+//    Runge-Kutta Cash-Karp 5(4) and Runge-Kutta-Fehlberg 7(8) (the paper's
+//    Table 1, fixed and dynamic step size), and the multi-step
+//    Adams-Bashforth methods of 1 to 8 steps (fixed step size).
 //    Tableaux: Kutta 1901, Dormand & Prince 1980 (Hairer, Norsett & Wanner,
-//    Solving ODEs I, Table II.5.2) and Cash & Karp 1990 (ACM TOMS 16, 201).
+//    Solving ODEs I, Table II.5.2), Cash & Karp 1990 (ACM TOMS 16, 201) and
+//    Fehlberg 1968 (NASA TR R-287).
 //    Dopri 5 is first-same-as-last: k7 of an accepted step is k1 of the next;
-//    Cash-Karp evaluates its 6 stages afresh every attempt.
+//    Cash-Karp and Fehlberg evaluate their stages afresh every attempt.
+//    Adams-Bashforth with s steps: y_{n+1} = y_n + h sum_j beta_j f_{n-j},
+//    beta_j the integral over one step of the Lagrange polynomial through
+//    the last s right-hand sides; the first s-1 steps, before s right-hand
+//    sides exist, are taken by the Fehlberg 7(8) fixed step, whose order 8
+//    keeps the start-up error below that of every s <= 8.
 //  * Systems: exponential dx/dt = x and sigmoidal (logistic) dx/dt = x(1-x),
 //    the two families of the accuracy benchmark read as autonomous ODEs whose
 //    solutions are x0 e^t and the logistic curve; and the 3D Gray-Scott
@@ -27,10 +34,12 @@
 //    Gray-Scott equation is taken as +u v^2 - (F+k) v (the System listing).
 //  * Error norm: max_i |e_i| / (atol + rtol max(|y_i|, |ynew_i|)).
 //  * Controller (the paper gives none): Gustafsson's PI controller
-//    (Hairer & Wanner, Solving ODEs II, section IV.2) with alpha = 0.7/5,
-//    beta = 0.4/5, safety 0.9, factor clamp [0.2, 5], no growth right after a
-//    reject, error floor 1e-10, err_prev starting at 1.  The I variant sets
-//    alpha = 1/5, beta = 0.
+//    (Hairer & Wanner, Solving ODEs II, section IV.2) with alpha = 0.7/k,
+//    beta = 0.4/k, safety 0.9, factor clamp [0.2, 5], no growth right after a
+//    reject (where the factor is max(0.2, 0.9 err^(-1/k))), error floor
+//    1e-10, err_prev starting at 1; k = 1 + the order of the embedded
+//    solution: 5 for the 5(4) pairs, 8 for Fehlberg 7(8).  The I variant sets
+//    alpha = 1/k, beta = 0.
 //
 // Serial loops define the semantics.  The OpenMP pragmas only parallelise
 // loops whose iterations are independent (and a max reduction, which is
@@ -46,7 +55,9 @@
 extern "C" {
 
 enum { ORC_EXP = 1, ORC_LOGISTIC = 2, ORC_GRAYSCOTT = 3 };
-enum { ORC_RK4 = 1, ORC_DOPRI5 = 2, ORC_CASHKARP = 3, ORC_EULER = 4 };
+enum { ORC_RK4 = 1, ORC_DOPRI5 = 2, ORC_CASHKARP = 3, ORC_EULER = 4, ORC_FEHLBERG78 = 5 };
+// Adams-Bashforth with s steps (1 <= s <= 8) is method ORC_AB0 + s.
+enum { ORC_AB0 = 10 };
 enum { ORC_CTRL_PI = 1, ORC_CTRL_I = 2 };
 enum {
   ORC_OK = 0,
@@ -116,6 +127,64 @@ const double CK_A[6][6] = {
 };
 const double CK_B[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
 const double CK_BHAT[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0, 277.0 / 14336.0, 1.0 / 4.0};
+
+// Runge-Kutta-Fehlberg 7(8), 13 stages: 8th-order weights b (the solution
+// carried on) and 7th-order embedded weights bhat.
+const double F78_C[13] = {0.0,       2.0 / 27.0, 1.0 / 9.0, 1.0 / 6.0, 5.0 / 12.0, 1.0 / 2.0, 5.0 / 6.0,
+                          1.0 / 6.0, 2.0 / 3.0,  1.0 / 3.0, 1.0,       0.0,        1.0};
+const double F78_A[13][13] = {
+    {0},
+    {2.0 / 27.0},
+    {1.0 / 36.0, 1.0 / 12.0},
+    {1.0 / 24.0, 0, 1.0 / 8.0},
+    {5.0 / 12.0, 0, -25.0 / 16.0, 25.0 / 16.0},
+    {1.0 / 20.0, 0, 0, 1.0 / 4.0, 1.0 / 5.0},
+    {-25.0 / 108.0, 0, 0, 125.0 / 108.0, -65.0 / 27.0, 125.0 / 54.0},
+    {31.0 / 300.0, 0, 0, 0, 61.0 / 225.0, -2.0 / 9.0, 13.0 / 900.0},
+    {2.0, 0, 0, -53.0 / 6.0, 704.0 / 45.0, -107.0 / 9.0, 67.0 / 90.0, 3.0},
+    {-91.0 / 108.0, 0, 0, 23.0 / 108.0, -976.0 / 135.0, 311.0 / 54.0, -19.0 / 60.0, 17.0 / 6.0, -1.0 / 12.0},
+    {2383.0 / 4100.0, 0, 0, -341.0 / 164.0, 4496.0 / 1025.0, -301.0 / 82.0, 2133.0 / 4100.0, 45.0 / 82.0,
+     45.0 / 164.0, 18.0 / 41.0},
+    {3.0 / 205.0, 0, 0, 0, 0, -6.0 / 41.0, -3.0 / 205.0, -3.0 / 41.0, 3.0 / 41.0, 6.0 / 41.0, 0},
+    {-1777.0 / 4100.0, 0, 0, -341.0 / 164.0, 4496.0 / 1025.0, -289.0 / 82.0, 2193.0 / 4100.0, 51.0 / 82.0,
+     33.0 / 164.0, 12.0 / 41.0, 0, 1.0},
+};
+const double F78_B[13] = {0, 0, 0, 0, 0, 34.0 / 105.0, 9.0 / 35.0, 9.0 / 35.0, 9.0 / 280.0, 9.0 / 280.0, 0,
+                          41.0 / 840.0, 41.0 / 840.0};
+const double F78_BHAT[13] = {41.0 / 840.0, 0, 0, 0, 0, 34.0 / 105.0, 9.0 / 35.0, 9.0 / 35.0, 9.0 / 280.0,
+                             9.0 / 280.0, 41.0 / 840.0, 0, 0};
+
+// Adams-Bashforth weights for s steps, from their definition: with the
+// right-hand sides f_{n-i} at the nodes u = -i (i = 0 .. s-1, in units of
+// h), beta_j = integral over u in [0, 1] of the Lagrange basis polynomial
+// prod_{i != j} (u + i) / (i - j).  The product is expanded into integer
+// coefficients c_d; with L = lcm(1 .. s), the numerator sum_d c_d L/(d+1)
+// and the denominator L prod_{i != j} (i - j) are exact integers, so the
+// one division rounds beta_j correctly.
+void ab_weights(int s, double* beta) {
+  int64_t L = 1;
+  for (int64_t d = 2; d <= s; ++d) {
+    int64_t a = L, b = d;
+    while (b) { const int64_t r = a % b; a = b; b = r; }
+    L = L / a * d;
+  }
+  for (int j = 0; j < s; ++j) {
+    int64_t poly[9] = {1};  // coefficients of u^0 .. u^8
+    int deg = 0;
+    int64_t denom = L;
+    for (int i = 0; i < s; ++i) {
+      if (i == j) continue;
+      // multiply by (u + i)
+      for (int d = deg + 1; d >= 1; --d) poly[d] = poly[d - 1] + (int64_t)i * poly[d];
+      poly[0] *= i;
+      ++deg;
+      denom *= (i - j);
+    }
+    int64_t num = 0;
+    for (int d = 0; d <= deg; ++d) num += poly[d] * (L / (d + 1));
+    beta[j] = (double)num / (double)denom;
+  }
+}
 
 // ---- the System: right-hand sides -----------------------------------------
 
@@ -285,15 +354,74 @@ void cashkarp_attempt(const orc_system& s, const double* y, double h, double* yn
   }
 }
 
+// One Fehlberg 7(8) attempt from y with k1 = f(y) given: twelve more stages;
+// writes ynew (8th order) and (if e != null) e = h * sum_j (b_j - bhat_j) k_j.
+void fehlberg78_attempt(const orc_system& s, const double* y, const double* k1, double h, double* ynew, double* e,
+                        Work& W) {
+  const int64_t n = s.n;
+  double* kp[13];
+  for (int j = 0; j < 13; ++j) kp[j] = W.k[j].data();
+  std::memcpy(kp[0], k1, sizeof(double) * n);
+  for (int st = 1; st < 13; ++st) {
+    stage_input(n, y, h, st, F78_A[st], kp, W.w.data());
+    rhs(s, W.w.data(), kp[st]);
+  }
+  stage_input(n, y, h, 13, F78_B, kp, ynew);
+  if (e) {
+    double d[13];
+    for (int j = 0; j < 13; ++j) d[j] = F78_B[j] - F78_BHAT[j];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < 13; ++j)
+        if (d[j] != 0.0) acc += d[j] * kp[j][i];
+      e[i] = h * acc;
+    }
+  }
+}
+
+// Adams-Bashforth with s steps over nsteps fixed steps of size h from a fresh
+// start (no stored right-hand sides): f_n = f(y_n) is kept for the last s
+// steps; steps 0 .. s-2 are Fehlberg 7(8) steps (whose k1 is that f_n), later
+// steps y_{n+1} = y_n + h sum_{j<s} beta_j f_{n-j}.  Returns the right-hand
+// side evaluations made.
+int64_t adams_bashforth(const orc_system& s, int steps, double* y, double h, int64_t nsteps) {
+  const int64_t n = s.n;
+  double beta[8];
+  ab_weights(steps, beta);
+  std::vector<std::vector<double>> f(steps, std::vector<double>(n));  // f[m % steps] = f_m
+  Work W(n, 13);
+  std::vector<double> ynew(n);
+  int64_t evals = 0;
+  for (int64_t m = 0; m < nsteps; ++m) {
+    double* fm = f[m % steps].data();
+    rhs(s, y, fm);
+    evals += 1;
+    if (m < steps - 1) {
+      fehlberg78_attempt(s, y, fm, h, ynew.data(), nullptr, W);
+      evals += 12;
+      std::swap_ranges(ynew.begin(), ynew.end(), y);
+      continue;
+    }
+    double* past[8];
+    for (int j = 0; j < steps; ++j) past[j] = f[(m - j) % steps].data();
+    stage_input(n, y, h, steps, beta, past, ynew.data());
+    std::swap_ranges(ynew.begin(), ynew.end(), y);
+  }
+  return evals;
+}
+
 // ---- step-size controller -------------------------------------------------------
 
+// k = 1 + the order of the embedded solution (5 for the 5(4) pairs, 8 for
+// Fehlberg 7(8)).
 struct Ctrl {
-  double alpha, beta, safety = 0.9, fac_min = 0.2, fac_max = 5.0;
+  double k, alpha, beta, safety = 0.9, fac_min = 0.2, fac_max = 5.0;
   double err_prev = 1.0;
   bool last_rejected = false;
-  explicit Ctrl(int kind) {
-    if (kind == ORC_CTRL_I) { alpha = 1.0 / 5.0; beta = 0.0; }
-    else { alpha = 0.7 / 5.0; beta = 0.4 / 5.0; }
+  explicit Ctrl(int kind, double order_k = 5.0) : k(order_k) {
+    if (kind == ORC_CTRL_I) { alpha = 1.0 / k; beta = 0.0; }
+    else { alpha = 0.7 / k; beta = 0.4 / k; }
   }
   // Returns whether the attempt is accepted and the factor for the next step.
   bool decide(double err, double* fac) {
@@ -307,7 +435,7 @@ struct Ctrl {
       *fac = f;
       return true;
     }
-    *fac = std::isnan(err) ? fac_min : std::max(fac_min, safety * std::pow(err, -1.0 / 5.0));
+    *fac = std::isnan(err) ? fac_min : std::max(fac_min, safety * std::pow(err, -1.0 / k));
     last_rejected = true;
     return false;
   }
@@ -330,6 +458,13 @@ void orc_tableau(int method, double* a, double* b, double* bhat, double* c) {
       b[i] = RK4_B[i];
       c[i] = RK4_C[i];
       if (bhat) bhat[i] = 0.0;
+    }
+  } else if (method == ORC_FEHLBERG78) {
+    for (int i = 0; i < 13; ++i) {
+      for (int j = 0; j < 13; ++j) a[i * 13 + j] = F78_A[i][j];
+      b[i] = F78_B[i];
+      bhat[i] = F78_BHAT[i];
+      c[i] = F78_C[i];
     }
   } else if (method == ORC_CASHKARP) {
     for (int i = 0; i < 6; ++i) {
@@ -354,6 +489,20 @@ double orc_err_norm(int64_t n, const double* y, const double* ynew, const double
 
 // One controller decision: returns 1 if accepted; writes the step factor and the
 // updated (err_prev, last_rejected).
+void orc_ab_weights(int steps, double* beta) {
+  if (steps >= 1 && steps <= 8) ab_weights(steps, beta);
+}
+
+int orc_ctrl_decide_k(int kind, double order_k, double err, double* err_prev, int* last_rejected, double* fac) {
+  Ctrl c(kind, order_k);
+  c.err_prev = *err_prev;
+  c.last_rejected = *last_rejected != 0;
+  const bool acc = c.decide(err, fac);
+  *err_prev = c.err_prev;
+  *last_rejected = c.last_rejected ? 1 : 0;
+  return acc ? 1 : 0;
+}
+
 int orc_ctrl_decide(int kind, double err, double* err_prev, int* last_rejected, double* fac) {
   Ctrl c(kind);
   c.err_prev = *err_prev;
@@ -381,6 +530,15 @@ int orc_dopri5_attempt(const orc_system* s, const double* y, double h, double* y
   return ORC_OK;
 }
 
+int orc_fehlberg78_attempt(const orc_system* s, const double* y, double h, double* ynew, double* e) {
+  if (!valid(s)) return ORC_EINVAL;
+  Work W(s->n, 13);
+  std::vector<double> k1(s->n);
+  rhs(*s, y, k1.data());
+  fehlberg78_attempt(*s, y, k1.data(), h, ynew, e, W);
+  return ORC_OK;
+}
+
 int orc_cashkarp_attempt(const orc_system* s, const double* y, double h, double* ynew, double* e) {
   if (!valid(s)) return ORC_EINVAL;
   Work W(s->n, 6);
@@ -388,14 +546,29 @@ int orc_cashkarp_attempt(const orc_system* s, const double* y, double h, double*
   return ORC_OK;
 }
 
-// Fixed steps: t_n = t0 + n dt (Odeint integrate_const / do_step).
-int orc_integrate_n_steps(const orc_system* s, int method, double* y, double t0, double dt, int64_t nsteps,
-                          double* t_end) {
+// Fixed steps: t_n = t0 + n dt (Odeint integrate_const / do_step).  An
+// Adams-Bashforth run starts afresh (no stored right-hand sides).
+int orc_integrate_n_steps_e(const orc_system* s, int method, double* y, double t0, double dt, int64_t nsteps,
+                            double* t_end, int64_t* rhs_evals) {
+  const bool ab = method > ORC_AB0 && method <= ORC_AB0 + 8;
   if (!valid(s) || nsteps < 0 ||
-      !(method == ORC_RK4 || method == ORC_DOPRI5 || method == ORC_CASHKARP || method == ORC_EULER))
+      !(method == ORC_RK4 || method == ORC_DOPRI5 || method == ORC_CASHKARP || method == ORC_EULER ||
+        method == ORC_FEHLBERG78 || ab))
     return ORC_EINVAL;
   const int64_t n = s->n;
-  if (method == ORC_EULER) {
+  int64_t evals = 0;
+  if (ab) {
+    evals = adams_bashforth(*s, method - ORC_AB0, y, dt, nsteps);
+  } else if (method == ORC_FEHLBERG78) {
+    Work W(n, 13);
+    std::vector<double> k1(n), ynew(n);
+    for (int64_t i = 0; i < nsteps; ++i) {
+      rhs(*s, y, k1.data());
+      fehlberg78_attempt(*s, y, k1.data(), dt, ynew.data(), nullptr, W);
+      std::swap_ranges(ynew.begin(), ynew.end(), y);
+    }
+    evals = 13 * nsteps;
+  } else if (method == ORC_EULER) {
     Work W(n, 1);
     for (int64_t i = 0; i < nsteps; ++i) euler_step(*s, y, dt, W);
   } else if (method == ORC_RK4) {
@@ -418,8 +591,18 @@ int orc_integrate_n_steps(const orc_system* s, int method, double* y, double t0,
       k1.swap(k7);
     }
   }
+  if (!ab && method != ORC_FEHLBERG78) {
+    const int per = method == ORC_EULER ? 1 : (method == ORC_RK4 ? 4 : 6);
+    evals = per * nsteps + (method == ORC_DOPRI5 && nsteps > 0 ? 1 : 0);
+  }
   if (t_end) *t_end = t0 + (double)nsteps * dt;
+  if (rhs_evals) *rhs_evals = evals;
   return ORC_OK;
+}
+
+int orc_integrate_n_steps(const orc_system* s, int method, double* y, double t0, double dt, int64_t nsteps,
+                          double* t_end) {
+  return orc_integrate_n_steps_e(s, method, y, t0, dt, nsteps, t_end, nullptr);
 }
 
 // Error-controlled integration from t0 to t1 with an embedded pair (Dopri5 or
@@ -430,6 +613,7 @@ int orc_integrate_n_steps(const orc_system* s, int method, double* y, double t0,
 // proposed step, the controller and the counters.
 struct Adaptive {
   const orc_system& s;
+  int method;
   bool dp;
   double atol, rtol;
   Work W;
@@ -438,8 +622,8 @@ struct Adaptive {
   double dt, last_err = 0.0;
   int64_t acc = 0, rej = 0, evals = 0, att = 0;
   Adaptive(const orc_system& sys, int method, const double* y, double dt0, double a, double r, int ctrl_kind)
-      : s(sys), dp(method == ORC_DOPRI5), atol(a), rtol(r), W(sys.n, 7), k1(sys.n), k7(sys.n), ynew(sys.n),
-        e(sys.n), c(ctrl_kind), dt(dt0) {
+      : s(sys), method(method), dp(method == ORC_DOPRI5), atol(a), rtol(r), W(sys.n, 13), k1(sys.n), k7(sys.n),
+        ynew(sys.n), e(sys.n), c(ctrl_kind, method == ORC_FEHLBERG78 ? 8.0 : 5.0), dt(dt0) {
     if (dp) {
       rhs(s, y, k1.data());
       evals = 1;
@@ -454,9 +638,17 @@ struct Adaptive {
       const bool last = dt >= t1 - *t;
       const double h = last ? t1 - *t : dt;
       if (h < 1e-12 * std::max(1.0, std::fabs(*t))) return std::isfinite(last_err) ? ORC_EDT_UNDERFLOW : ORC_ENONFINITE;
-      if (dp) dopri5_attempt(s, y, k1.data(), h, ynew.data(), k7.data(), e.data(), W);
-      else cashkarp_attempt(s, y, h, ynew.data(), e.data(), W);
-      evals += 6;
+      if (dp) {
+        dopri5_attempt(s, y, k1.data(), h, ynew.data(), k7.data(), e.data(), W);
+        evals += 6;
+      } else if (method == ORC_FEHLBERG78) {
+        rhs(s, y, k1.data());
+        fehlberg78_attempt(s, y, k1.data(), h, ynew.data(), e.data(), W);
+        evals += 13;
+      } else {
+        cashkarp_attempt(s, y, h, ynew.data(), e.data(), W);
+        evals += 6;
+      }
       ++att;
       const double err = err_norm(n, y, ynew.data(), e.data(), atol, rtol);
       last_err = err;
@@ -489,7 +681,7 @@ int orc_integrate_adaptive_m(const orc_system* s, int method, double* y, double 
                              double atol, double rtol, int ctrl_kind, int64_t max_steps, orc_stats* st,
                              double* trace, int64_t trace_cap) {
   if (!valid(s) || !(t1 >= t0) || !(dt0 > 0) || !(atol >= 0) || !(rtol >= 0) || (atol == 0 && rtol == 0) ||
-      !(method == ORC_DOPRI5 || method == ORC_CASHKARP))
+      !(method == ORC_DOPRI5 || method == ORC_CASHKARP || method == ORC_FEHLBERG78))
     return ORC_EINVAL;
   Adaptive A(*s, method, y, dt0, atol, rtol, ctrl_kind);
   double t = t0;
@@ -506,7 +698,7 @@ int orc_integrate_adaptive_m(const orc_system* s, int method, double* y, double 
 int orc_integrate_times(const orc_system* s, int method, double* y, const double* times, int64_t nt, double dt0,
                         double atol, double rtol, int ctrl_kind, int64_t max_steps, double* out, orc_stats* st) {
   if (!valid(s) || nt < 1 || !(dt0 > 0) || !(atol >= 0) || !(rtol >= 0) || (atol == 0 && rtol == 0) ||
-      !(method == ORC_DOPRI5 || method == ORC_CASHKARP) || !out)
+      !(method == ORC_DOPRI5 || method == ORC_CASHKARP || method == ORC_FEHLBERG78) || !out)
     return ORC_EINVAL;
   for (int64_t i = 1; i < nt; ++i)
     if (!(times[i] > times[i - 1])) return ORC_EINVAL;
@@ -536,16 +728,23 @@ int orc_integrate_adaptive(const orc_system* s, double* y, double t0, double t1,
 int orc_integrate_replay_m(const orc_system* s, int method, double* y, double t0, const double* hs,
                            const int32_t* accepted, int64_t n_att, double atol, double rtol, double* t_end,
                            double* errs) {
-  if (!valid(s) || n_att < 0 || !(method == ORC_DOPRI5 || method == ORC_CASHKARP)) return ORC_EINVAL;
+  if (!valid(s) || n_att < 0 || !(method == ORC_DOPRI5 || method == ORC_CASHKARP || method == ORC_FEHLBERG78))
+    return ORC_EINVAL;
   const bool dp = method == ORC_DOPRI5;
   const int64_t n = s->n;
-  Work W(n, 7);
+  Work W(n, 13);
   std::vector<double> k1(n), k7(n), ynew(n), e(n);
   if (dp) rhs(*s, y, k1.data());
   double t = t0;
   for (int64_t i = 0; i < n_att; ++i) {
-    if (dp) dopri5_attempt(*s, y, k1.data(), hs[i], ynew.data(), k7.data(), e.data(), W);
-    else cashkarp_attempt(*s, y, hs[i], ynew.data(), e.data(), W);
+    if (dp) {
+      dopri5_attempt(*s, y, k1.data(), hs[i], ynew.data(), k7.data(), e.data(), W);
+    } else if (method == ORC_FEHLBERG78) {
+      rhs(*s, y, k1.data());
+      fehlberg78_attempt(*s, y, k1.data(), hs[i], ynew.data(), e.data(), W);
+    } else {
+      cashkarp_attempt(*s, y, hs[i], ynew.data(), e.data(), W);
+    }
     if (errs) errs[i] = err_norm(n, y, ynew.data(), e.data(), atol, rtol);
     if (accepted[i]) {
       std::swap_ranges(ynew.begin(), ynew.end(), y);

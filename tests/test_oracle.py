@@ -424,7 +424,7 @@ def test_controller_pi_values_and_limits(orc):
 # ------------------------------------------------------------ adaptive
 
 @pytest.mark.parametrize("kind", [1, 2])
-@pytest.mark.parametrize("method", [2, 3])
+@pytest.mark.parametrize("method", [2, 3, 5])
 def test_adaptive_accuracy_and_landing(orc, kind, method):
     x0 = inputs.exp_family_x0(4096, seed=2)
     sysd = orc.ew_system(kind, x0.size)
@@ -441,8 +441,10 @@ def test_adaptive_accuracy_and_landing(orc, kind, method):
         if prev is not None:
             assert err < prev
         prev = err
-        # first same as last: Dopri5 evaluates k1 once; Cash-Karp every attempt
-        assert st["rhs_evals"] == (1 if method == 2 else 0) + 6 * (st["accepted"] + st["rejected"])
+        # first same as last: Dopri5 evaluates k1 once; Cash-Karp and
+        # Fehlberg every attempt
+        per = 13 if method == 5 else 6
+        assert st["rhs_evals"] == (1 if method == 2 else 0) + per * (st["accepted"] + st["rejected"])
 
 
 @pytest.mark.parametrize("ctrl,target", [(1, 0.9 ** (1 / 0.06)), (2, 0.9 ** 5)])
@@ -469,7 +471,7 @@ def test_adaptive_exp_steady_step_matches_error_model(orc, ctrl, target):
     assert st["status"] == 0 and st["rejected"] == 0
 
 
-@pytest.mark.parametrize("method", [2, 3])
+@pytest.mark.parametrize("method", [2, 3, 5])
 def test_adaptive_replay_reproduces_free_run(orc, method):
     N = 6
     y0 = inputs.gray_scott_ic(N, seed=1).ravel()
@@ -552,7 +554,7 @@ def test_periodic_window_reproduces_full_grid_centre(orc):
     assert np.max(np.abs(ynw2[cs] - yn_full2.reshape(2, N, N, N)[:, 20, 20, 20])) > 0
 
 
-@pytest.mark.parametrize("method", [2, 3])
+@pytest.mark.parametrize("method", [2, 3, 5])
 def test_integrate_times_closed_form_and_single_interval(orc, method):
     # the states at the requested times follow the closed forms to the
     # tolerance; with only [t0, t1] requested it is integrate_adaptive itself
@@ -571,3 +573,223 @@ def test_integrate_times_closed_form_and_single_interval(orc, method):
         assert np.array_equal(out1[1], y1) and st2["accepted"] == st1["accepted"]
     with pytest.raises(ValueError):
         orc.integrate_times(orc.ew_system(1, 4), x0[:4], [0.0, 1.0, 1.0], 0.01, 1e-6, 1e-6)
+
+
+# ------------------------------------------ Fehlberg 7(8), Adams-Bashforth
+
+def _rooted_trees(nmax):
+    """All rooted trees with at most nmax vertices, by order.  A tree is the
+    tuple of its subtrees (in a canonical order), the single vertex ()."""
+    by = {1: [()]}
+    key = {(): (1, 0)}
+
+    def forests(m, maxkey):
+        # multisets of trees of total order m, listed with non-increasing keys
+        if m == 0:
+            yield ()
+            return
+        for k in range(1, m + 1):
+            for i, t in enumerate(by[k]):
+                if maxkey is not None and (k, i) > maxkey:
+                    continue
+                for rest in forests(m - k, (k, i)):
+                    yield (t,) + rest
+
+    for n in range(2, nmax + 1):
+        by[n] = list(forests(n - 1, None))
+        for i, t in enumerate(by[n]):
+            key[t] = (n, i)
+    return by
+
+
+def _order_conditions(A, b, nmax):
+    """(order, b^T Phi(t), 1/gamma(t)) for every rooted tree t up to nmax:
+    Phi(leaf) = 1, Phi([t1 .. tm]) = prod_i A Phi(t_i) (elementwise),
+    gamma([t1 .. tm]) = |t| prod_i gamma(t_i)."""
+    s = len(b)
+    by = _rooted_trees(nmax)
+    phi, gam = {}, {}
+    out = []
+    for n in range(1, nmax + 1):
+        for t in by[n]:
+            v = [Fr(1)] * s
+            g = n
+            for sub in t:
+                w = phi[sub]
+                Aw = [sum(A[i][j] * w[j] for j in range(s)) for i in range(s)]
+                v = [x * y for x, y in zip(v, Aw)]
+                g *= gam[sub]
+            phi[t], gam[t] = v, g
+            out.append((n, sum(bi * vi for bi, vi in zip(b, v)), Fr(1, g)))
+    return out
+
+
+def test_tree_enumeration_matches_textbook(orc):
+    # the number of rooted trees of order 1..8 (1, 1, 2, 4, 9, 20, 48, 115)
+    # and, up to order 5, the densities of the textbook table in the fixture
+    by = _rooted_trees(8)
+    assert [len(by[n]) for n in range(1, 9)] == [1, 1, 2, 4, 9, 20, 48, 115]
+    conds = json.load(open(os.path.join(GOLDEN, "rk_order_conditions.json")))["conditions"]
+    a, _, _, _ = orc.tableau(orc.DOPRI5)
+    dens = sorted((n, 1 / want) for n, _, want in _order_conditions(_rational(a), [Fr(1)] * 7, 5))
+    assert len(dens) == 17 and dens == sorted((cd["order"], cd["gamma"]) for cd in conds)
+
+
+def test_fehlberg78_tableau_orders(orc):
+    # Fehlberg 1968: 13 stages; the carried solution satisfies every order
+    # condition up to order 8 (all 200 rooted trees), the embedded one those
+    # up to order 7 but not all of order 8
+    a, b, bh, c = orc.tableau(orc.FEHLBERG78)
+    A = _rational(a)
+    B = [Fr(x).limit_denominator(10 ** 7) for x in b]
+    BH = [Fr(x).limit_denominator(10 ** 7) for x in bh]
+    Cc = [Fr(x).limit_denominator(10 ** 7) for x in c]
+    for M, Mq in ((a, A), ([b], [B]), ([bh], [BH]), ([c], [Cc])):
+        for row, rowq in zip(M, Mq):
+            for x, q in zip(row, rowq):
+                _check_rounding(x, q)
+    for i in range(13):
+        assert sum(A[i]) == Cc[i], i
+        assert all(A[i][j] == 0 for j in range(i, 13))  # explicit
+    conds = _order_conditions(A, B, 8)
+    assert len(conds) == 200
+    for order, w, want in conds:
+        assert w == want, ("b", order)
+    emb = _order_conditions(A, BH, 8)
+    for order, w, want in emb:
+        if order <= 7:
+            assert w == want, ("bhat", order)
+    assert any(w != want for order, w, want in emb if order == 8)
+    # the error weights b - bhat: 41/840 times (-1, 0 .. 0, -1, 1, 1)
+    d = [x - y for x, y in zip(B, BH)]
+    assert d == [Fr(-41, 840)] + [0] * 9 + [Fr(-41, 840), Fr(41, 840), Fr(41, 840)]
+
+
+@pytest.mark.parametrize("h", [0.05, 0.3, 1.1, -2.0])
+def test_fehlberg78_one_step_amplification_and_error(orc, h):
+    # on x' = x one attempt multiplies x by R(h) = 1 + sum_j h^j b^T A^(j-1) 1
+    # (exact rationals from the tableau; its first nine coefficients are 1/j!)
+    # and estimates E(h) x with b - bhat in place of b, of order h^8
+    a, b, bh, _ = orc.tableau(orc.FEHLBERG78)
+    A = _rational(a)
+    B = [Fr(x).limit_denominator(10 ** 7) for x in b]
+    BH = [Fr(x).limit_denominator(10 ** 7) for x in bh]
+    v = [Fr(1)] * 13
+    rc, ec = [Fr(1)], [Fr(0)]
+    for j in range(1, 14):
+        rc.append(sum(bi * vi for bi, vi in zip(B, v)))
+        ec.append(sum((bi - ci) * vi for bi, ci, vi in zip(B, BH, v)))
+        v = [sum(A[i][k] * v[k] for k in range(13)) for i in range(13)]
+    assert rc[:9] == [Fr(1, math.factorial(j)) for j in range(9)]
+    assert ec[:8] == [0] * 8 and ec[8] != 0
+    R = float(sum(cf * Fr(h) ** j for j, cf in enumerate(rc)))
+    E = float(sum(cf * Fr(h) ** j for j, cf in enumerate(ec)))
+    x0 = inputs.exp_family_x0(257, seed=16)
+    yn, e = orc.fehlberg78_attempt(orc.ew_system(orc.EXP, x0.size), x0, h)
+    mag = sum(abs(h) ** j / math.factorial(j) for j in range(14)) * 8
+    tol = 64 * 2.0 ** -52 * mag * x0
+    assert np.all(np.abs(yn - R * x0) <= tol)
+    assert np.all(np.abs(e - E * x0) <= tol)
+
+
+# Step-halving windows (n steps on [0, 5], then 2n) in the asymptotic range
+# and above round-off: the high-order Adams-Bashforth methods are unstable on
+# the logistic family at the coarsest steps and reach round-off soon after.
+_WINDOWS = {
+    (1, "F78"): 20, (2, "F78"): 20,
+    **{(1, s): 320 for s in range(1, 7)}, (1, 7): 160, (1, 8): 80,
+    **{(2, s): 320 for s in range(1, 6)}, (2, 6): 160, (2, 7): 100,
+}
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_fehlberg78_convergence_order(orc, kind):
+    x0 = inputs.exp_family_x0(4096, seed=2)
+    sysd = orc.ew_system(kind, x0.size)
+    exact = _closed(kind, x0, 5.0)
+    n = _WINDOWS[(kind, "F78")]
+    errs = []
+    for m in (n // 4, n // 2, n, 2 * n):
+        y, _ = orc.integrate_n_steps(sysd, orc.FEHLBERG78, x0, 0.0, 5.0 / m, m)
+        errs.append(np.max(np.abs(y - exact)))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert abs(ratios[-1] / 256 - 1) < 0.2, (errs, ratios)
+    assert ratios[0] < ratios[1] < ratios[2]  # approaching 2^8 from below
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("steps", range(1, 9))
+def test_adams_bashforth_convergence_order(orc, kind, steps):
+    # the paper's multi-step accuracy test: s steps converge with order s
+    x0 = inputs.exp_family_x0(4096, seed=2)
+    sysd = orc.ew_system(kind, x0.size)
+    exact = _closed(kind, x0, 5.0)
+    if (kind, steps) not in _WINDOWS:
+        # AB8 on the logistic family is at round-off once it is stable
+        y, _ = orc.integrate_n_steps(sysd, orc.AB(steps), x0, 0.0, 5.0 / 280, 280)
+        assert np.max(np.abs(y - exact)) < 2e-14
+        return
+    n = _WINDOWS[(kind, steps)]
+    errs = []
+    for m in (n, 2 * n):
+        y, _ = orc.integrate_n_steps(sysd, orc.AB(steps), x0, 0.0, 5.0 / m, m)
+        errs.append(np.max(np.abs(y - exact)))
+    r = errs[0] / errs[1]
+    assert abs(r / 2 ** steps - 1) < 0.2, (errs, r)
+
+
+@pytest.mark.parametrize("steps", range(1, 9))
+def test_adams_bashforth_weights_moments(orc, steps):
+    # exactness on polynomials of degree < s: sum_j beta_j (-j)^m = 1/(m+1)
+    # for m < s, and not for m = s (order exactly s)
+    beta = [Fr(x).limit_denominator(10 ** 7) for x in orc.ab_weights(steps)]
+    for x in beta:
+        assert x.denominator <= 120960
+    for m in range(steps + 1):
+        mom = sum(bj * Fr(-j) ** m for j, bj in enumerate(beta))
+        assert (mom == Fr(1, m + 1)) == (m < steps), m
+    for x, q in zip(orc.ab_weights(steps), beta):
+        _check_rounding(x, q)
+
+
+def test_adams_bashforth_start_up_and_special_cases(orc):
+    x0 = inputs.exp_family_x0(513, seed=17)
+    for kind in (1, 2):
+        sysd = orc.ew_system(kind, x0.size)
+        # one step is explicit Euler, bitwise
+        for n in (1, 7):
+            y1, te = orc.integrate_n_steps(sysd, orc.AB(1), x0, 0.25, 0.1, n)
+            ye, _ = orc.integrate_n_steps(sysd, orc.EULER, x0, 0.25, 0.1, n)
+            assert np.array_equal(y1, ye) and te == 0.25 + n * 0.1
+        # the first s-1 steps are Fehlberg 7(8) steps, bitwise
+        for s in (2, 5, 8):
+            for n in range(s):
+                ya, _, ev = orc.integrate_n_steps(sysd, orc.AB(s), x0, 0.0, 0.1, n, evals=True)
+                yf, _ = orc.integrate_n_steps(sysd, orc.FEHLBERG78, x0, 0.0, 0.1, n)
+                assert np.array_equal(ya, yf), (s, n)
+                assert ev == 13 * n
+            _, _, ev = orc.integrate_n_steps(sysd, orc.AB(s), x0, 0.0, 0.1, 20, evals=True)
+            assert ev == 13 * (s - 1) + (20 - s + 1)
+    # zero steps change nothing; on x' = 0 (logistic fixed points) every step is exact
+    fp = np.array([0.0, 1.0, 0.0, 1.0])
+    y, _ = orc.integrate_n_steps(orc.ew_system(orc.LOGISTIC, 4), orc.AB(8), fp, 0.0, 0.3, 25)
+    assert np.array_equal(y, fp)
+    y, _ = orc.integrate_n_steps(orc.ew_system(orc.EXP, x0.size), orc.AB(4), x0, 0.0, 0.1, 0)
+    assert np.array_equal(y, x0)
+
+
+def test_controller_order_exponent(orc):
+    # k = 8 (Fehlberg 7(8)): the I controller's factor 0.9 err^(-1/8) is 2
+    # at err = 0.45^8, and a reject at err = 2^8 shrinks by 0.45; k = 5 is the
+    # default controller bitwise
+    acc, fac, ep, _ = orc.ctrl_decide(orc.CTRL_I, 0.45 ** 8, 1.0, False, order_k=8.0)
+    assert acc and fac == pytest.approx(2.0, rel=1e-14) and ep == 0.45 ** 8
+    acc, fac, _, lr = orc.ctrl_decide(orc.CTRL_I, 256.0, 1.0, False, order_k=8.0)
+    assert not acc and fac == pytest.approx(0.45, rel=1e-15) and lr
+    # PI: 0.9 * err^(-0.7/8) * prev^(0.4/8)
+    acc, fac, _, _ = orc.ctrl_decide(orc.CTRL_PI, 2.0 ** -8, 2.0 ** -8, False, order_k=8.0)
+    assert fac == pytest.approx(0.9 * 2 ** 0.7 * 2 ** -0.4, rel=1e-14)
+    for err in (1e-7, 0.3, 0.99, 1.7, float("nan")):
+        for prev, lr in ((1.0, False), (0.02, True)):
+            assert orc.ctrl_decide(orc.CTRL_PI, err, prev, lr, order_k=5.0)[1:] == \
+                orc.ctrl_decide(orc.CTRL_PI, err, prev, lr)[1:] or math.isnan(err)
