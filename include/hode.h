@@ -48,9 +48,14 @@ enum { HODE_F32 = 1, HODE_F64 = 2 };
 enum { HODE_RHS_EXP = 1, HODE_RHS_LOGISTIC = 2, HODE_RHS_GRAYSCOTT3D = 3 };
 /* Steppers (the paper's Table 1): classical Runge-Kutta 4; Dormand-Prince
  * 5(4) ("Dopri5", 7 stages, first same as last); Cash-Karp 5(4) (6 stages,
- * Cash & Karp 1990); explicit Euler (fixed steps only).  The embedded pairs
- * carry the 5th-order solution. */
-enum { HODE_RK4 = 1, HODE_DOPRI5 = 2, HODE_CASHKARP54 = 3, HODE_EULER = 4 };
+ * Cash & Karp 1990); explicit Euler (fixed steps only); Runge-Kutta-Fehlberg
+ * 7(8) (13 stages, Fehlberg 1968; carries the 8th-order solution); and the
+ * multi-step Adams-Bashforth methods with s = 1 .. 8 steps, HODE_AB1 + s - 1
+ * (fixed steps only; y_{n+1} = y_n + h sum_j beta_j f_{n-j} over the last s
+ * right-hand sides, the first s - 1 steps of a fresh history taken by the
+ * Fehlberg 7(8) step).  The 5(4) pairs carry the 5th-order solution. */
+enum { HODE_RK4 = 1, HODE_DOPRI5 = 2, HODE_CASHKARP54 = 3, HODE_EULER = 4, HODE_FEHLBERG78 = 5 };
+enum { HODE_AB1 = 11, HODE_AB2, HODE_AB3, HODE_AB4, HODE_AB5, HODE_AB6, HODE_AB7, HODE_AB8 };
 enum { HODE_CTRL_PI = 1, HODE_CTRL_I = 2, HODE_CTRL_MLP = 3 };
 enum {
   HODE_OK = 0,
@@ -121,12 +126,22 @@ int hode_set_controller(hode_ctx *ctx, int kind, const void *weights, size_t nby
 int hode_do_step(hode_ctx *ctx, int method, double t, double dt);
 
 /* n fixed steps (Odeint integrate_const with n = (tf - t0)/dt):
- * t_n = t0 + n dt.  *t_end (may be NULL) receives t_n. */
+ * t_n = t0 + n dt.  *t_end (may be NULL) receives t_n.
+ * Adams-Bashforth keeps its history of right-hand sides in the context, as an
+ * Odeint stepper object does: a call with the same s and dt continues it (n
+ * steps in several calls equal n in one); a different s or dt, any other
+ * stepping call, hode_set_rhs or hode_init_state starts a fresh history.
+ * Its ring of s right-hand sides (and, Gray-Scott, the 12 Fehlberg stage
+ * arrays for the start-up) is allocated on first use. */
 int hode_integrate_n_steps(hode_ctx *ctx, int method, double t0, double dt, int64_t n, double *t_end);
 
 /* Embedded pair of the adaptive calls (hode_try_step,
- * hode_integrate_adaptive): HODE_DOPRI5 (default) or HODE_CASHKARP54.  Both
- * use the same error norm and controller (embedded order 4).  Not for
+ * hode_integrate_adaptive, hode_integrate_times): HODE_DOPRI5 (default),
+ * HODE_CASHKARP54 or HODE_FEHLBERG78.  All use the same error norm; the
+ * controller's exponents follow the embedded order (k = 5 for the 5(4)
+ * pairs, 8 for Fehlberg 7(8): alpha = 0.7/k, beta = 0.4/k, reject factor
+ * 0.9 err^(-1/k)).  The learned controller (trained on the 5(4) pairs) is
+ * refused with Fehlberg 7(8) (HODE_EINVAL at the integrate call).  Not for
  * ensemble contexts (they step with Dopri5). */
 int hode_set_stepper(hode_ctx *ctx, int method);
 
@@ -189,19 +204,21 @@ int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);  /* the widest stage's
  * for the widest that divides N (16-byte loads where possible). */
 int hode_set_vector_width(hode_ctx *ctx, int vw);
 
-/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..16 as D1,
- * R2, R3, R4, D2..D7, D7F, C4, C5, C6, C6F, E1, D6F; element-wise: kind =
- * method) on the context's
+/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..38 as D1,
+ * R2, R3, R4, D2..D7, D7F, C4, C5, C6, C6F, E1, D6F, F1..F13, F13F,
+ * AB1..AB8; element-wise: kind = method) on the context's
  * stream with HIP events and returns the mean duration in milliseconds.
- * The state is left unchanged for Gray-Scott non-final kinds only. */
+ * The state is left unchanged for Gray-Scott non-final kinds only; timing an
+ * Adams-Bashforth kind ends the Adams-Bashforth history. */
 int hode_time_kernel(hode_ctx *ctx, int kind, int reps, double *avg_ms);
 
 /* Gray-Scott: runs `reps` attempts of `method` (RK4: stages D1 R2 R3 R4;
  * DOPRI5: stages D2..D7 of an adaptive attempt; CASHKARP54: D1 D2 D3 C4 C5
- * C6) with the control kernel in a
- * no-op timing mode, HIP events around every stage kernel on the context's
- * stream, and writes the mean duration of each stage in milliseconds to
- * ms[0..3] or ms[0..5].  The current state is left unchanged (and k1 = f(y)). */
+ * C6; FEHLBERG78: F1..F13; HODE_AB<s>: its one kernel) with the control
+ * kernel in a no-op timing mode, HIP events around every stage kernel on the
+ * context's stream, and writes the mean duration of each stage in
+ * milliseconds to ms[0 .. stages-1] (ms holds at least 13).  The current
+ * state is left unchanged (and k1 = f(y)); Adams-Bashforth ends its history. */
 int hode_profile_attempt(hode_ctx *ctx, int method, int reps, double *ms);
 
 /* Gray-Scott: times one attempt of `method` for every tile configuration
@@ -209,7 +226,8 @@ int hode_profile_attempt(hode_ctx *ctx, int method, int reps, double *ms);
  * 12, at least 8) with hode_profile_attempt and keeps, for every stage kernel
  * of the attempt, its fastest configuration (the first k1 and the fixed-step
  * stage variants take those of their shape twins); returned are the widest
- * stage's (stage 6 of Dopri5, stage 4 of RK4) and the sum of the stages'
+ * stage's (stage 6 of Dopri5 and Cash-Karp, stage 4 of RK4, stage 13 of
+ * Fehlberg 7(8), the one kernel of Adams-Bashforth) and the sum of the stages'
  * best times (ms); any output pointer may be NULL.  Results are bitwise
  * identical for every tile.  hode_set_tile sets one tile for all stages. */
 int hode_autotune(hode_ctx *ctx, int method, int reps, int *best_ry, int *best_zc, double *best_ms);

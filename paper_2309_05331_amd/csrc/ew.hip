@@ -2,11 +2,13 @@
 // exponential dx/dt = x and sigmoidal (logistic) dx/dt = x (1 - x), one
 // independent ODE per component.  With no spatial coupling every stage of a
 // step needs only the component itself, so the entire Euler or RK4 step, Dopri5
-// attempt (7 stages, first same as last) or Cash-Karp 5(4) attempt (6
-// stages) runs in registers: each component is
+// attempt (7 stages, first same as last), Cash-Karp 5(4) attempt (6 stages)
+// or Fehlberg 7(8) attempt (13 stages) runs in registers: each component is
 // read once and written once per attempt, and the embedded error's L-infinity
 // norm is reduced on the fly (wavefront shuffle, LDS, one atomic per
 // workgroup).  The one-wavefront control kernel then takes the decision.
+// An Adams-Bashforth step reads the component's s - 1 past right-hand sides
+// from the ring and writes the new one.
 #include "hode_internal.h"
 
 namespace hode {
@@ -188,6 +190,135 @@ __global__ __launch_bounds__(256) void ew_step(DevCtrl* __restrict__ c, T* __res
   if constexpr (mode_adaptive(MODE)) block_max_to<256>(emax, &c->errmax_bits);
 }
 
+// One Fehlberg 7(8) attempt of one component in registers (13 stages; zero
+// tableau entries are skipped at compile time).  q = h F78A, qb = h F78B in
+// the state's precision; the error h 41/840 (k12 + k13 - k1 - k11) in FP64.
+template <typename T, int RHS, bool ADAPT>
+__device__ __forceinline__ T f78_one(T x, const T (&q)[13][13], const T (&qb)[13], double qe, double atol,
+                                     double rtol, uint64_t& emax, T& k1) {
+  T k[13];
+  k[0] = frhs<T, RHS>(x);
+#pragma unroll
+  for (int s = 1; s < 13; ++s) {
+    T w = x;
+#pragma unroll
+    for (int j = 0; j < s; ++j)
+      if (F78A[s][j] != 0.0) w += q[s][j] * k[j];
+    k[s] = frhs<T, RHS>(w);
+  }
+  T xn = x;
+#pragma unroll
+  for (int j = 0; j < 13; ++j)
+    if (F78B[j] != 0.0) xn += qb[j] * k[j];
+  if constexpr (ADAPT) {
+    const double e = qe * (((double)k[11] - (double)k[0] - (double)k[10]) + (double)k[12]);
+    const double ratio = fabs(e) / (atol + rtol * fmax(fabs((double)x), fabs((double)xn)));
+    const uint64_t bits = (uint64_t)__double_as_longlong(ratio);
+    emax = bits > emax ? bits : emax;
+  }
+  k1 = k[0];
+  return xn;
+}
+
+// Fehlberg 7(8) attempt (adaptive) or fixed step over all components; kout,
+// if not null, receives k1 = f(y) (the right-hand side an Adams-Bashforth
+// start-up step records).
+template <typename T, int RHS, bool ADAPT>
+__global__ __launch_bounds__(256) void ew_f78(DevCtrl* __restrict__ c, T* __restrict__ b0, T* __restrict__ b1,
+                                              T* __restrict__ kout, int64_t n) {
+  if (c->done) return;
+  const double h = c->h;
+  const T* __restrict__ y = c->parity ? b1 : b0;
+  T* __restrict__ yn = c->parity ? b0 : b1;
+  const double atol = c->atol, rtol = c->rtol;
+  T q[13][13], qb[13];
+#pragma unroll
+  for (int s = 0; s < 13; ++s) {
+#pragma unroll
+    for (int j = 0; j < 13; ++j) q[s][j] = (T)(h * F78A[s][j]);
+    qb[s] = (T)(h * F78B[s]);
+  }
+  const double qe = h * F78E;
+  uint64_t emax = 0;
+  using V = typename Vec<T>::V;
+  constexpr int W = Vec<T>::W;
+  const int64_t nv = n / W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    V v = reinterpret_cast<const V*>(y)[i];
+    V kv;
+    T* e = reinterpret_cast<T*>(&v);
+    T* k1 = reinterpret_cast<T*>(&kv);
+#pragma unroll
+    for (int j = 0; j < W; ++j) e[j] = f78_one<T, RHS, ADAPT>(e[j], q, qb, qe, atol, rtol, emax, k1[j]);
+    reinterpret_cast<V*>(yn)[i] = v;
+    if (kout) reinterpret_cast<V*>(kout)[i] = kv;
+  }
+  const int64_t tail = nv * W;
+  if (blockIdx.x == gridDim.x - 1 && tail + threadIdx.x < n) {
+    const int64_t i = tail + threadIdx.x;
+    T k1;
+    yn[i] = f78_one<T, RHS, ADAPT>(y[i], q, qb, qe, atol, rtol, emax, k1);
+    if (kout) kout[i] = k1;
+  }
+  if constexpr (ADAPT) block_max_to<256>(emax, &c->errmax_bits);
+}
+
+// One Adams-Bashforth step with S steps over all components: f_n = f(y_n)
+// goes into ring slot c->ring (S > 1), and y_{n+1} = y_n + h sum_{j>=1}
+// beta_j f_{n-j} + h beta_0 f_n with f_{n-j} from the ring (table xk).
+template <typename T, int RHS, int S>
+__global__ __launch_bounds__(256) void ew_ab(DevCtrl* __restrict__ c, T* __restrict__ b0, T* __restrict__ b1,
+                                             void* const* __restrict__ xk, int64_t n) {
+  if (c->done) return;
+  const double h = c->h;
+  const T* __restrict__ y = c->parity ? b1 : b0;
+  T* __restrict__ yn = c->parity ? b0 : b1;
+  const int rg = c->ring;
+  T* __restrict__ fn = S > 1 ? (T*)xk[kRingBase + rg] : nullptr;
+  const T* fp[S > 1 ? S : 1];
+  T q[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    q[j] = (T)(h * ABW[S - 1][j]);
+    if (j > 0) fp[j] = (const T*)xk[kRingBase + (rg + S - j) % S];
+  }
+  using V = typename Vec<T>::V;
+  constexpr int W = Vec<T>::W;
+  const int64_t nv = n / W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    V v = reinterpret_cast<const V*>(y)[i];
+    V past[S > 1 ? S : 1];
+#pragma unroll
+    for (int j = 1; j < S; ++j) past[j] = reinterpret_cast<const V*>(fp[j])[i];
+    V fv;
+    T* e = reinterpret_cast<T*>(&v);
+    T* f = reinterpret_cast<T*>(&fv);
+#pragma unroll
+    for (int l = 0; l < W; ++l) {
+      f[l] = frhs<T, RHS>(e[l]);
+      T acc = e[l];
+#pragma unroll
+      for (int j = 1; j < S; ++j) acc += q[j] * reinterpret_cast<const T*>(&past[j])[l];
+      e[l] = acc + q[0] * f[l];
+    }
+    reinterpret_cast<V*>(yn)[i] = v;
+    if constexpr (S > 1) reinterpret_cast<V*>(fn)[i] = fv;
+  }
+  const int64_t tail = nv * W;
+  if (blockIdx.x == gridDim.x - 1 && tail + threadIdx.x < n) {
+    const int64_t i = tail + threadIdx.x;
+    const T x = y[i];
+    const T f = frhs<T, RHS>(x);
+    T acc = x;
+#pragma unroll
+    for (int j = 1; j < S; ++j) acc += q[j] * fp[j][i];
+    yn[i] = acc + q[0] * f;
+    if constexpr (S > 1) fn[i] = f;
+  }
+}
+
 __global__ __launch_bounds__(64) void ctrl_kernel(DevCtrl* c) {
   if (c->done) return;
   ctrl_step(c);
@@ -210,7 +341,38 @@ hipError_t launch_rhs(int mode, T* y0, T* y1, int64_t n, int grid, DevCtrl* c, h
   return hipGetLastError();
 }
 
+template <typename T, int RHS>
+hipError_t launch_x(int mode, int ab_steps, T* y0, T* y1, void* const* xk, T* kout, int64_t n, int grid,
+                    DevCtrl* c, hipStream_t s) {
+  if (mode == MODE_FIXED_F78) ew_f78<T, RHS, false><<<grid, 256, 0, s>>>(c, y0, y1, kout, n);
+  else if (mode == MODE_ADAPTIVE_F78) ew_f78<T, RHS, true><<<grid, 256, 0, s>>>(c, y0, y1, kout, n);
+  else if (mode == MODE_FIXED_AB) {
+    if (xk == nullptr && ab_steps > 1) return hipErrorInvalidValue;
+    switch (ab_steps) {
+#define HODE_AB(S) \
+  case S: ew_ab<T, RHS, S><<<grid, 256, 0, s>>>(c, y0, y1, xk, n); break;
+      HODE_AB(1) HODE_AB(2) HODE_AB(3) HODE_AB(4) HODE_AB(5) HODE_AB(6) HODE_AB(7) HODE_AB(8)
+#undef HODE_AB
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_ewx(int dtype, int rhs, int mode, int ab_steps, void* y0, void* y1, void* const* xk, void* kout,
+                      int64_t n, int grid, DevCtrl* c, hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  if (dtype == 1) {
+    if (rhs == 1) return launch_x<float, 1>(mode, ab_steps, (float*)y0, (float*)y1, xk, (float*)kout, n, grid, c, s);
+    return launch_x<float, 2>(mode, ab_steps, (float*)y0, (float*)y1, xk, (float*)kout, n, grid, c, s);
+  }
+  if (rhs == 1) return launch_x<double, 1>(mode, ab_steps, (double*)y0, (double*)y1, xk, (double*)kout, n, grid, c, s);
+  return launch_x<double, 2>(mode, ab_steps, (double*)y0, (double*)y1, xk, (double*)kout, n, grid, c, s);
+}
 
 hipError_t launch_ctrl(DevCtrl* c, hipStream_t s) {
   ctrl_kernel<<<1, 64, 0, s>>>(c);

@@ -1,40 +1,12 @@
-// Single-grid launches of the fused Runge-Kutta stage kernels: one tile
-// (stage_tile, in stage.h) per workgroup over the whole grid.
-//
-// Block order is XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so
-// the linear block id is remapped to give each XCD a contiguous range of
-// tiles, keeping y- and z-adjacent tiles (whose halo rows overlap) on one L2.
+// Single-grid launches of the fused Runge-Kutta stage kernels of RK4, Dopri5,
+// Cash-Karp 5(4) and Euler: one tile (stage_tile, in stage.h) per workgroup
+// over the whole grid (gs_stage, in stage.h).  The Fehlberg 7(8) and
+// Adams-Bashforth kinds are launched from gsx.hip.
 #include "stage.h"
 
 namespace hode {
 
 namespace {
-
-// One stage over a whole grid: one tile per workgroup.  The linear block id
-// is remapped XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so
-// each XCD gets a contiguous range of tiles and y/z-adjacent tiles (whose
-// halo rows overlap) share an L2.  Consecutive stages sweep those ranges in
-// opposite directions.
-template <typename T, int KIND, int RY, int VW>
-__global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __restrict__ c) {
-  __shared__ __align__(16) char smem[kTileSmem];
-  if (c->done) return;
-  const int N = a.N;
-  const int nx = (N + 64 * VW - 1) / (64 * VW);
-  const int ny = (N + 4 * RY - 1) / (4 * RY);
-  const int nz = (N + a.zc - 1) / a.zc;
-  const int per = (gridDim.x + 7) / 8;
-  // Stages alternate their direction through each XCD's range, so a stage
-  // starts on the tiles the previous stage wrote last, which are still in the
-  // memory-side Infinity Cache.
-  constexpr bool rev = KIND == K_R2 || KIND == K_R4 || KIND == K_D3 || KIND == K_D5 || KIND == K_D7 ||
-                       KIND == K_D7F || KIND == K_C5;
-  const int slot = rev ? per - 1 - (int)(blockIdx.x >> 3) : (int)(blockIdx.x >> 3);
-  const int bb = (blockIdx.x & 7) * per + slot;
-  if (bb >= nx * ny * nz) return;  // padding block of the remap (whole block)
-  const int tz = bb / (nx * ny);
-  stage_tile<T, KIND, RY, VW>(a, c, smem, bb % nx, (bb / nx) % ny, tz * a.zc, min(N, (tz + 1) * a.zc));
-}
 
 template <typename T, int RY, int VW>
 hipError_t launch_t(int kind, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
@@ -72,7 +44,8 @@ bool gs_ry_supported(int ry) { return ry == 1 || ry == 2 || ry == 4; }
 // kind K_COUNT is the fixed-step stage 6 (new state only).  vw: cells per
 // lane (0 = widest that divides N: 16-byte loads when possible).
 hipError_t launch_gs(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
-  if (a.N < 1 || a.zc < 1 || kind < 0 || kind > K_COUNT) return hipErrorInvalidValue;
+  if (kind > K_COUNT) return launch_gsx(kind, dtype, ry, vw, a, c, s);
+  if (a.N < 1 || a.zc < 1 || kind < 0) return hipErrorInvalidValue;
   if (dtype == 1) {
     if (vw == 0) vw = a.N % 4 == 0 ? 4 : (a.N % 2 == 0 ? 2 : 1);
     if (a.N % vw) return hipErrorInvalidValue;

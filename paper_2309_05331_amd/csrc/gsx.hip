@@ -1,0 +1,65 @@
+// Single-grid launches of the Gray-Scott stage kernels of the higher-order
+// and multi-step methods of the paper's Table 1: Runge-Kutta-Fehlberg 7(8)
+// (13 stages; F13 forms the new state and, adaptive, the error norm at the
+// own cell) and Adams-Bashforth with 1 to 8 steps (one right-hand side per
+// step: f_n goes into the ring of past right-hand sides and the new state is
+// formed from it and the s - 1 before).  Same tiles and block order as the
+// other stage kernels (stage.h); a translation unit of its own so the two
+// build in parallel.
+#include "stage.h"
+
+namespace hode {
+
+namespace {
+
+template <typename T, int RY, int VW>
+hipError_t launch_t(int kind, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
+  constexpr int TX = 64 * VW;
+  const int nx = (a.N + TX - 1) / TX;
+  const int ny = (a.N + 4 * RY - 1) / (4 * RY);
+  const int nz = (a.N + a.zc - 1) / a.zc;
+  const int64_t nb = (int64_t)nx * ny * nz;
+  const int64_t grid = (nb + 7) / 8 * 8;  // whole rounds of the XCD remap
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  switch (kind) {
+#define HODE_CASE(K) \
+  case K: gs_stage<T, K, RY, VW><<<dim3((unsigned)grid), dim3(256), 0, s>>>(a, c); break;
+    HODE_CASE(K_F1) HODE_CASE(K_F2) HODE_CASE(K_F3) HODE_CASE(K_F4) HODE_CASE(K_F5) HODE_CASE(K_F6)
+    HODE_CASE(K_F7) HODE_CASE(K_F8) HODE_CASE(K_F9) HODE_CASE(K_F10) HODE_CASE(K_F11) HODE_CASE(K_F12)
+    HODE_CASE(K_F13) HODE_CASE(K_F13F) HODE_CASE(K_AB1) HODE_CASE(K_AB2) HODE_CASE(K_AB3) HODE_CASE(K_AB4)
+    HODE_CASE(K_AB5) HODE_CASE(K_AB6) HODE_CASE(K_AB7) HODE_CASE(K_AB8)
+#undef HODE_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int VW>
+hipError_t launch_vw(int kind, int ry, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
+  if (ry == 1) return launch_t<T, 1, VW>(kind, a, c, s);
+  if (ry == 2) return launch_t<T, 2, VW>(kind, a, c, s);
+  if (ry == 4) return launch_t<T, 4, VW>(kind, a, c, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+// Every kind here reads extra arrays through the table xk(a), which must hold them.
+hipError_t launch_gsx(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
+  if (a.N < 1 || a.zc < 1 || kind < K_F1 || kind >= K_ALL || xk(a) == nullptr) return hipErrorInvalidValue;
+  if (dtype == 1) {
+    if (vw == 0) vw = a.N % 4 == 0 ? 4 : (a.N % 2 == 0 ? 2 : 1);
+    if (a.N % vw) return hipErrorInvalidValue;
+    if (vw == 4) return launch_vw<float, 4>(kind, ry, a, c, s);
+    if (vw == 2) return launch_vw<float, 2>(kind, ry, a, c, s);
+    if (vw == 1) return launch_vw<float, 1>(kind, ry, a, c, s);
+    return hipErrorInvalidValue;
+  }
+  if (vw == 0) vw = a.N % 2 == 0 ? 2 : 1;
+  if (a.N % vw) return hipErrorInvalidValue;
+  if (vw == 2) return launch_vw<double, 2>(kind, ry, a, c, s);
+  if (vw == 1) return launch_vw<double, 1>(kind, ry, a, c, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace hode

@@ -75,7 +75,17 @@ struct hode_ctx {
   int ctrl_kind = hode::CTRL_PI;
   double atol = 1e-6, rtol = 1e-6;
   int ry = 0, zc = 0, ew_grid = 0, vw = 0;  // ry, zc: the tile of the widest stage kind
-  int kry[hode::K_COUNT + 1] = {0}, kzc[hode::K_COUNT + 1] = {0};  // tile of every stage kind
+  int kry[hode::K_ALL] = {0}, kzc[hode::K_ALL] = {0};  // tile of every stage kind
+  // extra arrays (Fehlberg 7(8) stages k1 .. k12 on the Gray-Scott path, the
+  // Adams-Bashforth ring of past right-hand sides), allocated on first use,
+  // and their device table
+  void* xk_arr[hode::kXkCount] = {nullptr};
+  void** d_xk = nullptr;
+  // Adams-Bashforth history (as an Odeint stepper object keeps it): steps s
+  // (0: none), its step size, and the steps taken since it started
+  int ab_steps = 0;
+  double ab_dt = 0;
+  int64_t ab_n = 0;
   bool k1_valid = false;
   int parity = 0, k1slot = 0;
   bool use_graphs = true;      // replay captured chunks (else enqueue every kernel)
@@ -115,6 +125,10 @@ void free_state(hode_ctx* c) {
   for (void*& p : c->y) { if (p) (void)hipFree(p); p = nullptr; }
   for (void*& p : c->ks) { if (p) (void)hipFree(p); p = nullptr; }
   for (void*& p : c->k) { if (p) (void)hipFree(p); p = nullptr; }
+  for (void*& p : c->xk_arr) { if (p) (void)hipFree(p); p = nullptr; }
+  if (c->d_xk) (void)hipFree(c->d_xk);
+  c->d_xk = nullptr;
+  c->ab_steps = 0;
   c->nelem = 0;
   c->N = 0;
   c->dtype = 0;
@@ -126,6 +140,7 @@ hode::GSLaunch gs_args(const hode_ctx* c) {
   hode::GSLaunch a{};
   for (int i = 0; i < 2; ++i) { a.y[i] = c->y[i]; a.ks[i] = c->ks[i]; }
   for (int i = 0; i < 7; ++i) a.k[i] = c->k[i];
+  a.k[0] = (void*)c->d_xk;  // the extra arrays' table (see hode::xk)
   a.N = c->N;
   a.n3 = (int64_t)c->N * c->N * c->N;
   a.zc = c->zc;
@@ -146,7 +161,7 @@ hipError_t launch_stage(const hode_ctx* c, int kind, hode::GSLaunch a) {
 void set_all_tiles(hode_ctx* c, int ry, int zc) {
   c->ry = ry;
   c->zc = zc;
-  for (int k = 0; k <= hode::K_COUNT; ++k) {
+  for (int k = 0; k < hode::K_ALL; ++k) {
     c->kry[k] = ry;
     c->kzc[k] = zc;
   }
@@ -170,11 +185,65 @@ int default_ew_grid(int64_t n, int dtype) {
   return (int)g;
 }
 
-// Enqueues the kernels of one attempt (or fixed step) in `mode`.
+// Allocates the extra arrays a run needs (Gray-Scott Fehlberg stages; the
+// first `ring` Adams-Bashforth ring slots) and refreshes their device table.
+int ensure_xk(hode_ctx* c, bool f78, int ring) {
+  bool changed = false;
+  const size_t bytes = std::max<size_t>(256, (size_t)c->nelem * c->esize);
+  auto need = [&](int i) -> bool {
+    if (c->xk_arr[i]) return true;
+    if (hipMalloc(&c->xk_arr[i], bytes) != hipSuccess) {
+      c->xk_arr[i] = nullptr;
+      return false;
+    }
+    changed = true;
+    return true;
+  };
+  if (f78 && is_gs(c))
+    for (int i = 0; i < hode::kXkF78; ++i)
+      if (!need(i)) return fail(c, HODE_ENOMEM, "device allocation failed (Fehlberg stages)");
+  for (int i = 0; i < ring; ++i)
+    if (!need(hode::kRingBase + i)) return fail(c, HODE_ENOMEM, "device allocation failed (Adams-Bashforth ring)");
+  if (!c->d_xk) {
+    if (hipMalloc(&c->d_xk, sizeof(void*) * hode::kXkCount) != hipSuccess) {
+      c->d_xk = nullptr;
+      return fail(c, HODE_ENOMEM, "device allocation failed");
+    }
+    changed = true;
+    clear_graphs(c);  // captured launches hold the table's address
+  }
+  if (changed) {
+    HIPCHK(c, hipMemcpyAsync(c->d_xk, c->xk_arr, sizeof(void*) * hode::kXkCount, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return HODE_OK;
+}
+
+bool mode_f78(int mode) { return mode == hode::MODE_FIXED_F78 || mode == hode::MODE_ADAPTIVE_F78; }
+
+// Enqueues the kernels of one attempt (or fixed step) in `mode`
+// (Adams-Bashforth: with the context's current number of steps).
 hipError_t enqueue_attempt(hode_ctx* c, int mode) {
   if (!is_gs(c)) {
-    hipError_t e = hode::launch_ew(c->dtype, c->rhs, mode, c->y[0], c->y[1], c->nelem, c->ew_grid, c->d_ctrl,
-                                   c->stream);
+    hipError_t e = mode_f78(mode) || mode == hode::MODE_FIXED_AB
+                       ? hode::launch_ewx(c->dtype, c->rhs, mode, c->ab_steps, c->y[0], c->y[1], c->d_xk, nullptr,
+                                          c->nelem, c->ew_grid, c->d_ctrl, c->stream)
+                       : hode::launch_ew(c->dtype, c->rhs, mode, c->y[0], c->y[1], c->nelem, c->ew_grid,
+                                         c->d_ctrl, c->stream);
+    return e != hipSuccess ? e : hode::launch_ctrl(c->d_ctrl, c->stream);
+  }
+  if (mode_f78(mode) || mode == hode::MODE_FIXED_AB) {
+    const hode::GSLaunch a = gs_args(c);
+    if (mode == hode::MODE_FIXED_AB) {
+      if (c->ab_steps < 1 || c->ab_steps > 8) return hipErrorInvalidValue;
+      hipError_t e = launch_stage(c, hode::K_AB1 + c->ab_steps - 1, a);
+      return e != hipSuccess ? e : hode::launch_ctrl(c->d_ctrl, c->stream);
+    }
+    for (int k = hode::K_F1; k <= hode::K_F12; ++k) {
+      hipError_t e = launch_stage(c, k, a);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_stage(c, mode == hode::MODE_ADAPTIVE_F78 ? hode::K_F13 : hode::K_F13F, a);
     return e != hipSuccess ? e : hode::launch_ctrl(c->d_ctrl, c->stream);
   }
   const hode::GSLaunch a = gs_args(c);
@@ -200,7 +269,8 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
 }
 
 int get_graph(hode_ctx* c, int mode, int M, hipGraphExec_t* out) {
-  auto key = std::make_pair(mode, M);
+  // Adams-Bashforth chunks differ by the number of steps
+  auto key = std::make_pair(mode == hode::MODE_FIXED_AB ? mode | (c->ab_steps << 8) : mode, M);
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) { *out = it->second; return HODE_OK; }
   hipGraph_t g = nullptr;
@@ -228,7 +298,16 @@ double gs_stiffness(const double* prm, int N) {
 }
 
 int adaptive_mode(const hode_ctx* c) {
-  return c->stepper == HODE_CASHKARP54 ? hode::MODE_ADAPTIVE_CK : hode::MODE_ADAPTIVE;
+  return c->stepper == HODE_CASHKARP54   ? hode::MODE_ADAPTIVE_CK
+         : c->stepper == HODE_FEHLBERG78 ? hode::MODE_ADAPTIVE_F78
+                                         : hode::MODE_ADAPTIVE;
+}
+
+// The learned controller was trained on the 5(4) pairs' error sequences.
+int check_adaptive(hode_ctx* c) {
+  if (c->ctrl_kind == hode::CTRL_MLP && c->stepper == HODE_FEHLBERG78)
+    return fail(c, HODE_EINVAL, "the learned controller serves the 5(4) pairs; use PI or I with Fehlberg 7(8)");
+  return HODE_OK;
 }
 
 DevCtrl base_ctrl(const hode_ctx* c, int mode) {
@@ -265,6 +344,12 @@ int pow2_floor(int64_t x) {
 
 // Runs the device-resident loop from the control block `init` until done.
 int run_loop(hode_ctx* c, const DevCtrl& init, bool need_k1) {
+  if (mode_f78(init.mode) || init.mode == hode::MODE_FIXED_AB) {
+    int rc = ensure_xk(c, mode_f78(init.mode), init.mode == hode::MODE_FIXED_AB ? init.ab_steps : 0);
+    if (rc) return rc;
+  }
+  // every other stepping ends the Adams-Bashforth history
+  if (init.mode != hode::MODE_FIXED_AB) c->ab_steps = 0;
   *c->h_ctrl = init;
   HIPCHK(c, hipMemcpyAsync(c->d_ctrl, c->h_ctrl, sizeof(DevCtrl), hipMemcpyHostToDevice, c->stream));
   int64_t extra_evals = 0;
@@ -311,6 +396,71 @@ int run_loop(hode_ctx* c, const DevCtrl& init, bool need_k1) {
   c->last.status = cur.status;
   c->last_attempts = cur.attempts;
   c->persist = cur;
+  return HODE_OK;
+}
+
+// One Adams-Bashforth start-up step: a Fehlberg 7(8) fixed step from the
+// current state that also records f(y_n) (its k1) in ring slot `slot`.  d
+// carries time and counters from step to step.
+int ab_startup_step(hode_ctx* c, DevCtrl& d, int slot) {
+  d.mode = hode::MODE_FIXED_F78;
+  d.nsteps = d.accepted + 1;
+  d.done = 0;
+  d.parity = c->parity;
+  d.k1slot = c->k1slot;
+  *c->h_ctrl = d;
+  HIPCHK(c, hipMemcpyAsync(c->d_ctrl, c->h_ctrl, sizeof(DevCtrl), hipMemcpyHostToDevice, c->stream));
+  void* ring = c->xk_arr[hode::kRingBase + slot];
+  if (is_gs(c)) {
+    const hode::GSLaunch a = gs_args(c);
+    for (int k = hode::K_F1; k <= hode::K_F12; ++k) HIPCHK(c, launch_stage(c, k, a));
+    HIPCHK(c, launch_stage(c, hode::K_F13F, a));
+    HIPCHK(c, hipMemcpyAsync(ring, c->xk_arr[0], (size_t)c->nelem * c->esize, hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    HIPCHK(c, hode::launch_ewx(c->dtype, c->rhs, hode::MODE_FIXED_F78, 0, c->y[0], c->y[1], c->d_xk, ring,
+                               c->nelem, c->ew_grid, c->d_ctrl, c->stream));
+  }
+  HIPCHK(c, hode::launch_ctrl(c->d_ctrl, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, sizeof(DevCtrl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  d = *c->h_ctrl;
+  c->parity = d.parity;
+  c->k1slot = d.k1slot;
+  c->k1_valid = false;
+  return HODE_OK;
+}
+
+// n fixed Adams-Bashforth steps with s steps.  The history (the last s
+// right-hand sides) continues from the previous call when s and dt are the
+// same and no other stepping came in between; otherwise it starts afresh,
+// and the first s - 1 steps are Fehlberg 7(8) steps that record f(y_n).
+int ab_run(hode_ctx* c, int s, double t0, double dt, int64_t n) {
+  if (!(c->ab_steps == s && c->ab_dt == dt)) {
+    c->ab_steps = s;
+    c->ab_dt = dt;
+    c->ab_n = 0;
+  }
+  int rc = ensure_xk(c, c->ab_n < s - 1 && n > 0, s);
+  if (rc) return rc;
+  DevCtrl d = base_ctrl(c, hode::MODE_FIXED_AB);
+  d.t = d.t0 = t0;
+  d.h = d.dt = dt;
+  d.ab_steps = s;
+  int64_t i = 0;
+  for (; i < n && c->ab_n < s - 1; ++i) {
+    rc = ab_startup_step(c, d, (int)(c->ab_n % s));
+    if (rc) return rc;
+    ++c->ab_n;
+  }
+  d.mode = hode::MODE_FIXED_AB;
+  d.nsteps = n;
+  d.done = i >= n;
+  d.ring = (int)(c->ab_n % s);
+  d.parity = c->parity;
+  d.k1slot = c->k1slot;
+  rc = run_loop(c, d, false);
+  if (rc) return rc;
+  c->ab_n += n - i;
   return HODE_OK;
 }
 
@@ -469,6 +619,7 @@ int hode_set_rhs(hode_ctx* c, int rhs, const double* params, int nparams) {
   }
   c->rhs = rhs;
   c->k1_valid = false;
+  c->ab_steps = 0;
   clear_graphs(c);
   return HODE_OK;
 }
@@ -525,10 +676,17 @@ int hode_init_state(hode_ctx* c, int dtype, int nfields, int ndim, const int64_t
   c->k1slot = 0;
   c->k1_valid = false;
   c->persist_valid = false;
+  c->ab_steps = 0;
   if (!reuse) {
     if (is_gs(c)) {
       const int ry = c->ry ? c->ry : (dtype == HODE_F32 ? 4 : 2);
       set_all_tiles(c, ry, default_zc(N, ry));
+      // the Fehlberg and Adams-Bashforth kinds hold up to 10 source rows per
+      // register row: one row per wavefront keeps them out of scratch
+      for (int k = hode::K_F1; k < hode::K_ALL; ++k) {
+        c->kry[k] = 1;
+        c->kzc[k] = default_zc(N, 1);
+      }
     } else {
       c->ew_grid = default_ew_grid(nelem, dtype);
     }
@@ -579,14 +737,24 @@ int hode_set_controller(hode_ctx* c, int kind, const void* weights, size_t nbyte
 int hode_integrate_n_steps(hode_ctx* c, int method, double t0, double dt, int64_t n, double* t_end) {
   int rc = check_ready(c);
   if (rc) return rc;
-  if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54 && method != HODE_EULER)
+  const bool ab = method >= HODE_AB1 && method <= HODE_AB8;
+  if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54 && method != HODE_EULER &&
+      method != HODE_FEHLBERG78 && !ab)
     return fail(c, HODE_EINVAL, "method");
   if (n < 0 || !std::isfinite(t0) || !std::isfinite(dt)) return fail(c, HODE_EINVAL, "bad step arguments");
   HIPCHK(c, hipSetDevice(c->device));
-  const int mode = method == HODE_RK4      ? hode::MODE_FIXED_RK4
-                   : method == HODE_DOPRI5   ? hode::MODE_FIXED_DP5
-                   : method == HODE_CASHKARP54 ? hode::MODE_FIXED_CK
-                                               : hode::MODE_FIXED_EULER;
+  if (ab) {
+    rc = ab_run(c, method - HODE_AB1 + 1, t0, dt, n);
+    if (rc) return rc;
+    c->persist_valid = false;
+    if (t_end) *t_end = t0 + (double)n * dt;
+    return HODE_OK;
+  }
+  const int mode = method == HODE_RK4          ? hode::MODE_FIXED_RK4
+                   : method == HODE_DOPRI5       ? hode::MODE_FIXED_DP5
+                   : method == HODE_CASHKARP54   ? hode::MODE_FIXED_CK
+                   : method == HODE_FEHLBERG78   ? hode::MODE_FIXED_F78
+                                                 : hode::MODE_FIXED_EULER;
   DevCtrl d = base_ctrl(c, mode);
   d.t = d.t0 = t0;
   d.h = d.dt = dt;
@@ -608,6 +776,8 @@ int hode_integrate_adaptive(hode_ctx* c, double t0, double t1, double dt0, int64
   if (rc) return rc;
   if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0) || !(dt0 > 0) || !std::isfinite(dt0) || max_steps < 0)
     return fail(c, HODE_EINVAL, "bad integration arguments");
+  rc = check_adaptive(c);
+  if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
   DevCtrl d = base_ctrl(c, adaptive_mode(c));
   d.t = d.t0 = t0;
@@ -644,6 +814,8 @@ int hode_integrate_times(hode_ctx* c, const double* times, int64_t n_times, doub
       return fail(c, HODE_EINVAL, "times must be finite and increasing");
   const size_t bytes = (size_t)c->nelem * c->esize;
   if (!dst || dst_bytes / (size_t)n_times < bytes) return fail(c, HODE_ESTATE, "destination too small");
+  rc = check_adaptive(c);
+  if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
   const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   // the observation at times[0]: the current state
@@ -713,6 +885,8 @@ int hode_try_step(hode_ctx* c, double* t, double* dt, int* accepted) {
   if (rc) return rc;
   if (!t || !dt || !accepted || !std::isfinite(*t) || !(*dt > 0) || !std::isfinite(*dt))
     return fail(c, HODE_EINVAL, "bad try_step arguments");
+  rc = check_adaptive(c);
+  if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
   DevCtrl d = base_ctrl(c, adaptive_mode(c));
   if (c->persist_valid) {
@@ -830,9 +1004,16 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
   int rc = check_ready(c);
   if (rc) return rc;
   if (reps < 1 || !avg_ms) return fail(c, HODE_EINVAL, "reps >= 1 and avg_ms required");
-  if (is_gs(c) && (kind < 0 || kind > hode::K_D6F)) return fail(c, HODE_EINVAL, "kernel kind");
+  if (is_gs(c) && (kind < 0 || kind >= hode::K_ALL)) return fail(c, HODE_EINVAL, "kernel kind");
   if (!is_gs(c) && kind != HODE_RK4 && kind != HODE_DOPRI5) return fail(c, HODE_EINVAL, "kernel kind");
   HIPCHK(c, hipSetDevice(c->device));
+  if (is_gs(c) && kind >= hode::K_F1) {
+    // the Adams-Bashforth kinds write ring slot 0: the history ends
+    const int ring = kind >= hode::K_AB1 ? kind - hode::K_AB1 + 1 : 0;
+    rc = ensure_xk(c, ring == 0, ring);
+    if (rc) return rc;
+    if (ring) c->ab_steps = 0;
+  }
   // a control block in timing mode: kernels run with the last step size but
   // the epilogue changes nothing, so the current state and k1 stay intact
   DevCtrl d = base_ctrl(c, 0);
@@ -863,8 +1044,17 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
   return HODE_OK;
 }
 
-// Stage sequence of one attempt of `method` (adaptive for the embedded pairs).
+// Stage sequence of one attempt of `method` (adaptive for the embedded pairs;
+// Adams-Bashforth: its one kernel).  seq holds up to 13 kinds.
 static int stage_seq(int method, int* seq) {
+  if (method >= HODE_AB1 && method <= HODE_AB8) {
+    seq[0] = hode::K_AB1 + method - HODE_AB1;
+    return 1;
+  }
+  if (method == HODE_FEHLBERG78) {
+    for (int i = 0; i < 13; ++i) seq[i] = hode::K_F1 + i;
+    return 13;
+  }
   if (method == HODE_RK4) {
     const int s[] = {hode::K_D1, hode::K_R2, hode::K_R3, hode::K_R4};
     for (int i = 0; i < 4; ++i) seq[i] = s[i];
@@ -884,10 +1074,17 @@ int hode_profile_attempt(hode_ctx* c, int method, int reps, double* ms) {
   int rc = check_ready(c);
   if (rc) return rc;
   if (!is_gs(c)) return fail(c, HODE_EINVAL, "stage profiling is for the Gray-Scott path");
-  if (reps < 1 || !ms || (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54))
+  const bool ab = method >= HODE_AB1 && method <= HODE_AB8;
+  if (reps < 1 || !ms ||
+      (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54 && method != HODE_FEHLBERG78 && !ab))
     return fail(c, HODE_EINVAL, "arguments");
   HIPCHK(c, hipSetDevice(c->device));
-  int seq[8];
+  if (method == HODE_FEHLBERG78 || ab) {
+    rc = ensure_xk(c, !ab, ab ? method - HODE_AB1 + 1 : 0);
+    if (rc) return rc;
+    if (ab) c->ab_steps = 0;  // the timed steps overwrite ring slot 0
+  }
+  int seq[16];
   const int ns = stage_seq(method, seq);
   DevCtrl d = base_ctrl(c, 0);
   d.h = c->last.dt_next > 0 ? c->last.dt_next : 0.01;
@@ -898,9 +1095,9 @@ int hode_profile_attempt(hode_ctx* c, int method, int reps, double* ms) {
     HIPCHK(c, launch_stage(c, hode::K_D1, a));
     c->k1_valid = true;
   }
-  hipEvent_t ev[9];
+  hipEvent_t ev[17];
   for (int i = 0; i <= ns; ++i) HIPCHK(c, hipEventCreate(&ev[i]));
-  double acc[8] = {0};
+  double acc[16] = {0};
   hipError_t e = hipSuccess;
   for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // first round is warm-up
     for (int i = 0; i < ns && e == hipSuccess; ++i) {
@@ -926,7 +1123,9 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   int rc = check_ready(c);
   if (rc) return rc;
   if (!is_gs(c)) return fail(c, HODE_EINVAL, "autotuning is for the Gray-Scott path");
-  if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54) return fail(c, HODE_EINVAL, "method");
+  if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54 && method != HODE_FEHLBERG78 &&
+      !(method >= HODE_AB1 && method <= HODE_AB8))
+    return fail(c, HODE_EINVAL, "method");
   const int rys[] = {1, 2, 4};
   // plane chunks: powers of two, and the even splits of the grid into 1 .. 12
   // chunks (block counts that fill whole rounds of resident workgroups)
@@ -935,17 +1134,17 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   for (int nz = 1; nz <= 12; ++nz) zcs.push_back((c->N + nz - 1) / nz);
   std::sort(zcs.begin(), zcs.end());
   zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
-  int seq[8];
+  int seq[16];
   const int ns = stage_seq(method, seq);
   // every stage kind keeps its own fastest tile
-  double best[8];
-  int bry[8], bzc[8];
+  double best[16];
+  int bry[16], bzc[16];
   for (int i = 0; i < ns; ++i) { best[i] = 1e300; bry[i] = c->kry[seq[i]]; bzc[i] = c->kzc[seq[i]]; }
   for (int ry : rys) {
     for (int zc : zcs) {
       if ((zc > c->N || zc < 8) && zc != 8) continue;
       set_all_tiles(c, ry, zc);
-      double ms[8];
+      double ms[16];
       rc = hode_profile_attempt(c, method, reps, ms);
       if (rc) return rc;
       for (int i = 0; i < ns; ++i)
@@ -972,7 +1171,15 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
     c->kry[hode::K_C6F] = c->kry[hode::K_C6];
     c->kzc[hode::K_C6F] = c->kzc[hode::K_C6];
   }
-  const int widest = method == HODE_RK4 ? hode::K_R4 : (method == HODE_CASHKARP54 ? hode::K_C6 : hode::K_D6);
+  if (method == HODE_FEHLBERG78) {
+    c->kry[hode::K_F13F] = c->kry[hode::K_F13];
+    c->kzc[hode::K_F13F] = c->kzc[hode::K_F13];
+  }
+  const int widest = method == HODE_RK4           ? hode::K_R4
+                     : method == HODE_CASHKARP54  ? hode::K_C6
+                     : method == HODE_FEHLBERG78  ? hode::K_F13
+                     : method >= HODE_AB1         ? seq[0]
+                                                  : hode::K_D6;
   c->ry = c->kry[widest];
   c->zc = c->kzc[widest];
   clear_graphs(c);
@@ -984,7 +1191,8 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
 
 int hode_set_stepper(hode_ctx* c, int method) {
   if (!c) return HODE_EINVAL;
-  if (method != HODE_DOPRI5 && method != HODE_CASHKARP54) return fail(c, HODE_EINVAL, "adaptive stepper: Dopri5 or Cash-Karp");
+  if (method != HODE_DOPRI5 && method != HODE_CASHKARP54 && method != HODE_FEHLBERG78)
+    return fail(c, HODE_EINVAL, "adaptive stepper: Dopri5, Cash-Karp or Fehlberg 7(8)");
   if (c->ens) return fail(c, HODE_EINVAL, "the ensemble steps with Dopri5");
   c->stepper = method;
   c->persist_valid = false;

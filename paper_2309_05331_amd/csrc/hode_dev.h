@@ -21,10 +21,22 @@ namespace hode {
 enum Mode : int32_t {
   MODE_FIXED_RK4 = 1, MODE_FIXED_DP5 = 2, MODE_ADAPTIVE = 3,  // RK4, Dopri5 fixed, Dopri5 adaptive
   MODE_FIXED_CK = 4, MODE_ADAPTIVE_CK = 5,                    // Cash-Karp 5(4) fixed, adaptive
-  MODE_FIXED_EULER = 6                                        // explicit Euler
+  MODE_FIXED_EULER = 6,                                       // explicit Euler
+  MODE_FIXED_F78 = 7, MODE_ADAPTIVE_F78 = 8,                  // Fehlberg 7(8) fixed, adaptive
+  MODE_FIXED_AB = 9                                           // Adams-Bashforth (ab_steps steps)
 };
 
-__host__ __device__ constexpr bool mode_adaptive(int m) { return m == MODE_ADAPTIVE || m == MODE_ADAPTIVE_CK; }
+__host__ __device__ constexpr bool mode_adaptive(int m) {
+  return m == MODE_ADAPTIVE || m == MODE_ADAPTIVE_CK || m == MODE_ADAPTIVE_F78;
+}
+// Right-hand side evaluations of one attempt or fixed step (Dopri5: k1 of
+// the first attempt comes on top; Adams-Bashforth steps after the start-up).
+__host__ __device__ constexpr int mode_rhs_evals(int m) {
+  return m == MODE_FIXED_RK4 ? 4
+         : (m == MODE_FIXED_EULER || m == MODE_FIXED_AB) ? 1
+         : (m == MODE_FIXED_F78 || m == MODE_ADAPTIVE_F78) ? 13
+                                                           : 6;
+}
 enum CtrlKind : int32_t { CTRL_PI = 1, CTRL_I = 2, CTRL_MLP = 3 };
 enum Status : int32_t {
   ST_OK = 0,
@@ -60,7 +72,9 @@ struct DevCtrl {
   const uint16_t* mlp_w;  // bf16 weights in device memory (CTRL_MLP)
   int64_t mlp_used, mlp_fallback;
   double stiff;  // spectral-radius scale of the System's Jacobian (feature of the learned controller)
-  double pad[3];
+  int32_t ab_steps;  // Adams-Bashforth: steps s (ring of s past right-hand sides)
+  int32_t ring;      // Adams-Bashforth: ring slot receiving f_n of the next step
+  double pad[2];
 };
 
 // ---- tableaux (Dormand & Prince 1980; classical RK4) ------------------------
@@ -83,6 +97,46 @@ __device__ constexpr double DPD[7] = {
     -1.0 / 40.0,
 };
 __device__ constexpr double RKA[4] = {0.0, 0.5, 0.5, 1.0};  // stage s input: y + RKA[s] h k_{s}
+
+// Runge-Kutta-Fehlberg 7(8) (Fehlberg 1968): stage-input coefficients
+// F78A[s][j] (stage s+1 uses k_{j+1}), the 8th-order weights F78B; the error
+// weights b - bhat are F78E times (-1, 0, .., 0, -1, 1, 1).
+__device__ constexpr double F78A[13][13] = {
+    {0},
+    {2.0 / 27.0},
+    {1.0 / 36.0, 1.0 / 12.0},
+    {1.0 / 24.0, 0, 1.0 / 8.0},
+    {5.0 / 12.0, 0, -25.0 / 16.0, 25.0 / 16.0},
+    {1.0 / 20.0, 0, 0, 1.0 / 4.0, 1.0 / 5.0},
+    {-25.0 / 108.0, 0, 0, 125.0 / 108.0, -65.0 / 27.0, 125.0 / 54.0},
+    {31.0 / 300.0, 0, 0, 0, 61.0 / 225.0, -2.0 / 9.0, 13.0 / 900.0},
+    {2.0, 0, 0, -53.0 / 6.0, 704.0 / 45.0, -107.0 / 9.0, 67.0 / 90.0, 3.0},
+    {-91.0 / 108.0, 0, 0, 23.0 / 108.0, -976.0 / 135.0, 311.0 / 54.0, -19.0 / 60.0, 17.0 / 6.0, -1.0 / 12.0},
+    {2383.0 / 4100.0, 0, 0, -341.0 / 164.0, 4496.0 / 1025.0, -301.0 / 82.0, 2133.0 / 4100.0, 45.0 / 82.0,
+     45.0 / 164.0, 18.0 / 41.0},
+    {3.0 / 205.0, 0, 0, 0, 0, -6.0 / 41.0, -3.0 / 205.0, -3.0 / 41.0, 3.0 / 41.0, 6.0 / 41.0, 0},
+    {-1777.0 / 4100.0, 0, 0, -341.0 / 164.0, 4496.0 / 1025.0, -289.0 / 82.0, 2193.0 / 4100.0, 51.0 / 82.0,
+     33.0 / 164.0, 12.0 / 41.0, 0, 1.0},
+};
+__device__ constexpr double F78B[13] = {0, 0, 0, 0, 0, 34.0 / 105.0, 9.0 / 35.0, 9.0 / 35.0, 9.0 / 280.0,
+                                        9.0 / 280.0, 0, 41.0 / 840.0, 41.0 / 840.0};
+__device__ constexpr double F78E = 41.0 / 840.0;
+
+// Adams-Bashforth weights: with s steps, y_{n+1} = y_n + h sum_j ABW[s-1][j]
+// f_{n-j} (the integral over one step of the polynomial through the last s
+// right-hand sides; Hairer, Norsett & Wanner I, section III.1).
+__device__ constexpr double ABW[8][8] = {
+    {1.0},
+    {3.0 / 2.0, -1.0 / 2.0},
+    {23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0},
+    {55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0},
+    {1901.0 / 720.0, -2774.0 / 720.0, 2616.0 / 720.0, -1274.0 / 720.0, 251.0 / 720.0},
+    {4277.0 / 1440.0, -7923.0 / 1440.0, 9982.0 / 1440.0, -7298.0 / 1440.0, 2877.0 / 1440.0, -475.0 / 1440.0},
+    {198721.0 / 60480.0, -447288.0 / 60480.0, 705549.0 / 60480.0, -688256.0 / 60480.0, 407139.0 / 60480.0,
+     -134472.0 / 60480.0, 19087.0 / 60480.0},
+    {434241.0 / 120960.0, -1152169.0 / 120960.0, 2183877.0 / 120960.0, -2664477.0 / 120960.0,
+     2102243.0 / 120960.0, -1041723.0 / 120960.0, 295767.0 / 120960.0, -36799.0 / 120960.0},
+};
 __device__ constexpr double RKB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
 
 // ---- reductions ---------------------------------------------------------------
@@ -175,9 +229,10 @@ __device__ inline float mlp_forward_wave(const uint16_t* W, const float* x, floa
 
 // ---- the control decision -----------------------------------------------------
 // Runs after the error norm of the attempt is complete, in the last workgroup.
-// Gustafsson PI controller (alpha = 0.7/5, beta = 0.4/5, safety 0.9, factor in
-// [0.2, 5], no growth right after a reject, error floor 1e-10); the I variant
-// uses alpha = 1/5, beta = 0.  With the learned controller the proposal for an
+// Gustafsson PI controller (alpha = 0.7/k, beta = 0.4/k, safety 0.9, factor in
+// [0.2, 5], no growth right after a reject, error floor 1e-10, reject factor
+// 0.9 err^(-1/k)); the I variant uses alpha = 1/k, beta = 0.  k is 1 + the
+// order of the embedded solution: 5 for the 5(4) pairs, 8 for Fehlberg 7(8).  With the learned controller the proposal for an
 // accepted step comes from the network (log-ratio clamped to [log 0.2, log 5],
 // never above 0 after a reject); a non-finite network output falls back to
 // the PI proposal, and a rejected attempt always retries with the PI shrink.
@@ -196,7 +251,8 @@ __device__ inline void fixed_step_done(DevCtrl* c) {
   c->t = c->t0 + (double)c->accepted * c->h;
   c->parity ^= 1;
   c->k1slot ^= 1;
-  c->rhs_evals += c->mode == MODE_FIXED_RK4 ? 4 : (c->mode == MODE_FIXED_EULER ? 1 : 6);
+  c->rhs_evals += mode_rhs_evals(c->mode);
+  if (c->mode == MODE_FIXED_AB) c->ring = c->ring + 1 == c->ab_steps ? 0 : c->ring + 1;
   if (c->accepted >= c->nsteps) c->done = 1;
 }
 
@@ -204,11 +260,12 @@ __device__ inline void fixed_step_done(DevCtrl* c) {
 __device__ inline void decide_a(DevCtrl* c, double err, CtrlScratch* s) {
   const double h = c->h;
   c->attempts += 1;
-  c->rhs_evals += 6;
+  c->rhs_evals += mode_rhs_evals(c->mode);
   c->last_err = err;
   const bool pi_kind = c->ctrl_kind != CTRL_I;
-  const double alpha = pi_kind ? 0.7 / 5.0 : 1.0 / 5.0;
-  const double beta = pi_kind ? 0.4 / 5.0 : 0.0;
+  const double k = c->mode == MODE_ADAPTIVE_F78 ? 8.0 : 5.0;
+  const double alpha = pi_kind ? 0.7 / k : 1.0 / k;
+  const double beta = pi_kind ? 0.4 / k : 0.0;
   const bool ok = err <= 1.0;
   for (int i = HIST - 1; i > 0; --i) {
     c->hist_lerr[i] = c->hist_lerr[i - 1];
@@ -232,7 +289,7 @@ __device__ inline void decide_a(DevCtrl* c, double err, CtrlScratch* s) {
     c->parity ^= 1;
     c->k1slot ^= 1;
   } else {
-    fac = isnan(err) ? 0.2 : fmax(0.2, 0.9 * pow(err, -1.0 / 5.0));
+    fac = isnan(err) ? 0.2 : fmax(0.2, 0.9 * pow(err, -1.0 / k));
     c->rejected += 1;
   }
   s->err = err;

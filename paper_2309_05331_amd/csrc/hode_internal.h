@@ -18,15 +18,27 @@ namespace hode {
 // step), Cash-Karp 5(4) (D1 D2 D3 share the Dopri5 stage shapes and
 // coefficients; C4 C5, then C6 = stage 6 with new state and error norm, C6F
 // its fixed-step form) and explicit Euler (E1: the new state y + h f(y)).
+// Fehlberg 7(8): F1 .. F12 write k1 .. k12, F13 evaluates k13 and forms the
+// new state and the error norm at the own cell (F13F: new state only).
+// Adams-Bashforth with s steps: AB<s> writes f_n = f(y_n) into the ring of
+// past right-hand sides and forms y_{n+1} from it and the s - 1 before.
 enum GSKind : int {
   K_D1 = 0, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_C4, K_C5, K_C6, K_C6F, K_E1, K_COUNT,
-  K_D6F = K_COUNT  // fixed-step stage 6: the new state only
+  K_D6F = K_COUNT,  // fixed-step stage 6: the new state only
+  K_F1, K_F2, K_F3, K_F4, K_F5, K_F6, K_F7, K_F8, K_F9, K_F10, K_F11, K_F12, K_F13, K_F13F,
+  K_AB1, K_AB2, K_AB3, K_AB4, K_AB5, K_AB6, K_AB7, K_AB8,
+  K_ALL  // number of kinds
 };
+
+// Extra arrays of the Fehlberg and Adams-Bashforth kinds (device table
+// xk(GSLaunch)): k1 .. k12 of Fehlberg 7(8) at 0 .. 11, the ring of the last
+// s right-hand sides of Adams-Bashforth at kRingBase .. kRingBase + s - 1.
+constexpr int kXkF78 = 12, kRingBase = 16, kXkCount = 24;
 
 struct GSLaunch {
   void* y[2];    // state, indexed by the device-side parity
   void* ks[2];   // first-same-as-last pair: k1 = ks[k1slot], k7 = ks[k1slot ^ 1]
-  void* k[7];    // k[2] .. k[6]
+  void* k[7];    // k[2] .. k[6]; k[0]: device table of the extra arrays (void* [kXkCount], see xk())
   int64_t n3;    // N^3, the stride between the u and v fields
   int32_t N;
   int32_t zc;    // z-planes marched by one workgroup
@@ -35,13 +47,26 @@ struct GSLaunch {
 
 // ry: rows per wavefront strip (tile = 64*vw x 4*ry cells); vw: cells per
 // lane (1, 2 or 4 for fp32, 1 or 2 for fp64, dividing N; 0 picks the widest).
+// The device table of the extra arrays (null if none), kept in the unused
+// stage slot k[0] so the layout of the launch arguments stays that of the
+// other kinds.
+__host__ __device__ inline void* const* xk(const GSLaunch& a) { return (void* const*)a.k[0]; }
+
 hipError_t launch_gs(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s);
+// The Fehlberg and Adams-Bashforth kinds (K_F1 .. K_AB8), same arguments.
+hipError_t launch_gsx(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s);
 bool gs_ry_supported(int ry);
 
 // Element-wise families: the whole step runs in registers (one kernel per
 // attempt).  mode: one of the Mode values (RK4, Dopri5 or Cash-Karp; fixed or adaptive).
 hipError_t launch_ew(int dtype, int rhs, int mode, void* y0, void* y1, int64_t n, int grid, DevCtrl* c,
                      hipStream_t s);
+// Fehlberg 7(8) and Adams-Bashforth steps of the element-wise families.
+// xk: device table as for the Gray-Scott kinds (the ring of past right-hand
+// sides); kout: if not null, the fixed Fehlberg step also stores k1 = f(y)
+// there.
+hipError_t launch_ewx(int dtype, int rhs, int mode, int ab_steps, void* y0, void* y1, void* const* xk, void* kout,
+                      int64_t n, int grid, DevCtrl* c, hipStream_t s);
 
 // The step controller: one wavefront, run after the final stage kernel of
 // every attempt or fixed step.

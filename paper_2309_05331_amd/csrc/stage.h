@@ -36,20 +36,24 @@ namespace hode {
 
 namespace {
 
-// array ids
-enum : int { A_Y = 0, A_K1 = 1, A_K2, A_K3, A_K4, A_K5, A_E6 = 6, A_K7 = 7, A_YN = 8 };
+// array ids: the state pair and the Runge-Kutta stages of RK4, Dopri5 and
+// Cash-Karp; Fehlberg's k_j at A_X0 + j - 1; Adams-Bashforth's f_{n-j} (ring
+// of past right-hand sides) at A_RG0 + j
+enum : int { A_Y = 0, A_K1 = 1, A_K2, A_K3, A_K4, A_K5, A_E6 = 6, A_K7 = 7, A_YN = 8, A_X0 = 16, A_RG0 = 40 };
 
 struct KindDesc {
   int ns;          // source arrays forming the stage input (first has coefficient 1)
-  int src[6];
-  double a[6];     // stage-input coefficients (times h); a[0] unused
+  int src[10];
+  double a[10];    // stage-input coefficients (times h); a[0] unused
   int nx;          // extra arrays needed at the own cell only
-  int extra[2];
+  int extra[8];
   int out;         // array receiving f(stage input), -1 none
   int fin;         // own-cell finish: 0 none, 1 RK4 new state, 2 Dopri5 new state (+ partial error),
                    // 3 Dopri5 error completion, 4 Cash-Karp new state (+ error norm),
-                   // 5 Euler new state
+                   // 5 Euler new state, 6 Fehlberg 7(8) new state (+ error norm),
+                   // 7 Adams-Bashforth new state
   bool err;        // error norm computed
+  int ab;          // Adams-Bashforth steps (ring size), 0 otherwise
 };
 
 constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0, B5 = -2187.0 / 6784.0,
@@ -97,13 +101,69 @@ constexpr KindDesc kD6F = {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
                            {0, 9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0},
                            0, {0, 0}, -1, 2, false};
 
+// Runge-Kutta-Fehlberg 7(8) (Fehlberg 1968): rows of the stage-input
+// coefficients over the stages they use (zero columns skipped), the 8th-order
+// weights FB (b1 = .. = b5 = b11 = 0) and the error weights: b - bhat is
+// 41/840 times (-1, 0, .., 0, -1, 1, 1) over k1, k11, k12, k13.
+constexpr int X1 = A_X0, X2 = A_X0 + 1, X3 = A_X0 + 2, X4 = A_X0 + 3, X5 = A_X0 + 4, X6 = A_X0 + 5,
+              X7 = A_X0 + 6, X8 = A_X0 + 7, X9 = A_X0 + 8, X10 = A_X0 + 9, X11 = A_X0 + 10, X12 = A_X0 + 11;
+constexpr double FB6 = 34.0 / 105.0, FB7 = 9.0 / 35.0, FB9 = 9.0 / 280.0, FB12 = 41.0 / 840.0, FE = 41.0 / 840.0;
+#define HODE_F13_ROW                                                                                      \
+  10, {A_Y, X1, X4, X5, X6, X7, X8, X9, X10, X12},                                                         \
+      {0, -1777.0 / 4100.0, -341.0 / 164.0, 4496.0 / 1025.0, -289.0 / 82.0, 2193.0 / 4100.0, 51.0 / 82.0, \
+       33.0 / 164.0, 12.0 / 41.0, 1.0}
+constexpr KindDesc kDescX[K_ALL - K_F1] = {
+    /* F1  */ {1, {A_Y}, {0}, 0, {0}, X1, 0, false, 0},
+    /* F2  */ {2, {A_Y, X1}, {0, 2.0 / 27.0}, 0, {0}, X2, 0, false, 0},
+    /* F3  */ {3, {A_Y, X1, X2}, {0, 1.0 / 36.0, 1.0 / 12.0}, 0, {0}, X3, 0, false, 0},
+    /* F4  */ {3, {A_Y, X1, X3}, {0, 1.0 / 24.0, 1.0 / 8.0}, 0, {0}, X4, 0, false, 0},
+    /* F5  */ {4, {A_Y, X1, X3, X4}, {0, 5.0 / 12.0, -25.0 / 16.0, 25.0 / 16.0}, 0, {0}, X5, 0, false, 0},
+    /* F6  */ {4, {A_Y, X1, X4, X5}, {0, 1.0 / 20.0, 1.0 / 4.0, 1.0 / 5.0}, 0, {0}, X6, 0, false, 0},
+    /* F7  */ {5, {A_Y, X1, X4, X5, X6}, {0, -25.0 / 108.0, 125.0 / 108.0, -65.0 / 27.0, 125.0 / 54.0}, 0, {0},
+               X7, 0, false, 0},
+    /* F8  */ {5, {A_Y, X1, X5, X6, X7}, {0, 31.0 / 300.0, 61.0 / 225.0, -2.0 / 9.0, 13.0 / 900.0}, 0, {0}, X8,
+               0, false, 0},
+    /* F9  */ {7, {A_Y, X1, X4, X5, X6, X7, X8},
+               {0, 2.0, -53.0 / 6.0, 704.0 / 45.0, -107.0 / 9.0, 67.0 / 90.0, 3.0}, 0, {0}, X9, 0, false, 0},
+    /* F10 */ {8, {A_Y, X1, X4, X5, X6, X7, X8, X9},
+               {0, -91.0 / 108.0, 23.0 / 108.0, -976.0 / 135.0, 311.0 / 54.0, -19.0 / 60.0, 17.0 / 6.0,
+                -1.0 / 12.0},
+               0, {0}, X10, 0, false, 0},
+    /* F11 */ {9, {A_Y, X1, X4, X5, X6, X7, X8, X9, X10},
+               {0, 2383.0 / 4100.0, -341.0 / 164.0, 4496.0 / 1025.0, -301.0 / 82.0, 2133.0 / 4100.0,
+                45.0 / 82.0, 45.0 / 164.0, 18.0 / 41.0},
+               0, {0}, X11, 0, false, 0},
+    /* F12 */ {7, {A_Y, X1, X6, X7, X8, X9, X10},
+               {0, 3.0 / 205.0, -6.0 / 41.0, -3.0 / 205.0, -3.0 / 41.0, 3.0 / 41.0, 6.0 / 41.0}, 0, {0}, X12, 0,
+               false, 0},
+    /* F13 */ {HODE_F13_ROW, 1, {X11}, -1, 6, true, 0},
+    /* F13F*/ {HODE_F13_ROW, 0, {0}, -1, 6, false, 0},
+    /* AB1 */ {1, {A_Y}, {0}, 0, {0}, -1, 7, false, 1},
+    /* AB2 */ {1, {A_Y}, {0}, 1, {A_RG0 + 1}, A_RG0, 7, false, 2},
+    /* AB3 */ {1, {A_Y}, {0}, 2, {A_RG0 + 1, A_RG0 + 2}, A_RG0, 7, false, 3},
+    /* AB4 */ {1, {A_Y}, {0}, 3, {A_RG0 + 1, A_RG0 + 2, A_RG0 + 3}, A_RG0, 7, false, 4},
+    /* AB5 */ {1, {A_Y}, {0}, 4, {A_RG0 + 1, A_RG0 + 2, A_RG0 + 3, A_RG0 + 4}, A_RG0, 7, false, 5},
+    /* AB6 */ {1, {A_Y}, {0}, 5, {A_RG0 + 1, A_RG0 + 2, A_RG0 + 3, A_RG0 + 4, A_RG0 + 5}, A_RG0, 7, false, 6},
+    /* AB7 */ {1, {A_Y}, {0}, 6, {A_RG0 + 1, A_RG0 + 2, A_RG0 + 3, A_RG0 + 4, A_RG0 + 5, A_RG0 + 6}, A_RG0, 7,
+               false, 7},
+    /* AB8 */ {1, {A_Y}, {0}, 7, {A_RG0 + 1, A_RG0 + 2, A_RG0 + 3, A_RG0 + 4, A_RG0 + 5, A_RG0 + 6, A_RG0 + 7},
+               A_RG0, 7, false, 8},
+};
+#undef HODE_F13_ROW
+
 template <int KIND>
 __host__ __device__ constexpr KindDesc desc() {
-  return KIND == K_COUNT ? kD6F : kDesc[KIND];
+  return KIND < K_COUNT ? kDesc[KIND] : (KIND == K_COUNT ? kD6F : kDescX[KIND - K_F1]);
 }
 
+// rg: ring slot of f_n (Adams-Bashforth kinds), S: ring size
 template <typename T>
-__device__ inline T* array_ptr(const GSLaunch& a, int id, int p, int ks) {
+__device__ inline T* array_ptr(const GSLaunch& a, int id, int p, int ks, int rg, int S) {
+  if (id >= A_RG0) {
+    const int j = id - A_RG0;
+    return (T*)xk(a)[kRingBase + (rg + S - j) % S];
+  }
+  if (id >= A_X0) return (T*)xk(a)[id - A_X0];
   switch (id) {
     case A_Y: return (T*)a.y[p];
     case A_YN: return (T*)a.y[p ^ 1];
@@ -213,6 +273,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 
   const double h = c->h;
   const int p = c->parity, ksl = c->k1slot;
+  const int rg = D.ab > 1 ? c->ring : 0;
   const int N = a.N;
   const int64_t n3 = a.n3;
   const int64_t NN = (int64_t)N * N;
@@ -222,17 +283,17 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   const int x0 = tx * TX, yt = ty * TY;
   const int y0 = yt + wv * RY * SEG + seg;  // first row of this lane's strip
 
-  const T* src[6];
+  const T* src[10];
 #pragma unroll
-  for (int i = 0; i < D.ns; ++i) src[i] = array_ptr<T>(a, D.src[i], p, ksl);
-  const T* ext[2];
+  for (int i = 0; i < D.ns; ++i) src[i] = array_ptr<T>(a, D.src[i], p, ksl, rg, D.ab);
+  const T* ext[8];
 #pragma unroll
-  for (int i = 0; i < D.nx; ++i) ext[i] = array_ptr<T>(a, D.extra[i], p, ksl);
-  T* out = D.out >= 0 ? array_ptr<T>(a, D.out, p, ksl) : nullptr;
-  T* ynew = (D.fin == 1 || D.fin == 2 || D.fin == 4 || D.fin == 5) ? (T*)a.y[p ^ 1] : nullptr;
+  for (int i = 0; i < D.nx; ++i) ext[i] = array_ptr<T>(a, D.extra[i], p, ksl, rg, D.ab);
+  T* out = D.out >= 0 ? array_ptr<T>(a, D.out, p, ksl, rg, D.ab) : nullptr;
+  T* ynew = (D.fin == 1 || D.fin == 2 || D.fin >= 4) ? (T*)a.y[p ^ 1] : nullptr;
   T* e6 = (D.fin == 2 && D.err) ? (T*)a.k[A_E6] : nullptr;
 
-  T cf[6];
+  T cf[10];
 #pragma unroll
   for (int i = 1; i < D.ns; ++i) cf[i] = (T)(h * D.a[i]);
   const T Du = (T)a.Du_h2, Dv = (T)a.Dv_h2, F = (T)a.F, Fk = (T)(a.F + a.kk);
@@ -245,6 +306,11 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   const T cq1 = (T)(h * CB1), cq3 = (T)(h * CB3), cq4 = (T)(h * CB4), cq6 = (T)(h * CB6);
   const T hT = (T)h;
   const double ce1 = h * CE1, ce3 = h * CE3, ce4 = h * CE4, ce5 = h * CE5, ce6 = h * CE6;
+  const T fb6 = (T)(h * FB6), fb7 = (T)(h * FB7), fb9 = (T)(h * FB9), fb12 = (T)(h * FB12);
+  const double fe = h * FE;
+  T abq[D.ab > 0 ? D.ab : 1];  // Adams-Bashforth weights times h
+#pragma unroll
+  for (int j = 0; j < D.ab; ++j) abq[j] = (T)(h * ABW[D.ab > 0 ? D.ab - 1 : 0][j]);
 
   // ---- offsets (periodic wrap folded in)
   const int xl = x0 + VW * jl;
@@ -275,12 +341,12 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   // stage 7 the stored partial error and y.
   struct Fin {
     T a[VW];
-    double e[((D.fin == 2 || D.fin == 4) && D.err) ? VW : 1];
-    T b[(D.fin == 3 || (D.fin == 4 && D.err)) ? VW : 1];
+    double e[((D.fin == 2 || D.fin == 4 || D.fin == 6) && D.err) ? VW : 1];
+    T b[(D.fin == 3 || ((D.fin == 4 || D.fin == 6) && D.err)) ? VW : 1];
   };
 
   auto stage_in = [&](int64_t g, Fin* fin) -> P {
-    P s[6];
+    P s[10];
 #pragma unroll
     for (int i = 0; i < D.ns; ++i) s[i] = ldv<T, VW>(src[i], g);
     P w = s[0];
@@ -290,7 +356,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
       for (int e = 0; e < VW; ++e) w.v[e] += cf[i] * s[i].v[e];
     if constexpr (D.fin != 0) {
       if (fin == nullptr) return w;  // halo cells need no finish
-      P x[2];
+      P x[8];
 #pragma unroll
       for (int i = 0; i < D.nx; ++i) x[i] = ldv<T, VW>(ext[i], g);
 #pragma unroll
@@ -307,6 +373,21 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
         } else if constexpr (D.fin == 5) {
           // source y: Euler keeps the own cell's state for the new state
           fin->a[e] = s[0].v[e];
+        } else if constexpr (D.fin == 6) {
+          // sources y, k1, k4 .. k10, k12; extra k11: Fehlberg new state and
+          // error without k13
+          fin->a[e] = s[0].v[e] + fb6 * s[4].v[e] + fb7 * s[5].v[e] + fb7 * s[6].v[e] + fb9 * s[7].v[e] +
+                      fb9 * s[8].v[e] + fb12 * s[9].v[e];
+          if constexpr (D.err) {
+            fin->e[e] = fe * ((double)s[9].v[e] - (double)s[1].v[e] - (double)x[0].v[e]);
+            fin->b[e] = s[0].v[e];
+          }
+        } else if constexpr (D.fin == 7) {
+          // source y; extras f_{n-1} .. f_{n-s+1}: Adams-Bashforth without f_n
+          T acc = s[0].v[e];
+#pragma unroll
+          for (int j = 1; j < D.ab; ++j) acc += abq[j] * x[j - 1].v[e];
+          fin->a[e] = acc;
         } else if constexpr (D.fin == 4) {
           // sources y, k1 .. k5: Cash-Karp new state and error without k6
           fin->a[e] = s[0].v[e] + cq1 * s[1].v[e] + cq3 * s[3].v[e] + cq4 * s[4].v[e];
@@ -485,6 +566,34 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
             for (int e = 0; e < VW; ++e) yn.v[e] = fc[f][r].a[e] + hT * fo[f].v[e];
             stv<T, VW>(ynew, f * n3 + g, yn);
           }
+        } else if constexpr (D.fin == 7) {
+          // Adams-Bashforth new state y + h sum_j beta_j f_{n-j}
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            P yn;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) yn.v[e] = fc[f][r].a[e] + abq[0] * fo[f].v[e];
+            stv<T, VW>(ynew, f * n3 + g, yn);
+          }
+        } else if constexpr (D.fin == 6) {
+          // Fehlberg 7(8) new state y + h sum b_j k_j and, adaptive, the error
+          // |h 41/840 (k12 + k13 - k1 - k11)| / (atol + rtol max(|y|, |ynew|))
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            P yn;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) yn.v[e] = fc[f][r].a[e] + fb12 * fo[f].v[e];
+            stv<T, VW>(ynew, f * n3 + g, yn);
+            if constexpr (D.err) {
+#pragma unroll
+              for (int e = 0; e < VW; ++e) {
+                const double err = fc[f][r].e[e] + fe * (double)fo[f].v[e];
+                const double sc = atol + rtol * fmax(fabs((double)fc[f][r].b[e]), fabs((double)yn.v[e]));
+                const uint64_t bits = (uint64_t)__double_as_longlong(fabs(err) / sc);
+                emax = bits > emax ? bits : emax;
+              }
+            }
+          }
         } else if constexpr (D.fin == 4) {
           // Cash-Karp new state y + h sum b_j k_j and, adaptive, the error
           // |h sum (b_j - bhat_j) k_j| / (atol + rtol max(|y|, |ynew|))
@@ -532,10 +641,39 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
     }
   }
 
-  if constexpr (D.err && (D.fin == 3 || D.fin == 4)) {
+  if constexpr (D.err && (D.fin == 3 || D.fin == 4 || D.fin == 6)) {
     emax = wave_max_u64(emax);
     if (lane == 0 && emax) atomicMax((unsigned long long*)&c->errmax_bits, (unsigned long long)emax);
   }
+}
+
+// One stage over a whole grid: one tile per workgroup.  The linear block id
+// is remapped XCD-aware: workgroups are dealt round-robin to the 8 XCDs, so
+// each XCD gets a contiguous range of tiles and y/z-adjacent tiles (whose
+// halo rows overlap) share an L2.  Consecutive stages sweep those ranges in
+// opposite directions.
+template <typename T, int KIND, int RY, int VW>
+__global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __restrict__ c) {
+  __shared__ __align__(16) char smem[kTileSmem];
+  if (c->done) return;
+  const int N = a.N;
+  const int nx = (N + 64 * VW - 1) / (64 * VW);
+  const int ny = (N + 4 * RY - 1) / (4 * RY);
+  const int nz = (N + a.zc - 1) / a.zc;
+  const int per = (gridDim.x + 7) / 8;
+  // Stages alternate their direction through each XCD's range, so a stage
+  // starts on the tiles the previous stage wrote last, which are still in the
+  // memory-side Infinity Cache.
+  // (The Adams-Bashforth kinds, one per step, alternate with the step.)
+  constexpr bool rev_k = KIND == K_R2 || KIND == K_R4 || KIND == K_D3 || KIND == K_D5 || KIND == K_D7 ||
+                         KIND == K_D7F || KIND == K_C5 || KIND == K_F2 || KIND == K_F4 || KIND == K_F6 ||
+                         KIND == K_F8 || KIND == K_F10 || KIND == K_F12;
+  const bool rev = desc<KIND>().ab > 0 ? (c->parity & 1) != 0 : rev_k;
+  const int slot = rev ? per - 1 - (int)(blockIdx.x >> 3) : (int)(blockIdx.x >> 3);
+  const int bb = (blockIdx.x & 7) * per + slot;
+  if (bb >= nx * ny * nz) return;  // padding block of the remap (whole block)
+  const int tz = bb / (nx * ny);
+  stage_tile<T, KIND, RY, VW>(a, c, smem, bb % nx, (bb / nx) % ny, tz * a.zc, min(N, (tz + 1) * a.zc));
 }
 
 }  // namespace

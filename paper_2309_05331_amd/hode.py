@@ -17,7 +17,16 @@ LIBPATH = os.path.join(HERE, "libhode.so")
 
 F32, F64 = 1, 2
 RHS_EXP, RHS_LOGISTIC, RHS_GRAYSCOTT3D = 1, 2, 3
-RK4, DOPRI5, CASHKARP54, EULER = 1, 2, 3, 4
+RK4, DOPRI5, CASHKARP54, EULER, FEHLBERG78 = 1, 2, 3, 4, 5
+
+
+def AB(steps):
+    """Method code of Adams-Bashforth with `steps` steps (1 .. 8)."""
+    if not 1 <= steps <= 8:
+        raise ValueError("Adams-Bashforth steps must be 1 .. 8")
+    return 10 + steps
+
+
 CTRL_PI, CTRL_I, CTRL_MLP = 1, 2, 3
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EDT_UNDERFLOW, EMAXSTEPS, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 TRACE_W = 24  # h, err, accepted, t after, dt next, PI log-ratio, learned log-ratio, landed, 16 features
@@ -25,6 +34,9 @@ MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 
 # Gray-Scott stage kernels, as numbered by hode_time_kernel
 K_D1, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_C4, K_C5, K_C6, K_C6F, K_E1, K_D6F = range(17)
+K_F = list(range(17, 30))  # Fehlberg 7(8) stages F1 .. F13
+K_F13F = 30
+K_AB = list(range(31, 39))  # Adams-Bashforth with 1 .. 8 steps
 
 
 class hode_stats(C.Structure):
@@ -265,9 +277,10 @@ class Context:
         return a.value, b.value
 
     def profile_attempt(self, method, reps):
-        ms = (C.c_double * 8)()
+        ms = (C.c_double * 16)()
         self._check(self.L.hode_profile_attempt(self.h, method, reps, ms))
-        return list(ms)[: (4 if method == RK4 else 6)]
+        ns = 4 if method == RK4 else (13 if method == FEHLBERG78 else (1 if method > 10 else 6))
+        return list(ms)[:ns]
 
     def autotune(self, method, reps=3):
         ry, zc, ms = C.c_int(), C.c_int(), C.c_double()
