@@ -622,7 +622,8 @@ struct Adaptive {
   double dt, last_err = 0.0;
   int64_t acc = 0, rej = 0, evals = 0, att = 0;
   Adaptive(const orc_system& sys, int method, const double* y, double dt0, double a, double r, int ctrl_kind)
-      : s(sys), method(method), dp(method == ORC_DOPRI5), atol(a), rtol(r), W(sys.n, 13), k1(sys.n), k7(sys.n),
+      : s(sys), method(method), dp(method == ORC_DOPRI5), atol(a), rtol(r),
+        W(sys.n, method == ORC_FEHLBERG78 ? 13 : 7), k1(sys.n), k7(sys.n),
         ynew(sys.n), e(sys.n), c(ctrl_kind, method == ORC_FEHLBERG78 ? 8.0 : 5.0), dt(dt0) {
     if (dp) {
       rhs(s, y, k1.data());
@@ -732,7 +733,7 @@ int orc_integrate_replay_m(const orc_system* s, int method, double* y, double t0
     return ORC_EINVAL;
   const bool dp = method == ORC_DOPRI5;
   const int64_t n = s->n;
-  Work W(n, 13);
+  Work W(n, method == ORC_FEHLBERG78 ? 13 : 7);
   std::vector<double> k1(n), k7(n), ynew(n), e(n);
   if (dp) rhs(*s, y, k1.data());
   double t = t0;
