@@ -40,16 +40,27 @@ GS_PRM = [2e-5, 1e-5, 0.053, 0.014, 2.5]
 #   D4: y,k1..k3 -> k4               D5: y,k1..k4 -> k5
 #   D6: y,k1..k5 -> ynew, partial error                D7: ynew,partial error,y -> k7
 #   Cash-Karp: D1 D2 D3 (shared), C4: y,k1..k3 -> k4   C5: y,k1..k4 -> k5   C6: y,k1..k5 -> ynew (+ error norm)
+#   Fehlberg 7(8): Fs reads y and the k_j of its tableau row (zero columns
+#   skipped) and writes k_s; F13 reads y, k1, k4..k10, k12 and k11 and writes
+#   ynew (82 arrays per attempt)
+#   Adams-Bashforth s: y and f_{n-1} .. f_{n-s+1} -> f_n, ynew (s + 2 arrays)
 GS_ARRAYS = {0: 2, 1: 3, 2: 3, 3: 5, 4: 3, 5: 4, 6: 5, 7: 6, 8: 8, 9: 4, 10: 2, 11: 5, 12: 6, 13: 7, 14: 7, 15: 2,
-             16: 7}
+             16: 7,
+             17: 2, 18: 3, 19: 4, 20: 4, 21: 5, 22: 5, 23: 6, 24: 6, 25: 8, 26: 9, 27: 10, 28: 8, 29: 12, 30: 11,
+             31: 2, **{30 + s: s + 2 for s in range(2, 9)}}
 GS_NAMES = {0: "D1", 1: "R2", 2: "R3", 3: "R4", 4: "D2", 5: "D3", 6: "D4", 7: "D5", 8: "D6", 9: "D7", 10: "D7F",
-            11: "C4", 12: "C5", 13: "C6", 14: "C6F", 15: "E1", 16: "D6F"}
-STAGES = {"rk4": [0, 1, 2, 3], "dp5": [4, 5, 6, 7, 8, 9], "ck54": [0, 4, 5, 11, 12, 13]}
+            11: "C4", 12: "C5", 13: "C6", 14: "C6F", 15: "E1", 16: "D6F",
+            **{16 + i: "F%d" % i for i in range(1, 14)}, 30: "F13F", **{30 + s: "AB%d" % s for s in range(1, 9)}}
+STAGES = {"rk4": [0, 1, 2, 3], "dp5": [4, 5, 6, 7, 8, 9], "ck54": [0, 4, 5, 11, 12, 13], "f78": list(range(17, 30)),
+          "ab4": [34]}
 
 WORKLOADS = {
     "gs512-dp5": dict(kind="gs", N=512, dtype="f32", method="dp5", window=10.0, seed=5, dt0=0.1),
     "gs256-dp5": dict(kind="gs", N=256, dtype="f32", method="dp5", window=10.0, seed=3, dt0=0.1),
     "gs512-ck54": dict(kind="gs", N=512, dtype="f32", method="ck54", window=10.0, seed=5, dt0=0.1),
+    "gs512-f78": dict(kind="gs", N=512, dtype="f32", method="f78", window=10.0, seed=5, dt0=0.1),
+    # Adams-Bashforth 4 at h lambda_max = 0.25 (its real stability interval is 0.3)
+    "gs512-ab4": dict(kind="gs", N=512, dtype="f32", method="ab4", steps_per=400, dt=0.025, seed=5),
     "gs256-rk4": dict(kind="gs", N=256, dtype="f32", method="rk4", steps_per=100, dt=0.1, seed=3),
     "gs32-rk4-fp64": dict(kind="gs", N=32, dtype="f64", method="rk4", steps_per=500, dt=0.1, seed=1,
                           compare_graphs=True),
@@ -91,15 +102,20 @@ def cpu_baseline_leg(wl, budget_s=10.0):
             if wl["method"] == "rk4":
                 y, t = oracle.integrate_n_steps(sysd, oracle.RK4, y, t, 0.1, 5)
                 units += 5 * Ns ** 3
+            elif wl["method"] == "ab4":
+                # one fresh history per call: 3 Fehlberg start-up steps, then 97 AB4 steps
+                y, t = oracle.integrate_n_steps(sysd, oracle.AB(4), y, t, wl["dt"], 100)
+                units += 100 * Ns ** 3
             else:
-                om = oracle.CASHKARP if wl["method"] == "ck54" else oracle.DOPRI5
+                om = {"ck54": oracle.CASHKARP, "f78": oracle.FEHLBERG78}.get(wl["method"], oracle.DOPRI5)
                 y, st, _ = oracle.integrate_adaptive(sysd, y, t, 1e9, 0.3, 1e-6, 1e-6, max_steps=4, method=om)
                 t = st["t"]
                 units += st["accepted"] * Ns ** 3
             done += 1
         el = time.perf_counter() - t0
         what = {"rk4": "RK4 steps", "dp5": "adaptive Dopri5 accepted steps",
-                "ck54": "adaptive Cash-Karp accepted steps"}[wl["method"]]
+                "ck54": "adaptive Cash-Karp accepted steps", "f78": "adaptive Fehlberg 7(8) accepted steps",
+                "ab4": "Adams-Bashforth 4 steps (100 per call, each call with 3 Fehlberg start-up steps)"}[wl["method"]]
         sample = "%s on a %d^3 grid (same parameters), %d calls, %.1f s" % (what, Ns, done, el)
         unit = "cell-updates/s"
     elif wl["kind"] == "ens":
@@ -208,9 +224,10 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     torch.cuda.synchronize()
     ctx.set_tolerances(1e-6, 1e-6)
     ctx.set_controller(ctrl_kind, weights)
-    method = {"rk4": hode.RK4, "dp5": hode.DOPRI5, "ck54": hode.CASHKARP54}[wl["method"]]
-    if method == hode.CASHKARP54:
-        ctx.set_stepper(hode.CASHKARP54)
+    method = {"rk4": hode.RK4, "dp5": hode.DOPRI5, "ck54": hode.CASHKARP54, "f78": hode.FEHLBERG78,
+              "ab4": hode.AB(4)}[wl["method"]]
+    if method in (hode.CASHKARP54, hode.FEHLBERG78):
+        ctx.set_stepper(method)
     if tile is None:
         ctx.autotune(method, 3)  # project autotuner: fastest (ry, zc) for this grid
     else:
@@ -218,8 +235,9 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     state = {"t": 0.0, "dt": wl.get("dt0", 0.1), "acc": 0, "rej": 0}
 
     def one_step():
-        if wl["method"] == "rk4":
-            ctx.integrate_n_steps(hode.RK4, state["t"], wl["dt"], wl["steps_per"])
+        if wl["method"] in ("rk4", "ab4"):
+            # (Adams-Bashforth: the history continues from step to step)
+            ctx.integrate_n_steps(method, state["t"], wl["dt"], wl["steps_per"])
             state["t"] += wl["steps_per"] * wl["dt"]
             state["acc"] += wl["steps_per"]
         else:
@@ -248,7 +266,7 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     # replayed in the same order on the library's stream, right after the
     # timed region
     kinds = STAGES[wl["method"]]
-    prof = ctx.profile_attempt(method, 10)
+    prof = ctx.profile_attempt(method, 10)  # (ends an Adams-Bashforth history: after the timed steps)
     ms = dict(zip(kinds, prof))
     dom = max(kinds, key=lambda k: ms[k])
     esz = 4 if wl["dtype"] == "f32" else 8
@@ -357,8 +375,9 @@ def main():
         r = run_gs(wl, args.steps, args.warmup, ctrl, tile=tile)
         unit = "cell-updates/s"
         cfg = {"workload": args.workload, "grid": [wl["N"]] * 3, "fields": 2,
-               "method": {"dp5": "dopri5-adaptive", "ck54": "cashkarp54-adaptive", "rk4": "rk4-fixed"}[wl["method"]],
-               "rtol": None if wl["method"] == "rk4" else 1e-6, "controller": args.controller,
+               "method": {"dp5": "dopri5-adaptive", "ck54": "cashkarp54-adaptive", "rk4": "rk4-fixed",
+                          "f78": "fehlberg78-adaptive", "ab4": "adams-bashforth4-fixed"}[wl["method"]],
+               "rtol": None if wl["method"] in ("rk4", "ab4") else 1e-6, "controller": args.controller,
                "window_time_units": wl.get("window"), "dt": wl.get("dt"), "tile_ry_zc": r["tile"],
                "params": {"Du": GS_PRM[0], "Dv": GS_PRM[1], "F": GS_PRM[2], "k": GS_PRM[3], "L": GS_PRM[4]}}
     elif wl["kind"] == "ens":
