@@ -83,6 +83,10 @@ def lib():
                                            C.c_double, C.c_double, C.POINTER(C.c_double), P]
         L.orc_cashkarp_attempt.argtypes = [C.POINTER(System), P, C.c_double, P, P]
         L.orc_fehlberg78_attempt.argtypes = [C.POINTER(System), P, C.c_double, P, P]
+        L.orc_integrate_dense_times.argtypes = [C.POINTER(System), P, P, C.c_int64, C.c_double, C.c_double,
+                                                C.c_double, C.c_int, C.c_int64, P, C.POINTER(Stats)]
+        L.orc_dopri5_dense_weights.argtypes = [C.c_double, P]
+        L.orc_dopri5_dense_weights.restype = None
         L.orc_ab_weights.argtypes = [C.c_int, P]
         L.orc_ab_weights.restype = None
         L.orc_ctrl_decide_k.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double),
@@ -227,6 +231,28 @@ def integrate_times(sysd: System, y, times, dt0, atol, rtol, ctrl=CTRL_PI, max_s
     if rc == EINVAL:
         raise ValueError("integrate_times: invalid arguments (times must increase)")
     return out, {f: getattr(st, f) for f, _ in Stats._fields_ if f != "pad"}
+
+
+def integrate_dense_times(sysd: System, y, times, dt0, atol, rtol, ctrl=CTRL_PI, max_steps=10 ** 7):
+    """Dopri5 dense output: free controlled steps from times[0] to
+    times[-1], intermediate states from the continuous extension.  Returns
+    (rows of states, stats dict)."""
+    y = _f64(y).ravel().copy()
+    times = _f64(times).ravel()
+    out = np.zeros((times.size, y.size))
+    st = Stats()
+    rc = lib().orc_integrate_dense_times(C.byref(sysd), _ptr(y), _ptr(times), times.size, dt0, atol, rtol, ctrl,
+                                         max_steps, _ptr(out), C.byref(st))
+    if rc == EINVAL:
+        raise ValueError("integrate_dense_times: invalid arguments (times must increase)")
+    return out, {f: getattr(st, f) for f, _ in Stats._fields_ if f != "pad"}
+
+
+def dopri5_dense_weights(theta: float) -> np.ndarray:
+    """w_j(theta) of the continuous extension: y(t_n + theta h) = y_n + h sum_j w_j k_j."""
+    w = np.zeros(7)
+    lib().orc_dopri5_dense_weights(theta, _ptr(w))
+    return w
 
 
 def integrate_replay(sysd: System, y, t0, hs, accepted, atol=1e-6, rtol=1e-6, method=None):

@@ -114,6 +114,26 @@ const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.
 const double DP_BHAT[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
                            -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
 
+// Continuous extension of Dormand-Prince 5(4) (Dormand & Prince 1986;
+// Hairer, Norsett & Wanner I, section II.6): the quartic through y_n and
+// y_{n+1} with slopes k1 and k7 at the ends, corrected by
+// theta^2 (1-theta)^2 h sum_j DPD_j k_j, which makes it 4th-order accurate.
+// Written as weights: y(t_n + theta h) = y_n + h sum_j w_j(theta) k_j.
+const double DPD[7] = {-12715105075.0 / 11282082432.0, 0.0, 87487479700.0 / 32700410799.0,
+                       -10690763975.0 / 1880347072.0, 701980252875.0 / 199316789632.0,
+                       -1453857185.0 / 822651844.0, 69997945.0 / 29380423.0};
+
+// w_j(theta) = b_j (3 theta^2 - 2 theta^3) + DPD_j theta^2 (1-theta)^2
+//              + [j = 1] theta (1-theta)^2 - [j = 7] theta^2 (1-theta)
+// (expanding y_n + theta D + theta (1-theta) (h k1 - D) + theta^2 (1-theta)
+// (2 D - h k1 - h k7) + theta^2 (1-theta)^2 h sum_j DPD_j k_j, D = y_{n+1} - y_n).
+void dopri5_dense_weights(double th, double* w) {
+  const double u = 1.0 - th;
+  for (int j = 0; j < 7; ++j) w[j] = DP_B[j] * (3.0 * th * th - 2.0 * th * th * th) + DPD[j] * th * th * u * u;
+  w[0] += th * u * u;
+  w[6] -= th * th * u;
+}
+
 // Cash-Karp 5(4), 6 stages: 5th-order weights b (the solution carried on) and
 // 4th-order embedded weights bhat.
 const double CK_C[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
@@ -715,6 +735,79 @@ int orc_integrate_times(const orc_system* s, int method, double* y, const double
   A.stats(st, t, status);
   return status;
 }
+
+// Dense output (Odeint's dense-output Dopri5 with integrate_times): the
+// controlled steps run from times[0] to times[nt-1] exactly as
+// integrate_adaptive does (only the last step clipped, to land on the end),
+// and the state at every intermediate requested time comes from the
+// continuous extension of the accepted step that covers it:
+// t_prev < times[i] <= t_prev + h, theta = (times[i] - t_prev) / h with
+// t_prev = t - h.  out[0] is the start state, out[nt-1] the end state.
+int orc_integrate_dense_times(const orc_system* s, double* y, const double* times, int64_t nt, double dt0,
+                              double atol, double rtol, int ctrl_kind, int64_t max_steps, double* out,
+                              orc_stats* st) {
+  if (!valid(s) || nt < 1 || !(dt0 > 0) || !(atol >= 0) || !(rtol >= 0) || (atol == 0 && rtol == 0) || !out)
+    return ORC_EINVAL;
+  for (int64_t i = 1; i < nt; ++i)
+    if (!(times[i] > times[i - 1])) return ORC_EINVAL;
+  const int64_t n = s->n;
+  std::memcpy(out, y, sizeof(double) * n);
+  const double t1 = times[nt - 1];
+  Work W(n, 7);
+  std::vector<double> k1(n), k7(n), ynew(n), e(n);
+  rhs(*s, y, k1.data());
+  Ctrl c(ctrl_kind);
+  double t = times[0], dt = dt0, last_err = 0.0;
+  int64_t acc = 0, rej = 0, evals = 1, att = 0, next = 1;
+  int status = ORC_OK;
+  while (t < t1) {
+    if (att >= max_steps) { status = ORC_EMAXSTEPS; break; }
+    const bool last = dt >= t1 - t;
+    const double h = last ? t1 - t : dt;
+    if (h < 1e-12 * std::max(1.0, std::fabs(t))) {
+      status = std::isfinite(last_err) ? ORC_EDT_UNDERFLOW : ORC_ENONFINITE;
+      break;
+    }
+    dopri5_attempt(*s, y, k1.data(), h, ynew.data(), k7.data(), e.data(), W);
+    evals += 6;
+    ++att;
+    const double err = err_norm(n, y, ynew.data(), e.data(), atol, rtol);
+    last_err = err;
+    double fac;
+    if (c.decide(err, &fac)) {
+      const double tn = last ? t1 : t + h;
+      // observations inside (t, tn], before y moves on (W.k holds k1 .. k7)
+      for (; next < nt - 1 && times[next] <= tn; ++next) {
+        const double th = (times[next] - (tn - h)) / h;
+        double w[7];
+        dopri5_dense_weights(th, w);
+        double* o = out + next * n;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+          double sum = 0.0;
+          for (int j = 0; j < 7; ++j)
+            if (w[j] != 0.0) sum += w[j] * W.k[j][i];
+          o[i] = y[i] + h * sum;
+        }
+      }
+      std::swap_ranges(ynew.begin(), ynew.end(), y);
+      k1.swap(k7);
+      t = tn;
+      ++acc;
+    } else {
+      ++rej;
+    }
+    dt = h * fac;
+  }
+  if (status == ORC_OK && nt > 1) std::memcpy(out + (nt - 1) * n, y, sizeof(double) * n);
+  if (st) {
+    st->accepted = acc; st->rejected = rej; st->rhs_evals = evals;
+    st->t = t; st->dt_next = dt; st->last_err = last_err; st->status = status;
+  }
+  return status;
+}
+
+void orc_dopri5_dense_weights(double theta, double* w) { dopri5_dense_weights(theta, w); }
 
 int orc_integrate_adaptive(const orc_system* s, double* y, double t0, double t1, double dt0, double atol,
                            double rtol, int ctrl_kind, int64_t max_steps, orc_stats* st, double* trace,

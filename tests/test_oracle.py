@@ -793,3 +793,67 @@ def test_controller_order_exponent(orc):
         for prev, lr in ((1.0, False), (0.02, True)):
             assert orc.ctrl_decide(orc.CTRL_PI, err, prev, lr, order_k=5.0)[1:] == \
                 orc.ctrl_decide(orc.CTRL_PI, err, prev, lr)[1:] or math.isnan(err)
+
+
+# --------------------------------------------------- Dopri5 dense output
+
+@pytest.mark.parametrize("th", [0.1, 0.3, 0.5, 0.8])
+def test_dense_output_continuous_order_conditions(orc, th):
+    # the continuous extension y_n + h sum_j w_j(theta) k_j satisfies every
+    # order condition up to order 4 at each theta, sum_j w_j Phi_j(t) =
+    # theta^|t| / gamma(t), and not all of order 5
+    a, _, _, _ = orc.tableau(orc.DOPRI5)
+    w = [Fr(float(x)) for x in orc.dopri5_dense_weights(th)]
+    conds = _order_conditions(_rational(a), w, 5)
+    for order, got, inv_gamma in conds:
+        want = Fr(th) ** order * inv_gamma
+        if order <= 4:
+            assert abs(float(got - want)) < 1e-14, (order, float(got), float(want))
+    assert any(abs(float(got - Fr(th) ** order * inv_gamma)) > 1e-6 for order, got, inv_gamma in conds if order == 5)
+
+
+def test_dense_output_hermite_end_conditions(orc):
+    # value y_n at theta = 0, y_{n+1} (the weights b) at theta = 1, slope k1
+    # at the start and k7 at the end
+    _, b, _, _ = orc.tableau(orc.DOPRI5)
+    assert np.all(orc.dopri5_dense_weights(0.0) == 0.0)
+    assert np.allclose(orc.dopri5_dense_weights(1.0), b, rtol=0, atol=1e-16)
+    eps = 1e-7
+    d0 = orc.dopri5_dense_weights(eps) / eps
+    d1 = (orc.dopri5_dense_weights(1.0) - orc.dopri5_dense_weights(1.0 - eps)) / eps
+    assert np.allclose(d0, np.eye(7)[0], atol=1e-6)
+    assert np.allclose(d1, np.eye(7)[6], atol=1e-6)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_dense_output_local_order(orc, kind):
+    # within one step the interpolant's error is O(h^5) (order 4)
+    x0 = inputs.exp_family_x0(257, seed=18)
+    sysd = orc.ew_system(kind, x0.size)
+    for th in (0.3, 0.5, 0.77):
+        errs = []
+        for h in (0.2, 0.1, 0.05):
+            # tolerances so loose that the single step of size h is accepted
+            out, st = orc.integrate_dense_times(sysd, x0, [0.0, th * h, h], 1e9, 1.0, 1.0)
+            assert st["accepted"] == 1 and st["rejected"] == 0
+            errs.append(np.max(np.abs(out[1] - _closed(kind, x0, th * h))))
+        r = errs[-2] / errs[-1]
+        assert abs(r / 32 - 1) < 0.12, (th, errs)
+
+
+def test_dense_output_run_matches_adaptive_and_closed_forms(orc):
+    # the steps are integrate_adaptive's (final state bitwise, same counts)
+    # and every interpolated state follows the closed form to the tolerance
+    x0 = inputs.exp_family_x0(1024, seed=19)
+    times = [0.0, 0.013, 0.37, 1.0, 2.5, 2.51, 4.999, 5.0]
+    for kind in (1, 2):
+        sysd = orc.ew_system(kind, x0.size)
+        out, st = orc.integrate_dense_times(sysd, x0, times, 0.01, 1e-8, 1e-8)
+        y, ast, _ = orc.integrate_adaptive(sysd, x0, 0.0, 5.0, 0.01, 1e-8, 1e-8)
+        assert np.array_equal(out[-1], y) and np.array_equal(out[0], x0)
+        assert (st["accepted"], st["rejected"], st["rhs_evals"]) == (ast["accepted"], ast["rejected"], ast["rhs_evals"])
+        for i, t in enumerate(times):
+            exact = _closed(kind, x0, t)
+            assert np.max(np.abs(out[i] - exact) / (1 + np.abs(exact))) < 30e-8, (kind, t)
+    with pytest.raises(ValueError):
+        orc.integrate_dense_times(orc.ew_system(1, 4), x0[:4], [0.0, 1.0, 0.5], 0.01, 1e-6, 1e-6)
