@@ -97,6 +97,22 @@ __device__ inline CKCoef<T> ck_coef(double h) {
   return q;
 }
 
+// The seven Dopri5 stages of one component and the 5th-order solution
+// (k7 = f(xn)); shared by the step and the dense output, which must see the
+// same stage values.
+template <typename T, int RHS>
+__device__ __forceinline__ T dp_stages(T x, const DPCoef<T>& q, T (&k)[7]) {
+  k[0] = frhs<T, RHS>(x);
+  k[1] = frhs<T, RHS>(x + q.a21 * k[0]);
+  k[2] = frhs<T, RHS>(x + q.a31 * k[0] + q.a32 * k[1]);
+  k[3] = frhs<T, RHS>(x + q.a41 * k[0] + q.a42 * k[1] + q.a43 * k[2]);
+  k[4] = frhs<T, RHS>(x + q.a51 * k[0] + q.a52 * k[1] + q.a53 * k[2] + q.a54 * k[3]);
+  k[5] = frhs<T, RHS>(x + q.a61 * k[0] + q.a62 * k[1] + q.a63 * k[2] + q.a64 * k[3] + q.a65 * k[4]);
+  const T xn = x + q.b1 * k[0] + q.b3 * k[2] + q.b4 * k[3] + q.b5 * k[4] + q.b6 * k[5];
+  k[6] = frhs<T, RHS>(xn);
+  return xn;
+}
+
 template <typename T, int RHS, int MODE>
 __device__ __forceinline__ T step_one(T x, const DPCoef<T>& q, const CKCoef<T>& ck, T r2, T r1, T r16, T r13,
                                       double atol, double rtol, uint64_t& emax) {
@@ -125,17 +141,11 @@ __device__ __forceinline__ T step_one(T x, const DPCoef<T>& q, const CKCoef<T>& 
     const T k4 = frhs<T, RHS>(x + r1 * k3);
     return x + r16 * k1 + r13 * k2 + r13 * k3 + r16 * k4;
   } else {
-    const T k1 = frhs<T, RHS>(x);
-    const T k2 = frhs<T, RHS>(x + q.a21 * k1);
-    const T k3 = frhs<T, RHS>(x + q.a31 * k1 + q.a32 * k2);
-    const T k4 = frhs<T, RHS>(x + q.a41 * k1 + q.a42 * k2 + q.a43 * k3);
-    const T k5 = frhs<T, RHS>(x + q.a51 * k1 + q.a52 * k2 + q.a53 * k3 + q.a54 * k4);
-    const T k6 = frhs<T, RHS>(x + q.a61 * k1 + q.a62 * k2 + q.a63 * k3 + q.a64 * k4 + q.a65 * k5);
-    const T xn = x + q.b1 * k1 + q.b3 * k3 + q.b4 * k4 + q.b5 * k5 + q.b6 * k6;
+    T k[7];
+    const T xn = dp_stages<T, RHS>(x, q, k);  // (k7 is dead code in fixed mode)
     if constexpr (MODE == MODE_ADAPTIVE) {
-      const T k7 = frhs<T, RHS>(xn);
-      const double e = q.e1 * (double)k1 + q.e3 * (double)k3 + q.e4 * (double)k4 + q.e5 * (double)k5 +
-                       q.e6 * (double)k6 + q.e7 * (double)k7;
+      const double e = q.e1 * (double)k[0] + q.e3 * (double)k[2] + q.e4 * (double)k[3] + q.e5 * (double)k[4] +
+                       q.e6 * (double)k[5] + q.e7 * (double)k[6];
       const double ratio = fabs(e) / (atol + rtol * fmax(fabs((double)x), fabs((double)xn)));
       const uint64_t bits = (uint64_t)__double_as_longlong(ratio);
       emax = bits > emax ? bits : emax;
@@ -319,6 +329,52 @@ __global__ __launch_bounds__(256) void ew_ab(DevCtrl* __restrict__ c, T* __restr
   }
 }
 
+// Weights h w_j(theta) of the Dopri5 continuous extension, in the state's
+// precision (w_2 = 0).
+template <typename T>
+__device__ inline void dense_coef(double h, double th, T (&cw)[7]) {
+  const double u = 1.0 - th;
+  const double b[7] = {DPA[6][0], DPA[6][1], DPA[6][2], DPA[6][3], DPA[6][4], DPA[6][5], 0.0};
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    double w = b[j] * (3.0 * th * th - 2.0 * th * th * th) + DPC[j] * th * th * u * u;
+    if (j == 0) w += th * u * u;
+    if (j == 6) w -= th * th * u;
+    cw[j] = (T)(h * w);
+  }
+}
+
+// Dense output from stored stages (Gray-Scott): out = y_n + sum_j (h w_j) k_j.
+template <typename T>
+__global__ __launch_bounds__(256) void dense_k(T* __restrict__ out, const T* __restrict__ yn,
+                                               const T* __restrict__ k1, const T* __restrict__ k3,
+                                               const T* __restrict__ k4, const T* __restrict__ k5,
+                                               const T* __restrict__ k6, const T* __restrict__ k7, int64_t n,
+                                               double h, double th) {
+  T cw[7];
+  dense_coef<T>(h, th, cw);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = yn[i] + cw[0] * k1[i] + cw[2] * k3[i] + cw[3] * k4[i] + cw[4] * k5[i] + cw[5] * k6[i] + cw[6] * k7[i];
+}
+
+// Dense output of the element-wise families: the step's seven stages are
+// evaluated again from y_n (same expressions, so the same values).
+template <typename T, int RHS>
+__global__ __launch_bounds__(256) void dense_ew(T* __restrict__ out, const T* __restrict__ yn, int64_t n, double h,
+                                                double th) {
+  const DPCoef<T> q = dp_coef<T>(h);
+  T cw[7];
+  dense_coef<T>(h, th, cw);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const T x = yn[i];
+    T k[7];
+    (void)dp_stages<T, RHS>(x, q, k);
+    out[i] = x + cw[0] * k[0] + cw[2] * k[2] + cw[3] * k[3] + cw[4] * k[4] + cw[5] * k[5] + cw[6] * k[6];
+  }
+}
+
 __global__ __launch_bounds__(64) void ctrl_kernel(DevCtrl* c) {
   if (c->done) return;
   ctrl_step(c);
@@ -372,6 +428,34 @@ hipError_t launch_ewx(int dtype, int rhs, int mode, int ab_steps, void* y0, void
   }
   if (rhs == 1) return launch_x<double, 1>(mode, ab_steps, (double*)y0, (double*)y1, xk, (double*)kout, n, grid, c, s);
   return launch_x<double, 2>(mode, ab_steps, (double*)y0, (double*)y1, xk, (double*)kout, n, grid, c, s);
+}
+
+hipError_t launch_dense_k(int dtype, void* out, const void* yn, const void* k1, const void* k3, const void* k4,
+                          const void* k5, const void* k6, const void* k7, int64_t n, int grid, double h, double theta,
+                          hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  if (dtype == 1)
+    dense_k<float><<<grid, 256, 0, s>>>((float*)out, (const float*)yn, (const float*)k1, (const float*)k3,
+                                        (const float*)k4, (const float*)k5, (const float*)k6, (const float*)k7, n, h,
+                                        theta);
+  else
+    dense_k<double><<<grid, 256, 0, s>>>((double*)out, (const double*)yn, (const double*)k1, (const double*)k3,
+                                         (const double*)k4, (const double*)k5, (const double*)k6, (const double*)k7,
+                                         n, h, theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_ew(int dtype, int rhs, void* out, const void* yn, int64_t n, int grid, double h,
+                           double theta, hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  if (dtype == 1) {
+    if (rhs == 1) dense_ew<float, 1><<<grid, 256, 0, s>>>((float*)out, (const float*)yn, n, h, theta);
+    else dense_ew<float, 2><<<grid, 256, 0, s>>>((float*)out, (const float*)yn, n, h, theta);
+  } else {
+    if (rhs == 1) dense_ew<double, 1><<<grid, 256, 0, s>>>((double*)out, (const double*)yn, n, h, theta);
+    else dense_ew<double, 2><<<grid, 256, 0, s>>>((double*)out, (const double*)yn, n, h, theta);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_ctrl(DevCtrl* c, hipStream_t s) {

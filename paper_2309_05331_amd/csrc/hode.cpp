@@ -86,6 +86,7 @@ struct hode_ctx {
   int ab_steps = 0;
   double ab_dt = 0;
   int64_t ab_n = 0;
+  void* d_obs = nullptr;  // staging for dense-output observations bound for host memory
   bool k1_valid = false;
   int parity = 0, k1slot = 0;
   bool use_graphs = true;      // replay captured chunks (else enqueue every kernel)
@@ -126,6 +127,8 @@ void free_state(hode_ctx* c) {
   for (void*& p : c->ks) { if (p) (void)hipFree(p); p = nullptr; }
   for (void*& p : c->k) { if (p) (void)hipFree(p); p = nullptr; }
   for (void*& p : c->xk_arr) { if (p) (void)hipFree(p); p = nullptr; }
+  if (c->d_obs) (void)hipFree(c->d_obs);
+  c->d_obs = nullptr;
   if (c->d_xk) (void)hipFree(c->d_xk);
   c->d_xk = nullptr;
   c->ab_steps = 0;
@@ -186,8 +189,9 @@ int default_ew_grid(int64_t n, int dtype) {
 }
 
 // Allocates the extra arrays a run needs (Gray-Scott Fehlberg stages; the
-// first `ring` Adams-Bashforth ring slots) and refreshes their device table.
-int ensure_xk(hode_ctx* c, bool f78, int ring) {
+// first `ring` Adams-Bashforth ring slots; Gray-Scott k6 for dense output)
+// and refreshes their device table.
+int ensure_xk(hode_ctx* c, bool f78, int ring, bool k6 = false) {
   bool changed = false;
   const size_t bytes = std::max<size_t>(256, (size_t)c->nelem * c->esize);
   auto need = [&](int i) -> bool {
@@ -204,6 +208,7 @@ int ensure_xk(hode_ctx* c, bool f78, int ring) {
       if (!need(i)) return fail(c, HODE_ENOMEM, "device allocation failed (Fehlberg stages)");
   for (int i = 0; i < ring; ++i)
     if (!need(hode::kRingBase + i)) return fail(c, HODE_ENOMEM, "device allocation failed (Adams-Bashforth ring)");
+  if (k6 && is_gs(c) && !need(hode::kXkK6)) return fail(c, HODE_ENOMEM, "device allocation failed (k6)");
   if (!c->d_xk) {
     if (hipMalloc(&c->d_xk, sizeof(void*) * hode::kXkCount) != hipSuccess) {
       c->d_xk = nullptr;
@@ -250,6 +255,7 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
   static const int rk4[] = {hode::K_D1, hode::K_R2, hode::K_R3, hode::K_R4};
   static const int dp5f[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6F, hode::K_D7F};
   static const int dp5a[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6, hode::K_D7};
+  static const int dp5d[] = {hode::K_D2, hode::K_D3, hode::K_D4, hode::K_D5, hode::K_D6K, hode::K_D7};
   // Cash-Karp: stages 1-3 have the Dopri5 shapes and coefficients
   static const int ckf[] = {hode::K_D1, hode::K_D2, hode::K_D3, hode::K_C4, hode::K_C5, hode::K_C6F};
   static const int cka[] = {hode::K_D1, hode::K_D2, hode::K_D3, hode::K_C4, hode::K_C5, hode::K_C6};
@@ -259,6 +265,7 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
                    : mode == hode::MODE_FIXED_CK  ? ckf
                    : mode == hode::MODE_ADAPTIVE_CK ? cka
                    : mode == hode::MODE_FIXED_EULER ? eul
+                   : mode == hode::MODE_ADAPTIVE_DENSE ? dp5d
                                                     : dp5a;
   const int ns = mode == hode::MODE_FIXED_RK4 ? 4 : (mode == hode::MODE_FIXED_EULER ? 1 : 6);
   for (int i = 0; i < ns; ++i) {
@@ -344,8 +351,9 @@ int pow2_floor(int64_t x) {
 
 // Runs the device-resident loop from the control block `init` until done.
 int run_loop(hode_ctx* c, const DevCtrl& init, bool need_k1) {
-  if (mode_f78(init.mode) || init.mode == hode::MODE_FIXED_AB) {
-    int rc = ensure_xk(c, mode_f78(init.mode), init.mode == hode::MODE_FIXED_AB ? init.ab_steps : 0);
+  if (mode_f78(init.mode) || init.mode == hode::MODE_FIXED_AB || init.mode == hode::MODE_ADAPTIVE_DENSE) {
+    int rc = ensure_xk(c, mode_f78(init.mode), init.mode == hode::MODE_FIXED_AB ? init.ab_steps : 0,
+                       init.mode == hode::MODE_ADAPTIVE_DENSE);
     if (rc) return rc;
   }
   // every other stepping ends the Adams-Bashforth history
@@ -386,7 +394,8 @@ int run_loop(hode_ctx* c, const DevCtrl& init, bool need_k1) {
   c->k1slot = cur.k1slot;
   // k1 = f(y) of the current state is in the first-same-as-last slot only
   // after the Dopri5 modes
-  c->k1_valid = init.mode == hode::MODE_FIXED_DP5 || init.mode == hode::MODE_ADAPTIVE;
+  c->k1_valid = init.mode == hode::MODE_FIXED_DP5 || init.mode == hode::MODE_ADAPTIVE ||
+                init.mode == hode::MODE_ADAPTIVE_DENSE;
   c->last.accepted = cur.accepted;
   c->last.rejected = cur.rejected;
   c->last.rhs_evals = cur.rhs_evals + extra_evals;
@@ -878,6 +887,90 @@ int hode_integrate_times(hode_ctx* c, const double* times, int64_t n_times, doub
   c->last = tot;
   if (out) *out = tot;
   return tot.status;
+}
+
+int hode_integrate_times_dense(hode_ctx* c, const double* times, int64_t n_times, double dt0, int64_t max_steps,
+                               void* dst, size_t dst_bytes, int dst_on_device, hode_stats* out) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!times || n_times < 1 || !(dt0 > 0) || !std::isfinite(dt0) || max_steps < 0)
+    return fail(c, HODE_EINVAL, "bad integrate_times_dense arguments");
+  for (int64_t i = 0; i < n_times; ++i)
+    if (!std::isfinite(times[i]) || (i > 0 && !(times[i] > times[i - 1])))
+      return fail(c, HODE_EINVAL, "times must be finite and increasing");
+  if (c->stepper != HODE_DOPRI5) return fail(c, HODE_EINVAL, "dense output is Dopri5's continuous extension");
+  const size_t bytes = (size_t)c->nelem * c->esize;
+  if (!dst || dst_bytes / (size_t)n_times < bytes) return fail(c, HODE_ESTATE, "destination too small");
+  rc = check_adaptive(c);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (!dst_on_device && !c->d_obs && hipMalloc(&c->d_obs, std::max<size_t>(bytes, 256)) != hipSuccess) {
+    c->d_obs = nullptr;
+    return fail(c, HODE_ENOMEM, "device allocation failed (observation staging)");
+  }
+  rc = ensure_xk(c, false, 0, true);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(dst, c->y[c->parity], bytes, kind, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double t0 = times[0], t1 = times[n_times - 1];
+  DevCtrl d = base_ctrl(c, hode::MODE_ADAPTIVE_DENSE);
+  d.t = d.t0 = t0;
+  d.t1 = t1;
+  d.dt = dt0;
+  d.max_attempts = max_steps;
+  const bool last = dt0 >= t1 - t0;
+  d.h = last ? t1 - t0 : dt0;
+  d.last_flag = last;
+  if (t0 >= t1) {
+    d.done = 1;
+  } else if (max_steps == 0) {
+    d.done = 1;
+    d.status = hode::ST_EMAXSTEPS;
+  } else if (d.h < 1e-12 * std::fmax(1.0, std::fabs(t0))) {
+    d.done = 1;
+    d.status = hode::ST_EDT_UNDERFLOW;
+  }
+  int64_t next = 1;  // next intermediate observation
+  const bool need_k1 = !c->k1_valid && !d.done;
+  bool first = true;
+  for (;;) {
+    d.stop_at = next < n_times - 1 ? times[next] : HUGE_VAL;
+    rc = run_loop(c, d, first && need_k1);
+    if (rc) return rc;
+    first = false;
+    const DevCtrl cur = c->persist;
+    // every requested time the last accepted step reached lies inside it
+    // (the run pauses at the first step that reaches one)
+    const double tp = cur.t - cur.h_acc;
+    for (; next < n_times - 1 && cur.accepted > 0 && times[next] <= cur.t; ++next) {
+      const double th = (times[next] - tp) / cur.h_acc;
+      void* o = dst_on_device ? (void*)((char*)dst + (size_t)next * bytes) : c->d_obs;
+      const void* yn = c->y[cur.parity ^ 1];
+      if (is_gs(c)) {
+        HIPCHK(c, hode::launch_dense_k(c->dtype, o, yn, c->ks[cur.k1slot ^ 1], c->k[3], c->k[4], c->k[5],
+                                       c->xk_arr[hode::kXkK6], c->ks[cur.k1slot], c->nelem,
+                                       default_ew_grid(c->nelem, c->dtype), cur.h_acc, th, c->stream));
+      } else {
+        HIPCHK(c, hode::launch_dense_ew(c->dtype, c->rhs, o, yn, c->nelem, c->ew_grid, cur.h_acc, th, c->stream));
+      }
+      if (!dst_on_device)
+        HIPCHK(c, hipMemcpyAsync((char*)dst + (size_t)next * bytes, c->d_obs, bytes, kind, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (cur.status != hode::ST_OK || cur.t >= t1 || !cur.done) break;
+    d = cur;  // paused at an observation: resume where it stopped
+    d.done = 0;
+  }
+  // the counters ran on across the pauses; the first k1 comes on top
+  c->last.rhs_evals = c->persist.rhs_evals + (need_k1 ? 1 : 0);
+  if (c->last.status == HODE_OK && n_times > 1) {
+    HIPCHK(c, hipMemcpyAsync((char*)dst + (size_t)(n_times - 1) * bytes, c->y[c->parity], bytes, kind, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  c->persist_valid = false;
+  if (out) *out = c->last;
+  return c->last.status;
 }
 
 int hode_try_step(hode_ctx* c, double* t, double* dt, int* accepted) {

@@ -23,11 +23,12 @@ enum Mode : int32_t {
   MODE_FIXED_CK = 4, MODE_ADAPTIVE_CK = 5,                    // Cash-Karp 5(4) fixed, adaptive
   MODE_FIXED_EULER = 6,                                       // explicit Euler
   MODE_FIXED_F78 = 7, MODE_ADAPTIVE_F78 = 8,                  // Fehlberg 7(8) fixed, adaptive
-  MODE_FIXED_AB = 9                                           // Adams-Bashforth (ab_steps steps)
+  MODE_FIXED_AB = 9,                                          // Adams-Bashforth (ab_steps steps)
+  MODE_ADAPTIVE_DENSE = 10  // Dopri5 adaptive, pausing after the accepted step that reaches stop_at
 };
 
 __host__ __device__ constexpr bool mode_adaptive(int m) {
-  return m == MODE_ADAPTIVE || m == MODE_ADAPTIVE_CK || m == MODE_ADAPTIVE_F78;
+  return m == MODE_ADAPTIVE || m == MODE_ADAPTIVE_CK || m == MODE_ADAPTIVE_F78 || m == MODE_ADAPTIVE_DENSE;
 }
 // Right-hand side evaluations of one attempt or fixed step (Dopri5: k1 of
 // the first attempt comes on top; Adams-Bashforth steps after the start-up).
@@ -74,7 +75,8 @@ struct DevCtrl {
   double stiff;  // spectral-radius scale of the System's Jacobian (feature of the learned controller)
   int32_t ab_steps;  // Adams-Bashforth: steps s (ring of s past right-hand sides)
   int32_t ring;      // Adams-Bashforth: ring slot receiving f_n of the next step
-  double pad[2];
+  double stop_at;    // dense output: the run pauses (done) after the accepted step that reaches it
+  double h_acc;      // size of the last accepted step
 };
 
 // ---- tableaux (Dormand & Prince 1980; classical RK4) ------------------------
@@ -121,6 +123,16 @@ __device__ constexpr double F78A[13][13] = {
 __device__ constexpr double F78B[13] = {0, 0, 0, 0, 0, 34.0 / 105.0, 9.0 / 35.0, 9.0 / 35.0, 9.0 / 280.0,
                                         9.0 / 280.0, 0, 41.0 / 840.0, 41.0 / 840.0};
 __device__ constexpr double F78E = 41.0 / 840.0;
+
+// Continuous extension of Dormand-Prince 5(4) (Dormand & Prince 1986;
+// Hairer, Norsett & Wanner I, section II.6): y(t_n + theta h) = y_n + h
+// sum_j w_j(theta) k_j with w_j = b_j (3 theta^2 - 2 theta^3) + DPC_j theta^2
+// (1 - theta)^2 + [j = 1] theta (1 - theta)^2 - [j = 7] theta^2 (1 - theta):
+// the quartic through y_n, y_{n+1} with end slopes k1, k7, made 4th-order
+// accurate by the DPC term.
+__device__ constexpr double DPC[7] = {-12715105075.0 / 11282082432.0, 0.0, 87487479700.0 / 32700410799.0,
+                                      -10690763975.0 / 1880347072.0, 701980252875.0 / 199316789632.0,
+                                      -1453857185.0 / 822651844.0, 69997945.0 / 29380423.0};
 
 // Adams-Bashforth weights: with s steps, y_{n+1} = y_n + h sum_j ABW[s-1][j]
 // f_{n-j} (the integral over one step of the polynomial through the last s
@@ -285,6 +297,7 @@ __device__ inline void decide_a(DevCtrl* c, double err, CtrlScratch* s) {
     fac = f;
     c->err_prev = e;
     c->t = c->last_flag ? c->t1 : c->t + h;
+    c->h_acc = h;
     c->accepted += 1;
     c->parity ^= 1;
     c->k1slot ^= 1;
@@ -349,6 +362,8 @@ __device__ inline void decide_c(DevCtrl* c, CtrlScratch* s) {
   }
   c->h = hn;
   c->last_flag = last ? 1 : 0;
+  // dense output: hand back to the host, which interpolates inside this step
+  if (c->mode == MODE_ADAPTIVE_DENSE && s->ok && c->t >= c->stop_at) c->done = 1;
 }
 
 // The whole control step: the body of the one-wavefront control kernel that

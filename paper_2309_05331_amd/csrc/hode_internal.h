@@ -27,13 +27,15 @@ enum GSKind : int {
   K_D6F = K_COUNT,  // fixed-step stage 6: the new state only
   K_F1, K_F2, K_F3, K_F4, K_F5, K_F6, K_F7, K_F8, K_F9, K_F10, K_F11, K_F12, K_F13, K_F13F,
   K_AB1, K_AB2, K_AB3, K_AB4, K_AB5, K_AB6, K_AB7, K_AB8,
-  K_ALL  // number of kinds
+  K_D6K,  // Dopri5 stage 6 that also stores k6 (dense output)
+  K_ALL   // number of kinds
 };
 
 // Extra arrays of the Fehlberg and Adams-Bashforth kinds (device table
 // xk(GSLaunch)): k1 .. k12 of Fehlberg 7(8) at 0 .. 11, the ring of the last
 // s right-hand sides of Adams-Bashforth at kRingBase .. kRingBase + s - 1.
-constexpr int kXkF78 = 12, kRingBase = 16, kXkCount = 24;
+// k6 of Dopri5 for dense output at kXkK6.
+constexpr int kXkF78 = 12, kXkK6 = 12, kRingBase = 16, kXkCount = 24;
 
 struct GSLaunch {
   void* y[2];    // state, indexed by the device-side parity
@@ -67,6 +69,16 @@ hipError_t launch_ew(int dtype, int rhs, int mode, void* y0, void* y1, int64_t n
 // there.
 hipError_t launch_ewx(int dtype, int rhs, int mode, int ab_steps, void* y0, void* y1, void* const* xk, void* kout,
                       int64_t n, int grid, DevCtrl* c, hipStream_t s);
+
+// Dense output of Dopri5 at theta in [0, 1] of the last accepted step of
+// size h: out = y_n + h sum_j w_j(theta) k_j.  Gray-Scott: from the stored
+// stages (k2 has weight 0); element-wise: the stages are evaluated again from
+// y_n in registers, exactly as the step evaluated them.
+hipError_t launch_dense_k(int dtype, void* out, const void* yn, const void* k1, const void* k3, const void* k4,
+                          const void* k5, const void* k6, const void* k7, int64_t n, int grid, double h, double theta,
+                          hipStream_t s);
+hipError_t launch_dense_ew(int dtype, int rhs, void* out, const void* yn, int64_t n, int grid, double h,
+                           double theta, hipStream_t s);
 
 // The step controller: one wavefront, run after the final stage kernel of
 // every attempt or fixed step.

@@ -148,6 +148,9 @@ constexpr KindDesc kDescX[K_ALL - K_F1] = {
                false, 7},
     /* AB8 */ {1, {A_Y}, {0}, 7, {A_RG0 + 1, A_RG0 + 2, A_RG0 + 3, A_RG0 + 4, A_RG0 + 5, A_RG0 + 6, A_RG0 + 7},
                A_RG0, 7, false, 8},
+    /* D6K */ {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
+               {0, 9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0}, 0, {0},
+               A_X0 + kXkK6, 2, true, 0},
 };
 #undef HODE_F13_ROW
 

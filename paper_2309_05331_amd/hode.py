@@ -37,6 +37,7 @@ K_D1, K_R2, K_R3, K_R4, K_D2, K_D3, K_D4, K_D5, K_D6, K_D7, K_D7F, K_C4, K_C5, K
 K_F = list(range(17, 30))  # Fehlberg 7(8) stages F1 .. F13
 K_F13F = 30
 K_AB = list(range(31, 39))  # Adams-Bashforth with 1 .. 8 steps
+K_D6K = 39  # Dopri5 stage 6 storing k6 (dense output)
 
 
 class hode_stats(C.Structure):
@@ -83,6 +84,7 @@ def lib():
             "hode_do_step": ([P, I, D, D], I),
             "hode_integrate_n_steps": ([P, I, D, D, I64, C.POINTER(D)], I),
             "hode_integrate_times": ([P, C.POINTER(D), I64, D, I64, P, S, I, C.POINTER(hode_stats)], I),
+            "hode_integrate_times_dense": ([P, C.POINTER(D), I64, D, I64, P, S, I, C.POINTER(hode_stats)], I),
             "hode_try_step": ([P, C.POINTER(D), C.POINTER(D), C.POINTER(I)], I),
             "hode_integrate_adaptive": ([P, D, D, D, I64, C.POINTER(hode_stats)], I),
             "hode_get_stats": ([P, C.POINTER(hode_stats)], I),
@@ -240,6 +242,18 @@ class Context:
         st = hode_stats()
         self._check(self.L.hode_integrate_times(self.h, arr, len(times), dt0, max_steps, p, nb, on_dev, C.byref(st)),
                     allow)
+        return st.as_dict()
+
+    def integrate_dense_times(self, times, dt0, dst, max_steps=10 ** 9,
+                              allow=(EMAXSTEPS, EDT_UNDERFLOW, ENONFINITE)):
+        """Dopri5 dense output: the states at the given times into dst (as
+        integrate_times), intermediate ones interpolated inside the free
+        steps; returns the stats."""
+        arr = (C.c_double * len(times))(*[float(t) for t in times])
+        p, nb, on_dev = _ptr_of(dst)
+        st = hode_stats()
+        self._check(self.L.hode_integrate_times_dense(self.h, arr, len(times), dt0, max_steps, p, nb, on_dev,
+                                                      C.byref(st)), allow)
         return st.as_dict()
 
     def get_stats(self):
