@@ -30,6 +30,12 @@ def AB(steps: int) -> int:
     return 10 + steps
 
 
+def ABM(steps: int) -> int:
+    """Method code of the Adams-Bashforth-Moulton predictor-corrector (1 .. 8 steps)."""
+    assert 1 <= steps <= 8
+    return 20 + steps
+
+
 CTRL_PI, CTRL_I = 1, 2
 OK, EINVAL, EDT_UNDERFLOW, EMAXSTEPS, ENONFINITE = 0, -1, -5, -6, -7
 
@@ -89,6 +95,8 @@ def lib():
         L.orc_dopri5_dense_weights.restype = None
         L.orc_ab_weights.argtypes = [C.c_int, P]
         L.orc_ab_weights.restype = None
+        L.orc_am_weights.argtypes = [C.c_int, P]
+        L.orc_am_weights.restype = None
         L.orc_ctrl_decide_k.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double),
                                         C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.orc_integrate_n_steps_e.argtypes = [C.POINTER(System), C.c_int, P, C.c_double, C.c_double,
@@ -154,6 +162,13 @@ def ctrl_decide(kind: int, err: float, err_prev: float, last_rejected: bool, ord
     else:
         acc = lib().orc_ctrl_decide_k(kind, order_k, err, C.byref(ep), C.byref(lr), C.byref(fac))
     return bool(acc), fac.value, ep.value, bool(lr.value)
+
+
+def am_weights(steps: int) -> np.ndarray:
+    """Adams-Moulton weights gamma_0 .. gamma_{steps-1} (gamma_j multiplies f_{n+1-j})."""
+    g = np.zeros(8)
+    lib().orc_am_weights(steps, _ptr(g))
+    return g[:steps]
 
 
 def ab_weights(steps: int) -> np.ndarray:

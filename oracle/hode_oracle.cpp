@@ -20,6 +20,11 @@
 //    Fehlberg 1968 (NASA TR R-287).
 //    Dopri 5 is first-same-as-last: k7 of an accepted step is k1 of the next;
 //    Cash-Karp and Fehlberg evaluate their stages afresh every attempt.
+//    Adams-Bashforth-Moulton with s steps (predict, evaluate, correct,
+//    evaluate): the Adams-Bashforth prediction p, then the Adams-Moulton
+//    correction y_{n+1} = y_n + h (gamma_0 f(p) + sum_{j>=1} gamma_j
+//    f_{n+1-j}) over s right-hand sides (order s); f_{n+1} = f(y_{n+1}) is
+//    the next step's first evaluation.
 //    Adams-Bashforth with s steps: y_{n+1} = y_n + h sum_j beta_j f_{n-j},
 //    beta_j the integral over one step of the Lagrange polynomial through
 //    the last s right-hand sides; the first s-1 steps, before s right-hand
@@ -56,8 +61,9 @@ extern "C" {
 
 enum { ORC_EXP = 1, ORC_LOGISTIC = 2, ORC_GRAYSCOTT = 3 };
 enum { ORC_RK4 = 1, ORC_DOPRI5 = 2, ORC_CASHKARP = 3, ORC_EULER = 4, ORC_FEHLBERG78 = 5 };
-// Adams-Bashforth with s steps (1 <= s <= 8) is method ORC_AB0 + s.
-enum { ORC_AB0 = 10 };
+// Adams-Bashforth with s steps (1 <= s <= 8) is method ORC_AB0 + s, the
+// Adams-Bashforth-Moulton predictor-corrector with s steps ORC_ABM0 + s.
+enum { ORC_AB0 = 10, ORC_ABM0 = 20 };
 enum { ORC_CTRL_PI = 1, ORC_CTRL_I = 2 };
 enum {
   ORC_OK = 0,
@@ -203,6 +209,36 @@ void ab_weights(int s, double* beta) {
     int64_t num = 0;
     for (int d = 0; d <= deg; ++d) num += poly[d] * (L / (d + 1));
     beta[j] = (double)num / (double)denom;
+  }
+}
+
+// Adams-Moulton weights for s values, from their definition: with the
+// right-hand sides at the nodes u = 1 - j (j = 0 .. s-1; u = 1 is the new
+// point), gamma_j = integral over u in [0, 1] of prod_{i != j} (u - (1 - i))
+// / ((1 - j) - (1 - i)) = prod_{i != j} (u - 1 + i) / (i - j); the same
+// exact-integer evaluation as ab_weights.
+void am_weights(int s, double* gamma) {
+  int64_t L = 1;
+  for (int64_t d = 2; d <= s; ++d) {
+    int64_t a = L, b = d;
+    while (b) { const int64_t r = a % b; a = b; b = r; }
+    L = L / a * d;
+  }
+  for (int j = 0; j < s; ++j) {
+    int64_t poly[9] = {1};  // coefficients of u^0 .. u^8
+    int deg = 0;
+    int64_t denom = L;
+    for (int i = 0; i < s; ++i) {
+      if (i == j) continue;
+      // multiply by (u + (i - 1))
+      for (int d = deg + 1; d >= 1; --d) poly[d] = poly[d - 1] + (int64_t)(i - 1) * poly[d];
+      poly[0] *= (i - 1);
+      ++deg;
+      denom *= (i - j);
+    }
+    int64_t num = 0;
+    for (int d = 0; d <= deg; ++d) num += poly[d] * (L / (d + 1));
+    gamma[j] = (double)num / (double)denom;
   }
 }
 
@@ -431,6 +467,45 @@ int64_t adams_bashforth(const orc_system& s, int steps, double* y, double h, int
   return evals;
 }
 
+// Adams-Bashforth-Moulton (PECE) with s steps over nsteps fixed steps from a
+// fresh start: the start-up as adams_bashforth, then per step f_n = f(y_n),
+// the prediction p = y_n + h sum_j beta_j f_{n-j}, and the correction
+// y_{n+1} = y_n + h (gamma_0 f(p) + sum_{j>=1} gamma_j f_{n+1-j}).  Returns
+// the right-hand side evaluations made.
+int64_t adams_bashforth_moulton(const orc_system& s, int steps, double* y, double h, int64_t nsteps) {
+  const int64_t n = s.n;
+  double beta[8], gamma[8];
+  ab_weights(steps, beta);
+  am_weights(steps, gamma);
+  std::vector<std::vector<double>> f(steps, std::vector<double>(n));  // f[m % steps] = f_m
+  Work W(n, 13);
+  std::vector<double> p(n), fp(n), ynew(n);
+  int64_t evals = 0;
+  for (int64_t m = 0; m < nsteps; ++m) {
+    double* fm = f[m % steps].data();
+    rhs(s, y, fm);
+    evals += 1;
+    if (m < steps - 1) {
+      fehlberg78_attempt(s, y, fm, h, ynew.data(), nullptr, W);
+      evals += 12;
+      std::swap_ranges(ynew.begin(), ynew.end(), y);
+      continue;
+    }
+    double* past[8];
+    for (int j = 0; j < steps; ++j) past[j] = f[(m - j) % steps].data();
+    stage_input(n, y, h, steps, beta, past, p.data());
+    rhs(s, p.data(), fp.data());
+    evals += 1;
+    // corrector values f(p), f_n, f_{n-1}, .., f_{n+2-s}
+    double* cv[8];
+    cv[0] = fp.data();
+    for (int j = 1; j < steps; ++j) cv[j] = f[(m + 1 - j) % steps].data();
+    stage_input(n, y, h, steps, gamma, cv, ynew.data());
+    std::swap_ranges(ynew.begin(), ynew.end(), y);
+  }
+  return evals;
+}
+
 // ---- step-size controller -------------------------------------------------------
 
 // k = 1 + the order of the embedded solution (5 for the 5(4) pairs, 8 for
@@ -513,6 +588,10 @@ void orc_ab_weights(int steps, double* beta) {
   if (steps >= 1 && steps <= 8) ab_weights(steps, beta);
 }
 
+void orc_am_weights(int steps, double* gamma) {
+  if (steps >= 1 && steps <= 8) am_weights(steps, gamma);
+}
+
 int orc_ctrl_decide_k(int kind, double order_k, double err, double* err_prev, int* last_rejected, double* fac) {
   Ctrl c(kind, order_k);
   c.err_prev = *err_prev;
@@ -571,14 +650,17 @@ int orc_cashkarp_attempt(const orc_system* s, const double* y, double h, double*
 int orc_integrate_n_steps_e(const orc_system* s, int method, double* y, double t0, double dt, int64_t nsteps,
                             double* t_end, int64_t* rhs_evals) {
   const bool ab = method > ORC_AB0 && method <= ORC_AB0 + 8;
+  const bool abm = method > ORC_ABM0 && method <= ORC_ABM0 + 8;
   if (!valid(s) || nsteps < 0 ||
       !(method == ORC_RK4 || method == ORC_DOPRI5 || method == ORC_CASHKARP || method == ORC_EULER ||
-        method == ORC_FEHLBERG78 || ab))
+        method == ORC_FEHLBERG78 || ab || abm))
     return ORC_EINVAL;
   const int64_t n = s->n;
   int64_t evals = 0;
   if (ab) {
     evals = adams_bashforth(*s, method - ORC_AB0, y, dt, nsteps);
+  } else if (abm) {
+    evals = adams_bashforth_moulton(*s, method - ORC_ABM0, y, dt, nsteps);
   } else if (method == ORC_FEHLBERG78) {
     Work W(n, 13);
     std::vector<double> k1(n), ynew(n);
@@ -611,7 +693,7 @@ int orc_integrate_n_steps_e(const orc_system* s, int method, double* y, double t
       k1.swap(k7);
     }
   }
-  if (!ab && method != ORC_FEHLBERG78) {
+  if (!ab && !abm && method != ORC_FEHLBERG78) {
     const int per = method == ORC_EULER ? 1 : (method == ORC_RK4 ? 4 : 6);
     evals = per * nsteps + (method == ORC_DOPRI5 && nsteps > 0 ? 1 : 0);
   }

@@ -857,3 +857,63 @@ def test_dense_output_run_matches_adaptive_and_closed_forms(orc):
             assert np.max(np.abs(out[i] - exact) / (1 + np.abs(exact))) < 30e-8, (kind, t)
     with pytest.raises(ValueError):
         orc.integrate_dense_times(orc.ew_system(1, 4), x0[:4], [0.0, 1.0, 0.5], 0.01, 1e-6, 1e-6)
+
+
+# ------------------------------------------- Adams-Bashforth-Moulton (PECE)
+
+@pytest.mark.parametrize("steps", range(1, 9))
+def test_adams_moulton_weights_moments(orc, steps):
+    # nodes u = 1 - j: exact for polynomials of degree < s,
+    # sum_j gamma_j (1 - j)^m = 1/(m+1) for m < s, and not for m = s
+    gamma = [Fr(x).limit_denominator(10 ** 7) for x in orc.am_weights(steps)]
+    for x in gamma:
+        assert x.denominator <= 120960
+    for m in range(steps + 1):
+        mom = sum(g * Fr(1 - j) ** m for j, g in enumerate(gamma))
+        assert (mom == Fr(1, m + 1)) == (m < steps), m
+    for x, q in zip(orc.am_weights(steps), gamma):
+        _check_rounding(x, q)
+
+
+_ABM_WINDOWS = {**{(1, s): 320 for s in range(1, 6)}, (1, 6): 160,
+                **{(2, s): 320 for s in range(1, 6)}, (2, 6): 160, (2, 7): 160, (2, 8): 80}
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("steps", range(1, 9))
+def test_adams_bashforth_moulton_convergence_order(orc, kind, steps):
+    x0 = inputs.exp_family_x0(4096, seed=2)
+    sysd = orc.ew_system(kind, x0.size)
+    exact = _closed(kind, x0, 5.0)
+    if (kind, steps) not in _ABM_WINDOWS:
+        # 7 and 8 steps on the exponential family reach round-off (growth
+        # to 74) before the asymptotic range
+        y, _ = orc.integrate_n_steps(sysd, orc.ABM(steps), x0, 0.0, 5.0 / 320, 320)
+        assert np.max(np.abs(y - exact)) < 2e-12
+        return
+    n = _ABM_WINDOWS[(kind, steps)]
+    errs = []
+    for m in (n, 2 * n):
+        y, _ = orc.integrate_n_steps(sysd, orc.ABM(steps), x0, 0.0, 5.0 / m, m)
+        errs.append(np.max(np.abs(y - exact)))
+    r = errs[0] / errs[1]
+    assert abs(r / 2 ** steps - 1) < 0.2, (errs, r)
+
+
+def test_adams_bashforth_moulton_start_up_and_counts(orc):
+    x0 = inputs.exp_family_x0(257, seed=20)
+    sysd = orc.ew_system(orc.LOGISTIC, x0.size)
+    for s in (1, 3, 8):
+        for n in range(s):
+            ya, _, ev = orc.integrate_n_steps(sysd, orc.ABM(s), x0, 0.0, 0.05, n, evals=True)
+            yf, _ = orc.integrate_n_steps(sysd, orc.FEHLBERG78, x0, 0.0, 0.05, n)
+            assert np.array_equal(ya, yf) and ev == 13 * n
+        _, _, ev = orc.integrate_n_steps(sysd, orc.ABM(s), x0, 0.0, 0.05, 30, evals=True)
+        assert ev == 13 * (s - 1) + 2 * (30 - s + 1)  # predict-evaluate-correct-evaluate
+        # the corrector moves the prediction: ABM differs from AB after the start-up
+        yb, _ = orc.integrate_n_steps(sysd, orc.AB(s), x0, 0.0, 0.05, 30)
+        ym, _ = orc.integrate_n_steps(sysd, orc.ABM(s), x0, 0.0, 0.05, 30)
+        assert not np.array_equal(yb, ym)
+    fp = np.array([0.0, 1.0, 1.0, 0.0])
+    y, _ = orc.integrate_n_steps(orc.ew_system(orc.LOGISTIC, 4), orc.ABM(6), fp, 0.0, 0.2, 17)
+    assert np.array_equal(y, fp)
