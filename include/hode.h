@@ -56,6 +56,13 @@ enum { HODE_RHS_EXP = 1, HODE_RHS_LOGISTIC = 2, HODE_RHS_GRAYSCOTT3D = 3 };
  * Fehlberg 7(8) step).  The 5(4) pairs carry the 5th-order solution. */
 enum { HODE_RK4 = 1, HODE_DOPRI5 = 2, HODE_CASHKARP54 = 3, HODE_EULER = 4, HODE_FEHLBERG78 = 5 };
 enum { HODE_AB1 = 11, HODE_AB2, HODE_AB3, HODE_AB4, HODE_AB5, HODE_AB6, HODE_AB7, HODE_AB8 };
+/* Adams-Bashforth-Moulton with s = 1 .. 8 steps, HODE_ABM1 + s - 1 (fixed
+ * steps only; the paper's Table 1 multi-step pair): per step f_n = f(y_n),
+ * the Adams-Bashforth prediction p, f(p), and the Adams-Moulton correction
+ * y_{n+1} = y_n + h (gamma_0 f(p) + sum_{j>=1} gamma_j f_{n+1-j}) over s
+ * right-hand sides (order s; two System evaluations per step); history and
+ * start-up as for Adams-Bashforth. */
+enum { HODE_ABM1 = 21, HODE_ABM2, HODE_ABM3, HODE_ABM4, HODE_ABM5, HODE_ABM6, HODE_ABM7, HODE_ABM8 };
 enum { HODE_CTRL_PI = 1, HODE_CTRL_I = 2, HODE_CTRL_MLP = 3 };
 enum {
   HODE_OK = 0,
@@ -222,9 +229,10 @@ int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);  /* the widest stage's
  * for the widest that divides N (16-byte loads where possible). */
 int hode_set_vector_width(hode_ctx *ctx, int vw);
 
-/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..39 as D1,
+/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..47 as D1,
  * R2, R3, R4, D2..D7, D7F, C4, C5, C6, C6F, E1, D6F, F1..F13, F13F,
- * AB1..AB8, D6K; element-wise: kind = method) on the context's
+ * AB1..AB8, D6K, ABC1..ABC8 (the Adams-Moulton correctors, which write the
+ * state); element-wise: kind = method) on the context's
  * stream with HIP events and returns the mean duration in milliseconds.
  * The state is left unchanged for Gray-Scott non-final kinds only; timing an
  * Adams-Bashforth kind ends the Adams-Bashforth history. */

@@ -8,7 +8,8 @@
 // norm is reduced on the fly (wavefront shuffle, LDS, one atomic per
 // workgroup).  The one-wavefront control kernel then takes the decision.
 // An Adams-Bashforth step reads the component's s - 1 past right-hand sides
-// from the ring and writes the new one.
+// from the ring and writes the new one; an Adams-Bashforth-Moulton step
+// does the same and corrects in registers, in place.
 #include "hode_internal.h"
 
 namespace hode {
@@ -375,6 +376,74 @@ __global__ __launch_bounds__(256) void dense_ew(T* __restrict__ out, const T* __
   }
 }
 
+// One Adams-Bashforth-Moulton step with S steps over all components, in
+// place: f_n = f(y_n) into ring slot c->ring (S > 1), the prediction
+// p = y_n + h sum_j beta_j f_{n-j} (as ew_ab), and y_{n+1} = y_n + h (gamma_0
+// f(p) + gamma_1 f_n + sum_{j>=2} gamma_j f_{n+1-j}) written over y_n.
+template <typename T, int RHS, int S>
+__global__ __launch_bounds__(256) void ew_abm(DevCtrl* __restrict__ c, T* __restrict__ b0, T* __restrict__ b1,
+                                              void* const* __restrict__ xk, int64_t n) {
+  if (c->done) return;
+  const double h = c->h;
+  T* __restrict__ y = c->parity ? b1 : b0;
+  const int rg = c->ring;
+  T* __restrict__ fn = S > 1 ? (T*)xk[kRingBase + rg] : nullptr;
+  const T* fp[S > 1 ? S : 1];
+  T q[S], g[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    q[j] = (T)(h * ABW[S - 1][j]);
+    g[j] = (T)(h * AMW[S - 1][j]);
+    if (j > 0) fp[j] = (const T*)xk[kRingBase + (rg + S - j) % S];
+  }
+  auto one = [&](T x, const T* past, T& f) -> T {
+    // past[j] = f_{n-j}, j = 1 .. S-1
+    f = frhs<T, RHS>(x);
+    T p = x;
+#pragma unroll
+    for (int j = 1; j < S; ++j) p += q[j] * past[j];
+    p = p + q[0] * f;
+    const T fpred = frhs<T, RHS>(p);
+    T acc = x;
+    if constexpr (S > 1) acc += g[1] * f;
+#pragma unroll
+    for (int j = 2; j < S; ++j) acc += g[j] * past[j - 1];
+    return acc + g[0] * fpred;
+  };
+  using V = typename Vec<T>::V;
+  constexpr int W = Vec<T>::W;
+  const int64_t nv = n / W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    V v = reinterpret_cast<const V*>(y)[i];
+    V pv[S > 1 ? S : 1];
+#pragma unroll
+    for (int j = 1; j < S; ++j) pv[j] = reinterpret_cast<const V*>(fp[j])[i];
+    V fv;
+    T* e = reinterpret_cast<T*>(&v);
+    T* f = reinterpret_cast<T*>(&fv);
+#pragma unroll
+    for (int l = 0; l < W; ++l) {
+      T past[S > 1 ? S : 1];
+#pragma unroll
+      for (int j = 1; j < S; ++j) past[j] = reinterpret_cast<const T*>(&pv[j])[l];
+      e[l] = one(e[l], past, f[l]);
+    }
+    reinterpret_cast<V*>(y)[i] = v;
+    if constexpr (S > 1) reinterpret_cast<V*>(fn)[i] = fv;
+  }
+  const int64_t tail = nv * W;
+  if (blockIdx.x == gridDim.x - 1 && tail + threadIdx.x < n) {
+    const int64_t i = tail + threadIdx.x;
+    T past[S > 1 ? S : 1];
+#pragma unroll
+    for (int j = 1; j < S; ++j) past[j] = fp[j][i];
+    T f;
+    y[i] = one(y[i], past, f);
+    if constexpr (S > 1) fn[i] = f;
+  }
+}
+
 __global__ __launch_bounds__(64) void ctrl_kernel(DevCtrl* c) {
   if (c->done) return;
   ctrl_step(c);
@@ -402,11 +471,15 @@ hipError_t launch_x(int mode, int ab_steps, T* y0, T* y1, void* const* xk, T* ko
                     DevCtrl* c, hipStream_t s) {
   if (mode == MODE_FIXED_F78) ew_f78<T, RHS, false><<<grid, 256, 0, s>>>(c, y0, y1, kout, n);
   else if (mode == MODE_ADAPTIVE_F78) ew_f78<T, RHS, true><<<grid, 256, 0, s>>>(c, y0, y1, kout, n);
-  else if (mode == MODE_FIXED_AB) {
+  else if (mode == MODE_FIXED_AB || mode == MODE_FIXED_ABM) {
     if (xk == nullptr && ab_steps > 1) return hipErrorInvalidValue;
+    const bool abm = mode == MODE_FIXED_ABM;
     switch (ab_steps) {
-#define HODE_AB(S) \
-  case S: ew_ab<T, RHS, S><<<grid, 256, 0, s>>>(c, y0, y1, xk, n); break;
+#define HODE_AB(S)                                                                 \
+  case S:                                                                          \
+    if (abm) ew_abm<T, RHS, S><<<grid, 256, 0, s>>>(c, y0, y1, xk, n);             \
+    else ew_ab<T, RHS, S><<<grid, 256, 0, s>>>(c, y0, y1, xk, n);                  \
+    break;
       HODE_AB(1) HODE_AB(2) HODE_AB(3) HODE_AB(4) HODE_AB(5) HODE_AB(6) HODE_AB(7) HODE_AB(8)
 #undef HODE_AB
       default: return hipErrorInvalidValue;

@@ -84,6 +84,7 @@ struct hode_ctx {
   // Adams-Bashforth history (as an Odeint stepper object keeps it): steps s
   // (0: none), its step size, and the steps taken since it started
   int ab_steps = 0;
+  bool ab_moulton = false;  // the history is that of Adams-Bashforth-Moulton
   double ab_dt = 0;
   int64_t ab_n = 0;
   void* d_obs = nullptr;  // staging for dense-output observations bound for host memory
@@ -226,22 +227,27 @@ int ensure_xk(hode_ctx* c, bool f78, int ring, bool k6 = false) {
 
 bool mode_f78(int mode) { return mode == hode::MODE_FIXED_F78 || mode == hode::MODE_ADAPTIVE_F78; }
 
+bool mode_multistep(int mode) { return mode == hode::MODE_FIXED_AB || mode == hode::MODE_FIXED_ABM; }
+
 // Enqueues the kernels of one attempt (or fixed step) in `mode`
-// (Adams-Bashforth: with the context's current number of steps).
+// (Adams-Bashforth(-Moulton): with the context's current number of steps).
 hipError_t enqueue_attempt(hode_ctx* c, int mode) {
   if (!is_gs(c)) {
-    hipError_t e = mode_f78(mode) || mode == hode::MODE_FIXED_AB
+    hipError_t e = mode_f78(mode) || mode_multistep(mode)
                        ? hode::launch_ewx(c->dtype, c->rhs, mode, c->ab_steps, c->y[0], c->y[1], c->d_xk, nullptr,
                                           c->nelem, c->ew_grid, c->d_ctrl, c->stream)
                        : hode::launch_ew(c->dtype, c->rhs, mode, c->y[0], c->y[1], c->nelem, c->ew_grid,
                                          c->d_ctrl, c->stream);
     return e != hipSuccess ? e : hode::launch_ctrl(c->d_ctrl, c->stream);
   }
-  if (mode_f78(mode) || mode == hode::MODE_FIXED_AB) {
+  if (mode_f78(mode) || mode_multistep(mode)) {
     const hode::GSLaunch a = gs_args(c);
-    if (mode == hode::MODE_FIXED_AB) {
+    if (mode_multistep(mode)) {
       if (c->ab_steps < 1 || c->ab_steps > 8) return hipErrorInvalidValue;
+      // Adams-Bashforth (the prediction, for Adams-Bashforth-Moulton), then
+      // the Adams-Moulton correction
       hipError_t e = launch_stage(c, hode::K_AB1 + c->ab_steps - 1, a);
+      if (e == hipSuccess && mode == hode::MODE_FIXED_ABM) e = launch_stage(c, hode::K_ABC1 + c->ab_steps - 1, a);
       return e != hipSuccess ? e : hode::launch_ctrl(c->d_ctrl, c->stream);
     }
     for (int k = hode::K_F1; k <= hode::K_F12; ++k) {
@@ -277,7 +283,7 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
 
 int get_graph(hode_ctx* c, int mode, int M, hipGraphExec_t* out) {
   // Adams-Bashforth chunks differ by the number of steps
-  auto key = std::make_pair(mode == hode::MODE_FIXED_AB ? mode | (c->ab_steps << 8) : mode, M);
+  auto key = std::make_pair(mode_multistep(mode) ? mode | (c->ab_steps << 8) : mode, M);
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) { *out = it->second; return HODE_OK; }
   hipGraph_t g = nullptr;
@@ -351,13 +357,13 @@ int pow2_floor(int64_t x) {
 
 // Runs the device-resident loop from the control block `init` until done.
 int run_loop(hode_ctx* c, const DevCtrl& init, bool need_k1) {
-  if (mode_f78(init.mode) || init.mode == hode::MODE_FIXED_AB || init.mode == hode::MODE_ADAPTIVE_DENSE) {
-    int rc = ensure_xk(c, mode_f78(init.mode), init.mode == hode::MODE_FIXED_AB ? init.ab_steps : 0,
+  if (mode_f78(init.mode) || mode_multistep(init.mode) || init.mode == hode::MODE_ADAPTIVE_DENSE) {
+    int rc = ensure_xk(c, mode_f78(init.mode), mode_multistep(init.mode) ? init.ab_steps : 0,
                        init.mode == hode::MODE_ADAPTIVE_DENSE);
     if (rc) return rc;
   }
-  // every other stepping ends the Adams-Bashforth history
-  if (init.mode != hode::MODE_FIXED_AB) c->ab_steps = 0;
+  // every other stepping ends the Adams-Bashforth(-Moulton) history
+  if (!mode_multistep(init.mode)) c->ab_steps = 0;
   *c->h_ctrl = init;
   HIPCHK(c, hipMemcpyAsync(c->d_ctrl, c->h_ctrl, sizeof(DevCtrl), hipMemcpyHostToDevice, c->stream));
   int64_t extra_evals = 0;
@@ -439,19 +445,21 @@ int ab_startup_step(hode_ctx* c, DevCtrl& d, int slot) {
   return HODE_OK;
 }
 
-// n fixed Adams-Bashforth steps with s steps.  The history (the last s
-// right-hand sides) continues from the previous call when s and dt are the
-// same and no other stepping came in between; otherwise it starts afresh,
-// and the first s - 1 steps are Fehlberg 7(8) steps that record f(y_n).
-int ab_run(hode_ctx* c, int s, double t0, double dt, int64_t n) {
-  if (!(c->ab_steps == s && c->ab_dt == dt)) {
+// n fixed Adams-Bashforth (moulton: Adams-Bashforth-Moulton) steps with s
+// steps.  The history (the last s right-hand sides) continues from the
+// previous call when the method, s and dt are the same and no other stepping
+// came in between; otherwise it starts afresh, and the first s - 1 steps are
+// Fehlberg 7(8) steps that record f(y_n).
+int ab_run(hode_ctx* c, int s, bool moulton, double t0, double dt, int64_t n) {
+  if (!(c->ab_steps == s && c->ab_moulton == moulton && c->ab_dt == dt)) {
     c->ab_steps = s;
+    c->ab_moulton = moulton;
     c->ab_dt = dt;
     c->ab_n = 0;
   }
   int rc = ensure_xk(c, c->ab_n < s - 1 && n > 0, s);
   if (rc) return rc;
-  DevCtrl d = base_ctrl(c, hode::MODE_FIXED_AB);
+  DevCtrl d = base_ctrl(c, moulton ? hode::MODE_FIXED_ABM : hode::MODE_FIXED_AB);
   d.t = d.t0 = t0;
   d.h = d.dt = dt;
   d.ab_steps = s;
@@ -461,7 +469,7 @@ int ab_run(hode_ctx* c, int s, double t0, double dt, int64_t n) {
     if (rc) return rc;
     ++c->ab_n;
   }
-  d.mode = hode::MODE_FIXED_AB;
+  d.mode = moulton ? hode::MODE_FIXED_ABM : hode::MODE_FIXED_AB;
   d.nsteps = n;
   d.done = i >= n;
   d.ring = (int)(c->ab_n % s);
@@ -747,13 +755,14 @@ int hode_integrate_n_steps(hode_ctx* c, int method, double t0, double dt, int64_
   int rc = check_ready(c);
   if (rc) return rc;
   const bool ab = method >= HODE_AB1 && method <= HODE_AB8;
+  const bool abm = method >= HODE_ABM1 && method <= HODE_ABM8;
   if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54 && method != HODE_EULER &&
-      method != HODE_FEHLBERG78 && !ab)
+      method != HODE_FEHLBERG78 && !ab && !abm)
     return fail(c, HODE_EINVAL, "method");
   if (n < 0 || !std::isfinite(t0) || !std::isfinite(dt)) return fail(c, HODE_EINVAL, "bad step arguments");
   HIPCHK(c, hipSetDevice(c->device));
-  if (ab) {
-    rc = ab_run(c, method - HODE_AB1 + 1, t0, dt, n);
+  if (ab || abm) {
+    rc = ab_run(c, ab ? method - HODE_AB1 + 1 : method - HODE_ABM1 + 1, abm, t0, dt, n);
     if (rc) return rc;
     c->persist_valid = false;
     if (t_end) *t_end = t0 + (double)n * dt;
@@ -1101,9 +1110,12 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
   if (!is_gs(c) && kind != HODE_RK4 && kind != HODE_DOPRI5) return fail(c, HODE_EINVAL, "kernel kind");
   HIPCHK(c, hipSetDevice(c->device));
   if (is_gs(c) && kind >= hode::K_F1) {
-    // the Adams-Bashforth kinds write ring slot 0: the history ends
-    const int ring = kind >= hode::K_AB1 ? kind - hode::K_AB1 + 1 : 0;
-    rc = ensure_xk(c, ring == 0, ring);
+    // the Adams-Bashforth kinds write ring slot 0 (the correctors the state):
+    // the history ends
+    const int ring = kind >= hode::K_AB1 && kind <= hode::K_AB8     ? kind - hode::K_AB1 + 1
+                     : kind >= hode::K_ABC1 && kind <= hode::K_ABC8 ? kind - hode::K_ABC1 + 1
+                                                                    : 0;
+    rc = ensure_xk(c, kind <= hode::K_F13F, ring, kind == hode::K_D6K);
     if (rc) return rc;
     if (ring) c->ab_steps = 0;
   }

@@ -24,7 +24,8 @@ enum Mode : int32_t {
   MODE_FIXED_EULER = 6,                                       // explicit Euler
   MODE_FIXED_F78 = 7, MODE_ADAPTIVE_F78 = 8,                  // Fehlberg 7(8) fixed, adaptive
   MODE_FIXED_AB = 9,                                          // Adams-Bashforth (ab_steps steps)
-  MODE_ADAPTIVE_DENSE = 10  // Dopri5 adaptive, pausing after the accepted step that reaches stop_at
+  MODE_ADAPTIVE_DENSE = 10,  // Dopri5 adaptive, pausing after the accepted step that reaches stop_at
+  MODE_FIXED_ABM = 11        // Adams-Bashforth-Moulton (ab_steps steps; new state in place)
 };
 
 __host__ __device__ constexpr bool mode_adaptive(int m) {
@@ -35,6 +36,7 @@ __host__ __device__ constexpr bool mode_adaptive(int m) {
 __host__ __device__ constexpr int mode_rhs_evals(int m) {
   return m == MODE_FIXED_RK4 ? 4
          : (m == MODE_FIXED_EULER || m == MODE_FIXED_AB) ? 1
+         : m == MODE_FIXED_ABM                         ? 2
          : (m == MODE_FIXED_F78 || m == MODE_ADAPTIVE_F78) ? 13
                                                            : 6;
 }
@@ -133,6 +135,23 @@ __device__ constexpr double F78E = 41.0 / 840.0;
 __device__ constexpr double DPC[7] = {-12715105075.0 / 11282082432.0, 0.0, 87487479700.0 / 32700410799.0,
                                       -10690763975.0 / 1880347072.0, 701980252875.0 / 199316789632.0,
                                       -1453857185.0 / 822651844.0, 69997945.0 / 29380423.0};
+
+// Adams-Moulton weights for s values: y_{n+1} = y_n + h (AMW[s-1][0]
+// f_{n+1} + sum_{j>=1} AMW[s-1][j] f_{n+1-j}) (the integral over one step of
+// the polynomial through f_{n+1} .. f_{n+2-s}; Hairer, Norsett & Wanner I,
+// section III.1), with f_{n+1} taken at the Adams-Bashforth prediction.
+__device__ constexpr double AMW[8][8] = {
+    {1.0},
+    {1.0 / 2.0, 1.0 / 2.0},
+    {5.0 / 12.0, 8.0 / 12.0, -1.0 / 12.0},
+    {9.0 / 24.0, 19.0 / 24.0, -5.0 / 24.0, 1.0 / 24.0},
+    {251.0 / 720.0, 646.0 / 720.0, -264.0 / 720.0, 106.0 / 720.0, -19.0 / 720.0},
+    {475.0 / 1440.0, 1427.0 / 1440.0, -798.0 / 1440.0, 482.0 / 1440.0, -173.0 / 1440.0, 27.0 / 1440.0},
+    {19087.0 / 60480.0, 65112.0 / 60480.0, -46461.0 / 60480.0, 37504.0 / 60480.0, -20211.0 / 60480.0,
+     6312.0 / 60480.0, -863.0 / 60480.0},
+    {36799.0 / 120960.0, 139849.0 / 120960.0, -121797.0 / 120960.0, 123133.0 / 120960.0, -88547.0 / 120960.0,
+     41499.0 / 120960.0, -11351.0 / 120960.0, 1375.0 / 120960.0},
+};
 
 // Adams-Bashforth weights: with s steps, y_{n+1} = y_n + h sum_j ABW[s-1][j]
 // f_{n-j} (the integral over one step of the polynomial through the last s
@@ -261,10 +280,11 @@ __device__ inline void fixed_step_done(DevCtrl* c) {
   c->accepted += 1;
   c->attempts += 1;
   c->t = c->t0 + (double)c->accepted * c->h;
-  c->parity ^= 1;
+  // (Adams-Bashforth-Moulton corrects the state in place: no parity flip)
+  if (c->mode != MODE_FIXED_ABM) c->parity ^= 1;
   c->k1slot ^= 1;
   c->rhs_evals += mode_rhs_evals(c->mode);
-  if (c->mode == MODE_FIXED_AB) c->ring = c->ring + 1 == c->ab_steps ? 0 : c->ring + 1;
+  if (c->mode == MODE_FIXED_AB || c->mode == MODE_FIXED_ABM) c->ring = c->ring + 1 == c->ab_steps ? 0 : c->ring + 1;
   if (c->accepted >= c->nsteps) c->done = 1;
 }
 

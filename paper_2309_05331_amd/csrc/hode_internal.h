@@ -28,6 +28,10 @@ enum GSKind : int {
   K_F1, K_F2, K_F3, K_F4, K_F5, K_F6, K_F7, K_F8, K_F9, K_F10, K_F11, K_F12, K_F13, K_F13F,
   K_AB1, K_AB2, K_AB3, K_AB4, K_AB5, K_AB6, K_AB7, K_AB8,
   K_D6K,  // Dopri5 stage 6 that also stores k6 (dense output)
+  // Adams-Moulton correctors of Adams-Bashforth-Moulton with s steps: f(p)
+  // of the prediction p (in the spare state buffer) and the corrected state,
+  // written over y_n (each cell's y_n is read only by the thread that writes it)
+  K_ABC1, K_ABC2, K_ABC3, K_ABC4, K_ABC5, K_ABC6, K_ABC7, K_ABC8,
   K_ALL   // number of kinds
 };
 

@@ -51,7 +51,7 @@ struct KindDesc {
   int fin;         // own-cell finish: 0 none, 1 RK4 new state, 2 Dopri5 new state (+ partial error),
                    // 3 Dopri5 error completion, 4 Cash-Karp new state (+ error norm),
                    // 5 Euler new state, 6 Fehlberg 7(8) new state (+ error norm),
-                   // 7 Adams-Bashforth new state
+                   // 7 Adams-Bashforth new state, 8 Adams-Moulton correction (in place)
   bool err;        // error norm computed
   int ab;          // Adams-Bashforth steps (ring size), 0 otherwise
 };
@@ -151,6 +151,18 @@ constexpr KindDesc kDescX[K_ALL - K_F1] = {
     /* D6K */ {6, {A_Y, A_K1, A_K2, A_K3, A_K4, A_K5},
                {0, 9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0}, 0, {0},
                A_X0 + kXkK6, 2, true, 0},
+    // correctors: the stencil over the prediction (spare state buffer); at the
+    // own cell y_n and f_n .. f_{n+2-s} from the ring
+    /* ABC1 */ {1, {A_YN}, {0}, 1, {A_Y}, -1, 8, false, 1},
+    /* ABC2 */ {1, {A_YN}, {0}, 2, {A_Y, A_RG0}, -1, 8, false, 2},
+    /* ABC3 */ {1, {A_YN}, {0}, 3, {A_Y, A_RG0, A_RG0 + 1}, -1, 8, false, 3},
+    /* ABC4 */ {1, {A_YN}, {0}, 4, {A_Y, A_RG0, A_RG0 + 1, A_RG0 + 2}, -1, 8, false, 4},
+    /* ABC5 */ {1, {A_YN}, {0}, 5, {A_Y, A_RG0, A_RG0 + 1, A_RG0 + 2, A_RG0 + 3}, -1, 8, false, 5},
+    /* ABC6 */ {1, {A_YN}, {0}, 6, {A_Y, A_RG0, A_RG0 + 1, A_RG0 + 2, A_RG0 + 3, A_RG0 + 4}, -1, 8, false, 6},
+    /* ABC7 */ {1, {A_YN}, {0}, 7, {A_Y, A_RG0, A_RG0 + 1, A_RG0 + 2, A_RG0 + 3, A_RG0 + 4, A_RG0 + 5}, -1, 8,
+                false, 7},
+    /* ABC8 */ {1, {A_YN}, {0}, 8,
+                {A_Y, A_RG0, A_RG0 + 1, A_RG0 + 2, A_RG0 + 3, A_RG0 + 4, A_RG0 + 5, A_RG0 + 6}, -1, 8, false, 8},
 };
 #undef HODE_F13_ROW
 
@@ -293,7 +305,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 #pragma unroll
   for (int i = 0; i < D.nx; ++i) ext[i] = array_ptr<T>(a, D.extra[i], p, ksl, rg, D.ab);
   T* out = D.out >= 0 ? array_ptr<T>(a, D.out, p, ksl, rg, D.ab) : nullptr;
-  T* ynew = (D.fin == 1 || D.fin == 2 || D.fin >= 4) ? (T*)a.y[p ^ 1] : nullptr;
+  T* ynew = (D.fin == 1 || D.fin == 2 || D.fin >= 4) ? (T*)a.y[D.fin == 8 ? p : p ^ 1] : nullptr;
   T* e6 = (D.fin == 2 && D.err) ? (T*)a.k[A_E6] : nullptr;
 
   T cf[10];
@@ -311,9 +323,9 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   const double ce1 = h * CE1, ce3 = h * CE3, ce4 = h * CE4, ce5 = h * CE5, ce6 = h * CE6;
   const T fb6 = (T)(h * FB6), fb7 = (T)(h * FB7), fb9 = (T)(h * FB9), fb12 = (T)(h * FB12);
   const double fe = h * FE;
-  T abq[D.ab > 0 ? D.ab : 1];  // Adams-Bashforth weights times h
+  T abq[D.ab > 0 ? D.ab : 1];  // Adams-Bashforth (corrector: Adams-Moulton) weights times h
 #pragma unroll
-  for (int j = 0; j < D.ab; ++j) abq[j] = (T)(h * ABW[D.ab > 0 ? D.ab - 1 : 0][j]);
+  for (int j = 0; j < D.ab; ++j) abq[j] = (T)(h * (D.fin == 8 ? AMW : ABW)[D.ab > 0 ? D.ab - 1 : 0][j]);
 
   // ---- offsets (periodic wrap folded in)
   const int xl = x0 + VW * jl;
@@ -390,6 +402,13 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
           T acc = s[0].v[e];
 #pragma unroll
           for (int j = 1; j < D.ab; ++j) acc += abq[j] * x[j - 1].v[e];
+          fin->a[e] = acc;
+        } else if constexpr (D.fin == 8) {
+          // source the prediction; extras y_n, f_n .. f_{n+2-s}: the
+          // Adams-Moulton correction without f(p)
+          T acc = x[0].v[e];
+#pragma unroll
+          for (int j = 1; j < D.ab; ++j) acc += abq[j] * x[j].v[e];
           fin->a[e] = acc;
         } else if constexpr (D.fin == 4) {
           // sources y, k1 .. k5: Cash-Karp new state and error without k6
@@ -569,8 +588,9 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
             for (int e = 0; e < VW; ++e) yn.v[e] = fc[f][r].a[e] + hT * fo[f].v[e];
             stv<T, VW>(ynew, f * n3 + g, yn);
           }
-        } else if constexpr (D.fin == 7) {
-          // Adams-Bashforth new state y + h sum_j beta_j f_{n-j}
+        } else if constexpr (D.fin == 7 || D.fin == 8) {
+          // Adams-Bashforth new state y + h sum_j beta_j f_{n-j}, or the
+          // Adams-Moulton correction y_n + h (gamma_0 f(p) + sum_j gamma_j f_{n+1-j})
 #pragma unroll
           for (int f = 0; f < 2; ++f) {
             P yn;
@@ -667,11 +687,12 @@ __global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __res
   // Stages alternate their direction through each XCD's range, so a stage
   // starts on the tiles the previous stage wrote last, which are still in the
   // memory-side Infinity Cache.
-  // (The Adams-Bashforth kinds, one per step, alternate with the step.)
+  // (The Adams-Bashforth kinds alternate with the step; the Adams-Moulton
+  // correctors, which keep the parity, sweep against their predictor.)
   constexpr bool rev_k = KIND == K_R2 || KIND == K_R4 || KIND == K_D3 || KIND == K_D5 || KIND == K_D7 ||
                          KIND == K_D7F || KIND == K_C5 || KIND == K_F2 || KIND == K_F4 || KIND == K_F6 ||
                          KIND == K_F8 || KIND == K_F10 || KIND == K_F12;
-  const bool rev = desc<KIND>().ab > 0 ? (c->parity & 1) != 0 : rev_k;
+  const bool rev = desc<KIND>().ab > 0 ? ((c->parity & 1) != 0) != (desc<KIND>().fin == 8) : rev_k;
   const int slot = rev ? per - 1 - (int)(blockIdx.x >> 3) : (int)(blockIdx.x >> 3);
   const int bb = (blockIdx.x & 7) * per + slot;
   if (bb >= nx * ny * nz) return;  // padding block of the remap (whole block)

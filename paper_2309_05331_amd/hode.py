@@ -20,6 +20,13 @@ RHS_EXP, RHS_LOGISTIC, RHS_GRAYSCOTT3D = 1, 2, 3
 RK4, DOPRI5, CASHKARP54, EULER, FEHLBERG78 = 1, 2, 3, 4, 5
 
 
+def ABM(steps):
+    """Method code of Adams-Bashforth-Moulton with `steps` steps (1 .. 8)."""
+    if not 1 <= steps <= 8:
+        raise ValueError("Adams-Bashforth-Moulton steps must be 1 .. 8")
+    return 20 + steps
+
+
 def AB(steps):
     """Method code of Adams-Bashforth with `steps` steps (1 .. 8)."""
     if not 1 <= steps <= 8:
@@ -38,6 +45,7 @@ K_F = list(range(17, 30))  # Fehlberg 7(8) stages F1 .. F13
 K_F13F = 30
 K_AB = list(range(31, 39))  # Adams-Bashforth with 1 .. 8 steps
 K_D6K = 39  # Dopri5 stage 6 storing k6 (dense output)
+K_ABC = list(range(40, 48))  # Adams-Moulton correctors with 1 .. 8 steps
 
 
 class hode_stats(C.Structure):

@@ -281,3 +281,91 @@ def test_time_and_profile_new_kinds():
     ry, zc, tot = ctx.autotune(hode.AB(8), 1)
     assert ry in (1, 2, 4) and tot > 0
     ctx.close()
+
+
+# ------------------------------------------- Adams-Bashforth-Moulton (PECE)
+
+@pytest.mark.parametrize("kind", [hode.RHS_EXP, hode.RHS_LOGISTIC])
+@pytest.mark.parametrize("steps", range(1, 9))
+def test_abm_fp64_elementwise(orc, kind, steps):
+    n = 40009
+    x0 = inputs.exp_family_x0(n, seed=85)
+    ctx = ew_ctx(kind, x0)
+    ctx.integrate_n_steps(hode.ABM(steps), 0.0, 0.01, 100)
+    g = read(ctx, np.float64, n)
+    o, _, ev = orc.integrate_n_steps(orc.ew_system(kind, n), orc.ABM(steps), x0, 0.0, 0.01, 100, evals=True)
+    assert rel_err(g, o) <= TOL64, rel_err(g, o)
+    st = ctx.get_stats()
+    assert st["accepted"] == 100 and st["rhs_evals"] == ev
+    ctx.close()
+
+
+@pytest.mark.parametrize("N", [12, 33])
+@pytest.mark.parametrize("steps", [1, 2, 5, 8])
+def test_abm_fp64_grayscott(orc, N, steps):
+    y0 = inputs.gray_scott_ic(N, seed=86)
+    ctx = gs_ctx(y0, N, PRM_D)
+    dt = _dt_ab(N, PRM_D)
+    ctx.integrate_n_steps(hode.ABM(steps), 0.0, dt, 30)
+    g = read(ctx, np.float64, 2 * N ** 3)
+    o, _, ev = orc.integrate_n_steps(orc.gs_system(N, **PRM_D), orc.ABM(steps), y0.ravel(), 0.0, dt, 30,
+                                     evals=True)
+    assert rel_err_fields(g, o, 2) <= TOL64
+    assert ctx.get_stats()["rhs_evals"] == ev
+    ctx.close()
+
+
+@pytest.mark.parametrize("gs", [False, True])
+def test_abm_history_and_switches(orc, gs):
+    if gs:
+        N = 20
+        y0 = inputs.gray_scott_ic(N, seed=87).ravel()
+        sysd = orc.gs_system(N, **PRM_D)
+        make = lambda: gs_ctx(y0, N, PRM_D)
+        h = _dt_ab(N, PRM_D)
+    else:
+        y0 = inputs.exp_family_x0(5003, seed=87)
+        sysd = orc.ew_system(orc.LOGISTIC, y0.size)
+        make = lambda: ew_ctx(hode.RHS_LOGISTIC, y0)
+        h = 0.01
+    for s in (3, 8):
+        one = make()
+        one.integrate_n_steps(hode.ABM(s), 0.0, h, 20)
+        want = read(one, np.float64, y0.size)
+        one.close()
+        split = make()
+        t = 0.0
+        for m in (2, 6, 5, 7):
+            split.integrate_n_steps(hode.ABM(s), t, h, m)
+            t += m * h
+        assert np.array_equal(read(split, np.float64, y0.size), want), s
+        # Adams-Bashforth with the same s and dt is another method: a fresh history
+        split.integrate_n_steps(hode.AB(s), t, h, 10)
+        o, _ = orc.integrate_n_steps(sysd, orc.AB(s), want, t, h, 10)
+        assert rel_err(read(split, np.float64, y0.size), o) <= TOL64
+        split.close()
+
+
+def test_abm_tile_independent_and_fp32(orc):
+    N = 40
+    y0 = inputs.gray_scott_ic(N, seed=88)
+    ref = None
+    for tile in (None, (1, 8), (2, 16), (4, 40)):
+        ctx = gs_ctx(y0, N, PRM_D, tile=tile)
+        ctx.integrate_n_steps(hode.ABM(8), 0.0, 0.001, 12)
+        g = read(ctx, np.float64, 2 * N ** 3)
+        ctx.close()
+        if ref is None:
+            ref = g
+        assert np.array_equal(g, ref), tile
+    N = 32
+    y32 = inputs.gray_scott_ic(N, seed=1, dtype=np.float32)
+    ctx = gs_ctx(y32, N, PRM)
+    dt = _dt_ab(N, PRM)
+    ctx.integrate_n_steps(hode.ABM(8), 0.0, dt, 200)
+    g = read(ctx, np.float32, 2 * N ** 3)
+    o, _ = orc.integrate_n_steps(orc.gs_system(N, **PRM), orc.ABM(8), y32.astype(np.float64).ravel(), 0.0, dt, 200)
+    err = np.max(np.abs(g.astype(np.float64) - o))
+    print("32^3 FP32 Adams-Bashforth-Moulton 8 x200 max-abs vs FP64 oracle: %.3e" % err)
+    assert err <= TOL32_ABS
+    ctx.close()
