@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "hode_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 EXP, LOGISTIC, GRAYSCOTT = 1, 2, 3
-RK4, DOPRI5, CASHKARP, EULER, FEHLBERG78 = 1, 2, 3, 4, 5
+RK4, DOPRI5, CASHKARP, EULER, FEHLBERG78, MIDPOINT = 1, 2, 3, 4, 5, 6
 
 
 def AB(steps: int) -> int:

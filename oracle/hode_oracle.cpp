@@ -11,7 +11,8 @@
 // combined by an *Algebra* (linear combinations of states); adaptive steppers
 // bound the error with the L-infinity norm of the embedded error estimate.
 //
-//  * Steppers: explicit Euler, classical Runge-Kutta 4, Runge-Kutta-Dopri 5,
+//  * Steppers: explicit Euler, the modified midpoint method (Gragg, two
+//    substeps), classical Runge-Kutta 4, Runge-Kutta-Dopri 5,
 //    Runge-Kutta Cash-Karp 5(4) and Runge-Kutta-Fehlberg 7(8) (the paper's
 //    Table 1, fixed and dynamic step size), and the multi-step
 //    Adams-Bashforth methods of 1 to 8 steps (fixed step size).
@@ -60,7 +61,7 @@
 extern "C" {
 
 enum { ORC_EXP = 1, ORC_LOGISTIC = 2, ORC_GRAYSCOTT = 3 };
-enum { ORC_RK4 = 1, ORC_DOPRI5 = 2, ORC_CASHKARP = 3, ORC_EULER = 4, ORC_FEHLBERG78 = 5 };
+enum { ORC_RK4 = 1, ORC_DOPRI5 = 2, ORC_CASHKARP = 3, ORC_EULER = 4, ORC_FEHLBERG78 = 5, ORC_MIDPOINT = 6 };
 // Adams-Bashforth with s steps (1 <= s <= 8) is method ORC_AB0 + s, the
 // Adams-Bashforth-Moulton predictor-corrector with s steps ORC_ABM0 + s.
 enum { ORC_AB0 = 10, ORC_ABM0 = 20 };
@@ -342,6 +343,26 @@ void euler_step(const orc_system& s, double* y, double h, Work& W) {
   const double* k = W.k[0].data();
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) y[i] = y[i] + h * k[i];
+}
+
+// One modified midpoint step of size H in place, with m = 2 substeps of
+// h = H/2 (Gragg; Hairer, Norsett & Wanner I, section II.9): z0 = y,
+// z1 = z0 + h f(z0), z2 = z0 + 2h f(z1), y_new = (z2 + z1 + h f(z2)) / 2.
+void midpoint_step(const orc_system& s, double* y, double H, Work& W) {
+  const int64_t n = s.n;
+  const double h = 0.5 * H;
+  double* f = W.k[0].data();
+  double* z1 = W.k[1].data();
+  double* z2 = W.k[2].data();
+  rhs(s, y, f);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) z1[i] = y[i] + h * f[i];
+  rhs(s, z1, f);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) z2[i] = y[i] + 2.0 * h * f[i];
+  rhs(s, z2, f);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) y[i] = 0.5 * (z2[i] + z1[i] + h * f[i]);
 }
 
 // One classical RK4 step in place.
@@ -653,11 +674,15 @@ int orc_integrate_n_steps_e(const orc_system* s, int method, double* y, double t
   const bool abm = method > ORC_ABM0 && method <= ORC_ABM0 + 8;
   if (!valid(s) || nsteps < 0 ||
       !(method == ORC_RK4 || method == ORC_DOPRI5 || method == ORC_CASHKARP || method == ORC_EULER ||
-        method == ORC_FEHLBERG78 || ab || abm))
+        method == ORC_FEHLBERG78 || method == ORC_MIDPOINT || ab || abm))
     return ORC_EINVAL;
   const int64_t n = s->n;
   int64_t evals = 0;
-  if (ab) {
+  if (method == ORC_MIDPOINT) {
+    Work W(n, 3);
+    for (int64_t i = 0; i < nsteps; ++i) midpoint_step(*s, y, dt, W);
+    evals = 3 * nsteps;
+  } else if (ab) {
     evals = adams_bashforth(*s, method - ORC_AB0, y, dt, nsteps);
   } else if (abm) {
     evals = adams_bashforth_moulton(*s, method - ORC_ABM0, y, dt, nsteps);
@@ -693,7 +718,7 @@ int orc_integrate_n_steps_e(const orc_system* s, int method, double* y, double t
       k1.swap(k7);
     }
   }
-  if (!ab && !abm && method != ORC_FEHLBERG78) {
+  if (!ab && !abm && method != ORC_FEHLBERG78 && method != ORC_MIDPOINT) {
     const int per = method == ORC_EULER ? 1 : (method == ORC_RK4 ? 4 : 6);
     evals = per * nsteps + (method == ORC_DOPRI5 && nsteps > 0 ? 1 : 0);
   }

@@ -917,3 +917,33 @@ def test_adams_bashforth_moulton_start_up_and_counts(orc):
     fp = np.array([0.0, 1.0, 1.0, 0.0])
     y, _ = orc.integrate_n_steps(orc.ew_system(orc.LOGISTIC, 4), orc.ABM(6), fp, 0.0, 0.2, 17)
     assert np.array_equal(y, fp)
+
+
+# ------------------------------------------------------ modified midpoint
+
+@pytest.mark.parametrize("h", [0.05, 0.3, 1.1, -0.7])
+def test_midpoint_amplification(orc, h):
+    # two substeps on x' = x: z1 = (1 + h/2) x, z2 = x + h z1 and
+    # (z2 + z1 + (h/2) z2) / 2 = (1 + h + h^2/2 + h^3/8) x
+    x0 = inputs.exp_family_x0(257, seed=21)
+    y, _, ev = orc.integrate_n_steps(orc.ew_system(orc.EXP, x0.size), orc.MIDPOINT, x0, 0.0, h, 1, evals=True)
+    R = 1 + h + h ** 2 / 2 + h ** 3 / 8
+    mag = 1 + abs(h) + h ** 2 / 2 + abs(h) ** 3 / 8
+    assert np.all(np.abs(y - R * x0) <= 8 * 2.0 ** -52 * mag * x0)
+    assert ev == 3
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_midpoint_convergence_order_2(orc, kind):
+    x0 = inputs.exp_family_x0(4096, seed=2)
+    sysd = orc.ew_system(kind, x0.size)
+    exact = _closed(kind, x0, 5.0)
+    errs = []
+    for n in (80, 160, 320):
+        y, _ = orc.integrate_n_steps(sysd, orc.MIDPOINT, x0, 0.0, 5.0 / n, n)
+        errs.append(np.max(np.abs(y - exact)))
+    r = errs[1] / errs[2]
+    assert abs(r / 4 - 1) < 0.05, errs
+    fp = np.array([0.0, 1.0])
+    y, _ = orc.integrate_n_steps(orc.ew_system(orc.LOGISTIC, 2), orc.MIDPOINT, fp, 0.0, 0.4, 9)
+    assert np.array_equal(y, fp)
