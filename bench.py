@@ -47,11 +47,12 @@ GS_PRM = [2e-5, 1e-5, 0.053, 0.014, 2.5]
 GS_ARRAYS = {0: 2, 1: 3, 2: 3, 3: 5, 4: 3, 5: 4, 6: 5, 7: 6, 8: 8, 9: 4, 10: 2, 11: 5, 12: 6, 13: 7, 14: 7, 15: 2,
              16: 7,
              17: 2, 18: 3, 19: 4, 20: 4, 21: 5, 22: 5, 23: 6, 24: 6, 25: 8, 26: 9, 27: 10, 28: 8, 29: 12, 30: 11,
-             31: 2, **{30 + s: s + 2 for s in range(2, 9)}, 39: 9, **{39 + s: s + 2 for s in range(1, 9)}}
+             31: 2, **{30 + s: s + 2 for s in range(2, 9)}, 39: 9, **{39 + s: s + 2 for s in range(1, 9)}, 48: 2, 49: 3,
+             50: 3}
 GS_NAMES = {0: "D1", 1: "R2", 2: "R3", 3: "R4", 4: "D2", 5: "D3", 6: "D4", 7: "D5", 8: "D6", 9: "D7", 10: "D7F",
             11: "C4", 12: "C5", 13: "C6", 14: "C6F", 15: "E1", 16: "D6F",
             **{16 + i: "F%d" % i for i in range(1, 14)}, 30: "F13F", **{30 + s: "AB%d" % s for s in range(1, 9)},
-            39: "D6K", **{39 + s: "ABC%d" % s for s in range(1, 9)}}
+            39: "D6K", **{39 + s: "ABC%d" % s for s in range(1, 9)}, 48: "MM1", 49: "MM2", 50: "MM3"}
 STAGES = {"rk4": [0, 1, 2, 3], "dp5": [4, 5, 6, 7, 8, 9], "ck54": [0, 4, 5, 11, 12, 13], "f78": list(range(17, 30)),
           "ab4": [34]}
 

@@ -48,13 +48,15 @@ enum { HODE_F32 = 1, HODE_F64 = 2 };
 enum { HODE_RHS_EXP = 1, HODE_RHS_LOGISTIC = 2, HODE_RHS_GRAYSCOTT3D = 3 };
 /* Steppers (the paper's Table 1): classical Runge-Kutta 4; Dormand-Prince
  * 5(4) ("Dopri5", 7 stages, first same as last); Cash-Karp 5(4) (6 stages,
- * Cash & Karp 1990); explicit Euler (fixed steps only); Runge-Kutta-Fehlberg
+ * Cash & Karp 1990); explicit Euler and the modified midpoint method (Gragg,
+ * two substeps of h/2: z1 = y + (h/2) f(y), z2 = y + h f(z1), y_new =
+ * (z2 + z1 + (h/2) f(z2)) / 2; fixed steps only); Runge-Kutta-Fehlberg
  * 7(8) (13 stages, Fehlberg 1968; carries the 8th-order solution); and the
  * multi-step Adams-Bashforth methods with s = 1 .. 8 steps, HODE_AB1 + s - 1
  * (fixed steps only; y_{n+1} = y_n + h sum_j beta_j f_{n-j} over the last s
  * right-hand sides, the first s - 1 steps of a fresh history taken by the
  * Fehlberg 7(8) step).  The 5(4) pairs carry the 5th-order solution. */
-enum { HODE_RK4 = 1, HODE_DOPRI5 = 2, HODE_CASHKARP54 = 3, HODE_EULER = 4, HODE_FEHLBERG78 = 5 };
+enum { HODE_RK4 = 1, HODE_DOPRI5 = 2, HODE_CASHKARP54 = 3, HODE_EULER = 4, HODE_FEHLBERG78 = 5, HODE_MIDPOINT = 6 };
 enum { HODE_AB1 = 11, HODE_AB2, HODE_AB3, HODE_AB4, HODE_AB5, HODE_AB6, HODE_AB7, HODE_AB8 };
 /* Adams-Bashforth-Moulton with s = 1 .. 8 steps, HODE_ABM1 + s - 1 (fixed
  * steps only; the paper's Table 1 multi-step pair): per step f_n = f(y_n),
@@ -229,10 +231,10 @@ int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);  /* the widest stage's
  * for the widest that divides N (16-byte loads where possible). */
 int hode_set_vector_width(hode_ctx *ctx, int vw);
 
-/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..47 as D1,
+/* Times `reps` launches of one stage kernel (Gray-Scott: kind 0..50 as D1,
  * R2, R3, R4, D2..D7, D7F, C4, C5, C6, C6F, E1, D6F, F1..F13, F13F,
  * AB1..AB8, D6K, ABC1..ABC8 (the Adams-Moulton correctors, which write the
- * state); element-wise: kind = method) on the context's
+ * state), MM1..MM3; element-wise: kind = method) on the context's
  * stream with HIP events and returns the mean duration in milliseconds.
  * The state is left unchanged for Gray-Scott non-final kinds only; timing an
  * Adams-Bashforth kind ends the Adams-Bashforth history. */

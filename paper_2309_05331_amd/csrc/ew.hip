@@ -119,6 +119,11 @@ __device__ __forceinline__ T step_one(T x, const DPCoef<T>& q, const CKCoef<T>& 
                                       double atol, double rtol, uint64_t& emax) {
   if constexpr (MODE == MODE_FIXED_EULER) {
     return x + r1 * frhs<T, RHS>(x);
+  } else if constexpr (MODE == MODE_FIXED_MM) {
+    // modified midpoint, two substeps of H/2 (r2 = H/2, r1 = H)
+    const T z1 = x + r2 * frhs<T, RHS>(x);
+    const T z2 = x + r1 * frhs<T, RHS>(z1);
+    return (T)0.5 * (z2 + z1 + r2 * frhs<T, RHS>(z2));
   } else if constexpr (MODE == MODE_FIXED_CK || MODE == MODE_ADAPTIVE_CK) {
     const T k1 = frhs<T, RHS>(x);
     const T k2 = frhs<T, RHS>(x + ck.a21 * k1);
@@ -461,6 +466,7 @@ hipError_t launch_rhs(int mode, T* y0, T* y1, int64_t n, int grid, DevCtrl* c, h
   else if (mode == MODE_FIXED_DP5) ew_step<T, RHS, MODE_FIXED_DP5><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else if (mode == MODE_FIXED_CK) ew_step<T, RHS, MODE_FIXED_CK><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else if (mode == MODE_FIXED_EULER) ew_step<T, RHS, MODE_FIXED_EULER><<<grid, 256, 0, s>>>(c, y0, y1, n);
+  else if (mode == MODE_FIXED_MM) ew_step<T, RHS, MODE_FIXED_MM><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else if (mode == MODE_ADAPTIVE_CK) ew_step<T, RHS, MODE_ADAPTIVE_CK><<<grid, 256, 0, s>>>(c, y0, y1, n);
   else ew_step<T, RHS, MODE_ADAPTIVE><<<grid, 256, 0, s>>>(c, y0, y1, n);
   return hipGetLastError();

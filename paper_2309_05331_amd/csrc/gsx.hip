@@ -5,7 +5,7 @@
 // step: f_n goes into the ring of past right-hand sides and the new state is
 // formed from it and the s - 1 before); the Adams-Moulton correctors of
 // Adams-Bashforth-Moulton (the Adams-Bashforth kinds write the prediction);
-// and the dense-output variant of
+// the modified midpoint substeps (MM1 .. MM3); and the dense-output variant of
 // Dopri5 stage 6 (D6K, which also stores k6).  Same tiles and block order as the
 // other stage kernels (stage.h); a translation unit of its own so the two
 // build in parallel.
@@ -32,7 +32,7 @@ hipError_t launch_t(int kind, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
     HODE_CASE(K_F13) HODE_CASE(K_F13F) HODE_CASE(K_AB1) HODE_CASE(K_AB2) HODE_CASE(K_AB3) HODE_CASE(K_AB4)
     HODE_CASE(K_AB5) HODE_CASE(K_AB6) HODE_CASE(K_AB7) HODE_CASE(K_AB8) HODE_CASE(K_D6K) HODE_CASE(K_ABC1)
     HODE_CASE(K_ABC2) HODE_CASE(K_ABC3) HODE_CASE(K_ABC4) HODE_CASE(K_ABC5) HODE_CASE(K_ABC6) HODE_CASE(K_ABC7)
-    HODE_CASE(K_ABC8)
+    HODE_CASE(K_ABC8) HODE_CASE(K_MM1) HODE_CASE(K_MM2) HODE_CASE(K_MM3)
 #undef HODE_CASE
     default: return hipErrorInvalidValue;
   }

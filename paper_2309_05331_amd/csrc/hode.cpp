@@ -192,7 +192,7 @@ int default_ew_grid(int64_t n, int dtype) {
 // Allocates the extra arrays a run needs (Gray-Scott Fehlberg stages; the
 // first `ring` Adams-Bashforth ring slots; Gray-Scott k6 for dense output)
 // and refreshes their device table.
-int ensure_xk(hode_ctx* c, bool f78, int ring, bool k6 = false) {
+int ensure_xk(hode_ctx* c, bool f78, int ring, bool k6 = false, bool mm = false) {
   bool changed = false;
   const size_t bytes = std::max<size_t>(256, (size_t)c->nelem * c->esize);
   auto need = [&](int i) -> bool {
@@ -210,6 +210,8 @@ int ensure_xk(hode_ctx* c, bool f78, int ring, bool k6 = false) {
   for (int i = 0; i < ring; ++i)
     if (!need(hode::kRingBase + i)) return fail(c, HODE_ENOMEM, "device allocation failed (Adams-Bashforth ring)");
   if (k6 && is_gs(c) && !need(hode::kXkK6)) return fail(c, HODE_ENOMEM, "device allocation failed (k6)");
+  if (mm && is_gs(c) && (!need(hode::kXkZ1) || !need(hode::kXkZ1 + 1)))
+    return fail(c, HODE_ENOMEM, "device allocation failed (midpoint substeps)");
   if (!c->d_xk) {
     if (hipMalloc(&c->d_xk, sizeof(void*) * hode::kXkCount) != hipSuccess) {
       c->d_xk = nullptr;
@@ -266,14 +268,19 @@ hipError_t enqueue_attempt(hode_ctx* c, int mode) {
   static const int ckf[] = {hode::K_D1, hode::K_D2, hode::K_D3, hode::K_C4, hode::K_C5, hode::K_C6F};
   static const int cka[] = {hode::K_D1, hode::K_D2, hode::K_D3, hode::K_C4, hode::K_C5, hode::K_C6};
   static const int eul[] = {hode::K_E1};
+  static const int mmd[] = {hode::K_MM1, hode::K_MM2, hode::K_MM3};
   const int* seq = mode == hode::MODE_FIXED_RK4   ? rk4
                    : mode == hode::MODE_FIXED_DP5 ? dp5f
                    : mode == hode::MODE_FIXED_CK  ? ckf
                    : mode == hode::MODE_ADAPTIVE_CK ? cka
                    : mode == hode::MODE_FIXED_EULER ? eul
                    : mode == hode::MODE_ADAPTIVE_DENSE ? dp5d
+                   : mode == hode::MODE_FIXED_MM ? mmd
                                                     : dp5a;
-  const int ns = mode == hode::MODE_FIXED_RK4 ? 4 : (mode == hode::MODE_FIXED_EULER ? 1 : 6);
+  const int ns = mode == hode::MODE_FIXED_RK4 ? 4
+                 : mode == hode::MODE_FIXED_EULER ? 1
+                 : mode == hode::MODE_FIXED_MM ? 3
+                                               : 6;
   for (int i = 0; i < ns; ++i) {
     hipError_t e = launch_stage(c, seq[i], a);
     if (e != hipSuccess) return e;
@@ -357,9 +364,10 @@ int pow2_floor(int64_t x) {
 
 // Runs the device-resident loop from the control block `init` until done.
 int run_loop(hode_ctx* c, const DevCtrl& init, bool need_k1) {
-  if (mode_f78(init.mode) || mode_multistep(init.mode) || init.mode == hode::MODE_ADAPTIVE_DENSE) {
+  if (mode_f78(init.mode) || mode_multistep(init.mode) || init.mode == hode::MODE_ADAPTIVE_DENSE ||
+      init.mode == hode::MODE_FIXED_MM) {
     int rc = ensure_xk(c, mode_f78(init.mode), mode_multistep(init.mode) ? init.ab_steps : 0,
-                       init.mode == hode::MODE_ADAPTIVE_DENSE);
+                       init.mode == hode::MODE_ADAPTIVE_DENSE, init.mode == hode::MODE_FIXED_MM);
     if (rc) return rc;
   }
   // every other stepping ends the Adams-Bashforth(-Moulton) history
@@ -757,7 +765,7 @@ int hode_integrate_n_steps(hode_ctx* c, int method, double t0, double dt, int64_
   const bool ab = method >= HODE_AB1 && method <= HODE_AB8;
   const bool abm = method >= HODE_ABM1 && method <= HODE_ABM8;
   if (method != HODE_RK4 && method != HODE_DOPRI5 && method != HODE_CASHKARP54 && method != HODE_EULER &&
-      method != HODE_FEHLBERG78 && !ab && !abm)
+      method != HODE_FEHLBERG78 && method != HODE_MIDPOINT && !ab && !abm)
     return fail(c, HODE_EINVAL, "method");
   if (n < 0 || !std::isfinite(t0) || !std::isfinite(dt)) return fail(c, HODE_EINVAL, "bad step arguments");
   HIPCHK(c, hipSetDevice(c->device));
@@ -772,6 +780,7 @@ int hode_integrate_n_steps(hode_ctx* c, int method, double t0, double dt, int64_
                    : method == HODE_DOPRI5       ? hode::MODE_FIXED_DP5
                    : method == HODE_CASHKARP54   ? hode::MODE_FIXED_CK
                    : method == HODE_FEHLBERG78   ? hode::MODE_FIXED_F78
+                   : method == HODE_MIDPOINT     ? hode::MODE_FIXED_MM
                                                  : hode::MODE_FIXED_EULER;
   DevCtrl d = base_ctrl(c, mode);
   d.t = d.t0 = t0;
@@ -1115,7 +1124,7 @@ int hode_time_kernel(hode_ctx* c, int kind, int reps, double* avg_ms) {
     const int ring = kind >= hode::K_AB1 && kind <= hode::K_AB8     ? kind - hode::K_AB1 + 1
                      : kind >= hode::K_ABC1 && kind <= hode::K_ABC8 ? kind - hode::K_ABC1 + 1
                                                                     : 0;
-    rc = ensure_xk(c, kind <= hode::K_F13F, ring, kind == hode::K_D6K);
+    rc = ensure_xk(c, kind <= hode::K_F13F, ring, kind == hode::K_D6K, kind >= hode::K_MM1);
     if (rc) return rc;
     if (ring) c->ab_steps = 0;
   }

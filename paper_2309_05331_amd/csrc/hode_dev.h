@@ -25,7 +25,8 @@ enum Mode : int32_t {
   MODE_FIXED_F78 = 7, MODE_ADAPTIVE_F78 = 8,                  // Fehlberg 7(8) fixed, adaptive
   MODE_FIXED_AB = 9,                                          // Adams-Bashforth (ab_steps steps)
   MODE_ADAPTIVE_DENSE = 10,  // Dopri5 adaptive, pausing after the accepted step that reaches stop_at
-  MODE_FIXED_ABM = 11        // Adams-Bashforth-Moulton (ab_steps steps; new state in place)
+  MODE_FIXED_ABM = 11,       // Adams-Bashforth-Moulton (ab_steps steps; new state in place)
+  MODE_FIXED_MM = 12         // modified midpoint (two substeps)
 };
 
 __host__ __device__ constexpr bool mode_adaptive(int m) {
@@ -37,6 +38,7 @@ __host__ __device__ constexpr int mode_rhs_evals(int m) {
   return m == MODE_FIXED_RK4 ? 4
          : (m == MODE_FIXED_EULER || m == MODE_FIXED_AB) ? 1
          : m == MODE_FIXED_ABM                         ? 2
+         : m == MODE_FIXED_MM                          ? 3
          : (m == MODE_FIXED_F78 || m == MODE_ADAPTIVE_F78) ? 13
                                                            : 6;
 }

@@ -32,14 +32,18 @@ enum GSKind : int {
   // of the prediction p (in the spare state buffer) and the corrected state,
   // written over y_n (each cell's y_n is read only by the thread that writes it)
   K_ABC1, K_ABC2, K_ABC3, K_ABC4, K_ABC5, K_ABC6, K_ABC7, K_ABC8,
+  // modified midpoint (two substeps of h = H/2): MM1 z1 = y + h f(y), MM2
+  // z2 = y + 2h f(z1), MM3 y_new = (z2 + z1 + h f(z2)) / 2
+  K_MM1, K_MM2, K_MM3,
   K_ALL   // number of kinds
 };
 
 // Extra arrays of the Fehlberg and Adams-Bashforth kinds (device table
 // xk(GSLaunch)): k1 .. k12 of Fehlberg 7(8) at 0 .. 11, the ring of the last
 // s right-hand sides of Adams-Bashforth at kRingBase .. kRingBase + s - 1.
-// k6 of Dopri5 for dense output at kXkK6.
-constexpr int kXkF78 = 12, kXkK6 = 12, kRingBase = 16, kXkCount = 24;
+// k6 of Dopri5 for dense output at kXkK6; the modified midpoint's z1, z2
+// at kXkZ1, kXkZ1 + 1.
+constexpr int kXkF78 = 12, kXkK6 = 12, kXkZ1 = 13, kRingBase = 16, kXkCount = 24;
 
 struct GSLaunch {
   void* y[2];    // state, indexed by the device-side parity

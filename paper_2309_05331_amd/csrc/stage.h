@@ -51,7 +51,8 @@ struct KindDesc {
   int fin;         // own-cell finish: 0 none, 1 RK4 new state, 2 Dopri5 new state (+ partial error),
                    // 3 Dopri5 error completion, 4 Cash-Karp new state (+ error norm),
                    // 5 Euler new state, 6 Fehlberg 7(8) new state (+ error norm),
-                   // 7 Adams-Bashforth new state, 8 Adams-Moulton correction (in place)
+                   // 7 Adams-Bashforth new state, 8 Adams-Moulton correction (in place),
+                   // 9, 10, 11 modified midpoint z1, z2, new state
   bool err;        // error norm computed
   int ab;          // Adams-Bashforth steps (ring size), 0 otherwise
 };
@@ -163,6 +164,9 @@ constexpr KindDesc kDescX[K_ALL - K_F1] = {
                 false, 7},
     /* ABC8 */ {1, {A_YN}, {0}, 8,
                 {A_Y, A_RG0, A_RG0 + 1, A_RG0 + 2, A_RG0 + 3, A_RG0 + 4, A_RG0 + 5, A_RG0 + 6}, -1, 8, false, 8},
+    /* MM1 */ {1, {A_Y}, {0}, 0, {0}, -1, 9, false, 0},
+    /* MM2 */ {1, {A_X0 + kXkZ1}, {0}, 1, {A_Y}, -1, 10, false, 0},
+    /* MM3 */ {1, {A_X0 + kXkZ1 + 1}, {0}, 1, {A_X0 + kXkZ1}, -1, 11, false, 0},
 };
 #undef HODE_F13_ROW
 
@@ -305,7 +309,10 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 #pragma unroll
   for (int i = 0; i < D.nx; ++i) ext[i] = array_ptr<T>(a, D.extra[i], p, ksl, rg, D.ab);
   T* out = D.out >= 0 ? array_ptr<T>(a, D.out, p, ksl, rg, D.ab) : nullptr;
-  T* ynew = (D.fin == 1 || D.fin == 2 || D.fin >= 4) ? (T*)a.y[D.fin == 8 ? p : p ^ 1] : nullptr;
+  T* ynew = D.fin == 9    ? (T*)xk(a)[kXkZ1]
+           : D.fin == 10 ? (T*)xk(a)[kXkZ1 + 1]
+           : (D.fin == 1 || D.fin == 2 || D.fin >= 4) ? (T*)a.y[D.fin == 8 ? p : p ^ 1]
+                                                       : nullptr;
   T* e6 = (D.fin == 2 && D.err) ? (T*)a.k[A_E6] : nullptr;
 
   T cf[10];
@@ -320,6 +327,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   const double h1 = h * D1, h3 = h * D3, h4 = h * D4, h5 = h * D5, h6 = h * D6, h7 = h * D7;
   const T cq1 = (T)(h * CB1), cq3 = (T)(h * CB3), cq4 = (T)(h * CB4), cq6 = (T)(h * CB6);
   const T hT = (T)h;
+  const T hm = (T)(0.5 * h), hm2 = (T)h;  // modified midpoint substep h/2 and 2 (h/2)
   const double ce1 = h * CE1, ce3 = h * CE3, ce4 = h * CE4, ce5 = h * CE5, ce6 = h * CE6;
   const T fb6 = (T)(h * FB6), fb7 = (T)(h * FB7), fb9 = (T)(h * FB9), fb12 = (T)(h * FB12);
   const double fe = h * FE;
@@ -403,6 +411,15 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 #pragma unroll
           for (int j = 1; j < D.ab; ++j) acc += abq[j] * x[j - 1].v[e];
           fin->a[e] = acc;
+        } else if constexpr (D.fin == 9) {
+          // source y: z1 = y + (h/2) f(y)
+          fin->a[e] = s[0].v[e];
+        } else if constexpr (D.fin == 10) {
+          // source z1; extra y: z2 = y + h f(z1)
+          fin->a[e] = x[0].v[e];
+        } else if constexpr (D.fin == 11) {
+          // source z2; extra z1: (z2 + z1 + (h/2) f(z2)) / 2
+          fin->a[e] = s[0].v[e] + x[0].v[e];
         } else if constexpr (D.fin == 8) {
           // source the prediction; extras y_n, f_n .. f_{n+2-s}: the
           // Adams-Moulton correction without f(p)
@@ -588,6 +605,19 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
             for (int e = 0; e < VW; ++e) yn.v[e] = fc[f][r].a[e] + hT * fo[f].v[e];
             stv<T, VW>(ynew, f * n3 + g, yn);
           }
+        } else if constexpr (D.fin == 9 || D.fin == 10 || D.fin == 11) {
+          // modified midpoint substeps
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            P yn;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+              if constexpr (D.fin == 9) yn.v[e] = fc[f][r].a[e] + hm * fo[f].v[e];
+              else if constexpr (D.fin == 10) yn.v[e] = fc[f][r].a[e] + hm2 * fo[f].v[e];
+              else yn.v[e] = (T)0.5 * (fc[f][r].a[e] + hm * fo[f].v[e]);
+            }
+            stv<T, VW>(ynew, f * n3 + g, yn);
+          }
         } else if constexpr (D.fin == 7 || D.fin == 8) {
           // Adams-Bashforth new state y + h sum_j beta_j f_{n-j}, or the
           // Adams-Moulton correction y_n + h (gamma_0 f(p) + sum_j gamma_j f_{n+1-j})
@@ -691,7 +721,7 @@ __global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __res
   // correctors, which keep the parity, sweep against their predictor.)
   constexpr bool rev_k = KIND == K_R2 || KIND == K_R4 || KIND == K_D3 || KIND == K_D5 || KIND == K_D7 ||
                          KIND == K_D7F || KIND == K_C5 || KIND == K_F2 || KIND == K_F4 || KIND == K_F6 ||
-                         KIND == K_F8 || KIND == K_F10 || KIND == K_F12;
+                         KIND == K_F8 || KIND == K_F10 || KIND == K_F12 || KIND == K_MM2;
   const bool rev = desc<KIND>().ab > 0 ? ((c->parity & 1) != 0) != (desc<KIND>().fin == 8) : rev_k;
   const int slot = rev ? per - 1 - (int)(blockIdx.x >> 3) : (int)(blockIdx.x >> 3);
   const int bb = (blockIdx.x & 7) * per + slot;

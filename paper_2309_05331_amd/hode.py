@@ -17,7 +17,7 @@ LIBPATH = os.path.join(HERE, "libhode.so")
 
 F32, F64 = 1, 2
 RHS_EXP, RHS_LOGISTIC, RHS_GRAYSCOTT3D = 1, 2, 3
-RK4, DOPRI5, CASHKARP54, EULER, FEHLBERG78 = 1, 2, 3, 4, 5
+RK4, DOPRI5, CASHKARP54, EULER, FEHLBERG78, MIDPOINT = 1, 2, 3, 4, 5, 6
 
 
 def ABM(steps):
@@ -46,6 +46,7 @@ K_F13F = 30
 K_AB = list(range(31, 39))  # Adams-Bashforth with 1 .. 8 steps
 K_D6K = 39  # Dopri5 stage 6 storing k6 (dense output)
 K_ABC = list(range(40, 48))  # Adams-Moulton correctors with 1 .. 8 steps
+K_MM = [48, 49, 50]  # modified midpoint substeps
 
 
 class hode_stats(C.Structure):
