@@ -201,6 +201,36 @@ int hode_integrate_times(hode_ctx *ctx, const double *times, int64_t n_times, do
 /* Statistics of the last run. */
 int hode_get_stats(hode_ctx *ctx, hode_stats *out);
 
+/* Checkpoint of the step control (with the state from hode_read_state, what
+ * a restarted run needs to continue an error-controlled step sequence).
+ * Layout of the blob, version 1: */
+typedef struct {
+  uint32_t magic;          /* HODE_CKPT_MAGIC */
+  uint32_t version;        /* 1 */
+  double t;                /* time reached */
+  double dt_next;          /* proposed next step */
+  double err_prev;         /* PI memory: the last accepted error norm (1 before any) */
+  int32_t last_rejected;   /* the last attempt was rejected (no growth on the next accept) */
+  int32_t hist_n;          /* attempts in the learned controller's history (<= 4) */
+  double hist_lerr[4], hist_lh[4], hist_acc[4];  /* that history, newest first */
+  int64_t accepted, rejected, rhs_evals;           /* counters of the last call */
+} hode_checkpoint;
+#define HODE_CKPT_MAGIC 0x48434b50u
+
+/* Writes the control state at the end of the last stepping call into blob
+ * (*nbytes in: its size; out: the size written, sizeof(hode_checkpoint)).
+ * blob == NULL only reports the size.  HODE_ESTATE before any stepping. */
+int hode_get_ctrl(hode_ctx *ctx, void *blob, size_t *nbytes);
+
+/* Restores a checkpoint: the next hode_try_step continues its controller
+ * memory (err_prev, last_rejected, history), so try_step sequences split by
+ * a checkpoint and a restore (into this or a fresh context, after
+ * hode_init_state with the saved state) equal the unsplit sequence bitwise
+ * when called with the saved t and dt_next.  hode_integrate_adaptive and
+ * the multi-step histories start afresh as always.  HODE_EINVAL for a blob
+ * of another size, magic or version. */
+int hode_set_ctrl(hode_ctx *ctx, const void *blob, size_t nbytes);
+
 /* Records one 24-double entry per adaptive attempt (h, err, accepted, t
  * after, dt proposed, PI log-ratio, learned log-ratio or NaN, landed-on-t1
  * flag, then for accepted attempts the 16 learned-controller features, else

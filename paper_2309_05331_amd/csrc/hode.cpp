@@ -1031,6 +1031,58 @@ int hode_get_stats(hode_ctx* c, hode_stats* out) {
   return HODE_OK;
 }
 
+int hode_get_ctrl(hode_ctx* c, void* blob, size_t* nbytes) {
+  if (!c || !nbytes) return HODE_EINVAL;
+  if (!blob) {
+    *nbytes = sizeof(hode_checkpoint);
+    return HODE_OK;
+  }
+  if (*nbytes < sizeof(hode_checkpoint)) return fail(c, HODE_ESTATE, "checkpoint buffer too small");
+  if (c->persist.mode == 0) return fail(c, HODE_ESTATE, "no stepping call to checkpoint");
+  const DevCtrl& d = c->persist;
+  hode_checkpoint k;
+  std::memset(&k, 0, sizeof(k));
+  k.magic = HODE_CKPT_MAGIC;
+  k.version = 1;
+  k.t = d.t;
+  k.dt_next = c->last.dt_next;
+  k.err_prev = d.err_prev;
+  k.last_rejected = d.last_rejected;
+  k.hist_n = (int32_t)d.hist_n;
+  for (int i = 0; i < hode::HIST; ++i) {
+    k.hist_lerr[i] = d.hist_lerr[i];
+    k.hist_lh[i] = d.hist_lh[i];
+    k.hist_acc[i] = d.hist_acc[i];
+  }
+  k.accepted = c->last.accepted;
+  k.rejected = c->last.rejected;
+  k.rhs_evals = c->last.rhs_evals;
+  std::memcpy(blob, &k, sizeof(k));
+  *nbytes = sizeof(k);
+  return HODE_OK;
+}
+
+int hode_set_ctrl(hode_ctx* c, const void* blob, size_t nbytes) {
+  if (!c) return HODE_EINVAL;
+  if (!blob || nbytes != sizeof(hode_checkpoint)) return fail(c, HODE_EINVAL, "checkpoint size");
+  hode_checkpoint k;
+  std::memcpy(&k, blob, sizeof(k));
+  if (k.magic != HODE_CKPT_MAGIC || k.version != 1) return fail(c, HODE_EINVAL, "not a version-1 checkpoint");
+  if (k.hist_n < 0 || k.hist_n > hode::HIST || !(k.err_prev > 0) || !std::isfinite(k.err_prev))
+    return fail(c, HODE_EINVAL, "checkpoint out of range");
+  DevCtrl& d = c->persist;
+  d.err_prev = k.err_prev;
+  d.last_rejected = k.last_rejected ? 1 : 0;
+  d.hist_n = (uint32_t)k.hist_n;
+  for (int i = 0; i < hode::HIST; ++i) {
+    d.hist_lerr[i] = k.hist_lerr[i];
+    d.hist_lh[i] = k.hist_lh[i];
+    d.hist_acc[i] = k.hist_acc[i];
+  }
+  c->persist_valid = true;
+  return HODE_OK;
+}
+
 int hode_set_trace(hode_ctx* c, int64_t capacity) {
   if (!c || capacity < 0) return HODE_EINVAL;
   if (c->d_trace) { (void)hipFree(c->d_trace); c->d_trace = nullptr; }

@@ -94,6 +94,8 @@ def lib():
             "hode_integrate_n_steps": ([P, I, D, D, I64, C.POINTER(D)], I),
             "hode_integrate_times": ([P, C.POINTER(D), I64, D, I64, P, S, I, C.POINTER(hode_stats)], I),
             "hode_integrate_times_dense": ([P, C.POINTER(D), I64, D, I64, P, S, I, C.POINTER(hode_stats)], I),
+            "hode_get_ctrl": ([P, P, C.POINTER(S)], I),
+            "hode_set_ctrl": ([P, P, S], I),
             "hode_try_step": ([P, C.POINTER(D), C.POINTER(D), C.POINTER(I)], I),
             "hode_integrate_adaptive": ([P, D, D, D, I64, C.POINTER(hode_stats)], I),
             "hode_get_stats": ([P, C.POINTER(hode_stats)], I),
@@ -264,6 +266,18 @@ class Context:
         self._check(self.L.hode_integrate_times_dense(self.h, arr, len(times), dt0, max_steps, p, nb, on_dev,
                                                       C.byref(st)), allow)
         return st.as_dict()
+
+    def get_ctrl(self):
+        """Checkpoint of the step control (bytes of a hode_checkpoint)."""
+        n = C.c_size_t(0)
+        self._check(self.L.hode_get_ctrl(self.h, None, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        self._check(self.L.hode_get_ctrl(self.h, buf, C.byref(n)))
+        return bytes(buf)[: n.value]
+
+    def set_ctrl(self, blob):
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        return self._check(self.L.hode_set_ctrl(self.h, buf, len(blob)))
 
     def get_stats(self):
         st = hode_stats()
