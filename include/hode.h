@@ -290,6 +290,17 @@ int hode_profile_attempt(hode_ctx *ctx, int method, int reps, double *ms);
  * identical for every tile.  hode_set_tile sets one tile for all stages. */
 int hode_autotune(hode_ctx *ctx, int method, int reps, int *best_ry, int *best_zc, double *best_ms);
 
+/* hode_autotune with a persistent cache: the tiles of every stage kind are
+ * read from the text file at cache_path when it holds an entry for this
+ * device architecture, precision, method, grid edge and cells-per-lane
+ * setting (the last such entry wins), else found with hode_autotune and
+ * appended to the file as one line ("hode-tune-v1 <arch> <dtype> <method>
+ * <N> <vw>" and ry:zc for every kind).  cache_path NULL: the environment
+ * variable HODE_TUNE_CACHE; without either no file is used.  *from_cache
+ * (may be NULL) receives 1 when the tiles came from the file.  HODE_EINVAL
+ * if the file cannot be written. */
+int hode_autotune_cached(hode_ctx *ctx, int method, int reps, const char *cache_path, int *from_cache);
+
 /* Measurement reference: copies `bytes` (a multiple of 16) from device
  * buffer src to device buffer dst with a plain 16-byte-per-lane streaming
  * kernel, `reps` times after one warm-up, on a stream of its own; returns the

@@ -13,6 +13,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <map>
@@ -1352,6 +1353,84 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   if (best_ry) *best_ry = c->ry;
   if (best_zc) *best_zc = c->zc;
   if (best_ms) *best_ms = tot;
+  return HODE_OK;
+}
+
+// Cache line: "hode-tune-v1 <arch> <dtype> <method> <N> <vw> <ry:zc for every stage kind>".
+static std::string tune_key(const hode_ctx* c, int method) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    for (char& ch : arch)
+      if (ch == ' ') ch = '_';
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "hode-tune-v1 %s %d %d %d %d", arch.c_str(), c->dtype, method, c->N, c->vw);
+  return buf;
+}
+
+int hode_autotune_cached(hode_ctx* c, int method, int reps, const char* cache_path, int* from_cache) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!is_gs(c)) return fail(c, HODE_EINVAL, "autotuning is for the Gray-Scott path");
+  if (from_cache) *from_cache = 0;
+  const char* path = cache_path ? cache_path : std::getenv("HODE_TUNE_CACHE");
+  const std::string key = tune_key(c, method);
+  if (path && *path) {
+    if (FILE* f = std::fopen(path, "r")) {
+      // the last entry for this key wins
+      std::vector<int> ry, zc;
+      char line[8192];
+      while (std::fgets(line, sizeof(line), f)) {
+        if (std::strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
+        std::vector<int> r, z;
+        const char* q = line + key.size();
+        int a, b, used;
+        while (std::sscanf(q, " %d:%d%n", &a, &b, &used) == 2) {
+          r.push_back(a);
+          z.push_back(b);
+          q += used;
+        }
+        if ((int)r.size() == hode::K_ALL) { ry = r; zc = z; }
+      }
+      std::fclose(f);
+      bool ok = !ry.empty();
+      for (int k = 0; ok && k < hode::K_ALL; ++k) ok = hode::gs_ry_supported(ry[k]) && zc[k] >= 1;
+      if (ok) {
+        for (int k = 0; k < hode::K_ALL; ++k) {
+          c->kry[k] = ry[k];
+          c->kzc[k] = zc[k];
+        }
+        int seq[16];
+        const int widest = stage_seq(method, seq) == 1 ? seq[0] : (method == HODE_RK4 ? hode::K_R4
+                                                                    : method == HODE_CASHKARP54 ? hode::K_C6
+                                                                    : method == HODE_FEHLBERG78 ? hode::K_F13
+                                                                                                : hode::K_D6);
+        c->ry = c->kry[widest];
+        c->zc = c->kzc[widest];
+        clear_graphs(c);
+        if (from_cache) *from_cache = 1;
+        return HODE_OK;
+      }
+    }
+  }
+  rc = hode_autotune(c, method, reps, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  if (path && *path) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return fail(c, HODE_EINVAL, std::string("cannot append to the tuning cache ") + path);
+    std::string line = key;
+    char buf[32];
+    for (int k = 0; k < hode::K_ALL; ++k) {
+      std::snprintf(buf, sizeof(buf), " %d:%d", c->kry[k], c->kzc[k]);
+      line += buf;
+    }
+    line += "\n";
+    const bool w = std::fputs(line.c_str(), f) >= 0;
+    const bool cl = std::fclose(f) == 0;
+    if (!w || !cl) return fail(c, HODE_EINVAL, std::string("cannot write the tuning cache ") + path);
+  }
   return HODE_OK;
 }
 

@@ -95,6 +95,7 @@ def lib():
             "hode_integrate_times": ([P, C.POINTER(D), I64, D, I64, P, S, I, C.POINTER(hode_stats)], I),
             "hode_integrate_times_dense": ([P, C.POINTER(D), I64, D, I64, P, S, I, C.POINTER(hode_stats)], I),
             "hode_get_ctrl": ([P, P, C.POINTER(S)], I),
+            "hode_autotune_cached": ([P, I, I, C.c_char_p, C.POINTER(I)], I),
             "hode_set_ctrl": ([P, P, S], I),
             "hode_try_step": ([P, C.POINTER(D), C.POINTER(D), C.POINTER(I)], I),
             "hode_integrate_adaptive": ([P, D, D, D, I64, C.POINTER(hode_stats)], I),
@@ -323,6 +324,14 @@ class Context:
         ry, zc, ms = C.c_int(), C.c_int(), C.c_double()
         self._check(self.L.hode_autotune(self.h, method, reps, C.byref(ry), C.byref(zc), C.byref(ms)))
         return ry.value, zc.value, ms.value
+
+    def autotune_cached(self, method, reps=3, cache_path=None):
+        """hode_autotune through a persistent cache file (cache_path, else
+        $HODE_TUNE_CACHE); returns True when the tiles came from the file."""
+        hit = C.c_int(0)
+        p = None if cache_path is None else os.fsencode(str(cache_path))
+        self._check(self.L.hode_autotune_cached(self.h, method, reps, p, C.byref(hit)))
+        return bool(hit.value)
 
     def set_vector_width(self, vw):
         return self._check(self.L.hode_set_vector_width(self.h, vw))
