@@ -290,6 +290,14 @@ int hode_profile_attempt(hode_ctx *ctx, int method, int reps, double *ms);
  * identical for every tile.  hode_set_tile sets one tile for all stages. */
 int hode_autotune(hode_ctx *ctx, int method, int reps, int *best_ry, int *best_zc, double *best_ms);
 
+/* Testing aid: fills every buffer the library may use as scratch (the spare
+ * state buffer, the stage arrays, the extra arrays, the first-same-as-last
+ * slot unless it holds a valid k1, the Adams ring unless a history is live)
+ * with NaN bit patterns, so a kernel that read one before writing it in the
+ * same call would spoil its result.  Leaves the state and every carried
+ * quantity intact. */
+int hode_debug_poison(hode_ctx *ctx);
+
 /* hode_autotune with a persistent cache: the tiles of every stage kind are
  * read from the text file at cache_path when it holds an entry for this
  * device architecture, precision, method, grid edge and cells-per-lane

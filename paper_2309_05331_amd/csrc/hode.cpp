@@ -1032,6 +1032,25 @@ int hode_get_stats(hode_ctx* c, hode_stats* out) {
   return HODE_OK;
 }
 
+int hode_debug_poison(hode_ctx* c) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  const size_t bytes = (size_t)c->nelem * c->esize;
+  if (!bytes) return HODE_OK;
+  // all-ones bytes are a NaN in FP32 and FP64
+  auto poison = [&](void* p) -> hipError_t { return p ? hipMemsetAsync(p, 0xFF, bytes, c->stream) : hipSuccess; };
+  HIPCHK(c, poison(c->y[c->parity ^ 1]));
+  HIPCHK(c, poison(c->ks[c->k1slot ^ 1]));
+  if (!c->k1_valid) HIPCHK(c, poison(c->ks[c->k1slot]));
+  for (int i = 2; i < 7; ++i) HIPCHK(c, poison(c->k[i]));
+  for (int i = 0; i < hode::kXkCount; ++i)
+    if (i < hode::kRingBase || c->ab_steps == 0) HIPCHK(c, poison(c->xk_arr[i]));
+  HIPCHK(c, poison(c->d_obs));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HODE_OK;
+}
+
 int hode_get_ctrl(hode_ctx* c, void* blob, size_t* nbytes) {
   if (!c || !nbytes) return HODE_EINVAL;
   if (!blob) {

@@ -96,6 +96,7 @@ def lib():
             "hode_integrate_times_dense": ([P, C.POINTER(D), I64, D, I64, P, S, I, C.POINTER(hode_stats)], I),
             "hode_get_ctrl": ([P, P, C.POINTER(S)], I),
             "hode_autotune_cached": ([P, I, I, C.c_char_p, C.POINTER(I)], I),
+            "hode_debug_poison": ([P], I),
             "hode_set_ctrl": ([P, P, S], I),
             "hode_try_step": ([P, C.POINTER(D), C.POINTER(D), C.POINTER(I)], I),
             "hode_integrate_adaptive": ([P, D, D, D, I64, C.POINTER(hode_stats)], I),
@@ -332,6 +333,10 @@ class Context:
         p = None if cache_path is None else os.fsencode(str(cache_path))
         self._check(self.L.hode_autotune_cached(self.h, method, reps, p, C.byref(hit)))
         return bool(hit.value)
+
+    def debug_poison(self):
+        """Fills the library's scratch buffers with NaN (testing aid)."""
+        return self._check(self.L.hode_debug_poison(self.h))
 
     def set_vector_width(self, vw):
         return self._check(self.L.hode_set_vector_width(self.h, vw))
