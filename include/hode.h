@@ -154,24 +154,6 @@ int hode_integrate_n_steps(hode_ctx *ctx, int method, double t0, double dt, int6
  * ensemble contexts (they step with Dopri5). */
 int hode_set_stepper(hode_ctx *ctx, int method);
 
-/* Dense output (Odeint's dense-output Dopri5 with integrate_times): Dopri5
- * error-controlled steps from times[0] to times[n_times-1], exactly those of
- * hode_integrate_adaptive over that interval (only the last step clipped,
- * to land on the end; same counts and final state), while the state at each
- * intermediate times[i] comes from the continuous extension of the accepted
- * step that covers it (Dormand & Prince 1986, 4th order: the quartic through
- * y_n and y_{n+1} with end slopes k1 and k7 plus a correction from all
- * stages).  Slot i of dst (n_times states, as for hode_integrate_times)
- * receives the state at times[i]; slot 0 the current state, the last slot
- * the end state.  The device loop pauses between graph chunks after the
- * step that reaches the next requested time, interpolates there and goes
- * on.  Gray-Scott keeps k6 for it (one more array, allocated on first use;
- * stage 6 then writes it); the element-wise families evaluate the step's
- * stages again in registers.  Adaptive stepper HODE_DOPRI5 only
- * (HODE_EINVAL otherwise).  Returns as hode_integrate_times does. */
-int hode_integrate_times_dense(hode_ctx *ctx, const double *times, int64_t n_times, double dt0, int64_t max_steps,
-                               void *dst, size_t dst_bytes, int dst_on_device, hode_stats *out);
-
 /* One error-controlled attempt of size *dt from *t.  On acceptance *t
  * advances and the state is updated; either way *dt receives the proposed
  * next step and *accepted 0/1.  Controller history carries over between
@@ -197,6 +179,24 @@ int hode_integrate_adaptive(hode_ctx *ctx, double t0, double t1, double dt0, int
  * interval's attempts. */
 int hode_integrate_times(hode_ctx *ctx, const double *times, int64_t n_times, double dt0, int64_t max_steps,
                          void *dst, size_t dst_bytes, int dst_on_device, hode_stats *out);
+
+/* Dense output (Odeint's dense-output Dopri5 with integrate_times): Dopri5
+ * error-controlled steps from times[0] to times[n_times-1], exactly those of
+ * hode_integrate_adaptive over that interval (only the last step clipped,
+ * to land on the end; same counts and final state), while the state at each
+ * intermediate times[i] comes from the continuous extension of the accepted
+ * step that covers it (Dormand & Prince 1986, 4th order: the quartic through
+ * y_n and y_{n+1} with end slopes k1 and k7 plus a correction from all
+ * stages).  Slot i of dst (n_times states, as for hode_integrate_times)
+ * receives the state at times[i]; slot 0 the current state, the last slot
+ * the end state.  The device loop pauses between graph chunks after the
+ * step that reaches the next requested time, interpolates there and goes
+ * on.  Gray-Scott keeps k6 for it (one more array, allocated on first use;
+ * stage 6 then writes it); the element-wise families evaluate the step's
+ * stages again in registers.  Adaptive stepper HODE_DOPRI5 only
+ * (HODE_EINVAL otherwise).  Returns as hode_integrate_times does. */
+int hode_integrate_times_dense(hode_ctx *ctx, const double *times, int64_t n_times, double dt0, int64_t max_steps,
+                               void *dst, size_t dst_bytes, int dst_on_device, hode_stats *out);
 
 /* Statistics of the last run. */
 int hode_get_stats(hode_ctx *ctx, hode_stats *out);
