@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -340,6 +341,46 @@ def run_ab(N, t1, weights_path, dtype="f32"):
     return res
 
 
+def run_accuracy(n=512 * 512, t1=5.0):
+    """The paper's accuracy benchmark on the GPU path: every fixed-step
+    method on the exponential and logistic families (n components, x0 in
+    [0.01, 0.5]) against the closed forms at t1, L-inf and L2 norms of the
+    error under step halving, and the observed order (log2 of successive
+    L-inf ratios).  FP64."""
+    import torch
+    from paper_2309_05331_amd import hode, inputs
+    x0 = inputs.exp_family_x0(n, seed=2)
+    dev = torch.from_numpy(x0).to("cuda:0")
+    methods = ([("euler", hode.EULER, 1), ("midpoint", hode.MIDPOINT, 2), ("rk4", hode.RK4, 4),
+                ("cashkarp54", hode.CASHKARP54, 5), ("dopri5", hode.DOPRI5, 5), ("fehlberg78", hode.FEHLBERG78, 8)]
+               + [("ab%d" % s, hode.AB(s), s) for s in range(1, 9)]
+               + [("abm%d" % s, hode.ABM(s), s) for s in range(1, 9)])
+    steps = [10, 20, 40, 80, 160, 320, 640, 1280]
+    out = []
+    for kind, kname in ((hode.RHS_EXP, "exp"), (hode.RHS_LOGISTIC, "logistic")):
+        exact = x0 * np.exp(t1) if kind == hode.RHS_EXP else x0 / (x0 + (1 - x0) * np.exp(-t1))
+        ctx = hode.Context(0)
+        ctx.set_rhs(kind)
+        y = np.empty(n)
+        for name, m, p in methods:
+            linf, l2 = [], []
+            for ns in steps:
+                ctx.init_state(dev)
+                ctx.integrate_n_steps(m, 0.0, t1 / ns, ns)
+                ctx.read_state(y)
+                e = y - exact
+                linf.append(float(np.max(np.abs(e))) if np.all(np.isfinite(e)) else float("inf"))
+                l2.append(float(np.sqrt(np.sum(e * e))) if np.all(np.isfinite(e)) else float("inf"))
+            orders = [round(math.log2(linf[i] / linf[i + 1]), 2) if 0 < linf[i + 1] < math.inf and linf[i] < math.inf
+                      else None for i in range(len(steps) - 1)]
+            rec = {"family": kname, "method": name, "expected_order": p, "steps": steps, "linf": linf, "l2": l2,
+                   "observed_order": orders}
+            out.append(rec)
+            print(json.dumps(rec), flush=True)
+        ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,6 +395,8 @@ def main():
     ap.add_argument("--ab", type=float, default=0.0, metavar="T1",
                     help="also integrate the workload grid from 0 to T1 with PI and with the learned controller")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2309_05331_amd", "controller_weights.npy"))
+    ap.add_argument("--accuracy", action="store_true",
+                    help="print the accuracy benchmark (error norms and observed orders of every fixed-step method)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="time only the plain 16-byte streaming copy of 1 GiB (bandwidth ceiling, counter calibration)")
     args = ap.parse_args()
@@ -362,6 +405,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     from paper_2309_05331_amd import hode
+    if args.accuracy:
+        run_accuracy()
+        return
     if args.copy_reference:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
