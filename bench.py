@@ -68,6 +68,7 @@ WORKLOADS = {
     "gs32-rk4-fp64": dict(kind="gs", N=32, dtype="f64", method="rk4", steps_per=500, dt=0.1, seed=1,
                           compare_graphs=True),
     "ew24-dp5": dict(kind="ew", n=1 << 24, dtype="f64", method="dp5", t1=5.0, seed=2, dt0=0.01),
+    "ew24-dp5-fp32": dict(kind="ew", n=1 << 24, dtype="f32", method="dp5", t1=5.0, seed=2, dt0=0.01),
     "ens512-dp5": dict(kind="ens", n=512, dtype="f32", method="dp5", t1=2000.0, seed=4, dt0=0.1, rtol=1e-5),
 }
 DP5_ARRAYS = 30  # arrays of 2 N^3 elements one Dopri5 attempt reads or writes
@@ -290,7 +291,8 @@ def run_ew(wl, steps, warmup):
     import torch
     from paper_2309_05331_amd import hode, inputs
     n = wl["n"]
-    x0 = inputs.exp_family_x0(n, seed=wl["seed"])
+    esz = 4 if wl["dtype"] == "f32" else 8
+    x0 = inputs.exp_family_x0(n, seed=wl["seed"]).astype(np.float32 if esz == 4 else np.float64)
     dev = torch.from_numpy(x0).to("cuda:0")
     ctx = hode.Context(0)
     ctx.set_rhs(hode.RHS_EXP)
@@ -309,7 +311,7 @@ def run_ew(wl, steps, warmup):
     ms = ctx.time_kernel(hode.DOPRI5, 20)
     ctx.close()
     return dict(elapsed=el, per_step=per, cells=n, accepted=acc[0], rejected=0, dom="ew_step_dp5", dom_ms=ms,
-                dom_bytes=2 * n * 8, stage_gbs=None, attempt_gbs=2 * n * 8 / (ms * 1e-3) / 1e9, tile=None)
+                dom_bytes=2 * n * esz, stage_gbs=None, attempt_gbs=2 * n * esz / (ms * 1e-3) / 1e9, tile=None)
 
 
 def run_ab(N, t1, weights_path, dtype="f32"):
