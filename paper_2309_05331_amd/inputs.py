@@ -68,6 +68,42 @@ def uniform(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
     return out
 
 
+def uniform_at(seed: int, stream: int, idx) -> np.ndarray:
+    """Draws at the 0-based positions ``idx`` of stream ``(seed, stream)``: the
+    same values as ``uniform(seed, stream, n)[idx]``, without drawing the rest."""
+    key = _key(seed, stream)
+    i = np.asarray(idx, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = _mix((i + np.uint64(1)) * GAMMA + key)
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def _signed(v) -> int:
+    """A 64-bit word as the int64 value with the same bits."""
+    v = int(v)
+    return v - (1 << 64) if v >= 1 << 63 else v
+
+
+def _mix_torch(z):
+    """The SplitMix64 finaliser on int64 tensors (products wrap modulo 2**64;
+    the right shifts are made logical by masking the sign extension)."""
+    z = z ^ ((z >> 30) & ((1 << 34) - 1))
+    z = z * _signed(_M1)
+    z = z ^ ((z >> 27) & ((1 << 37) - 1))
+    z = z * _signed(_M2)
+    return z ^ ((z >> 31) & ((1 << 33) - 1))
+
+
+def uniform_torch(seed: int, stream: int, n: int, start: int = 0, device=None):
+    """``uniform(seed, stream, n, start)`` drawn on a torch device (float64),
+    for inputs too large to draw on the host in reasonable time."""
+    import torch
+
+    idx = torch.arange(start + 1, start + n + 1, dtype=torch.int64, device=device)
+    z = _mix_torch(idx * _signed(GAMMA) + _signed(_key(seed, stream)))
+    return ((z >> 11) & ((1 << 53) - 1)).to(torch.float64) * (2.0 ** -53)
+
+
 def exp_family_x0(n: int, seed: int = 2) -> np.ndarray:
     """Initial values of ``n`` independent components, ``U[0.01, 0.5]`` (float64)."""
     return 0.01 + 0.49 * uniform(seed, 0, n)
@@ -89,6 +125,50 @@ def gray_scott_ic(N: int, seed: int, dtype=np.float64) -> np.ndarray:
     v += (0.01 * (2.0 * uniform(seed, 1, n3) - 1.0)).reshape(N, N, N)
     out = np.stack([u, v])
     return out.astype(dtype, copy=False)
+
+
+def exp_family_x0_torch(n: int, seed: int = 2, dtype=None, device=None, chunk: int = 1 << 26):
+    """``exp_family_x0(n, seed)`` built on a torch device in chunks and stored
+    as ``dtype`` (default float64)."""
+    import torch
+
+    out = torch.empty(n, dtype=dtype or torch.float64, device=device)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        out[lo:hi] = (0.01 + 0.49 * uniform_torch(seed, 0, hi - lo, lo, device)).to(out.dtype)
+    return out
+
+
+def gray_scott_ic_at(N: int, seed: int, f: int, z, y, x) -> np.ndarray:
+    """Field ``f`` of ``gray_scott_ic(N, seed)`` at the cells ``(z, y, x)``
+    (float64), without building the grid."""
+    z, y, x = (np.asarray(a, dtype=np.int64) for a in (z, y, x))
+    lo, hi = (3 * N) // 8, (5 * N) // 8
+    inside = (z >= lo) & (z < hi) & (y >= lo) & (y < hi) & (x >= lo) & (x < hi)
+    base = np.where(inside, 0.5, 1.0) if f == 0 else np.where(inside, 0.25, 0.0)
+    r = uniform_at(seed, f, x + N * (y + N * z))
+    return base + 0.01 * (2.0 * r - 1.0)
+
+
+def gray_scott_ic_torch(N: int, seed: int, dtype=None, device=None, planes: int = 32):
+    """``gray_scott_ic(N, seed)`` built on a torch device plane range by plane
+    range, flat in the same layout and stored as ``dtype`` (default float64)."""
+    import torch
+
+    n3, NN = N * N * N, N * N
+    lo, hi = (3 * N) // 8, (5 * N) // 8
+    out = torch.empty(2 * n3, dtype=dtype or torch.float64, device=device)
+    for f, (outer, inner) in enumerate(((1.0, 0.5), (0.0, 0.25))):
+        for z0 in range(0, N, planes):
+            z1 = min(N, z0 + planes)
+            base = torch.full((z1 - z0, N, N), outer, dtype=torch.float64, device=device)
+            a, b = max(lo, z0), min(hi, z1)
+            if a < b:
+                base[a - z0:b - z0, lo:hi, lo:hi] = inner
+            r = uniform_torch(seed, f, (z1 - z0) * NN, z0 * NN, device)
+            v = base.reshape(-1) + 0.01 * (2.0 * r - 1.0)
+            out[f * n3 + z0 * NN:f * n3 + z1 * NN] = v.to(out.dtype)
+    return out
 
 
 ENSEMBLE_EDGES = tuple(range(16, 97, 8))
