@@ -9,8 +9,8 @@ dispatches only.  The integration loop launches graph chunks whose kernels
 return at once after the run has finished; those empty launches (shorter than
 --min-us) are counted separately instead of diluting the mean.
 
-counters: per-kernel mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from
-two rocprofv3 --pmc runs, scaled by the factors the reference copy kernel
+counters: per-kernel mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch, real
+dispatches only, as above) from two rocprofv3 --pmc runs, scaled by the factors the reference copy kernel
 establishes (what the counter reads for a known byte count), and the HBM
 bytes per dispatch.
 """
@@ -60,23 +60,29 @@ def kernel_trace(db: str, min_us: float):
     return "\n".join(lines)
 
 
-def _load(path, cname):
+def _load(path, cname, min_us=20.0):
+    """Counter values per kernel over real dispatches only: graph-chunk
+    launches that return at once (shorter than min_us) are left out, as in
+    the kernel trace, so they do not dilute the per-dispatch means."""
     agg = collections.defaultdict(list)
     for r in csv.DictReader(open(path)):
-        if r["Counter_Name"] == cname:
-            agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        if r["Counter_Name"] != cname:
+            continue
+        if (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 < min_us:
+            continue
+        agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
     return agg
 
 
-def counters_record(fetch_csv, write_csv, fs, ws, kernel, tag, workload, source, per="launch"):
+def counters_record(fetch_csv, write_csv, fs, ws, kernel, tag, workload, source, per="launch", min_us=20.0):
     """JSON record of one kernel's mean scaled HBM bytes per dispatch (or the
     sum over all its dispatches with per="run"), stamped with the SHA-256 of
     the kernel's source files (concatenated in the order given) so a reader
     can tell whether it still applies."""
     import hashlib
     import os
-    f = _load(fetch_csv, "FETCH_SIZE")[kernel]
-    w = _load(write_csv, "WRITE_SIZE")[kernel]
+    f = _load(fetch_csv, "FETCH_SIZE", min_us)[kernel]
+    w = _load(write_csv, "WRITE_SIZE", min_us)[kernel]
     if not f or not w:
         raise SystemExit("kernel %r not in the counter files" % kernel)
     agg = (lambda v: sum(v)) if per == "run" else (lambda v: sum(v) / len(v))
@@ -92,9 +98,9 @@ def counters_record(fetch_csv, write_csv, fs, ws, kernel, tag, workload, source,
             "hbm_bytes_per_launch" if per == "launch" else "hbm_bytes_per_run": int(round((fk * fs + wk * ws) * 1024))}
 
 
-def counters(fetch_csv: str, write_csv: str, fs: float, ws: float):
-    f = _load(fetch_csv, "FETCH_SIZE")
-    w = _load(write_csv, "WRITE_SIZE")
+def counters(fetch_csv: str, write_csv: str, fs: float, ws: float, min_us: float = 20.0):
+    f = _load(fetch_csv, "FETCH_SIZE", min_us)
+    w = _load(write_csv, "WRITE_SIZE", min_us)
     lines = ["%-40s %6s %14s %14s %16s" % ("kernel", "n", "FETCH_KiB", "WRITE_KiB", "HBM_bytes_scaled")]
     for k in sorted(set(f) | set(w)):
         fm = sum(f[k]) / len(f[k]) if f.get(k) else 0.0
@@ -115,6 +121,7 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("--fetch-scale", type=float, default=2.0)
     b.add_argument("--write-scale", type=float, default=1.0)
+    b.add_argument("--min-us", type=float, default=20.0)
     j = sub.add_parser("counters-json")
     j.add_argument("fetch_csv")
     j.add_argument("write_csv")
@@ -125,15 +132,17 @@ def main():
     j.add_argument("--per", choices=["launch", "run"], default="launch")
     j.add_argument("--fetch-scale", type=float, default=2.0)
     j.add_argument("--write-scale", type=float, default=1.0)
+    j.add_argument("--min-us", type=float, default=20.0)
     args = ap.parse_args()
     if args.cmd == "kernel-trace":
         print(kernel_trace(args.db, args.min_us))
     elif args.cmd == "counters":
-        print(counters(args.fetch_csv, args.write_csv, args.fetch_scale, args.write_scale))
+        print(counters(args.fetch_csv, args.write_csv, args.fetch_scale, args.write_scale, args.min_us))
     else:
         import json
         print(json.dumps(counters_record(args.fetch_csv, args.write_csv, args.fetch_scale, args.write_scale,
-                                         args.kernel, args.tag, args.workload, args.source, args.per), indent=1))
+                                         args.kernel, args.tag, args.workload, args.source, args.per,
+                                         args.min_us), indent=1))
 
 
 if __name__ == "__main__":
