@@ -351,6 +351,15 @@ int hode_ensemble_set_weights(hode_ctx *ctx, const double *w);
  * tiles sooner and relaunch more often. */
 int hode_ensemble_set_epoch(hode_ctx *ctx, int first, int rest);
 
+/* Polls a grid barrier of the persistent ensemble kernel makes before it
+ * gives up (at least 1; default 2^30, about a minute).  A barrier that gives
+ * up sets an error flag on which every workgroup leaves the kernel, and the
+ * integration returns HODE_EHIP; the instances' states are then undefined
+ * until they are initialised again.  This bounds every wait of the kernel
+ * (failure detection if workgroups were ever not all resident) and lets a
+ * test force that path from the host. */
+int hode_ensemble_set_barrier_limit(hode_ctx *ctx, int64_t polls);
+
 /* The last integration's summed kernel durations (HIP events around every
  * launch, in ms) and its number of launches; either pointer may be NULL. */
 int hode_ensemble_timing(hode_ctx *ctx, double *kernel_ms, int *launches);

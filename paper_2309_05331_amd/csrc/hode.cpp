@@ -41,6 +41,7 @@ struct Ensemble {
   double kernel_ms_last = 0;  // summed launch durations of the last integration
   int launches_last = 0;
   int epoch_first = 64, epoch_len = 64;  // attempts per instance per launch
+  int64_t barrier_polls = (int64_t)1 << 30;  // polls before a grid barrier gives up
   void* pool = nullptr;
   hode::EnsInst* d_inst = nullptr;
   hode::EnsTile* d_tiles = nullptr;
@@ -1650,6 +1651,20 @@ int hode_ensemble_set_epoch(hode_ctx* c, int first, int rest) {
   return HODE_OK;
 }
 
+int hode_ensemble_set_barrier_limit(hode_ctx* c, int64_t polls) {
+  int rc = ens_check(c, 0);
+  if (rc) return rc;
+  if (polls < 1) return fail(c, HODE_EINVAL, "barrier poll limit must be >= 1");
+  Ensemble* e = c->ens;
+  if (polls != e->barrier_polls && e->graph) {
+    // the limit is a kernel argument of the captured launch: capture again
+    (void)hipGraphExecDestroy(e->graph);
+    e->graph = nullptr;
+  }
+  e->barrier_polls = polls;
+  return HODE_OK;
+}
+
 int hode_ensemble_timing(hode_ctx* c, double* kernel_ms, int* launches) {
   int rc = ens_check(c, 0);
   if (rc) return rc;
@@ -1756,7 +1771,7 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
                          (uint32_t*)(sb + L.live),
                          (uint32_t*)(sb + L.error),
                          (const hode::EnsParams*)(sb + L.params),
-                         (int64_t)1 << 30};
+                         e->barrier_polls};
       HIPCHK(c, hipStreamSynchronize(c->stream));
       hipGraph_t g = nullptr;
       HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));

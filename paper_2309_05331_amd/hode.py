@@ -119,6 +119,7 @@ def lib():
             "hode_ensemble_read_state": ([P, I, P, S, I], I),
             "hode_ensemble_set_weights": ([P, C.POINTER(D)], I),
             "hode_ensemble_set_epoch": ([P, I, I], I),
+            "hode_ensemble_set_barrier_limit": ([P, I64], I),
             "hode_ensemble_timing": ([P, C.POINTER(D), C.POINTER(I)], I),
             "hode_ensemble_set_vector_width": ([P, I, I], I),
             "hode_ensemble_set_trace": ([P, I64], I),
@@ -381,6 +382,9 @@ class Ensemble(Context):
 
     def set_epoch(self, first, rest):
         return self._check(self.L.hode_ensemble_set_epoch(self.h, first, rest))
+
+    def set_barrier_limit(self, polls):
+        return self._check(self.L.hode_ensemble_set_barrier_limit(self.h, polls))
 
     def timing(self):
         """(summed kernel ms, launches) of the last integration."""

@@ -175,3 +175,35 @@ def test_ensemble_instance_failure_is_contained():
             assert stats[i]["status"] == hode.EMAXSTEPS and stats[i]["t"] < 10.0, i
             assert stats[i]["accepted"] + stats[i]["rejected"] == budget, i
     ens.close()
+
+
+def test_ensemble_barrier_give_up_is_reported_and_recoverable():
+    # the persistent kernel's grid barriers are bounded waits; a limit of one
+    # poll, set from the host, makes the first barrier give up (workgroups
+    # without a tile arrive long before those with one), every workgroup
+    # leaves on the error flag, and the call reports it.  Re-initialised, the
+    # same ensemble then runs normally and gives a fresh ensemble's results.
+    edges = [16, 24, 16, 32]
+    _, prms = _params(len(edges))
+    ref, ys, ref_outs, ref_stats = _run_ensemble(edges, prms, hode.F32, 5.0, 1e-5)
+    ref.close()
+    ens = hode.Ensemble(edges, prms, dtype=hode.F32)
+    ens.set_tolerances(1e-5, 1e-5)
+    with pytest.raises(hode.HodeError):
+        ens.set_barrier_limit(0)
+    for i in range(len(edges)):
+        ens.init_instance(i, np.ascontiguousarray(ys[i]).ravel())
+    ens.set_barrier_limit(1)
+    with pytest.raises(hode.HodeError) as err:
+        ens.integrate_adaptive(0.0, 5.0, 0.1, max_steps=100000)
+    assert err.value.code == hode.EHIP and "barrier" in str(err.value)
+    ens.set_barrier_limit(1 << 30)
+    for i in range(len(edges)):
+        ens.init_instance(i, np.ascontiguousarray(ys[i]).ravel())
+    stats = ens.integrate_adaptive(0.0, 5.0, 0.1, max_steps=100000)
+    for i, N in enumerate(edges):
+        out = np.empty(2 * N ** 3, dtype=np.float32)
+        ens.read_instance(i, out)
+        assert np.array_equal(out, ref_outs[i]), i
+        assert (stats[i]["accepted"], stats[i]["rejected"]) == (ref_stats[i]["accepted"], ref_stats[i]["rejected"])
+    ens.close()
