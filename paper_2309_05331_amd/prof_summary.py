@@ -128,7 +128,8 @@ def main():
     j.add_argument("--kernel", required=True, help="summary name of the kernel, e.g. 'gs_stage D6 float ry=1 vw=4'")
     j.add_argument("--tag", required=True, help="short kernel tag used by bench.py, e.g. D6")
     j.add_argument("--workload", required=True)
-    j.add_argument("--source", default="stage.h,gs.hip", help="comma-separated kernel sources under csrc/")
+    j.add_argument("--source", default="stage.h,gs.hip,hode_dev.h,hode_internal.h",
+                   help="comma-separated kernel sources and the headers they include, under csrc/")
     j.add_argument("--per", choices=["launch", "run"], default="launch")
     j.add_argument("--fetch-scale", type=float, default=2.0)
     j.add_argument("--write-scale", type=float, default=1.0)
