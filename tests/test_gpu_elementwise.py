@@ -95,6 +95,34 @@ def test_full_size_fp64_adaptive_exp(orc):
         ctx.close()
 
 
+def test_full_size_fp32_adaptive_exp_replay(orc):
+    # the FP32 benchmark workload: 2^24 components of the exponential family,
+    # adaptive Dopri5 at rtol 1e-6, the oracle replaying the GPU's steps
+    n = 1 << 24
+    x32 = inputs.exp_family_x0(n, seed=2).astype(np.float32)
+    ctx = ew_ctx(hode.RHS_EXP, x32)
+    ctx.set_tolerances(1e-6, 1e-6)
+    ctx.set_trace(10000)
+    st = ctx.integrate_adaptive(0.0, 5.0, 0.01, max_steps=200000)
+    assert st["status"] == 0 and st["t"] == 5.0
+    g = read(ctx, np.float32, n)
+    tr = ctx.read_trace()
+    ctx.close()
+    r, te, errs = orc.integrate_replay(orc.ew_system(hode.RHS_EXP, n), x32.astype(np.float64), 0.0, tr[:, 0],
+                                       tr[:, 2].astype(np.int32))
+    d = np.abs(g.astype(np.float64) - r)
+    err, rel = float(np.max(d)), float(np.max(d / np.maximum(1.0, np.abs(r))))
+    n_acc = int(tr[:, 2].sum())
+    print("2^24 FP32 exp Dopri5 (%d attempts): max-abs %.3e, relative %.3e vs FP64 oracle (replay)"
+          % (len(tr), err, rel))
+    # the exponential family grows to x0 e^5 ~ 74, where one FP32 ulp is
+    # 7.6e-6: each accepted step rounds the state to FP32 once (relative
+    # 2^-24) and the stages add as much again, and the linear dynamics carry
+    # relative errors unchanged, so the bar is 2 n 2^-24 relative for n
+    # accepted steps (the 1e-4 max-abs target is for states of order one)
+    assert te == 5.0 and rel <= 2 * n_acc * 2.0 ** -24
+
+
 def test_failure_modes_and_edges(orc):
     x0 = inputs.exp_family_x0(1000, seed=3)
     ctx = ew_ctx(hode.RHS_EXP, x0)
