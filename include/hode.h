@@ -310,7 +310,8 @@ int hode_debug_poison(hode_ctx *ctx);
 int hode_autotune_cached(hode_ctx *ctx, int method, int reps, const char *cache_path, int *from_cache);
 
 /* Measurement reference: copies `bytes` (a multiple of 16) from device
- * buffer src to device buffer dst with a plain 16-byte-per-lane streaming
+ * buffer src to device buffer dst (both 16-byte aligned; HODE_EINVAL
+ * otherwise, and for reps < 1) with a plain 16-byte-per-lane streaming
  * kernel, `reps` times after one warm-up, on a stream of its own; returns the
  * mean duration per copy in milliseconds.  Used as the achievable-bandwidth
  * ceiling and to calibrate HBM traffic counters. */

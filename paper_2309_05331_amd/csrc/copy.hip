@@ -35,6 +35,7 @@ __global__ __launch_bounds__(256) void copy16(const f4* __restrict__ s, f4* __re
 
 extern "C" int hode_stream_copy(void* dst, const void* src, size_t bytes, int reps, double* avg_ms) {
   if (!dst || !src || bytes % 16 || reps < 1 || !avg_ms) return HODE_EINVAL;
+  if (((uintptr_t)dst | (uintptr_t)src) % 16) return HODE_EINVAL;  // 16-byte vector accesses
   const int64_t n = (int64_t)(bytes / 16);
   const int64_t grid = std::max<int64_t>(1, (n + 1023) / 1024);
   if (grid > INT32_MAX) return HODE_EINVAL;
