@@ -39,21 +39,27 @@ extern "C" int hode_stream_copy(void* dst, const void* src, size_t bytes, int re
   const int64_t n = (int64_t)(bytes / 16);
   const int64_t grid = std::max<int64_t>(1, (n + 1023) / 1024);
   if (grid > INT32_MAX) return HODE_EINVAL;
-  hipStream_t s;
-  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return HODE_EHIP;
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
-  copy16<<<(unsigned)grid, 256, 0, s>>>((const f4*)src, (f4*)dst, n);  // warm-up
-  hipEventRecord(e0, s);
-  for (int i = 0; i < reps; ++i) copy16<<<(unsigned)grid, 256, 0, s>>>((const f4*)src, (f4*)dst, n);
-  hipEventRecord(e1, s);
-  hipError_t e = hipEventSynchronize(e1);
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
   float ms = 0;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipStreamDestroy(s);
+  if (e == hipSuccess) {
+    copy16<<<(unsigned)grid, 256, 0, s>>>((const f4*)src, (f4*)dst, n);  // warm-up
+    e = hipEventRecord(e0, s);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) {
+      copy16<<<(unsigned)grid, 256, 0, s>>>((const f4*)src, (f4*)dst, n);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) (void)hipStreamSynchronize(s);  // nothing left in flight on the buffers
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
   if (e != hipSuccess) return HODE_EHIP;
   *avg_ms = (double)ms / reps;
   return HODE_OK;
