@@ -8,8 +8,13 @@ central 128^3 cube (u = 0.5, v = 0.25) in u = 1, v = 0 plus seeded uniform
 noise +-0.01 (seed 5).  One benchmark step integrates one window of `--window`
 time units along the same trajectory (the next window starts where the last
 ended, with the last proposed step); the value is cells x accepted steps /
-wall time over the timed windows.  Other workloads: --workload
-gs256-rk4 | gs256-dp5 | ew24-dp5 | gs32-rk4-fp64 | ens512-dp5 (the
+wall time over the timed windows.  After the timed windows the default
+workload also integrates the same grid from t = 0 to 100 with the PI and with
+the learned step-size controller (`controller_ab`: wall time to rtol 1e-6 of
+each and their ratio; `--ab T1` sets the horizon, `--ab 0` skips it).
+
+Other workloads (--workload): gs256-dp5, gs256-rk4, gs512-ck54, gs512-f78,
+gs512-ab4, gs32-rk4-fp64, ew24-dp5, ew24-dp5-fp32 and ens512-dp5 (the
 512-instance batched ensemble, edges 16..96, rtol 1e-5, t 0 -> 2000; one
 step integrates the whole horizon from the initial conditions).
 
@@ -394,8 +399,9 @@ def main():
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip timing the plain streaming copy beside the workload")
     ap.add_argument("--tile", default="auto", help="auto (autotune) or RY,ZC")
-    ap.add_argument("--ab", type=float, default=0.0, metavar="T1",
-                    help="also integrate the workload grid from 0 to T1 with PI and with the learned controller")
+    ap.add_argument("--ab", type=float, default=None, metavar="T1",
+                    help="also integrate the workload grid from 0 to T1 with PI and with the learned controller "
+                         "(default: T1 = 100 for the default workload, the metric's wall-time comparison; 0 = off)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2309_05331_amd", "controller_weights.npy"))
     ap.add_argument("--accuracy", action="store_true",
                     help="print the accuracy benchmark (error norms and observed orders of every fixed-step method)")
@@ -469,8 +475,9 @@ def main():
         out["copy_ceiling"] = {"kernel": "hode_stream_copy", "bytes": 2 << 30, "GBps": round(cgbs, 1),
                                "frac_of_peak": round(cgbs / PEAK_HBM_GBS, 4),
                                "dominant_kernel_frac_of_copy": round(achieved / cgbs, 4)}
-    if args.ab > 0 and wl["kind"] == "gs":
-        out["controller_ab"] = dict(run_ab(wl["N"], args.ab, args.weights, wl["dtype"]), t1=args.ab, rtol=1e-6)
+    ab_t1 = args.ab if args.ab is not None else (100.0 if args.workload == "gs512-dp5" else 0.0)
+    if ab_t1 > 0 and wl["kind"] == "gs":
+        out["controller_ab"] = dict(run_ab(wl["N"], ab_t1, args.weights, wl["dtype"]), t1=ab_t1, rtol=1e-6)
     if not args.no_cpu_baseline:
         cb = cpu_baseline_leg(wl)
         out["cpu_baseline"] = cb
