@@ -89,12 +89,15 @@ typedef struct {
   int32_t pad;
 } hode_stats;
 
-/* Creates a context on HIP device `device`.  `stream` is a hipStream_t to run
- * on (borrowed, must outlive the context) or NULL for a context-owned
- * stream. */
+/* Creates a context on HIP device `device`: the holder of one state, its
+ * System and stepper (the objects a user creates before integrating, Reuse
+ * potential, main-program listing).  `stream` is a hipStream_t to run on
+ * (borrowed, must outlive the context) or NULL for a context-owned stream.
+ * *out receives the context (NULL on error). */
 int hode_create(hode_ctx **out, int device, void *stream);
 
-/* Frees every device buffer and the context.  NULL is ignored. */
+/* Frees every device buffer and the context (the end of the objects'
+ * lifetime in the same listing).  NULL is ignored. */
 void hode_destroy(hode_ctx *ctx);
 
 /* Selects the System.  HODE_RHS_GRAYSCOTT3D takes params = {Du, Dv, F, k, L}
@@ -111,16 +114,22 @@ int hode_set_rhs(hode_ctx *ctx, int rhs, const double *params, int nparams);
 int hode_init_state(hode_ctx *ctx, int dtype, int nfields, int ndim, const int64_t *shape, const void *src,
                     int src_on_device);
 
-/* Copies the current state out; dst_bytes must be at least the state size
- * (HODE_ESTATE otherwise). */
+/* Copies the current state out (the state the caller reads after
+ * integrate_adaptive returns, Reuse potential, main-program listing), in the
+ * layout of hode_init_state, to host memory (dst_on_device == 0) or device
+ * memory; dst_bytes must be at least the state size (HODE_ESTATE
+ * otherwise).  The caller owns dst. */
 int hode_read_state(hode_ctx *ctx, void *dst, size_t dst_bytes, int dst_on_device);
 
-/* Size of the state in bytes (0 before init). */
+/* Size of the state in bytes (0 before init): 2 N^3 or n elements of the
+ * state precision (layout above). */
 size_t hode_state_bytes(const hode_ctx *ctx);
 
 /* Absolute and relative tolerance of the error norm
- * max_i |e_i| / (atol + rtol * max(|y_i|, |ynew_i|)).  Both >= 0, not both 0.
- * Defaults: 1e-6, 1e-6. */
+ * max_i |e_i| / (atol + rtol * max(|y_i|, |ynew_i|)) (the predefined
+ * tolerance adaptive steppers keep the embedded estimate within, measured in
+ * the L-infinity norm: Architecture and nomenclature of Boost Odeint).
+ * Both >= 0, not both 0 (HODE_EINVAL).  Defaults: 1e-6, 1e-6. */
 int hode_set_tolerances(hode_ctx *ctx, double atol, double rtol);
 
 /* Step-size controller for adaptive runs: HODE_CTRL_PI (default,
@@ -198,7 +207,9 @@ int hode_integrate_times(hode_ctx *ctx, const double *times, int64_t n_times, do
 int hode_integrate_times_dense(hode_ctx *ctx, const double *times, int64_t n_times, double dt0, int64_t max_steps,
                                void *dst, size_t dst_bytes, int dst_on_device, hode_stats *out);
 
-/* Statistics of the last run. */
+/* Statistics of the last run (accepted steps are the step count that
+ * integrate_adaptive returns, Reuse potential; rejected attempts and System
+ * evaluations beside it). */
 int hode_get_stats(hode_ctx *ctx, hode_stats *out);
 
 /* Checkpoint of the step control (with the state from hode_read_state, what
@@ -231,14 +242,21 @@ int hode_get_ctrl(hode_ctx *ctx, void *blob, size_t *nbytes);
  * of another size, magic or version. */
 int hode_set_ctrl(hode_ctx *ctx, const void *blob, size_t nbytes);
 
-/* Records one 24-double entry per adaptive attempt (h, err, accepted, t
- * after, dt proposed, PI log-ratio, learned log-ratio or NaN, landed-on-t1
- * flag, then for accepted attempts the 16 learned-controller features, else
- * NaN) for the next runs, up to `capacity` attempts (0 disables). */
+/* Doubles per trace record: h, err, accepted, t after, dt proposed, PI
+ * log-ratio, learned log-ratio or NaN, landed-on-t1 flag, then for accepted
+ * attempts the 16 learned-controller features, else NaN.  A trace buffer
+ * for cap records holds cap * HODE_TRACE_W doubles. */
+#define HODE_TRACE_W 24
+
+/* Records one HODE_TRACE_W-double entry per adaptive attempt (the accept /
+ * reject history the step control produces, the training data of the learned
+ * controller) for the next runs, up to `capacity` attempts (0 disables).  The
+ * trace is device memory owned by the context. */
 int hode_set_trace(hode_ctx *ctx, int64_t capacity);
 
-/* Copies up to `cap` recorded entries to host `dst`; *n receives the number
- * of attempts of the last run (may exceed cap). */
+/* Copies up to `cap` recorded entries (cap * HODE_TRACE_W doubles) to host
+ * `dst` (owned by the caller; NULL with cap 0 only queries); *n receives
+ * the number of attempts of the last run (may exceed cap). */
 int hode_read_trace(hode_ctx *ctx, double *dst, int64_t cap, int64_t *n);
 
 /* Evaluates the System at the current state into dst (same layout/dtype as
@@ -370,7 +388,10 @@ int hode_ensemble_timing(hode_ctx *ctx, double *kernel_ms, int *launches);
  * pack one row per segment of a wavefront (the default for such grids). */
 int hode_ensemble_set_vector_width(hode_ctx *ctx, int i, int vw);
 
-/* Per-instance attempt traces (8 doubles per attempt, as hode_set_trace). */
+/* Per-instance attempt traces, HODE_TRACE_W doubles per attempt with the
+ * fields of hode_set_trace; capacity is per instance.  read_trace copies up
+ * to cap records (cap * HODE_TRACE_W doubles) of instance i to host dst and
+ * stores the instance's attempt count of the last run in *n. */
 int hode_ensemble_set_trace(hode_ctx *ctx, int64_t capacity);
 int hode_ensemble_read_trace(hode_ctx *ctx, int i, double *dst, int64_t cap, int64_t *n);
 
@@ -383,9 +404,11 @@ int hode_ensemble_read_trace(hode_ctx *ctx, int i, double *dst, int64_t cap, int
 int hode_ensemble_autotune(hode_ctx *ctx, int reps, int *vw_out, double *ms_out);
 
 /* Integrates every instance from t0 to t1 (first trial step dt0, at most
- * max_steps attempts each; tolerances and controller of the context).
+ * max_steps attempts each; tolerances and controller of the context), each
+ * with its own integrate_adaptive step control (Reuse potential).
  * per_instance (may be NULL) receives n stats.  Returns HODE_OK, the first
- * failing instance's status, or HODE_EHIP if a gang barrier timed out. */
+ * failing instance's status, or HODE_EHIP if a HIP call failed or a wait of
+ * the persistent kernel gave up (hode_ensemble_set_barrier_limit). */
 int hode_ensemble_integrate_adaptive(hode_ctx *ctx, double t0, double t1, double dt0, int64_t max_steps,
                                      hode_stats *per_instance);
 
@@ -413,8 +436,13 @@ int hode_mlp_train_step(const float *X, const float *T, const float *Wt, int64_t
                         float *m, float *v, float *grad, double *acc, int64_t step, float lr, double *loss_out,
                         void *stream);
 
-/* Text of the last error on this context (valid until the next call). */
+/* Text of the last error on this context (valid until the next call on it;
+ * owned by the context). */
 const char *hode_last_error(const hode_ctx *ctx);
+
+/* HODE_TRACE_W of the built library (for bindings that cannot read this
+ * header). */
+int hode_trace_width(void);
 
 #ifdef __cplusplus
 }

@@ -723,6 +723,8 @@ int hode_init_state(hode_ctx* c, int dtype, int nfields, int ndim, const int64_t
 
 size_t hode_state_bytes(const hode_ctx* c) { return c ? (size_t)c->nelem * c->esize : 0; }
 
+int hode_trace_width(void) { return HODE_TRACE_W; }
+
 int hode_read_state(hode_ctx* c, void* dst, size_t dst_bytes, int dst_on_device) {
   int rc = check_ready(c);
   if (rc) return rc;

@@ -36,7 +36,10 @@ def AB(steps):
 
 CTRL_PI, CTRL_I, CTRL_MLP = 1, 2, 3
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EDT_UNDERFLOW, EMAXSTEPS, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
-TRACE_W = 24  # h, err, accepted, t after, dt next, PI log-ratio, learned log-ratio, landed, 16 features
+# doubles per trace record (h, err, accepted, t after, dt next, PI log-ratio,
+# learned log-ratio, landed, 16 features): HODE_TRACE_W, read from the library
+# by lib()
+TRACE_W = None
 MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 
 # Gray-Scott stage kernels, as numbered by hode_time_kernel
@@ -131,11 +134,14 @@ def lib():
             "hode_mlp_loss_grad": ([P, P, P, P, I64, P, P, C.POINTER(D), P], I),
             "hode_mlp_train_step": ([P, P, P, I64, P, P, P, P, P, P, I64, C.c_float, C.POINTER(D), P], I),
             "hode_last_error": ([P], C.c_char_p),
+            "hode_trace_width": ([], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
+        global TRACE_W
+        TRACE_W = L.hode_trace_width()
         _lib = L
     return _lib
 

@@ -31,3 +31,22 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(hode, "LIBPATH", str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError, match="not built"):
         hode.lib()
+
+
+def _header_trace_width():
+    import re
+    hdr = os.path.join(os.path.dirname(hode.HERE), "include", "hode.h")
+    m = re.search(r"#define\s+HODE_TRACE_W\s+(\d+)", open(hdr).read())
+    assert m, "HODE_TRACE_W missing from the header"
+    return int(m.group(1))
+
+
+def test_trace_width_matches_header():
+    # a C caller sizes trace buffers from the header's constant: the library
+    # (and the binding, which asks the library) must agree with it
+    if not os.path.exists(hode.LIBPATH):
+        pytest.skip("libhode.so not built")
+    w = _header_trace_width()
+    assert w == 8 + 16
+    assert hode.lib().hode_trace_width() == w
+    assert hode.TRACE_W == w

@@ -207,3 +207,44 @@ def test_ensemble_barrier_give_up_is_reported_and_recoverable():
         assert np.array_equal(out, ref_outs[i]), i
         assert (stats[i]["accepted"], stats[i]["rejected"]) == (ref_stats[i]["accepted"], ref_stats[i]["rejected"])
     ens.close()
+
+
+def test_trace_buffers_sized_from_header_constant():
+    # A C caller sizes trace buffers as cap * HODE_TRACE_W doubles (the
+    # header's constant, read from the header text here): the library must
+    # write exactly cap records and nothing past them, for the ensemble and
+    # for a single context.
+    import ctypes
+    import os
+    import re
+    hdr = os.path.join(os.path.dirname(hode.HERE), "include", "hode.h")
+    W = int(re.search(r"#define\s+HODE_TRACE_W\s+(\d+)", open(hdr).read()).group(1))
+    canary = np.float64(-12345.678)
+    cap, tail = 3, 4 * W
+    edges = [8, 16, 24]
+    _, prms = _params(len(edges))
+    ens, _, _, stats = _run_ensemble(edges, prms, hode.F32, 20.0, 1e-5, trace=64)
+    L = hode.lib()
+    for i in range(len(edges)):
+        buf = np.full(cap * W + tail, canary)
+        n = ctypes.c_int64()
+        rc = L.hode_ensemble_read_trace(ens.h, i, buf.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(n))
+        assert rc == 0
+        attempts = stats[i]["accepted"] + stats[i]["rejected"]
+        assert n.value == attempts > cap
+        assert np.all(buf[cap * W:] == canary), i
+        rec = buf[:cap * W].reshape(cap, W)
+        assert np.all(rec[:, 0] > 0) and np.all(np.isin(rec[:, 2], (0.0, 1.0))), i
+        np.testing.assert_array_equal(rec, ens.read_instance_trace(i)[:cap])
+    ens.close()
+    ctx = hode.Context(0)
+    ctx.set_rhs(hode.RHS_GRAYSCOTT3D, prms[0])
+    ctx.init_state(inputs.ensemble_ic(0, 8, dtype=np.float32).ravel(), grid=8)
+    ctx.set_trace(64)
+    st = ctx.integrate_adaptive(0.0, 20.0, 0.1, max_steps=100000)
+    buf = np.full(cap * W + tail, canary)
+    n = ctypes.c_int64()
+    assert L.hode_read_trace(ctx.h, buf.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(n)) == 0
+    assert n.value == st["accepted"] + st["rejected"] > cap
+    assert np.all(buf[cap * W:] == canary)
+    ctx.close()
