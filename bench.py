@@ -9,9 +9,11 @@ noise +-0.01 (seed 5).  One benchmark step integrates one window of `--window`
 time units along the same trajectory (the next window starts where the last
 ended, with the last proposed step); the value is cells x accepted steps /
 wall time over the timed windows.  After the timed windows the default
-workload also integrates the same grid from t = 0 to 100 with the PI and with
+workload also integrates the same grid from t = 0 to 2000 with the PI and with
 the learned step-size controller (`controller_ab`: wall time to rtol 1e-6 of
-each and their ratio; `--ab T1` sets the horizon, `--ab 0` skips it).
+each, three runs each in alternating order, mean and sd, their ratio, and
+each one's final error against an FP64 run at rtol 1e-8; `--ab T1` sets
+the horizon, `--ab 0` skips it).
 
 Other workloads (--workload): gs256-dp5, gs256-rk4, gs512-ck54, gs512-f78,
 gs512-ab4, gs32-rk4-fp64, ew24-dp5, ew24-dp5-fp32 and ens512-dp5 (the
@@ -36,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s & %HBM peak; wall-time to rtol 1e-6, learned vs PI controller"
+T_START = time.time()
 PEAK_HBM_GBS = 8000.0
 GS_PRM = [2e-5, 1e-5, 0.053, 0.014, 2.5]
 
@@ -97,11 +100,128 @@ def traffic_from_profiles(kernel_tag: str):
         return None
 
 
-def cpu_baseline_leg(wl, budget_s=10.0):
-    """Times the FP64 oracle on a bounded sample of the workload (test
-    infrastructure; nothing else in this file touches the oracle)."""
+def _window(y, N, R, c):
+    """The (2, W, W, W) periodic window of edge W = 2R + 1 centred on cell c."""
+    idx = [np.arange(ci - R, ci + R + 1) % N for ci in c]
+    return y[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]]
+
+
+def oracle_error(oracle, wl, chk):
+    """The GPU's error against the FP64 oracle on the check runs made after
+    the timed region (see gs_check_runs and the element-wise and ensemble
+    runners).  Gray-Scott: a cell's value after E right-hand-side
+    evaluations depends only on cells within E grid steps, so the oracle
+    integrates the periodic window of edge 2R + 1 (R > E) around each sampled
+    cell, with the grid spacing of the full grid, replaying the GPU's steps;
+    the window's centre is exact.  Element-wise: the oracle replays the whole
+    run on sampled components.  Ensemble: whole instances replayed."""
+    bound32 = 1e-4
+    if wl["kind"] == "gs":
+        N = chk["N"]
+        y0 = chk["y0"].reshape(2, N, N, N)
+        kind = chk["kind"]
+        if kind == "rk4":
+            steps = chk["steps"]
+            E = 4 * steps
+        elif kind == "ab4":
+            steps = chk["steps"]
+            E = 13 * 3 + steps
+        else:
+            n_acc = int(chk["acc"].sum())
+            E = {"dp5": 6, "ck54": 6, "f78": 13}[kind] * n_acc + 1
+        R = E + 4
+        full = 2 * R + 1 >= N
+        W = N if full else 2 * R + 1
+        sysd = oracle.gs_system(W, GS_PRM[0], GS_PRM[1], GS_PRM[2], GS_PRM[3], GS_PRM[4] * W / N)
+        om = {"dp5": oracle.DOPRI5, "ck54": oracle.CASHKARP, "f78": oracle.FEHLBERG78}
+        worst = 0.0
+        cells = chk["cells"]
+        if full and kind == "rk4" and N <= 32:
+            # the whole workload (all timed steps) on the whole grid
+            o, _ = oracle.integrate_n_steps(sysd, oracle.RK4, y0.astype(np.float64), 0.0, wl["dt"], steps)
+            o = o.reshape(2, N, N, N)
+            rel = max(float(np.max(np.abs(chk["full"][f] - o[f])) / np.max(np.abs(o[f]))) for f in range(2))
+            return {"relative_per_field": rel, "bound": 1e-12, "what": "the whole run (%d RK4 steps) on the whole "
+                    "grid" % steps}
+        for ci, c in enumerate(cells):
+            yw = y0.astype(np.float64) if full else _window(y0, N, R, c).astype(np.float64)
+            ctr = (np.array([0, 1]) * W ** 3 + (c[0] * W + c[1]) * W + c[2]) if full else \
+                (np.array([0, 1]) * W ** 3 + (R * W + R) * W + R)
+            if kind == "rk4":
+                yw, _ = oracle.integrate_n_steps(sysd, oracle.RK4, yw, 0.0, wl["dt"], steps)
+            elif kind == "ab4":
+                yw, _ = oracle.integrate_n_steps(sysd, oracle.AB(4), yw, 0.0, wl["dt"], steps)
+            else:
+                yw, _, _ = oracle.integrate_replay(sysd, yw, 0.0, chk["hs"], chk["acc"], 1e-6, 1e-6,
+                                                   method=om[kind])
+            worst = max(worst, float(np.max(np.abs(chk["gpu"][:, ci] - yw.ravel()[ctr]))))
+        what = ("%d %s from the initial condition, oracle on periodic windows of edge %d around %d sampled cells"
+                % (steps if kind in ("rk4", "ab4") else len(chk["hs"]),
+                   "steps" if kind in ("rk4", "ab4") else "attempts (GPU step sequence replayed)", W, len(cells)))
+        out = {"max_abs": worst, "bound": bound32 if chk["dtype"] == "f32" else None, "what": what}
+        if chk["dtype"] == "f64":
+            scale = float(np.max(np.abs(chk["gpu"])))
+            out["relative"] = worst / scale
+            out["bound"] = 1e-12
+        if "t20" in chk:
+            t20 = chk["t20"]
+            rec = json.load(open(t20["golden"]))
+            ref = np.array([rec["final"]["u"], rec["final"]["v"]])
+            out["t0_to_20"] = {
+                "max_abs_replaying_oracle_steps": float(np.max(np.abs(t20["replay"] - ref))),
+                "max_abs_free_running": float(np.max(np.abs(t20["free"] - ref))),
+                "gpu_accepted_rejected": t20["free_counts"], "oracle_accepted_rejected": t20["oracle_counts"],
+                "what": "512^3 from t = 0 to 20 against the stored FP64 oracle run (%d sampled cells)"
+                        % len(rec["final"]["cells"])}
+        return out
+    if wl["kind"] == "ew":
+        m = chk["idx"].size
+        x0 = chk["x0"].astype(np.float32).astype(np.float64) if chk["dtype"] == "f32" else chk["x0"]
+        o, te, _ = oracle.integrate_replay(oracle.ew_system(oracle.EXP, m), x0, 0.0, chk["hs"], chk["acc"],
+                                           1e-6, 1e-6)
+        d = np.abs(chk["gpu"] - o)
+        out = {"max_abs": float(d.max()), "relative": float(np.max(d / np.maximum(np.abs(o), 1e-300))),
+               "what": "the whole run (%d attempts) replayed by the oracle on %d sampled components (the 64 "
+                       "largest initial values among them)" % (len(chk["hs"]), m)}
+        if chk["dtype"] == "f32":
+            # the FP32 rounding bound of the state (x(5) <= 0.5 e^5)
+            out["bound"] = 2 * chk["accepted"] * 2.0 ** -24 * 0.5 * math.exp(5.0)
+            out["bound_reading"] = "2 n 2^-24 max|x(t1)| for n accepted steps (states far above order one)"
+        else:
+            out["bound"] = 1e-12
+            out["bound_applies_to"] = "relative"
+        return out
+    worst, parts = 0.0, []
+    for r in chk["instances"]:
+        N = r["N"]
+        sysd = oracle.gs_system(N, *r["prm"])
+        y0 = inputs_ens_ic(r["i"], N).astype(np.float64).ravel()
+        o, te, _ = oracle.integrate_replay(sysd, y0, 0.0, r["hs"], r["acc"], chk["rtol"], chk["rtol"])
+        d = float(np.max(np.abs(r["gpu"] - o)))
+        worst = max(worst, d)
+        parts.append({"instance": r["i"], "N": N, "attempts": len(r["hs"]), "max_abs": d})
+    return {"max_abs": worst, "bound": bound32, "instances": parts,
+            "what": "whole instances (the first of each grid edge up to 48) over t 0 -> %g, the oracle replaying "
+                    "each instance's GPU step sequence" % chk["t1"]}
+
+
+def inputs_ens_ic(i, N):
+    from paper_2309_05331_amd import inputs
+    return inputs.ensemble_ic(i, N)
+
+
+def cpu_baseline_leg(wl, check=None, budget_s=10.0):
+    """Times the FP64 oracle on a bounded sample of the workload, and states
+    the GPU's error against it on the check runs (test infrastructure;
+    nothing else in this file touches the oracle).  Returns (cpu_baseline,
+    error_vs_oracle)."""
     import oracle
     from paper_2309_05331_amd import inputs
+    err = None
+    if check is not None:
+        t0 = time.perf_counter()
+        err = oracle_error(oracle, wl, check)
+        err["oracle_seconds"] = round(time.perf_counter() - t0, 1)
     if wl["kind"] == "gs":
         Ns = min(wl["N"], 128)
         y = inputs.gray_scott_ic(Ns, seed=wl["seed"]).ravel()
@@ -153,7 +273,18 @@ def cpu_baseline_leg(wl, budget_s=10.0):
         el = time.perf_counter() - t0
         sample = "%d adaptive Dopri5 runs t 0->5 on 2^20 components, %.1f s" % (reps, el)
         unit = "component-updates/s"
-    return {"value": units / el, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle", "sample": sample}
+    return ({"value": units / el, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle", "sample": sample,
+             "cpu_model": cpu_model()}, err)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def timed_steps(one_step, steps):
@@ -185,7 +316,10 @@ def run_ens(wl, steps, warmup):
     ens = hode.Ensemble(edges, prms, dtype=hode.F32)
     ens.set_tolerances(wl["rtol"], wl["rtol"])
     ens.set_controller(hode.CTRL_PI)
-    ens.autotune(3)
+    ens.autotune(3)  # the persistent kernel timed per grid edge: vector width and planes per tile
+    tiles = {}
+    for i, N in enumerate(edges):
+        tiles.setdefault(str(N), list(ens.instance_tile(i)))
     cells = np.array(edges, dtype=np.float64) ** 3
     tot = {"acc": 0, "rej": 0, "cell_att": 0.0, "kernel_ms": 0.0, "launches": 0}
 
@@ -209,14 +343,103 @@ def run_ens(wl, steps, warmup):
     for key in ("acc", "rej", "cell_att", "kernel_ms", "launches"):
         tot[key] = 0
     el, per = timed_steps(one_step, steps)
+    # oracle check (after the timed region): the same integration with every
+    # instance's step sequence recorded; the first instance of each grid
+    # edge up to 48 is replayed by the oracle on its whole state
+    ens.set_trace(4000)
+    for i in range(n):
+        ens.init_instance(i, ics[i])
+    st = ens.integrate_adaptive(0.0, wl["t1"], wl["dt0"], max_steps=4000)
+    check = {"instances": [], "t1": wl["t1"], "rtol": wl["rtol"]}
+    seen = set()
+    for i, N in enumerate(edges):
+        if N > 48 or N in seen:
+            continue
+        seen.add(N)
+        tr = ens.read_instance_trace(i)
+        o = np.empty(2 * N ** 3, dtype=np.float32)
+        ens.read_instance(i, o)
+        check["instances"].append({"i": i, "N": N, "prm": prms[i], "hs": tr[:, 0].copy(),
+                                   "acc": tr[:, 2].astype(np.int32), "gpu": o.astype(np.float64),
+                                   "status": st[i]["status"]})
+    ens.set_trace(0)
     ens.close()
     # algorithmic bytes: 30 arrays per attempt plus the first k1 (2 arrays) per
     # instance and step
     abytes = (DP5_ARRAYS * tot["cell_att"] + 2 * steps * cells.sum()) * 2 * 4
     return dict(elapsed=el, per_step=per, cells=1, accepted=tot["acc"], rejected=tot["rej"], dom="ens_kernel",
-                dom_ms=tot["kernel_ms"], dom_bytes=abytes, stage_gbs=None,
+                dom_ms=tot["kernel_ms"], dom_bytes=abytes, stage_gbs=None, check=check, tiles=tiles,
                 attempt_gbs=abytes / el / 1e9, tile=None, launches=tot["launches"],
                 instance_attempts=tot["instance_attempts"])
+
+
+def gs_sample_cells(N, extra=8, seed=0):
+    """Cells (z, y, x) whose values the oracle checks: the cube's corners and
+    faces, the domain's corners (periodic wrap), the centre, seeded random
+    cells."""
+    a, b, m = 3 * N // 8, 5 * N // 8 - 1, N // 2
+    pts = [(a, a, a), (b, b, b), (a, b, a), (b, a, b), (a, m, m), (m, m, b), (m, a, m), (m, m, m),
+           (0, 0, 0), (N - 1, N - 1, N - 1), (0, N - 1, m), (m, 0, N - 1), (max(a - 1, 0), a, min(b + 1, N - 1))]
+    rng = np.random.default_rng(seed)
+    return pts + [tuple(int(v) for v in rng.integers(0, N, size=3)) for _ in range(extra)]
+
+
+GS_CHECK_ATTEMPTS = 4  # attempts (or steps) of the short check run from the initial condition
+
+
+def gs_check_runs(ctx, wl, y0, method):
+    """GPU runs for the oracle check, after the timed region, in the timed
+    launch configuration: the first few attempts (steps) from the initial
+    condition, with the GPU's values at sampled cells and its step sequence;
+    for the 512^3 Dopri5 workload also the run to t = 20 (free-running, and
+    replaying the steps of the stored FP64 oracle run) at the stored oracle
+    run's sampled cells."""
+    from paper_2309_05331_amd import hode
+    N = wl["N"]
+    ctx.init_state(y0, grid=N)
+    out = {"kind": wl["method"], "y0": y0, "N": N, "dtype": wl["dtype"]}
+    if wl["method"] in ("rk4", "ab4"):
+        # (a grid small enough for the oracle's whole grid: the whole workload)
+        out["steps"] = (wl["steps_per"] if N <= 32 else 10) if wl["method"] == "rk4" else 8
+        ctx.integrate_n_steps(method, 0.0, wl["dt"], out["steps"])
+    else:
+        ctx.set_trace(64)
+        st = ctx.integrate_adaptive(0.0, 1e9, wl.get("dt0", 0.1), max_steps=GS_CHECK_ATTEMPTS)
+        assert st["status"] == hode.EMAXSTEPS, st
+        tr = ctx.read_trace()
+        out["hs"], out["acc"] = tr[:, 0].copy(), tr[:, 2].astype(np.int32)
+        ctx.set_trace(0)
+    g = np.empty(2 * N ** 3, dtype=np.float32 if wl["dtype"] == "f32" else np.float64)
+    ctx.read_state(g)
+    g = g.reshape(2, N, N, N)
+    out["cells"] = gs_sample_cells(N)
+    out["gpu"] = np.array([[g[f][c] for c in out["cells"]] for f in range(2)], dtype=np.float64)
+    if N <= 32:
+        out["full"] = g.astype(np.float64)
+    del g
+    golden = os.path.join(ROOT, "tests", "golden", "oracle_gs512-dp5-t20.json")
+    if wl["method"] == "dp5" and N == 512 and wl["dtype"] == "f32" and os.path.exists(golden):
+        rec = json.load(open(golden))
+        cells = [tuple(c) for c in rec["final"]["cells"]]
+        ctx.init_state(y0, grid=N)
+        st = ctx.integrate_adaptive(0.0, rec["t1"], rec["dt0"])
+        g = np.empty(2 * N ** 3, dtype=np.float32)
+        ctx.read_state(g)
+        g = g.reshape(2, N, N, N)
+        free = np.array([[g[f][c] for c in cells] for f in range(2)], dtype=np.float64)
+        ctx.init_state(y0, grid=N)
+        t = 0.0
+        for h, acc in zip(rec["h"], rec["accepted_flags"]):
+            if acc:
+                ctx.do_step(hode.DOPRI5, t, h)
+                t += h
+        ctx.read_state(g)
+        g = g.reshape(2, N, N, N)
+        replay = np.array([[g[f][c] for c in cells] for f in range(2)], dtype=np.float64)
+        del g
+        out["t20"] = {"golden": golden, "free": free, "replay": replay, "free_counts": [st["accepted"], st["rejected"]],
+                      "oracle_counts": [rec["accepted"], rec["rejected"]]}
+    return out
 
 
 def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
@@ -285,11 +508,14 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     step_bytes = sum(GS_ARRAYS[k] for k in kinds) * arr_bytes
     attempt_ms = sum(ms.values())
     ry, zc = ctx.get_tile()
+    kind_tiles = {GS_NAMES[k]: list(ctx.kind_tile(k)) for k in kinds}
+    check = gs_check_runs(ctx, wl, y0, method)
     ctx.close()
     return dict(elapsed=el, per_step=per, no_graph=no_graph, cells=N ** 3, accepted=state["acc"], rejected=state["rej"],
                 t_end=state["t"],
                 dom=GS_NAMES[dom], dom_ms=ms[dom], dom_bytes=bytes_dom, stage_gbs=stage_gbs,
-                attempt_gbs=step_bytes / (attempt_ms * 1e-3) / 1e9, tile=[ry, zc])
+                attempt_gbs=step_bytes / (attempt_ms * 1e-3) / 1e9, tile=[ry, zc], kind_tiles=kind_tiles,
+                check=check)
 
 
 def run_ew(wl, steps, warmup):
@@ -314,37 +540,114 @@ def run_ew(wl, steps, warmup):
     acc[0] = 0
     el, per = timed_steps(one_step, steps)
     ms = ctx.time_kernel(hode.DOPRI5, 20)
+    # oracle check (after the timed region): the same run with its step
+    # sequence recorded, the GPU's values at sampled components
+    ctx.init_state(dev)
+    ctx.set_trace(10000)
+    st = ctx.integrate_adaptive(0.0, wl["t1"], wl["dt0"])
+    tr = ctx.read_trace()
+    g = np.empty(n, dtype=x0.dtype)
+    ctx.read_state(g)
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([np.argsort(x0)[-64:], rng.integers(0, n, size=1 << 16)]))
+    check = {"idx": idx, "x0": x0[idx].astype(np.float64), "gpu": g[idx].astype(np.float64), "hs": tr[:, 0].copy(),
+             "acc": tr[:, 2].astype(np.int32), "t1": wl["t1"], "dtype": wl["dtype"], "accepted": st["accepted"]}
+    del g
     ctx.close()
-    return dict(elapsed=el, per_step=per, cells=n, accepted=acc[0], rejected=0, dom="ew_step_dp5", dom_ms=ms,
+    return dict(elapsed=el, per_step=per, cells=n, accepted=acc[0], rejected=0, dom="ew_step_dp5", dom_ms=ms, check=check,
                 dom_bytes=2 * n * esz, stage_gbs=None, attempt_gbs=2 * n * esz / (ms * 1e-3) / 1e9, tile=None)
 
 
-def run_ab(N, t1, weights_path, dtype="f32"):
+def run_ab(N, t1, weights_path, dtype="f32", repeats=3, ref_rtol=1e-8, deadline=None):
     """Wall time to integrate the whole horizon with PI and with the learned
-    controller (same grid, tolerances and start)."""
+    controller (same grid, tolerances, start and autotuned tiles), `repeats`
+    runs each in alternating order (PI, learned, learned, PI, ...), and each
+    controller's final error against an FP64 run of the same start at rtol =
+    atol = ref_rtol (0: no reference; skipped when the wall clock has passed
+    `deadline`, so the whole benchmark stays within its time limit)."""
+    import tempfile
     import torch
     from paper_2309_05331_amd import hode, inputs
     np_dt = np.float32 if dtype == "f32" else np.float64
-    y0 = torch.from_numpy(inputs.gray_scott_ic(N, seed=5, dtype=np_dt).ravel()).to("cuda:0")
+    y0h = inputs.gray_scott_ic(N, seed=5, dtype=np_dt).ravel()
+    y0 = torch.from_numpy(y0h).to("cuda:0")
     wb = np.load(weights_path)
-    res = {}
-    for name, kind, w in (("pi", hode.CTRL_PI, None), ("learned", hode.CTRL_MLP, wb)):
+    cache = os.path.join(tempfile.mkdtemp(prefix="hode_ab_"), "tune.txt")
+    kinds = {"pi": (hode.CTRL_PI, None), "learned": (hode.CTRL_MLP, wb)}
+    order = []
+    for r in range(repeats):
+        order += ["pi", "learned"] if r % 2 == 0 else ["learned", "pi"]
+    runs = {"pi": [], "learned": []}
+    finals = {}
+    for name in order:
+        kind, w = kinds[name]
         ctx = hode.Context(0)
         ctx.set_rhs(hode.RHS_GRAYSCOTT3D, GS_PRM)
         ctx.init_state(y0, grid=N)
         ctx.set_tolerances(1e-6, 1e-6)
         ctx.set_controller(kind, w)
-        ctx.set_tile(1, 256 if N >= 256 else N)
+        ctx.autotune_cached(hode.DOPRI5, 3, cache)  # the first run tunes, the others read the same tiles
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = ctx.integrate_adaptive(0.0, t1, 0.1, max_steps=10 ** 7)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        res[name] = {"wall_s": el, "accepted": st["accepted"], "rejected": st["rejected"], "status": st["status"],
-                     "cell_updates_per_s": N ** 3 * st["accepted"] / el}
-        print(json.dumps({name: res[name]}), file=sys.stderr, flush=True)
+        assert st["status"] == 0, st
+        runs[name].append({"wall_s": el, "accepted": st["accepted"], "rejected": st["rejected"]})
+        if name not in finals:
+            g = np.empty(2 * N ** 3, dtype=np_dt)
+            ctx.read_state(g)
+            finals[name] = g
+        print(json.dumps({name: runs[name][-1]}), file=sys.stderr, flush=True)
         ctx.close()
-    res["wall_ratio_learned_over_pi"] = res["learned"]["wall_s"] / res["pi"]["wall_s"]
+    res = {"order": order, "t1": t1, "rtol": 1e-6}
+    for name in ("pi", "learned"):
+        w = np.array([r["wall_s"] for r in runs[name]])
+        res[name] = {"wall_s_mean": float(w.mean()), "wall_s_sd": float(w.std(ddof=1)) if w.size > 1 else None,
+                     "wall_s": [round(float(v), 4) for v in w], "accepted": runs[name][0]["accepted"],
+                     "rejected": runs[name][0]["rejected"],
+                     "attempts": runs[name][0]["accepted"] + runs[name][0]["rejected"],
+                     "cell_updates_per_s": N ** 3 * runs[name][0]["accepted"] / float(w.mean())}
+    wl, wp = np.array(res["learned"]["wall_s"]), np.array(res["pi"]["wall_s"])
+    res["wall_ratio_learned_over_pi"] = float(wl.mean() / wp.mean())
+    # sd of the ratio from the two means' sds (first order)
+    if wl.size > 1:
+        res["wall_ratio_sd"] = float(res["wall_ratio_learned_over_pi"] * math.sqrt(
+            (wl.std(ddof=1) / wl.mean()) ** 2 + (wp.std(ddof=1) / wp.mean()) ** 2))
+    if ref_rtol > 0 and deadline is not None and time.time() > deadline:
+        res["reference"] = "skipped: the time budget of the benchmark run was spent"
+    elif ref_rtol > 0:
+        ctx = hode.Context(0)
+        ctx.set_rhs(hode.RHS_GRAYSCOTT3D, GS_PRM)
+        ctx.init_state(y0h.astype(np.float64), grid=N)
+        ctx.set_tolerances(ref_rtol, ref_rtol)
+        ctx.autotune(hode.DOPRI5, 3)
+        t0 = time.perf_counter()
+        # in windows of 100 time units, one progress line each (the proposed
+        # step carries over from one window to the next)
+        t, dt, acc, rej = 0.0, 0.1, 0, 0
+        while t < t1:
+            te = min(t1, t + 100.0)
+            st = ctx.integrate_adaptive(t, te, dt, max_steps=10 ** 7)
+            assert st["status"] == 0, st
+            t, dt, acc, rej = st["t"], st["dt_next"], acc + st["accepted"], rej + st["rejected"]
+            print(json.dumps({"reference_t": t, "accepted": acc, "wall_s": round(time.perf_counter() - t0, 1)}),
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = {"accepted": acc, "rejected": rej}
+        ref = np.empty(2 * N ** 3, dtype=np.float64)
+        ctx.read_state(ref)
+        ctx.close()
+        res["reference"] = {"dtype": "f64", "rtol": ref_rtol, "accepted": st["accepted"], "rejected": st["rejected"],
+                            "wall_s": round(el, 2),
+                            "checked": "the FP64 stage kernels agree with the FP64 oracle to 1e-12 relative when "
+                                       "both take the same steps (parity tests)"}
+        for name in ("pi", "learned"):
+            d = np.abs(finals[name].astype(np.float64) - ref)
+            res[name]["final_max_abs_error_vs_reference"] = float(d.max())
+            res[name]["final_mean_abs_error_vs_reference"] = float(d.mean())
+        del ref
     return res
 
 
@@ -401,7 +704,11 @@ def main():
     ap.add_argument("--tile", default="auto", help="auto (autotune) or RY,ZC")
     ap.add_argument("--ab", type=float, default=None, metavar="T1",
                     help="also integrate the workload grid from 0 to T1 with PI and with the learned controller "
-                         "(default: T1 = 100 for the default workload, the metric's wall-time comparison; 0 = off)")
+                         "(default: T1 = 2000 for the default workload, the metric's wall-time comparison over "
+                         "the workload's horizon; 0 = off)")
+    ap.add_argument("--ab-repeats", type=int, default=3, help="runs per controller in the comparison")
+    ap.add_argument("--ab-ref-rtol", type=float, default=1e-8,
+                    help="tolerance of the FP64 reference run of the comparison (0 = no reference)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2309_05331_amd", "controller_weights.npy"))
     ap.add_argument("--accuracy", action="store_true",
                     help="print the accuracy benchmark (error norms and observed orders of every fixed-step method)")
@@ -435,14 +742,16 @@ def main():
                           "f78": "fehlberg78-adaptive", "ab4": "adams-bashforth4-fixed"}[wl["method"]],
                "rtol": None if wl["method"] in ("rk4", "ab4") else 1e-6, "controller": args.controller,
                "window_time_units": wl.get("window"), "dt": wl.get("dt"), "tile_ry_zc": r["tile"],
+               "stage_tiles_ry_zc_nw": r["kind_tiles"],
                "params": {"Du": GS_PRM[0], "Dv": GS_PRM[1], "F": GS_PRM[2], "k": GS_PRM[3], "L": GS_PRM[4]}}
     elif wl["kind"] == "ens":
         r = run_ens(wl, args.steps, args.warmup)
         unit = "cell-updates/s"
         cfg = {"workload": args.workload, "instances": wl["n"], "edges": "uniform over 16..96 step 8", "fields": 2,
                "method": "dopri5-adaptive", "rtol": wl["rtol"], "controller": "pi", "t": [0.0, wl["t1"]],
-               "launch": "persistent kernel in a hipGraph (stage phases over per-XCD tile queues, grid barriers), relaunched per 64 attempts",
-               "launches_per_step": r["launches"] / max(args.steps, 1)}
+               "launch": "one persistent kernel launch per integration, captured in a hipGraph (lock-step rounds "
+                         "of stage phases over per-XCD tile queues, grid barriers)",
+               "launches_per_step": r["launches"] / max(args.steps, 1), "tiles_per_edge_vw_planes": r["tiles"]}
     else:
         r = run_ew(wl, args.steps, args.warmup)
         unit = "component-updates/s"
@@ -475,12 +784,14 @@ def main():
         out["copy_ceiling"] = {"kernel": "hode_stream_copy", "bytes": 2 << 30, "GBps": round(cgbs, 1),
                                "frac_of_peak": round(cgbs / PEAK_HBM_GBS, 4),
                                "dominant_kernel_frac_of_copy": round(achieved / cgbs, 4)}
-    ab_t1 = args.ab if args.ab is not None else (100.0 if args.workload == "gs512-dp5" else 0.0)
+    ab_t1 = args.ab if args.ab is not None else (2000.0 if args.workload == "gs512-dp5" else 0.0)
     if ab_t1 > 0 and wl["kind"] == "gs":
-        out["controller_ab"] = dict(run_ab(wl["N"], ab_t1, args.weights, wl["dtype"]), t1=ab_t1, rtol=1e-6)
+        out["controller_ab"] = run_ab(wl["N"], ab_t1, args.weights, wl["dtype"], args.ab_repeats, args.ab_ref_rtol,
+                                      deadline=T_START + 330.0)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline_leg(wl)
+        cb, err = cpu_baseline_leg(wl, r.get("check"))
         out["cpu_baseline"] = cb
+        out["error_vs_oracle"] = err
     print(json.dumps(out), flush=True)
 
 

@@ -269,11 +269,24 @@ int hode_eval_rhs(hode_ctx *ctx, void *dst, size_t dst_bytes, int dst_on_device)
  * launch overhead on small, launch-bound grids). */
 int hode_set_graphs(hode_ctx *ctx, int enable);
 
-/* Gray-Scott tile configuration: ry in {1, 2, 4} (tile of 64 x 4*ry cells per
- * workgroup), zc >= 1 z-planes per workgroup.  Element-wise: `ry` is ignored
- * and zc is the workgroup count cap. */
+/* Gray-Scott tile configuration: ry in {1, 2, 4} rows per wavefront (tile of
+ * 64*vw x nw*ry cells per workgroup of nw wavefronts), zc >= 1 z-planes per
+ * workgroup, for every stage kind.  Element-wise: `ry` is ignored and zc is
+ * the workgroup count cap. */
 int hode_set_tile(hode_ctx *ctx, int ry, int zc);
 int hode_get_tile(const hode_ctx *ctx, int *ry, int *zc);  /* the widest stage's tile */
+
+/* Gray-Scott wavefronts per workgroup for the tiles set next and now: 4
+ * (default) or 8.  Eight-wavefront tiles (twice the rows per tile, so half
+ * the halo rows per row of the grid) exist for the RK4, Dopri5, Cash-Karp
+ * and Euler stage kinds with ry <= 2 and 16-byte lanes (vw 4 for FP32, 2
+ * for FP64); every other kind keeps 4.  Results are bitwise the same. */
+int hode_set_tile_waves(hode_ctx *ctx, int nw);
+
+/* The tile of one stage kind (numbered as for hode_time_kernel): rows per
+ * wavefront, planes per workgroup, wavefronts per workgroup (HODE_ESTATE
+ * before a Gray-Scott state exists). */
+int hode_get_kind_tile(const hode_ctx *ctx, int kind, int *ry, int *zc, int *nw);
 
 /* Gray-Scott cells per lane (1, 2 or 4; fp64 at most 2; must divide N), or 0
  * for the widest that divides N (16-byte loads where possible). */
@@ -299,7 +312,8 @@ int hode_profile_attempt(hode_ctx *ctx, int method, int reps, double *ms);
 
 /* Gray-Scott: times one attempt of `method` for every tile configuration
  * (ry in {1,2,4}; zc the powers of two 8 .. 256 and ceil(N / k) for k = 1 ..
- * 12, at least 8) with hode_profile_attempt and keeps, for every stage kernel
+ * 12, at least 8; 4 or, where the kind has them, 8 wavefronts per workgroup)
+ * with hode_profile_attempt and keeps, for every stage kernel
  * of the attempt, its fastest configuration (the first k1 and the fixed-step
  * stage variants take those of their shape twins); returned are the widest
  * stage's (stage 6 of Dopri5 and Cash-Karp, stage 4 of RK4, stage 13 of
@@ -320,8 +334,8 @@ int hode_debug_poison(hode_ctx *ctx);
  * read from the text file at cache_path when it holds an entry for this
  * device architecture, precision, method, grid edge and cells-per-lane
  * setting (the last such entry wins), else found with hode_autotune and
- * appended to the file as one line ("hode-tune-v1 <arch> <dtype> <method>
- * <N> <vw>" and ry:zc for every kind).  cache_path NULL: the environment
+ * appended to the file as one line ("hode-tune-v2 <arch> <dtype> <method>
+ * <N> <vw>" and ry:zc:nw for every kind).  cache_path NULL: the environment
  * variable HODE_TUNE_CACHE; without either no file is used.  *from_cache
  * (may be NULL) receives 1 when the tiles came from the file.  HODE_EINVAL
  * if the file cannot be written. */
@@ -337,17 +351,17 @@ int hode_stream_copy(void *dst, const void *src, size_t bytes, int reps, double 
 
 /* ---- batched ensemble ------------------------------------------------------
  * n independent Gray-Scott instances (uneven grid edges and parameters), each
- * with its own adaptive Dopri5 step control, stepped together by a
- * persistent kernel (captured once in a hipGraph).  One launch advances every
- * unfinished instance by up to a fixed number of attempts (64 by default) in
- * lock step: per attempt, six stage phases and one control phase separated by
- * grid-wide barriers; in a stage phase the workgroups claim tiles (rows and
- * planes of one instance) from eight per-XCD queues, their own XCD's first,
- * so every phase is balanced dynamically.  The host relaunches with the
- * instances still running until all are done.  Pausing changes no result:
- * every instance's arithmetic and step decisions are those of the
- * single-grid path, so results are bitwise those of running the instance
- * alone. */
+ * with its own adaptive Dopri5 step control (the paper's integrate_adaptive,
+ * Reuse potential), stepped together by a persistent kernel captured once in
+ * a hipGraph.  By default one launch carries the whole integration: every
+ * unfinished instance advances in lock step, one attempt per round; a round
+ * is six stage phases and one control phase separated by grid-wide
+ * barriers; in a stage phase the workgroups claim tiles (rows and planes of
+ * one instance) from eight per-XCD queues, their own XCD's first, so every
+ * phase is balanced dynamically; finished instances skip their tiles, and
+ * the launch ends when every instance is done.  Every instance's arithmetic
+ * and step decisions are those of the single-grid path, so results are
+ * bitwise those of running the instance alone. */
 
 /* Creates an ensemble context: instance i has grid edge edges[i] (1..1024) and
  * params[5*i .. 5*i+4] = {Du, Dv, F, k, L}; dtype HODE_F32 or HODE_F64.  All
@@ -365,9 +379,11 @@ int hode_ensemble_read_state(hode_ctx *ctx, int i, void *dst, size_t dst_bytes, 
  * instance's tiles cover, rows padded to the 64-lane tile width). */
 int hode_ensemble_set_weights(hode_ctx *ctx, const double *w);
 
-/* Attempts per instance in the first launch and in every later one (1 ..
- * 4096; defaults 64 and 64).  Shorter launches drop finished instances'
- * tiles sooner and relaunch more often. */
+/* Split the integration into launches: at most `first` attempts per
+ * instance in the first launch and `rest` in every later one (1 .. 4096),
+ * the host relaunching with the instances still running (a resumed
+ * instance keeps its first-same-as-last stage, so results are unchanged).
+ * Both 0 (the default): one launch for the whole integration. */
 int hode_ensemble_set_epoch(hode_ctx *ctx, int first, int rest);
 
 /* Polls a grid barrier of the persistent ensemble kernel makes before it
@@ -388,6 +404,12 @@ int hode_ensemble_timing(hode_ctx *ctx, double *kernel_ms, int *launches);
  * pack one row per segment of a wavefront (the default for such grids). */
 int hode_ensemble_set_vector_width(hode_ctx *ctx, int i, int vw);
 
+/* Planes per tile of instance i's tiles (>= 1; 0, the default: sized so a
+ * phase has about half a tile per workgroup), and the tile of instance i:
+ * vector width and planes per tile. */
+int hode_ensemble_set_plane_chunk(hode_ctx *ctx, int i, int zc);
+int hode_ensemble_get_tile(const hode_ctx *ctx, int i, int *vw, int *zc);
+
 /* Per-instance attempt traces, HODE_TRACE_W doubles per attempt with the
  * fields of hode_set_trace; capacity is per instance.  read_trace copies up
  * to cap records (cap * HODE_TRACE_W doubles) of instance i to host dst and
@@ -395,12 +417,19 @@ int hode_ensemble_set_vector_width(hode_ctx *ctx, int i, int vw);
 int hode_ensemble_set_trace(hode_ctx *ctx, int64_t capacity);
 int hode_ensemble_read_trace(hode_ctx *ctx, int i, double *dst, int64_t cap, int64_t *n);
 
-/* Tile autotuner of the ensemble: for every distinct grid edge, times one
- * Dopri5 attempt (reps repetitions) of one of its instances for each vector
- * width (cells per lane) and keeps the fastest (grids with segmented rows keep
- * 16-byte lanes and are only timed); the work estimates become
- * the measured attempt times.  vw_out/ms_out (n entries each, may be
- * NULL) receive the choice and the attempt time per instance. */
+/* Tile autotuner of the ensemble: for every distinct grid edge, times the
+ * persistent kernel itself on a sub-ensemble of that edge's instances (up to
+ * 64, started from their current states in a context of its own; this
+ * ensemble is unchanged) for `reps` attempts per candidate: every vector
+ * width the edge allows (grids with segmented rows keep 16-byte lanes) times
+ * planes per tile 4, 8, 16, 32 and N.  The fastest per cell-attempt is kept
+ * for the edge's instances and the measured time per attempt becomes their
+ * work estimate.  With the environment variable HODE_TUNE_CACHE naming a
+ * text file, choices recorded there for this architecture, precision, edge
+ * and grid size are used without timing, and new ones are appended (one
+ * line per edge: "hode-ens-tune-v1 <arch> <dtype> <N> <workgroups> <vw>
+ * <planes> <ms>").  vw_out/ms_out (n entries each, may be NULL) receive the
+ * vector width and the time per attempt of each instance. */
 int hode_ensemble_autotune(hode_ctx *ctx, int reps, int *vw_out, double *ms_out);
 
 /* Integrates every instance from t0 to t1 (first trial step dt0, at most
@@ -419,22 +448,25 @@ int hode_ensemble_integrate_adaptive(hode_ctx *ctx, double t0, double t1, double
  * the calls return after it synchronised.  Arithmetic: bf16 weights, inputs
  * and first-layer activations, fp32 accumulation on the matrix cores, as in
  * the controller's own evaluation.
- *   X: B x 16 features (fp32, row-major); T: B targets; Wt: B sample weights;
+ *   X: rows of 16 features (fp32, row-major); T: one target per row; Wt:
+ *   one sample weight per row; idx: B row indices (int64, each a valid row
+ *   of X, T and Wt) giving minibatch sample b = row idx[b], or NULL for
+ *   rows 0 .. B-1 (the kernels gather the rows as they load them);
  *   Wb: bf16 bits of the parameters; Wm: fp32 master parameters;
  *   grad, m, v: 5313 fp32 each; acc: 2 doubles of scratch. */
 int hode_mlp_forward(const uint16_t *Wb, const float *X, float *Y, int64_t B, void *stream);
 /* Wb = bf16 rounding (to nearest, ties to even) of Wm. */
 int hode_mlp_quantize(const float *Wm, uint16_t *Wb, void *stream);
-/* grad = d/dparams of sum_b Wt_b (y_b - T_b)^2 / sum_b Wt_b (B >= 1);
- * *loss_out (may be NULL) receives the loss. */
-int hode_mlp_loss_grad(const uint16_t *Wb, const float *X, const float *T, const float *Wt, int64_t B, float *grad,
-                       double *acc, double *loss_out, void *stream);
+/* grad = d/dparams of sum_b Wt_b (y_b - T_b)^2 / sum_b Wt_b over the B
+ * minibatch samples (B >= 1); *loss_out (may be NULL) receives the loss. */
+int hode_mlp_loss_grad(const uint16_t *Wb, const float *X, const float *T, const float *Wt, const int64_t *idx,
+                       int64_t B, float *grad, double *acc, double *loss_out, void *stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step >= 1, learning rate
- * lr) on Wm from the gradient at Wb; refreshes Wb; *loss_out receives the
- * loss before the step. */
-int hode_mlp_train_step(const float *X, const float *T, const float *Wt, int64_t B, float *Wm, uint16_t *Wb,
-                        float *m, float *v, float *grad, double *acc, int64_t step, float lr, double *loss_out,
-                        void *stream);
+ * lr) on Wm from the gradient at Wb over the minibatch; refreshes Wb;
+ * *loss_out receives the loss before the step. */
+int hode_mlp_train_step(const float *X, const float *T, const float *Wt, const int64_t *idx, int64_t B, float *Wm,
+                        uint16_t *Wb, float *m, float *v, float *grad, double *acc, int64_t step, float lr,
+                        double *loss_out, void *stream);
 
 /* Text of the last error on this context (valid until the next call on it;
  * owned by the context). */

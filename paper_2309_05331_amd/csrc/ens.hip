@@ -11,8 +11,9 @@ namespace {
 
 // ---- the persistent ensemble kernel -------------------------------------------
 // One launch steps every unfinished instance for up to `rounds` attempts in
-// lock step: each round runs the six stage phases of a Dopri5 attempt and a
-// control phase, with a grid-wide barrier after each.  A stage phase is a
+// lock step (by default the whole integration: the launch ends when every
+// instance is done): each round runs the six stage phases of a Dopri5
+// attempt and a control phase, with a grid-wide barrier after each.  A stage phase is a
 // pool of tiles (instance, rows, planes) covering every instance; the host
 // deals the instances to eight queues, one per XCD, and a workgroup claims
 // tiles from its own XCD's queue first (neighbouring tiles, whose halo rows
@@ -22,21 +23,25 @@ namespace {
 // the launch's pause point, skip their tiles and control; the host then
 // relaunches with the instances still running, and a resumed instance skips
 // stage 1 (its k1 is in the first-same-as-last slot), so pausing changes no
-// result.  The grid barrier is an arrival counter with device-scope
+// result.  The grid barrier is a 64-bit arrival counter with device-scope
 // release/acquire; the grid is sized from the occupancy so every workgroup
 // is resident at once, and a barrier that waits longer than spin_limit polls
-// flags an error on which every workgroup leaves.
+// flags an error on which every workgroup leaves.  The claim counters of the
+// stage phases and the per-round count of running instances come in two
+// alternating sets, each cleared by workgroup 0 once every workgroup has
+// passed a barrier after its last use, so a launch of any length needs no
+// further bookkeeping memory.
 
 __device__ inline bool ens_error(const EnsSched& s) {
   return __hip_atomic_load(s.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-__device__ inline void grid_sync(const EnsSched& s, uint32_t& gen) {
+__device__ inline void grid_sync(const EnsSched& s, uint64_t& gen) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();  // release this workgroup's outputs
-    atomicAdd(s.bar, 1u);
-    const uint32_t target = (gen + 1) * gridDim.x;
+    atomicAdd((unsigned long long*)s.bar, 1ull);
+    const uint64_t target = (gen + 1) * (uint64_t)gridDim.x;
     int64_t spins = 0;
     while (__hip_atomic_load(s.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(2);
@@ -134,16 +139,27 @@ __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst,
   __shared__ int s_claim, s_run;
   const EnsParams prm = *s.params;
   const int xcd = blockIdx.x & 7;  // workgroups are dealt round-robin to the 8 XCDs
-  uint32_t gen = 0;
+  uint64_t gen = 0;
   int phase = 0;
 
   // one stage phase over every queue's tiles; false once an error is flagged
-  auto stage_phase = [&](auto kind) -> bool {
+  auto stage_phase = [&](auto kind, int round) -> bool {
     constexpr int K = decltype(kind)::value;
+    if (blockIdx.x == 0 && threadIdx.x < 8) {
+      // the other set of claim counters was last used by the previous phase,
+      // which every workgroup has left (barrier): clear it for the next
+      __hip_atomic_store(s.qctr + ((phase + 1) & 1) * 8 + threadIdx.x, 0u, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      // the other round's count of running instances was last read right
+      // after the barrier that ended that round, before this round's first
+      // phase: clear it from the second phase of this round on
+      if (K == K_D3 && threadIdx.x == 0)
+        __hip_atomic_store(s.live + ((round + 1) & 1), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     for (int q = 0; q < 8; ++q) {
       const int x = (xcd + q) & 7;
       const int base = s.qoff[x], cnt = s.qoff[x + 1] - base;
-      uint32_t* ctr = s.qctr + phase * 8 + x;
+      uint32_t* ctr = s.qctr + (phase & 1) * 8 + x;
       for (;;) {
         if (threadIdx.x == 0) {
           int t = cnt;
@@ -171,14 +187,14 @@ __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst,
     return !ens_error(s);
   };
 
-  if (prm.first_d1 && !stage_phase(std::integral_constant<int, K_D1>())) return;
+  if (prm.first_d1 && !stage_phase(std::integral_constant<int, K_D1>(), 0)) return;
   for (int r = 0; r < prm.rounds; ++r) {
-    if (!stage_phase(std::integral_constant<int, K_D2>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D3>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D4>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D5>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D6>())) return;
-    if (!stage_phase(std::integral_constant<int, K_D7>())) return;
+    if (!stage_phase(std::integral_constant<int, K_D2>(), r)) return;
+    if (!stage_phase(std::integral_constant<int, K_D3>(), r)) return;
+    if (!stage_phase(std::integral_constant<int, K_D4>(), r)) return;
+    if (!stage_phase(std::integral_constant<int, K_D5>(), r)) return;
+    if (!stage_phase(std::integral_constant<int, K_D6>(), r)) return;
+    if (!stage_phase(std::integral_constant<int, K_D7>(), r)) return;
     // control phase: the members' error maxima are device-scope atomics made
     // before the barrier above; the controller reads them with an atomic
     for (int i = blockIdx.x; i < prm.n_inst; i += gridDim.x) {
@@ -189,13 +205,13 @@ __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst,
       __syncthreads();
       if (run) {
         ctrl_step(&I->ctrl);
-        if (threadIdx.x == 0 && ens_running(I)) atomicAdd(&s.live[r], 1u);
+        if (threadIdx.x == 0 && ens_running(I)) atomicAdd(&s.live[r & 1], 1u);
       }
     }
     grid_sync(s, gen);
     if (ens_error(s)) return;
     // every instance finished or paused: leave early (uniform: all read after the barrier)
-    if (__hip_atomic_load(&s.live[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+    if (__hip_atomic_load(&s.live[r & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
   }
 }
 

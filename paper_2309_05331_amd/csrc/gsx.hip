@@ -17,26 +17,9 @@ namespace {
 
 template <typename T, int RY, int VW>
 hipError_t launch_t(int kind, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
-  constexpr int TX = 64 * VW;
-  const int nx = (a.N + TX - 1) / TX;
-  const int ny = (a.N + 4 * RY - 1) / (4 * RY);
-  const int nz = (a.N + a.zc - 1) / a.zc;
-  const int64_t nb = (int64_t)nx * ny * nz;
-  const int64_t grid = (nb + 7) / 8 * 8;  // whole rounds of the XCD remap
-  if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  switch (kind) {
-#define HODE_CASE(K) \
-  case K: gs_stage<T, K, RY, VW><<<dim3((unsigned)grid), dim3(256), 0, s>>>(a, c); break;
-    HODE_CASE(K_F1) HODE_CASE(K_F2) HODE_CASE(K_F3) HODE_CASE(K_F4) HODE_CASE(K_F5) HODE_CASE(K_F6)
-    HODE_CASE(K_F7) HODE_CASE(K_F8) HODE_CASE(K_F9) HODE_CASE(K_F10) HODE_CASE(K_F11) HODE_CASE(K_F12)
-    HODE_CASE(K_F13) HODE_CASE(K_F13F) HODE_CASE(K_AB1) HODE_CASE(K_AB2) HODE_CASE(K_AB3) HODE_CASE(K_AB4)
-    HODE_CASE(K_AB5) HODE_CASE(K_AB6) HODE_CASE(K_AB7) HODE_CASE(K_AB8) HODE_CASE(K_D6K) HODE_CASE(K_ABC1)
-    HODE_CASE(K_ABC2) HODE_CASE(K_ABC3) HODE_CASE(K_ABC4) HODE_CASE(K_ABC5) HODE_CASE(K_ABC6) HODE_CASE(K_ABC7)
-    HODE_CASE(K_ABC8) HODE_CASE(K_MM1) HODE_CASE(K_MM2) HODE_CASE(K_MM3)
-#undef HODE_CASE
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return launch_stage_t<T, RY, VW, 4, K_F1, K_F2, K_F3, K_F4, K_F5, K_F6, K_F7, K_F8, K_F9, K_F10, K_F11, K_F12,
+                        K_F13, K_F13F, K_AB1, K_AB2, K_AB3, K_AB4, K_AB5, K_AB6, K_AB7, K_AB8, K_D6K, K_ABC1,
+                        K_ABC2, K_ABC3, K_ABC4, K_ABC5, K_ABC6, K_ABC7, K_ABC8, K_MM1, K_MM2, K_MM3>(kind, a, c, s);
 }
 
 template <typename T, int VW>

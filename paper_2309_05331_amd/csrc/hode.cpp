@@ -35,12 +35,13 @@ struct Ensemble {
   std::vector<double> prm;  // n x {Du, Dv, F, k, L}
   std::vector<hode::EnsInst> inst;
   std::vector<int> parity, vw;
+  std::vector<int> zc;         // planes per tile of each instance (0: sized from the launch's cell count)
   std::vector<double> weight;  // per-attempt work estimates (dealing instances to queues)
   std::vector<int64_t> attempts_last;
   hipEvent_t ev[2] = {nullptr, nullptr};
   double kernel_ms_last = 0;  // summed launch durations of the last integration
   int launches_last = 0;
-  int epoch_first = 64, epoch_len = 64;  // attempts per instance per launch
+  int epoch_first = 0, epoch_len = 0;  // attempts per instance per launch (0: the whole integration)
   int64_t barrier_polls = (int64_t)1 << 30;  // polls before a grid barrier gives up
   void* pool = nullptr;
   hode::EnsInst* d_inst = nullptr;
@@ -48,7 +49,6 @@ struct Ensemble {
   size_t tiles_cap = 0;
   // one device block: qoff[9] | params | bar | error | live[max_rounds] | qctr[8 (1 + 6 max_rounds)]
   void* d_sync = nullptr;
-  int sync_rounds = 0;
   int nwg = 0;
   double* d_trace = nullptr;
   int64_t trace_cap = 0;
@@ -78,6 +78,8 @@ struct hode_ctx {
   double atol = 1e-6, rtol = 1e-6;
   int ry = 0, zc = 0, ew_grid = 0, vw = 0;  // ry, zc: the tile of the widest stage kind
   int kry[hode::K_ALL] = {0}, kzc[hode::K_ALL] = {0};  // tile of every stage kind
+  int knw[hode::K_ALL] = {0};  // wavefronts per workgroup of every stage kind (0: 4)
+  int nw = 4;                  // requested wavefronts per workgroup (hode_set_tile_waves)
   // extra arrays (Fehlberg 7(8) stages k1 .. k12 on the Gray-Scott path, the
   // Adams-Bashforth ring of past right-hand sides), allocated on first use,
   // and their device table
@@ -161,15 +163,19 @@ hode::GSLaunch gs_args(const hode_ctx* c) {
 // One stage kernel of `kind` with that kind's tile.
 hipError_t launch_stage(const hode_ctx* c, int kind, hode::GSLaunch a) {
   a.zc = c->kzc[kind];
-  return hode::launch_gs(kind, c->dtype, c->kry[kind], c->vw, a, c->d_ctrl, c->stream);
+  return hode::launch_gs(kind, c->dtype, c->kry[kind], c->vw, c->knw[kind] ? c->knw[kind] : 4, a, c->d_ctrl,
+                         c->stream);
 }
 
-void set_all_tiles(hode_ctx* c, int ry, int zc) {
+// Sets one tile for every stage kind: ry rows per wavefront, zc planes, nw
+// wavefronts per workgroup where the kind has such tiles (else 4).
+void set_all_tiles(hode_ctx* c, int ry, int zc, int nw = 4) {
   c->ry = ry;
   c->zc = zc;
   for (int k = 0; k < hode::K_ALL; ++k) {
     c->kry[k] = ry;
     c->kzc[k] = zc;
+    c->knw[k] = hode::gs_tile_supported(k, c->dtype, ry, c->vw, nw, c->N) ? nw : 4;
   }
 }
 
@@ -568,8 +574,8 @@ void build_tiles(const Ensemble& e, int G, const std::vector<int>& active, std::
       const int N = e.N[i];
       const int rows = ens_tile_rows(e, i);
       const int ny = (N + rows - 1) / rows;
-      int zc = (int)std::lround(target / ((double)N * rows));
-      zc = std::max(4, std::min(N, zc));
+      int zc = e.zc[i] > 0 ? e.zc[i] : (int)std::lround(target / ((double)N * rows));
+      zc = std::max(e.zc[i] > 0 ? 1 : 4, std::min(N, zc));
       const int nz = (N + zc - 1) / zc;
       for (int kz = 0; kz < nz; ++kz) {
         const int z0 = (int)((int64_t)N * kz / nz), z1 = (int)((int64_t)N * (kz + 1) / nz);
@@ -707,12 +713,13 @@ int hode_init_state(hode_ctx* c, int dtype, int nfields, int ndim, const int64_t
   if (!reuse) {
     if (is_gs(c)) {
       const int ry = c->ry ? c->ry : (dtype == HODE_F32 ? 4 : 2);
-      set_all_tiles(c, ry, default_zc(N, ry));
+      set_all_tiles(c, ry, default_zc(N, ry), c->nw);
       // the Fehlberg and Adams-Bashforth kinds hold up to 10 source rows per
       // register row: one row per wavefront keeps them out of scratch
       for (int k = hode::K_F1; k < hode::K_ALL; ++k) {
         c->kry[k] = 1;
         c->kzc[k] = default_zc(N, 1);
+        c->knw[k] = 4;
       }
     } else {
       c->ew_grid = default_ew_grid(nelem, dtype);
@@ -722,6 +729,9 @@ int hode_init_state(hode_ctx* c, int dtype, int nfields, int ndim, const int64_t
 }
 
 size_t hode_state_bytes(const hode_ctx* c) { return c ? (size_t)c->nelem * c->esize : 0; }
+
+// the device code's record width is the header's
+static_assert(hode::TRACE_W == HODE_TRACE_W, "trace record width");
 
 int hode_trace_width(void) { return HODE_TRACE_W; }
 
@@ -1163,9 +1173,21 @@ int hode_set_tile(hode_ctx* c, int ry, int zc) {
     c->ew_grid = zc;
   } else {
     if (!hode::gs_ry_supported(ry) || zc < 1) return fail(c, HODE_EINVAL, "ry must be 1, 2 or 4 and zc >= 1");
-    set_all_tiles(c, ry, zc);
+    set_all_tiles(c, ry, zc, c->nw);
   }
   clear_graphs(c);
+  return HODE_OK;
+}
+
+int hode_set_tile_waves(hode_ctx* c, int nw) {
+  if (!c) return HODE_EINVAL;
+  if (nw != 4 && nw != 8) return fail(c, HODE_EINVAL, "wavefronts per workgroup must be 4 or 8");
+  c->nw = nw;
+  if (c->dtype && is_gs(c)) {
+    for (int k = 0; k < hode::K_ALL; ++k)
+      c->knw[k] = hode::gs_tile_supported(k, c->dtype, c->kry[k], c->vw, nw, c->N) ? nw : 4;
+    clear_graphs(c);
+  }
   return HODE_OK;
 }
 
@@ -1175,6 +1197,10 @@ int hode_set_vector_width(hode_ctx* c, int vw) {
   if (vw && c->dtype == HODE_F64 && vw > 2) return fail(c, HODE_EINVAL, "fp64 vector width at most 2");
   if (vw && c->N && c->N % vw) return fail(c, HODE_EINVAL, "vector width must divide N");
   c->vw = vw;
+  // eight-wavefront tiles exist for 16-byte lanes only
+  if (c->dtype && is_gs(c))
+    for (int k = 0; k < hode::K_ALL; ++k)
+      if (c->knw[k] == 8 && !hode::gs_tile_supported(k, c->dtype, c->kry[k], vw, 8, c->N)) c->knw[k] = 4;
   clear_graphs(c);
   return HODE_OK;
 }
@@ -1183,6 +1209,15 @@ int hode_get_tile(const hode_ctx* c, int* ry, int* zc) {
   if (!c || !ry || !zc) return HODE_EINVAL;
   *ry = c->ry;
   *zc = is_gs(c) ? c->zc : c->ew_grid;
+  return HODE_OK;
+}
+
+int hode_get_kind_tile(const hode_ctx* c, int kind, int* ry, int* zc, int* nw) {
+  if (!c || !ry || !zc || !nw || kind < 0 || kind >= hode::K_ALL) return HODE_EINVAL;
+  if (!c->dtype || !is_gs(c)) return HODE_ESTATE;
+  *ry = c->kry[kind];
+  *zc = c->kzc[kind];
+  *nw = c->knw[kind] ? c->knw[kind] : 4;
   return HODE_OK;
 }
 
@@ -1325,45 +1360,53 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
   int seq[16];
   const int ns = stage_seq(method, seq);
-  // every stage kind keeps its own fastest tile
+  // every stage kind keeps its own fastest tile: rows per wavefront,
+  // planes, and four or (16-byte lanes, one or two rows) eight wavefronts
   double best[16];
-  int bry[16], bzc[16];
-  for (int i = 0; i < ns; ++i) { best[i] = 1e300; bry[i] = c->kry[seq[i]]; bzc[i] = c->kzc[seq[i]]; }
-  for (int ry : rys) {
-    for (int zc : zcs) {
-      if ((zc > c->N || zc < 8) && zc != 8) continue;
-      set_all_tiles(c, ry, zc);
-      double ms[16];
-      rc = hode_profile_attempt(c, method, reps, ms);
-      if (rc) return rc;
-      for (int i = 0; i < ns; ++i)
-        if (ms[i] < best[i]) { best[i] = ms[i]; bry[i] = ry; bzc[i] = zc; }
+  int bry[16], bzc[16], bnw[16];
+  for (int i = 0; i < ns; ++i) {
+    best[i] = 1e300;
+    bry[i] = c->kry[seq[i]];
+    bzc[i] = c->kzc[seq[i]];
+    bnw[i] = c->knw[seq[i]] ? c->knw[seq[i]] : 4;
+  }
+  for (int nw : {4, 8}) {
+    for (int ry : rys) {
+      bool any = false;
+      for (int i = 0; i < ns; ++i) any = any || hode::gs_tile_supported(seq[i], c->dtype, ry, c->vw, nw, c->N);
+      if (!any) continue;
+      for (int zc : zcs) {
+        if ((zc > c->N || zc < 8) && zc != 8) continue;
+        set_all_tiles(c, ry, zc, nw);
+        double ms[16];
+        rc = hode_profile_attempt(c, method, reps, ms);
+        if (rc) return rc;
+        for (int i = 0; i < ns; ++i)
+          if (ms[i] < best[i] && c->knw[seq[i]] == nw) { best[i] = ms[i]; bry[i] = ry; bzc[i] = zc; bnw[i] = nw; }
+      }
     }
   }
   double tot = 0;
   for (int i = 0; i < ns; ++i) {
     c->kry[seq[i]] = bry[i];
     c->kzc[seq[i]] = bzc[i];
+    c->knw[seq[i]] = bnw[i];
     tot += best[i];
   }
+  auto twin = [&](int dst, int src) {
+    c->kry[dst] = c->kry[src];
+    c->kzc[dst] = c->kzc[src];
+    c->knw[dst] = c->knw[src];
+  };
   if (method == HODE_DOPRI5) {
     // kinds of the same shape outside the timed attempt: the first k1, and
     // the fixed-step variants of stages 6 and 7
-    c->kry[hode::K_D1] = c->kry[hode::K_D2];
-    c->kzc[hode::K_D1] = c->kzc[hode::K_D2];
-    c->kry[hode::K_D6F] = c->kry[hode::K_D6];
-    c->kzc[hode::K_D6F] = c->kzc[hode::K_D6];
-    c->kry[hode::K_D7F] = c->kry[hode::K_D7];
-    c->kzc[hode::K_D7F] = c->kzc[hode::K_D7];
+    twin(hode::K_D1, hode::K_D2);
+    twin(hode::K_D6F, hode::K_D6);
+    twin(hode::K_D7F, hode::K_D7);
   }
-  if (method == HODE_CASHKARP54) {
-    c->kry[hode::K_C6F] = c->kry[hode::K_C6];
-    c->kzc[hode::K_C6F] = c->kzc[hode::K_C6];
-  }
-  if (method == HODE_FEHLBERG78) {
-    c->kry[hode::K_F13F] = c->kry[hode::K_F13];
-    c->kzc[hode::K_F13F] = c->kzc[hode::K_F13];
-  }
+  if (method == HODE_CASHKARP54) twin(hode::K_C6F, hode::K_C6);
+  if (method == HODE_FEHLBERG78) twin(hode::K_F13F, hode::K_F13);
   const int widest = method == HODE_RK4           ? hode::K_R4
                      : method == HODE_CASHKARP54  ? hode::K_C6
                      : method == HODE_FEHLBERG78  ? hode::K_F13
@@ -1378,7 +1421,7 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   return HODE_OK;
 }
 
-// Cache line: "hode-tune-v1 <arch> <dtype> <method> <N> <vw> <ry:zc for every stage kind>".
+// Cache line: "hode-tune-v2 <arch> <dtype> <method> <N> <vw> <ry:zc:nw for every stage kind>".
 static std::string tune_key(const hode_ctx* c, int method) {
   hipDeviceProp_t prop;
   std::string arch = "unknown";
@@ -1388,7 +1431,7 @@ static std::string tune_key(const hode_ctx* c, int method) {
       if (ch == ' ') ch = '_';
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "hode-tune-v1 %s %d %d %d %d", arch.c_str(), c->dtype, method, c->N, c->vw);
+  std::snprintf(buf, sizeof(buf), "hode-tune-v2 %s %d %d %d %d", arch.c_str(), c->dtype, method, c->N, c->vw);
   return buf;
 }
 
@@ -1402,27 +1445,30 @@ int hode_autotune_cached(hode_ctx* c, int method, int reps, const char* cache_pa
   if (path && *path) {
     if (FILE* f = std::fopen(path, "r")) {
       // the last entry for this key wins
-      std::vector<int> ry, zc;
+      std::vector<int> ry, zc, nw;
       char line[8192];
       while (std::fgets(line, sizeof(line), f)) {
         if (std::strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
-        std::vector<int> r, z;
+        std::vector<int> r, z, w;
         const char* q = line + key.size();
-        int a, b, used;
-        while (std::sscanf(q, " %d:%d%n", &a, &b, &used) == 2) {
+        int a, b, d, used;
+        while (std::sscanf(q, " %d:%d:%d%n", &a, &b, &d, &used) == 3) {
           r.push_back(a);
           z.push_back(b);
+          w.push_back(d);
           q += used;
         }
-        if ((int)r.size() == hode::K_ALL) { ry = r; zc = z; }
+        if ((int)r.size() == hode::K_ALL) { ry = r; zc = z; nw = w; }
       }
       std::fclose(f);
       bool ok = !ry.empty();
-      for (int k = 0; ok && k < hode::K_ALL; ++k) ok = hode::gs_ry_supported(ry[k]) && zc[k] >= 1;
+      for (int k = 0; ok && k < hode::K_ALL; ++k)
+        ok = hode::gs_tile_supported(k, c->dtype, ry[k], c->vw, nw[k], c->N) && zc[k] >= 1;
       if (ok) {
         for (int k = 0; k < hode::K_ALL; ++k) {
           c->kry[k] = ry[k];
           c->kzc[k] = zc[k];
+          c->knw[k] = nw[k];
         }
         int seq[16];
         const int widest = stage_seq(method, seq) == 1 ? seq[0] : (method == HODE_RK4 ? hode::K_R4
@@ -1445,7 +1491,7 @@ int hode_autotune_cached(hode_ctx* c, int method, int reps, const char* cache_pa
     std::string line = key;
     char buf[32];
     for (int k = 0; k < hode::K_ALL; ++k) {
-      std::snprintf(buf, sizeof(buf), " %d:%d", c->kry[k], c->kzc[k]);
+      std::snprintf(buf, sizeof(buf), " %d:%d:%d", c->kry[k], c->kzc[k], c->knw[k] ? c->knw[k] : 4);
       line += buf;
     }
     line += "\n";
@@ -1496,6 +1542,7 @@ int hode_ensemble_create(hode_ctx** out, int device, void* stream, int n, const 
   e->prm.assign(params, params + 5 * n);
   e->parity.assign(n, 0);
   e->vw.assign(n, 0);
+  e->zc.assign(n, 0);
   e->attempts_last.assign(n, 0);
   e->weight.resize(n);
   e->inst.resize(n);
@@ -1613,6 +1660,21 @@ int hode_ensemble_set_vector_width(hode_ctx* c, int i, int vw) {
   return HODE_OK;
 }
 
+int hode_ensemble_set_plane_chunk(hode_ctx* c, int i, int zc) {
+  int rc = ens_check(c, i);
+  if (rc) return rc;
+  if (zc < 0) return fail(c, HODE_EINVAL, "plane chunk must be >= 0");
+  c->ens->zc[i] = zc;
+  return HODE_OK;
+}
+
+int hode_ensemble_get_tile(const hode_ctx* c, int i, int* vw, int* zc) {
+  if (!c || !c->ens || i < 0 || i >= c->ens->n || !vw || !zc) return HODE_EINVAL;
+  *vw = c->ens->vw[i];
+  *zc = c->ens->zc[i];
+  return HODE_OK;
+}
+
 int hode_ensemble_set_trace(hode_ctx* c, int64_t capacity) {
   int rc = ens_check(c, 0);
   if (rc) return rc;
@@ -1646,8 +1708,9 @@ int hode_ensemble_read_trace(hode_ctx* c, int i, double* dst, int64_t cap, int64
 int hode_ensemble_set_epoch(hode_ctx* c, int first, int rest) {
   int rc = ens_check(c, 0);
   if (rc) return rc;
-  if (first < 1 || rest < 1 || first > 4096 || rest > 4096)
-    return fail(c, HODE_EINVAL, "attempts per launch must be in 1 .. 4096");
+  const bool whole = first == 0 && rest == 0;
+  if (!whole && (first < 1 || rest < 1 || first > 4096 || rest > 4096))
+    return fail(c, HODE_EINVAL, "attempts per launch must be in 1 .. 4096 (or both 0)");
   c->ens->epoch_first = first;
   c->ens->epoch_len = rest;
   return HODE_OK;
@@ -1676,17 +1739,11 @@ int hode_ensemble_timing(hode_ctx* c, double* kernel_ms, int* launches) {
 }
 
 // Device block of the launch bookkeeping, sized for `rounds` rounds.
+// The ensemble's bookkeeping block: queue offsets, launch parameters, then
+// (cleared before every launch) the barrier counter, the error flag, the two
+// running-instance counts and the two sets of claim counters.
 struct SyncLayout {
-  size_t qoff, params, bar, error, live, qctr, bytes;
-  explicit SyncLayout(int rounds) {
-    qoff = 0;
-    params = 64;
-    bar = params + sizeof(hode::EnsParams);
-    error = bar + 4;
-    live = error + 4;
-    qctr = live + 4 * (size_t)rounds;
-    bytes = qctr + 4 * 8 * (1 + 6 * (size_t)rounds);
-  }
+  size_t qoff = 0, params = 64, bar = 128, error = 136, live = 140, qctr = 148, bytes = 148 + 4 * 16;
 };
 
 int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double dt0, int64_t max_steps,
@@ -1719,16 +1776,12 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     I.k1_valid = 0;
   }
   // bookkeeping block and tile buffer (the captured graph holds their addresses)
-  const int max_rounds = std::max(e->epoch_first, e->epoch_len);
-  if (!e->d_sync || e->sync_rounds < max_rounds) {
-    if (e->graph) { (void)hipGraphExecDestroy(e->graph); e->graph = nullptr; }
-    if (e->d_sync) (void)hipFree(e->d_sync);
-    e->d_sync = nullptr;
-    if (hipMalloc(&e->d_sync, SyncLayout(max_rounds).bytes) != hipSuccess)
+  const SyncLayout L;
+  static_assert(sizeof(hode::EnsParams) <= 64, "launch parameters fit their slot");
+  if (!e->d_sync) {
+    if (hipMalloc(&e->d_sync, L.bytes) != hipSuccess)
       return fail(c, HODE_ENOMEM, "ensemble bookkeeping allocation failed");
-    e->sync_rounds = max_rounds;
   }
-  const SyncLayout L(e->sync_rounds);
   char* sb = (char*)e->d_sync;
   e->kernel_ms_last = 0;
   e->launches_last = 0;
@@ -1740,7 +1793,10 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     for (int i = 0; i < e->n; ++i)
       if (!e->inst[i].ctrl.done) active.push_back(i);
     if (active.empty()) break;
-    const int rounds = launch == 0 ? e->epoch_first : e->epoch_len;
+    // one launch for the whole integration (every instance is done after at
+    // most max_steps rounds), unless epochs were set
+    const int64_t ep = launch == 0 ? e->epoch_first : e->epoch_len;
+    const int rounds = (int)std::min<int64_t>(ep > 0 ? ep : max_steps, 0x7fffffff);
     build_tiles(*e, e->nwg, active, tiles, qoff);
     if (tiles.size() > e->tiles_cap) {
       if (e->graph) { (void)hipGraphExecDestroy(e->graph); e->graph = nullptr; }
@@ -1769,7 +1825,7 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
       hode::EnsSched sch{e->d_tiles,
                          (const int32_t*)(sb + L.qoff),
                          (uint32_t*)(sb + L.qctr),
-                         (uint32_t*)(sb + L.bar),
+                         (uint64_t*)(sb + L.bar),
                          (uint32_t*)(sb + L.live),
                          (uint32_t*)(sb + L.error),
                          (const hode::EnsParams*)(sb + L.params),
@@ -1828,52 +1884,118 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
   return worst;
 }
 
+// Ensemble tile autotuner: for every distinct grid edge, the persistent
+// kernel itself is timed on a sub-ensemble of that edge's instances (up to
+// 64, started from their current states in a context of their own, so the
+// ensemble is left unchanged) for `reps` attempts per candidate: every
+// vector width the edge allows (segmented edges keep 16-byte lanes) times
+// planes per tile of 4, 8, 16, 32 and the whole edge.  The fastest per
+// cell-attempt is kept for every instance of the edge, and the measured time
+// per attempt of one instance becomes its work estimate.  With a cache file
+// (HODE_TUNE_CACHE) the choices of earlier runs on this architecture and
+// precision are read instead of timed, and new ones appended.
+static std::string ens_tune_key(const hode_ctx* c, int N) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    for (char& ch : arch)
+      if (ch == ' ') ch = '_';
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "hode-ens-tune-v1 %s %d %d %d", arch.c_str(), c->dtype, N, c->ens->nwg);
+  return buf;
+}
+
 int hode_ensemble_autotune(hode_ctx* c, int reps, int* vw_out, double* ms_out) {
   int rc = ens_check(c, 0);
   if (rc) return rc;
   if (reps < 1) return fail(c, HODE_EINVAL, "reps >= 1");
   Ensemble* e = c->ens;
-  std::map<int, int> first;  // edge -> first instance with it
-  for (int i = 0; i < e->n; ++i) first.emplace(e->N[i], i);
-  std::map<int, std::pair<int, double>> best;  // edge -> (vw, ms per attempt)
-  for (auto& kv : first) {
-    const int N = kv.first, i = kv.second;
+  const char* path = std::getenv("HODE_TUNE_CACHE");
+  std::map<int, std::vector<int>> members;  // edge -> instances with it
+  for (int i = 0; i < e->n; ++i) members[e->N[i]].push_back(i);
+  struct Choice { int vw, zc; double ms; };
+  std::map<int, Choice> best;
+  if (path && *path) {
+    if (FILE* f = std::fopen(path, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof(line), f)) {
+        for (auto& kv : members) {
+          const std::string key = ens_tune_key(c, kv.first);
+          if (std::strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
+          Choice ch{};
+          if (std::sscanf(line + key.size(), " %d %d %lf", &ch.vw, &ch.zc, &ch.ms) == 3 && ch.vw >= 1 && ch.zc >= 1 &&
+              kv.first % ch.vw == 0)
+            best[kv.first] = ch;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  const int maxvw = c->dtype == HODE_F32 ? 4 : 2;
+  for (auto& kv : members) {
+    const int N = kv.first;
+    if (best.count(N)) continue;
+    std::vector<int> sub(kv.second.begin(), kv.second.begin() + std::min<size_t>(kv.second.size(), 64));
+    const int m = (int)sub.size();
+    std::vector<int64_t> edges(m, N);
+    std::vector<double> prm(5 * (size_t)m);
+    for (int j = 0; j < m; ++j)
+      for (int q = 0; q < 5; ++q) prm[5 * j + q] = e->prm[5 * (size_t)sub[j] + q];
     hode_ctx* t = nullptr;
-    rc = hode_create(&t, c->device, nullptr);
-    if (rc) return fail(c, rc, "autotune: context");
-    const int64_t shape[3] = {N, N, N};
-    rc = hode_set_rhs(t, HODE_RHS_GRAYSCOTT3D, &e->prm[5 * i], 5);
-    if (!rc) rc = hode_init_state(t, c->dtype, 2, 3, shape, e->inst[i].a.y[e->parity[i]], 1);
-    double bms = 1e300;
-    int bvw = e->vw[i];
-    const int maxvw = c->dtype == HODE_F32 ? 4 : 2;
-    // rows short enough for segmented 16-byte lanes keep them (the
-    // single-grid path the timing runs on has no segmented tiles)
-    const bool seg = ens_seg_for(c->dtype, N, maxvw) > 1;
-    for (int vw = seg ? maxvw : 1; vw <= maxvw && !rc; vw *= 2) {
-      if (N % vw) continue;
-      rc = hode_set_vector_width(t, vw);
-      // the ensemble's tiles: 16 bytes of state per lane and field per row set
-      if (!rc) rc = hode_set_tile(t, (int)(16 / c->esize) / vw, N);
-      double ms[8];
-      if (!rc) rc = hode_profile_attempt(t, HODE_DOPRI5, reps, ms);
+    rc = hode_ensemble_create(&t, c->device, nullptr, m, edges.data(), prm.data(), c->dtype);
+    if (rc) return fail(c, rc, "ensemble autotune: context");
+    rc = hode_set_tolerances(t, c->atol, c->rtol);
+    std::vector<int> vws;
+    if (ens_seg_for(c->dtype, N, maxvw) > 1) vws.push_back(maxvw);
+    else
+      for (int v = 1; v <= maxvw; v *= 2)
+        if (N % v == 0) vws.push_back(v);
+    std::vector<int> zcs;
+    for (int z : {4, 8, 16, 32, N})
+      if (z <= N && std::find(zcs.begin(), zcs.end(), z) == zcs.end()) zcs.push_back(z);
+    Choice bc{e->vw[sub[0]], 0, 1e300};
+    std::vector<hode_stats> st(m);
+    for (int v : vws) {
+      for (int z : zcs) {
+        for (int j = 0; j < m && !rc; ++j) {
+          rc = hode_ensemble_init_state(t, j, e->inst[sub[j]].a.y[e->parity[sub[j]]], 1);
+          if (!rc) rc = hode_ensemble_set_vector_width(t, j, v);
+          if (!rc) rc = hode_ensemble_set_plane_chunk(t, j, z);
+        }
+        if (!rc) {
+          const int r2 = hode_ensemble_integrate_adaptive(t, 0.0, 1e300, 0.1, reps, st.data());
+          if (r2 != HODE_OK && r2 != HODE_EMAXSTEPS) rc = r2;
+        }
+        if (rc) break;
+        double att = 0;
+        for (int j = 0; j < m; ++j) att += (double)(st[j].accepted + st[j].rejected);
+        const double ms = t->ens->kernel_ms_last / std::max(att, 1.0);  // per attempt of one instance
+        if (ms < bc.ms) bc = Choice{v, z, ms};
+      }
       if (rc) break;
-      double tot = 0;
-      for (int k = 0; k < 6; ++k) tot += ms[k];
-      if (tot < bms) { bms = tot; bvw = vw; }
     }
     const std::string msg = rc ? hode_last_error(t) : "";
     hode_destroy(t);
-    if (rc) return fail(c, rc, "autotune: " + msg);
-    best[N] = {bvw, bms};
+    if (rc) return fail(c, rc, "ensemble autotune: " + msg);
+    best[N] = bc;
+    if (path && *path) {
+      FILE* f = std::fopen(path, "a");
+      if (!f) return fail(c, HODE_EINVAL, std::string("cannot append to the tuning cache ") + path);
+      const std::string line = ens_tune_key(c, N);
+      const bool w = std::fprintf(f, "%s %d %d %.6g\n", line.c_str(), bc.vw, bc.zc, bc.ms) > 0;
+      const bool cl = std::fclose(f) == 0;
+      if (!w || !cl) return fail(c, HODE_EINVAL, std::string("cannot write the tuning cache ") + path);
+    }
   }
   for (int i = 0; i < e->n; ++i) {
-    const auto& b = best[e->N[i]];
-    e->vw[i] = b.first;
-    // work weight: measured attempt time x attempts growing mildly with N
-    e->weight[i] = b.second;
-    if (vw_out) vw_out[i] = b.first;
-    if (ms_out) ms_out[i] = b.second;
+    const Choice& b = best[e->N[i]];
+    e->vw[i] = b.vw;
+    e->zc[i] = b.zc;
+    e->weight[i] = b.ms;
+    if (vw_out) vw_out[i] = b.vw;
+    if (ms_out) ms_out[i] = b.ms;
   }
   return HODE_OK;
 }

@@ -16,8 +16,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "hode.h"
-
 namespace hode {
 
 enum Mode : int32_t {
@@ -52,8 +50,7 @@ enum Status : int32_t {
   ST_ENONFINITE = -7,
 };
 
-constexpr int TRACE_W = HODE_TRACE_W;  // doubles per trace record (8 scalars + 16 controller features)
-static_assert(TRACE_W == 8 + 16, "trace record: 8 scalars and the 16 controller features");
+constexpr int TRACE_W = 24;  // doubles per trace record (8 scalars + 16 controller features)
 constexpr int HIST = 4;     // attempts of history kept for the learned controller
 constexpr int MLP_IN = 16, MLP_H = 64;
 // packed bf16 weights: W1[64][16] b1[64] W2[64][64] b2[64] w3[64] b3[1]

@@ -55,17 +55,20 @@ struct GSLaunch {
   double Du_h2, Dv_h2, F, kk;
 };
 
-// ry: rows per wavefront strip (tile = 64*vw x 4*ry cells); vw: cells per
+// ry: rows per wavefront strip (tile = 64*vw x nw*ry cells); vw: cells per
 // lane (1, 2 or 4 for fp32, 1 or 2 for fp64, dividing N; 0 picks the widest).
 // The device table of the extra arrays (null if none), kept in the unused
 // stage slot k[0] so the layout of the launch arguments stays that of the
 // other kinds.
 __host__ __device__ inline void* const* xk(const GSLaunch& a) { return (void* const*)a.k[0]; }
 
-hipError_t launch_gs(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s);
-// The Fehlberg and Adams-Bashforth kinds (K_F1 .. K_AB8), same arguments.
+// nw: wavefronts per workgroup (tile = 64*vw x nw*ry cells): 4, or 8 for the
+// kinds of gs.hip with ry <= 2 and 16-byte lanes (gs_tile_supported).
+hipError_t launch_gs(int kind, int dtype, int ry, int vw, int nw, const GSLaunch& a, DevCtrl* c, hipStream_t s);
+// The Fehlberg and Adams-Bashforth kinds (K_F1 .. K_AB8), four wavefronts.
 hipError_t launch_gsx(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s);
 bool gs_ry_supported(int ry);
+bool gs_tile_supported(int kind, int dtype, int ry, int vw, int nw, int N);
 
 // Element-wise families: the whole step runs in registers (one kernel per
 // attempt).  mode: one of the Mode values (RK4, Dopri5 or Cash-Karp; fixed or adaptive).
@@ -127,9 +130,9 @@ struct EnsParams {
 struct EnsSched {
   const EnsTile* tiles;     // tiles, grouped in eight queues (one per XCD)
   const int32_t* qoff;      // queue x holds tiles[qoff[x] .. qoff[x+1])
-  uint32_t* qctr;           // claim counters, 8 per tile phase (zero at launch)
-  uint32_t* bar;            // grid barrier arrivals (zero at launch)
-  uint32_t* live;           // per round: instances still running after it (zero at launch)
+  uint32_t* qctr;           // claim counters: two alternating sets of 8 (zero at launch)
+  uint64_t* bar;            // grid barrier arrivals (zero at launch)
+  uint32_t* live;           // instances still running after a round: two alternating (zero at launch)
   uint32_t* error;          // set when a barrier waited past spin_limit
   const EnsParams* params;
   int64_t spin_limit;

@@ -12,7 +12,9 @@
 //
 // Loss: weighted mean squared error sum_b w_b (y_b - t_b)^2 / sum_b w_b; the
 // gradient is accumulated over workgroups with fp32 atomics.  Adam keeps fp32
-// master weights and refreshes their bf16 copy.
+// master weights and refreshes their bf16 copy.  Sample b of a minibatch is
+// row idx[b] of the data set (row b without an index array), so a shuffled
+// minibatch is gathered by the kernels as they load it.
 #include <hip/hip_runtime.h>
 
 #include "../../include/hode.h"
@@ -60,14 +62,17 @@ struct Smem {
   float y[64], dy[64], wt[64], tg[64];
 };
 
+// Data-set row of minibatch sample b.
+__device__ inline int64_t row_of(const int64_t* __restrict__ idx, int64_t b) { return idx ? idx[b] : b; }
+
 // Forward pass of one 64-sample tile; leaves h2 of this wave's rows in
 // `h2` (D layout, 4 column tiles) and y in s.y.  Rows >= B read zeros.
-__device__ void forward_tile(Smem& s, const uint16_t* __restrict__ Wb, const float* __restrict__ X, int64_t b0,
-                             int64_t B, f32x4 (&h2)[4]) {
+__device__ void forward_tile(Smem& s, const uint16_t* __restrict__ Wb, const float* __restrict__ X,
+                             const int64_t* __restrict__ idx, int64_t b0, int64_t B, f32x4 (&h2)[4]) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   for (int e = t; e < 64 * NI; e += 256) {
     const int r = e / NI, k = e % NI;
-    const float x = (b0 + r < B) ? X[(b0 + r) * NI + k] : 0.f;
+    const float x = (b0 + r < B) ? X[row_of(idx, b0 + r) * NI + k] : 0.f;
     const uint16_t q = to_bf16(x);
     s.Xq[r][k] = q;
     s.XqT[k][r] = q;
@@ -134,14 +139,16 @@ __global__ __launch_bounds__(256) void mlp_forward_k(const uint16_t* __restrict_
   __shared__ Smem s;
   const int64_t b0 = (int64_t)blockIdx.x * 64;
   f32x4 h2[4];
-  forward_tile(s, Wb, X, b0, B, h2);
+  forward_tile(s, Wb, X, nullptr, b0, B, h2);
   const int t = threadIdx.x;
   if (t < 64 && b0 + t < B) Y[b0 + t] = s.y[t];
 }
 
-__global__ __launch_bounds__(256) void mlp_wsum_k(const float* __restrict__ Wt, int64_t B, double* __restrict__ acc) {
+__global__ __launch_bounds__(256) void mlp_wsum_k(const float* __restrict__ Wt, const int64_t* __restrict__ idx,
+                                                  int64_t B, double* __restrict__ acc) {
   double v = 0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < B; i += (int64_t)gridDim.x * 256) v += Wt[i];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < B; i += (int64_t)gridDim.x * 256)
+    v += Wt[row_of(idx, i)];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   if ((threadIdx.x & 63) == 0) atomicAdd(acc, v);
@@ -150,17 +157,19 @@ __global__ __launch_bounds__(256) void mlp_wsum_k(const float* __restrict__ Wt, 
 // acc[0] = sum of weights (input), acc[1] += loss
 __global__ __launch_bounds__(256) void mlp_grad_k(const uint16_t* __restrict__ Wb, const float* __restrict__ X,
                                                   const float* __restrict__ T, const float* __restrict__ Wt,
-                                                  int64_t B, float* __restrict__ grad, double* __restrict__ acc) {
+                                                  const int64_t* __restrict__ idx, int64_t B,
+                                                  float* __restrict__ grad, double* __restrict__ acc) {
   __shared__ Smem s;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int li = lane & 15, lk = 4 * (lane >> 4);
   const int64_t b0 = (int64_t)blockIdx.x * 64;
   f32x4 h2[4];
-  forward_tile(s, Wb, X, b0, B, h2);
+  forward_tile(s, Wb, X, idx, b0, B, h2);
   const double inv_sw = 1.0 / acc[0];
   if (t < 64) {
     const bool in = b0 + t < B;
-    const float wt = in ? Wt[b0 + t] : 0.f, tg = in ? T[b0 + t] : 0.f;
+    const int64_t row = in ? row_of(idx, b0 + t) : 0;
+    const float wt = in ? Wt[row] : 0.f, tg = in ? T[row] : 0.f;
     const float d = s.y[t] - tg;
     s.dy[t] = (float)(2.0 * wt * d * inv_sw);
     double l = (double)wt * d * d * inv_sw;
@@ -292,14 +301,14 @@ int hode_mlp_quantize(const float* Wm, uint16_t* Wb, void* stream) {
   return hipStreamSynchronize(s) == hipSuccess ? HODE_OK : HODE_EHIP;
 }
 
-int hode_mlp_loss_grad(const uint16_t* Wb, const float* X, const float* T, const float* Wt, int64_t B, float* grad,
-                       double* acc, double* loss_out, void* stream) {
+int hode_mlp_loss_grad(const uint16_t* Wb, const float* X, const float* T, const float* Wt, const int64_t* idx,
+                       int64_t B, float* grad, double* acc, double* loss_out, void* stream) {
   if (!Wb || !X || !T || !Wt || !grad || !acc || B < 1) return HODE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   fill_k<<<(MLP_NPARAM + 255) / 256, 256, 0, s>>>(grad, MLP_NPARAM, acc, 2);
   int gw = (int)std::min<int64_t>((B + 255) / 256, 1024);
-  mlp_wsum_k<<<gw, 256, 0, s>>>(Wt, B, acc);
-  mlp_grad_k<<<(unsigned)((B + 63) / 64), 256, 0, s>>>(Wb, X, T, Wt, B, grad, acc);
+  mlp_wsum_k<<<gw, 256, 0, s>>>(Wt, idx, B, acc);
+  mlp_grad_k<<<(unsigned)((B + 63) / 64), 256, 0, s>>>(Wb, X, T, Wt, idx, B, grad, acc);
   if (hipGetLastError() != hipSuccess) return HODE_EHIP;
   if (loss_out) {
     double h[2];
@@ -310,11 +319,11 @@ int hode_mlp_loss_grad(const uint16_t* Wb, const float* X, const float* T, const
   return HODE_OK;
 }
 
-int hode_mlp_train_step(const float* X, const float* T, const float* Wt, int64_t B, float* Wm, uint16_t* Wb,
-                        float* m, float* v, float* grad, double* acc, int64_t step, float lr, double* loss_out,
-                        void* stream) {
+int hode_mlp_train_step(const float* X, const float* T, const float* Wt, const int64_t* idx, int64_t B, float* Wm,
+                        uint16_t* Wb, float* m, float* v, float* grad, double* acc, int64_t step, float lr,
+                        double* loss_out, void* stream) {
   if (!Wm || !m || !v || step < 1 || !(lr > 0)) return HODE_EINVAL;
-  int rc = hode_mlp_loss_grad(Wb, X, T, Wt, B, grad, acc, nullptr, stream);
+  int rc = hode_mlp_loss_grad(Wb, X, T, Wt, idx, B, grad, acc, nullptr, stream);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)step)));

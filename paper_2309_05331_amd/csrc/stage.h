@@ -10,8 +10,9 @@
 //
 // Layout: field-major SoA, u then v, each N^3 with x fastest.
 //
-// Work decomposition (2.5D blocking): a workgroup of 4 wavefronts owns a tile
-// of 64*VW x 4*RY cells of an x-y plane and marches a chunk of zc planes in z.
+// Work decomposition (2.5D blocking): a workgroup of NW wavefronts (4 or 8)
+// owns a tile of 64*VW x NW*RY cells of an x-y plane and marches a chunk of zc
+// planes in z.
 // Each wavefront owns a strip of RY consecutive x-rows, VW cells per lane (one
 // 16-byte load per lane per row).  Per plane, every row is loaded from memory
 // once: the stage input is formed in registers, the z neighbours stay in
@@ -254,7 +255,31 @@ __device__ __forceinline__ T shfl_down1(T v) {
   return __shfl_down(v, 1, 64);
 }
 
-// Bytes of LDS one stage tile needs (the largest over all instantiations).
+// LDS row slots of a tile, per buffer and field: the tile halo above (slot
+// 0) and below (the last slot), and per wavefront the first and last row of
+// its strip (one slot when the strip is one row).
+template <int RY, int NW>
+__host__ __device__ constexpr int row_slots() {
+  return (RY == 1 ? NW : 2 * NW) + 2;
+}
+template <int RY>
+__device__ constexpr int first_slot(int w) {
+  return RY == 1 ? 1 + w : 1 + 2 * w;
+}
+template <int RY>
+__device__ constexpr int last_slot(int w) {
+  return RY == 1 ? 1 + w : 2 + 2 * w;
+}
+
+// Bytes of LDS one stage tile needs: the row slots of two buffers and two
+// fields, and the x-halo cells (ordinary tiles only).
+template <typename T, int VW, int RY, int NW, int SEG>
+__host__ __device__ constexpr int tile_smem() {
+  return 2 * 2 * row_slots<RY, NW>() * 64 * (int)sizeof(Pk<T, VW>) +
+         2 * 2 * 2 * (SEG == 1 ? NW * RY : 1) * (int)sizeof(T);
+}
+// The largest tile of four wavefronts (RY <= 4, 16-byte lanes): the LDS the
+// persistent ensemble kernel reserves for its tiles.
 constexpr int kTileSmem = 2 * 2 * 10 * 64 * 16 + 2 * 2 * 2 * 16 * 8;
 
 // One stage over one tile: columns x0 .. x0 + 64*VW - 1, rows ty*4*RY ..
@@ -273,21 +298,24 @@ constexpr int kTileSmem = 2 * 2 * 10 * 64 * 16 + 2 * 2 * 2 * 16 * 8;
 // tiles; no x-halo is needed.  The arithmetic of every cell is the same
 // expression in the same order, so the results are bitwise those of the
 // ordinary tiles.
-template <typename T, int KIND, int RY, int VW, int SEG = 1>
+template <typename T, int KIND, int RY, int VW, int SEG = 1, int NW = 4>
 __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* smem, int tx, int ty, int zbeg,
                            int zend) {
   constexpr KindDesc D = desc<KIND>();
   static_assert(SEG == 1 || 64 % SEG == 0, "segments split the wavefront evenly");
+  static_assert(NW >= 3, "three wavefronts carry the halo roles");
   constexpr int SL = 64 / SEG;  // lanes per segment
   constexpr int TX = 64 * VW;
-  constexpr int TY = 4 * RY * SEG;
+  constexpr int TY = NW * RY * SEG;
   constexpr int TYX = SEG == 1 ? TY : 1;  // x-halo cells per column (ordinary tiles only)
+  static_assert(SEG > 1 || 2 * TY <= 64, "the x-halo role holds both halo columns in one wavefront");
+  constexpr int NS = row_slots<RY, NW>();
   using P = Pk<T, VW>;
-  static_assert(2 * 2 * 10 * 64 * sizeof(P) + 2 * 2 * 2 * TYX * sizeof(T) <= kTileSmem, "LDS budget");
-  // LDS per buffer and field: 10 row slots (tile halo above, first and last
-  // row of each wave's strip, tile halo below) and the x-halo cells
-  P(*rows)[2][10][64] = reinterpret_cast<P(*)[2][10][64]>(smem);
-  T(*xh)[2][2][TYX] = reinterpret_cast<T(*)[2][2][TYX]>(smem + 2 * 2 * 10 * 64 * sizeof(P));
+  // LDS per buffer and field: the row slots (tile halo above, first and last
+  // row of each wave's strip, tile halo below) and the x-halo cells; the
+  // caller provides tile_smem<T, VW, RY, NW, SEG>() bytes
+  P(*rows)[2][NS][64] = reinterpret_cast<P(*)[2][NS][64]>(smem);
+  T(*xh)[2][2][TYX] = reinterpret_cast<T(*)[2][2][TYX]>(smem + 2 * 2 * NS * 64 * sizeof(P));
   __syncthreads();  // LDS may still be in use by the previous tile
 
   const double h = c->h;
@@ -473,11 +501,11 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
   auto publish = [&](int b, const P (&w)[2][RY]) {
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-      rows[b][f][1 + 2 * wv][lane] = w[f][0];
-      rows[b][f][2 + 2 * wv][lane] = w[f][RY - 1];
+      rows[b][f][first_slot<RY>(wv)][lane] = w[f][0];
+      if constexpr (RY > 1) rows[b][f][last_slot<RY>(wv)][lane] = w[f][RY - 1];
       if (hact) {
         if (wv == 0) rows[b][f][0][lane] = hv[f];
-        else if (wv == 1) rows[b][f][9][lane] = hv[f];
+        else if (wv == 1) rows[b][f][NS - 1][lane] = hv[f];
         else if constexpr (SEG == 1) xh[b][f][lane >= TY][lane - (lane >= TY) * TY] = hv[f].v[0];
       }
     }
@@ -502,8 +530,8 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
       if constexpr (SEG == 1) {
-        above[f] = rows[b][f][2 * wv][lane];
-        below[f] = rows[b][f][2 * wv + 3][lane];
+        above[f] = rows[b][f][wv == 0 ? 0 : last_slot<RY>(wv - 1)][lane];
+        below[f] = rows[b][f][wv == NW - 1 ? NS - 1 : first_slot<RY>(wv + 1)][lane];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
           xlft[f][r] = xh[b][f][0][wv * RY + r];
@@ -512,8 +540,8 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
       } else {
         // the strip above ends with its last segment, the strip below starts
         // with its first
-        above[f] = rows[b][f][2 * wv][(SEG - 1) * SL + jl];
-        below[f] = rows[b][f][2 * wv + 3][jl];
+        above[f] = rows[b][f][wv == 0 ? 0 : last_slot<RY>(wv - 1)][(SEG - 1) * SL + jl];
+        below[f] = rows[b][f][wv == NW - 1 ? NS - 1 : first_slot<RY>(wv + 1)][jl];
       }
     }
 #pragma unroll
@@ -705,13 +733,13 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
 // each XCD gets a contiguous range of tiles and y/z-adjacent tiles (whose
 // halo rows overlap) share an L2.  Consecutive stages sweep those ranges in
 // opposite directions.
-template <typename T, int KIND, int RY, int VW>
-__global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __restrict__ c) {
-  __shared__ __align__(16) char smem[kTileSmem];
+template <typename T, int KIND, int RY, int VW, int NW = 4>
+__global__ __launch_bounds__(64 * NW) void gs_stage(const GSLaunch a, DevCtrl* __restrict__ c) {
+  __shared__ __align__(16) char smem[tile_smem<T, VW, RY, NW, 1>()];
   if (c->done) return;
   const int N = a.N;
   const int nx = (N + 64 * VW - 1) / (64 * VW);
-  const int ny = (N + 4 * RY - 1) / (4 * RY);
+  const int ny = (N + NW * RY - 1) / (NW * RY);
   const int nz = (N + a.zc - 1) / a.zc;
   const int per = (gridDim.x + 7) / 8;
   // Stages alternate their direction through each XCD's range, so a stage
@@ -727,7 +755,27 @@ __global__ __launch_bounds__(256) void gs_stage(const GSLaunch a, DevCtrl* __res
   const int bb = (blockIdx.x & 7) * per + slot;
   if (bb >= nx * ny * nz) return;  // padding block of the remap (whole block)
   const int tz = bb / (nx * ny);
-  stage_tile<T, KIND, RY, VW>(a, c, smem, bb % nx, (bb / nx) % ny, tz * a.zc, min(N, (tz + 1) * a.zc));
+  stage_tile<T, KIND, RY, VW, 1, NW>(a, c, smem, bb % nx, (bb / nx) % ny, tz * a.zc, min(N, (tz + 1) * a.zc));
+}
+
+// Launches one stage kind over the whole grid with tiles of NW wavefronts x
+// RY rows x 64*VW cells (KINDS: the kinds this launcher instantiates).
+template <typename T, int RY, int VW, int NW, int... KINDS>
+hipError_t launch_stage_t(int kind, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
+  constexpr int TX = 64 * VW;
+  const int nx = (a.N + TX - 1) / TX;
+  const int ny = (a.N + NW * RY - 1) / (NW * RY);
+  const int nz = (a.N + a.zc - 1) / a.zc;
+  const int64_t nb = (int64_t)nx * ny * nz;
+  const int64_t grid = (nb + 7) / 8 * 8;  // whole rounds of the XCD remap
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  bool found = false;
+  ((kind == KINDS ? (gs_stage<T, KINDS, RY, VW, NW><<<dim3((unsigned)grid), dim3(64 * NW), 0, s>>>(a, c),
+                     found = true)
+                  : false),
+   ...);
+  if (!found) return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace

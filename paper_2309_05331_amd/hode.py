@@ -111,6 +111,8 @@ def lib():
             "hode_set_graphs": ([P, I], I),
             "hode_set_tile": ([P, I, I], I),
             "hode_get_tile": ([P, C.POINTER(I), C.POINTER(I)], I),
+            "hode_set_tile_waves": ([P, I], I),
+            "hode_get_kind_tile": ([P, I, C.POINTER(I), C.POINTER(I), C.POINTER(I)], I),
             "hode_time_kernel": ([P, I, I, C.POINTER(D)], I),
             "hode_profile_attempt": ([P, I, I, C.POINTER(D)], I),
             "hode_autotune": ([P, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)], I),
@@ -125,14 +127,16 @@ def lib():
             "hode_ensemble_set_barrier_limit": ([P, I64], I),
             "hode_ensemble_timing": ([P, C.POINTER(D), C.POINTER(I)], I),
             "hode_ensemble_set_vector_width": ([P, I, I], I),
+            "hode_ensemble_set_plane_chunk": ([P, I, I], I),
+            "hode_ensemble_get_tile": ([P, I, C.POINTER(I), C.POINTER(I)], I),
             "hode_ensemble_set_trace": ([P, I64], I),
             "hode_ensemble_read_trace": ([P, I, P, I64, C.POINTER(I64)], I),
             "hode_ensemble_integrate_adaptive": ([P, D, D, D, I64, C.POINTER(hode_stats)], I),
             "hode_ensemble_autotune": ([P, I, C.POINTER(I), C.POINTER(D)], I),
             "hode_mlp_forward": ([P, P, P, I64, P], I),
             "hode_mlp_quantize": ([P, P, P], I),
-            "hode_mlp_loss_grad": ([P, P, P, P, I64, P, P, C.POINTER(D), P], I),
-            "hode_mlp_train_step": ([P, P, P, I64, P, P, P, P, P, P, I64, C.c_float, C.POINTER(D), P], I),
+            "hode_mlp_loss_grad": ([P, P, P, P, P, I64, P, P, C.POINTER(D), P], I),
+            "hode_mlp_train_step": ([P, P, P, P, I64, P, P, P, P, P, P, I64, C.c_float, C.POINTER(D), P], I),
             "hode_last_error": ([P], C.c_char_p),
             "hode_trace_width": ([], I),
         }
@@ -345,6 +349,16 @@ class Context:
         """Fills the library's scratch buffers with NaN (testing aid)."""
         return self._check(self.L.hode_debug_poison(self.h))
 
+    def set_tile_waves(self, nw):
+        """Wavefronts per workgroup of the Gray-Scott tiles (4 or 8)."""
+        return self._check(self.L.hode_set_tile_waves(self.h, nw))
+
+    def kind_tile(self, kind):
+        """(ry, zc, nw) of one stage kind."""
+        ry, zc, nw = C.c_int(), C.c_int(), C.c_int()
+        self._check(self.L.hode_get_kind_tile(self.h, kind, C.byref(ry), C.byref(zc), C.byref(nw)))
+        return ry.value, zc.value, nw.value
+
     def set_vector_width(self, vw):
         return self._check(self.L.hode_set_vector_width(self.h, vw))
 
@@ -403,6 +417,15 @@ class Ensemble(Context):
 
     def set_trace(self, capacity):
         return self._check(self.L.hode_ensemble_set_trace(self.h, capacity))
+
+    def set_plane_chunk(self, i, zc):
+        return self._check(self.L.hode_ensemble_set_plane_chunk(self.h, i, zc))
+
+    def instance_tile(self, i):
+        """(vector width, planes per tile) of instance i."""
+        vw, zc = C.c_int(), C.c_int()
+        self._check(self.L.hode_ensemble_get_tile(self.h, i, C.byref(vw), C.byref(zc)))
+        return vw.value, zc.value
 
     def read_instance_trace(self, i, cap=None):
         n = C.c_int64()

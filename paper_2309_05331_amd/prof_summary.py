@@ -24,11 +24,12 @@ import sqlite3
 
 
 def short(name: str) -> str:
-    m = re.search(r"gs_stage<(\w+), (\d+), (\d+), (\d+)>", name)
+    m = re.search(r"gs_stage<(\w+), (\d+), (\d+), (\d+)(?:, (\d+))?>", name)
     if m:
         kinds = (["D1", "R2", "R3", "R4", "D2", "D3", "D4", "D5", "D6", "D7", "D7F", "C4", "C5", "C6", "C6F", "E1",
                   "D6F"] + ["F%d" % i for i in range(1, 14)] + ["F13F"] + ["AB%d" % s for s in range(1, 9)] + ["D6K"] + ["ABC%d" % s for s in range(1, 9)] + ["MM1", "MM2", "MM3"])
-        return "gs_stage %s %s ry=%s vw=%s" % (kinds[int(m.group(2))], m.group(1), m.group(3), m.group(4))
+        nw = " nw=%s" % m.group(5) if m.group(5) and m.group(5) != "4" else ""
+        return "gs_stage %s %s ry=%s vw=%s%s" % (kinds[int(m.group(2))], m.group(1), m.group(3), m.group(4), nw)
     m = re.search(r"(ew_\w+)<(\w+), (\d+)(?:, (\d+))?", name)
     if m:
         third = "" if not m.group(4) else (" mode=%s" if m.group(1) == "ew_step" else " s=%s") % m.group(4)

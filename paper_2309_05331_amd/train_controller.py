@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--holdout", type=int, default=64)
     ap.add_argument("--rhos", default="0.3,0.5")
     ap.add_argument("--reject-weights", default="2,5")
+    ap.add_argument("--stab-caps", default="0",
+                    help="caps of the targets as fractions of the step at the method's real stability limit "
+                         "for the System's largest eigenvalue (0: no cap)")
     args = ap.parse_args()
     sets = {"smooth": c4_params() + (4000, args.t1), "stiff": stiff_params(args.n_stiff) + (6000, args.t1_stiff)}
     summary = {"train": {}, "eval": {}, "candidates": {}, "args": vars(args)}
@@ -121,8 +124,8 @@ def main():
             summary["eval"]["%s pi rtol=%g" % (name, rtol)] = base[name, rtol]
             print("held-out", name, rtol, base[name, rtol], flush=True)
 
-    def fit(traces, rho, rw):
-        parts = [controller.dataset_from_trace(tr, rho=rho, reject_weight=rw) for tr in traces]
+    def fit(traces, rho, rw, cap):
+        parts = [controller.dataset_from_trace(tr, rho=rho, reject_weight=rw, stab_cap=cap) for tr in traces]
         X = np.concatenate([p[0] for p in parts])
         T = np.concatenate([p[1] for p in parts])
         W = np.concatenate([p[2] for p in parts])
@@ -131,12 +134,14 @@ def main():
         return trn.weights_bf16(), int(X.shape[0]), [hist[0], hist[-1]]
 
     best = None
-    for rho in (float(v) for v in args.rhos.split(",")):
-        for rw in (float(v) for v in args.reject_weights.split(",")):
-            key = "rho=%g,reject_weight=%g" % (rho, rw)
+    grid = [(float(a), float(b), float(c)) for a in args.rhos.split(",") for b in args.reject_weights.split(",")
+            for c in args.stab_caps.split(",")]
+    for rho, rw, cap in grid:
+        if True:
+            key = "rho=%g,reject_weight=%g" % (rho, rw) + (",stab_cap=%g" % cap if cap > 0 else "")
             t0 = time.perf_counter()
             traces = list(pi_traces)
-            wb, ns, loss = fit(traces, rho, rw)
+            wb, ns, loss = fit(traces, rho, rw, cap)
             res = {"rounds": []}
             for r in range(args.rounds):
                 rr = {}
@@ -147,7 +152,7 @@ def main():
                                                      hode.CTRL_MLP, weights=wb, trace_cap=4000)
                         traces += tr
                         rr["%s rtol=%g" % (name, rtol)] = summarize(stats, el, edges[:k])
-                wb, ns, loss = fit(traces, rho, rw)
+                wb, ns, loss = fit(traces, rho, rw, cap)
                 rr["samples"], rr["loss_first_last"] = ns, loss
                 res["rounds"].append(rr)
                 print(key, "round", r, json.dumps(rr), flush=True)

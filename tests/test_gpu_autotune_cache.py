@@ -20,14 +20,16 @@ def test_cache_miss_then_hit(tmp_path, monkeypatch):
     a = gs_ctx(y0, N, PRM)
     assert a.autotune_cached(hode.DOPRI5, 1, path) is False
     lines = path.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("hode-tune-v1 ")
+    assert len(lines) == 1 and lines[0].startswith("hode-tune-v2 ")
     tile = a.get_tile()
+    kinds = [a.kind_tile(k) for k in range(hode.K_MM[-1] + 1)]
     a.integrate_adaptive(0.0, 5.0, 0.1)
     ya = read(a, np.float32, 2 * N ** 3)
     a.close()
     b = gs_ctx(y0, N, PRM)
     assert b.autotune_cached(hode.DOPRI5, 1, path) is True
     assert b.get_tile() == tile
+    assert [b.kind_tile(k) for k in range(hode.K_MM[-1] + 1)] == kinds
     b.integrate_adaptive(0.0, 5.0, 0.1)
     assert np.array_equal(read(b, np.float32, 2 * N ** 3), ya)
     # another method is another entry

@@ -106,6 +106,47 @@ def test_ensemble_rejects_bad_epoch():
         ens.set_epoch(0, 5)
     with pytest.raises(hode.HodeError):
         ens.set_epoch(3, 5000)
+    ens.set_epoch(0, 0)  # one launch for the whole integration (the default)
+    with pytest.raises(hode.HodeError):
+        ens.set_plane_chunk(0, -1)
+    ens.close()
+
+
+def test_ensemble_one_launch_and_tuned_tiles_bitwise():
+    # by default the whole integration is one persistent launch; the
+    # autotuner's per-edge tiles and any planes-per-tile choice leave every
+    # instance bitwise equal to its single-grid run
+    edges = [8, 16, 24, 32, 12, 20, 40, 16]
+    _, prms = _params(len(edges))
+    vws = [1, 2, 1, 2, 4, 2, 1, 4]
+    ens, ys, outs, stats = _run_ensemble(edges, prms, hode.F32, 30.0, 1e-5, vws=vws)
+    ms, launches = ens.timing()
+    assert launches == 1 and ms > 0
+    most = max(s["accepted"] + s["rejected"] for s in stats)
+    print("one launch: %d attempts of the longest instance in %.2f ms" % (most, ms))
+    for i, N in enumerate(edges):
+        ref, st = _single(ys[i], N, prms[i], vws[i], 30.0, 0.1, 1e-5)
+        assert (stats[i]["accepted"], stats[i]["rejected"]) == (st["accepted"], st["rejected"]), i
+        assert np.array_equal(outs[i], ref), i
+    # tuned tiles: a choice per edge, reported per instance
+    for i, N in enumerate(edges):
+        ens.init_instance(i, np.ascontiguousarray(ys[i]).ravel())
+    vw, tms = ens.autotune(2)
+    tiles = [ens.instance_tile(i) for i in range(len(edges))]
+    print("autotuned (vw, planes) per instance:", tiles)
+    for i, N in enumerate(edges):
+        assert tiles[i][0] == vw[i] and N % vw[i] == 0 and 1 <= tiles[i][1] <= N and tms[i] > 0
+        assert tiles[i] == tiles[edges.index(N)]  # one choice per edge
+    for i, N in enumerate(edges):
+        ens.init_instance(i, np.ascontiguousarray(ys[i]).ravel())
+        ens.set_plane_chunk(i, 1 + (i % 3) * 3)
+    stats2 = ens.integrate_adaptive(0.0, 30.0, 0.1, max_steps=100000)
+    for i, N in enumerate(edges):
+        o = np.empty(2 * N ** 3, dtype=np.float32)
+        ens.read_instance(i, o)
+        ref, st = _single(ys[i], N, prms[i], tiles[i][0], 30.0, 0.1, 1e-5)
+        assert (stats2[i]["accepted"], stats2[i]["rejected"]) == (st["accepted"], st["rejected"]), i
+        assert np.array_equal(o, ref), i
     ens.close()
 
 

@@ -89,14 +89,19 @@ def test_dopri5_adaptive_fp64_free_and_replay(orc, N):
     np.testing.assert_allclose(tr[:, 0], otr[:, 0], rtol=1e-5)
     r, _, errs = orc.integrate_replay(sysd, y0, 0.0, tr[:, 0], tr[:, 2].astype(np.int32), 1e-6, 1e-6)
     assert rel_err_fields(g, r, 2) <= TOL64
-    bad = np.abs(tr[:, 1] - errs) > 1e-9 + 1e-6 * np.abs(errs)
+    derr = np.abs(tr[:, 1] - errs)
+    print("32^3 FP64 free-running Dopri5: %d attempts, error-norm trace vs oracle replay: max |d err| %.3e, "
+          "max relative %.3e" % (len(errs), derr.max(), float(np.max(derr / np.maximum(np.abs(errs), 1e-300)))))
+    bad = derr > 1e-9 + 1e-6 * np.abs(errs)
     for i in np.nonzero(bad)[0][:10]:
         print("attempt %d h=%.6g acc=%d err gpu=%.12g oracle=%.12g" % (i, tr[i, 0], tr[i, 2], tr[i, 1], errs[i]))
     # Near the stability edge the error norm measures a tiny high-frequency
-    # component (~1e-7 of the state, amplified by |E(z)| ~ 1), so state
-    # differences of ~1e-12 move it by ~1e-5 absolute; elsewhere it agrees far
-    # better.
-    np.testing.assert_allclose(tr[:, 1], errs, rtol=1e-6, atol=1e-5)
+    # component (~1e-7 of the state, amplified by |E(z)| ~ 1): with the scale
+    # atol + rtol |y| ~ 1e-6, state differences of ~1e-12 move the norm by
+    # ~1e-6 absolute (measured on MI355X: max |d err| 1.108e-6 over 144
+    # attempts, relative 2.8e-6); elsewhere it agrees far better.  The bar is
+    # 4.5x the measured value.
+    np.testing.assert_allclose(tr[:, 1], errs, rtol=1e-6, atol=5e-6)
 
 
 def test_dopri5_adaptive_fp32_replay(orc):
@@ -197,3 +202,41 @@ def test_graph_and_plain_launches_bitwise():
         ctx.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
 
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_eight_wavefront_tiles_bitwise(dtype):
+    # tiles of eight wavefronts (one or two rows each) give every stage kind's
+    # results bitwise those of four-wavefront tiles: RK4 and free-running
+    # Dopri5 on ragged grids (N = 76: one partial tile per row and a partial
+    # last tile row; N = 300: two or three tiles per row, the last partial)
+    # (the 300^3 grid takes the workload's diffusivities: with the stronger
+    # ones its explicit stability limit is below the steps taken here)
+    for N, prm in ((76, PRM_D), (300, PRM)):
+        y0 = inputs.gray_scott_ic(N, seed=40, dtype=dtype)
+        outs = []
+        for nw, ry, zc in ((4, 1, N), (8, 1, 16), (8, 2, 24), (8, 1, N)):
+            ctx = gs_ctx(y0, N, prm)
+            ctx.set_tile_waves(nw)
+            ctx.set_tile(ry, zc)
+            for k in (hode.K_D2, hode.K_D6, hode.K_R4):
+                assert ctx.kind_tile(k) == (ry, zc, nw)
+            ctx.integrate_n_steps(hode.RK4, 0.0, 0.05, 3)
+            st = ctx.integrate_adaptive(0.15, 1.0, 0.1)
+            assert st["status"] == 0
+            outs.append((read(ctx, dtype, 2 * N ** 3), st["accepted"], st["rejected"]))
+            ctx.close()
+        for o in outs[1:]:
+            assert o[1:] == outs[0][1:] and np.array_equal(o[0], outs[0][0]), N
+    # kinds without eight-wavefront tiles (Fehlberg) keep four, and a vector
+    # width other than 16-byte lanes drops the others back to four
+    y0 = inputs.gray_scott_ic(64, seed=41, dtype=np.float32)
+    ctx = gs_ctx(y0, 64, PRM_D)
+    ctx.set_tile_waves(8)
+    ctx.set_tile(1, 64)
+    assert ctx.kind_tile(hode.K_D6)[2] == 8 and ctx.kind_tile(hode.K_F[0])[2] == 4
+    ctx.set_vector_width(2)
+    assert ctx.kind_tile(hode.K_D6)[2] == 4
+    with pytest.raises(hode.HodeError):
+        ctx.set_tile_waves(16)
+    ctx.close()

@@ -130,21 +130,92 @@ def test_nonfinite_network_falls_back_to_pi_exactly():
     assert np.all(np.isnan(tr_ml[:, 6]))
 
 
+def _held_out_run(edges, prms, seeds, t1, rtol, ctrl, weights=None, dtype=hode.F32):
+    ens = hode.Ensemble(edges, prms, dtype=dtype)
+    npd = np.float32 if dtype == hode.F32 else np.float64
+    for i, N in enumerate(edges):
+        ens.init_instance(i, inputs.ensemble_ic(seeds[i], N, dtype=npd).ravel())
+    ens.set_tolerances(rtol, rtol)
+    ens.set_controller(ctrl, weights)
+    stats = ens.integrate_adaptive(0.0, t1, 0.1, max_steps=10 ** 6)
+    kms, _ = ens.timing()
+    outs = []
+    for i, N in enumerate(edges):
+        o = np.empty(2 * N ** 3, dtype=npd)
+        ens.read_instance(i, o)
+        outs.append(o.astype(np.float64))
+    ens.close()
+    return stats, kms, outs
+
+
 def test_trained_controller_beats_pi_on_held_out_instances():
-    # the committed network (trained on the integrator's own traces of the
-    # 512-instance workload) against PI on instances it has not seen: new
-    # initial conditions, rtol 1e-6, horizon 0..400
+    # The committed network (trained on the integrator's own traces of the
+    # 512-instance workload and a stiff set) against PI on instances it has
+    # not seen: grid edges, F and k from a parameter seed of their own (44;
+    # training used 4 and 6) and new initial conditions, rtol 1e-6, t 0..400.
+    # Compared: attempts, kernel time of the persistent launches, and the
+    # final error of each against an FP64 run of the same instances at rtol
+    # 1e-10 (the learned proposals must not buy speed with accuracy).
     import os
-    from paper_2309_05331_amd import train_controller as tc
     wb = np.load(os.path.join(os.path.dirname(hode.__file__), "controller_weights.npy"))
-    edges, prms = tc.c4_params()
     m = 24
-    he, hp = edges[:m], prms[:m]
+    edges, F, k = inputs.ensemble_draws(m, seed=44)
+    prms = [[2e-5, 1e-5, F[i], k[i], 2.5] for i in range(m)]
     seeds = list(range(9500, 9500 + m))
+    # the reference's own uncertainty per instance: FP64 runs at rtol 1e-8
+    # and 1e-10 differ by ~1e-9 where the final state is well conditioned;
+    # where the dynamics amplify perturbations (an instance near a
+    # transition at t = 400) they differ by far more, and any two runs at
+    # rtol 1e-6 can then end far apart whatever their controller
+    _, _, ref = _held_out_run(edges, prms, seeds, 400.0, 1e-10, hode.CTRL_PI, dtype=hode.F64)
+    _, _, ref8 = _held_out_run(edges, prms, seeds, 400.0, 1e-8, hode.CTRL_PI, dtype=hode.F64)
+    cond = np.array([float(np.max(np.abs(a - b))) for a, b in zip(ref8, ref)])
+    well = cond <= 1e-8
     res = {}
     for name, kind, w in (("pi", hode.CTRL_PI, None), ("mlp", hode.CTRL_MLP, wb)):
-        stats, el, _ = tc.run_ensemble(he, hp, seeds, 400.0, 1e-6, kind, weights=w)
+        stats, kms, outs = _held_out_run(edges, prms, seeds, 400.0, 1e-6, kind, w)
         assert all(s["status"] == 0 and s["t"] == 400.0 for s in stats)
-        res[name] = sum(s["accepted"] + s["rejected"] for s in stats)
-    print("attempts PI %d learned %d" % (res["pi"], res["mlp"]))
-    assert res["mlp"] < res["pi"]
+        err = np.array([float(np.max(np.abs(o - r))) for o, r in zip(outs, ref)])
+        res[name] = (sum(s["accepted"] + s["rejected"] for s in stats), sum(s["rejected"] for s in stats), kms, err)
+    ratio = res["mlp"][3] / res["pi"][3]
+    print("held-out (parameter seed 44): attempts PI %d learned %d; rejects %d / %d; kernel ms %.1f / %.1f "
+          "(ratio %.3f); final max-abs error vs FP64 rtol 1e-10 on the %d well-conditioned instances: PI %.2e "
+          "learned %.2e (per-instance ratio %.2f .. %.2f); ill-conditioned (references differ by %s): PI %s "
+          "learned %s"
+          % (res["pi"][0], res["mlp"][0], res["pi"][1], res["mlp"][1], res["pi"][2], res["mlp"][2],
+             res["mlp"][2] / res["pi"][2], well.sum(), res["pi"][3][well].max(), res["mlp"][3][well].max(),
+             ratio[well].min(), ratio[well].max(), np.array2string(cond[~well], precision=1),
+             np.array2string(res["pi"][3][~well], precision=1), np.array2string(res["mlp"][3][~well], precision=1)))
+    assert well.sum() >= 20
+    assert res["mlp"][0] < res["pi"][0]
+    assert res["mlp"][2] < res["pi"][2]
+    # accepted steps are judged by the same embedded estimate; the learned
+    # controller takes its steps closer to the tolerance, so its global error
+    # is somewhat larger (measured up to 2.6x PI's), not of another order
+    assert np.all(ratio[well] <= 4.0) and res["mlp"][3][well].max() <= 1e-5
+
+
+def test_minibatch_rows_gathered_by_the_kernels():
+    # a minibatch given as row indices into the data set equals the same rows
+    # gathered beforehand (up to the order of the fp32 gradient atomics), and
+    # both match the oracle on the gathered rows
+    import ctypes as C
+    import torch
+    X, T, W = _data(900, seed=5)
+    rows = np.random.default_rng(5).permutation(900)[:333].astype(np.int64)
+    p = controller.init_params(seed=6)
+    tr = controller.Trainer(params=p)
+    Lg, gg = tr.loss_grad(X[rows], T[rows], W[rows])
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda:0")
+    Xd, Td, Wd, Id = dev(X, torch.float32), dev(T, torch.float32), dev(W, torch.float32), dev(rows, torch.int64)
+    loss = C.c_double()
+    rc = hode.lib().hode_mlp_loss_grad(tr._p(tr.Wb), tr._p(Xd), tr._p(Td), tr._p(Wd), tr._p(Id), rows.size,
+                                       tr._p(tr.g), tr._p(tr.acc), C.byref(loss), None)
+    assert rc == 0
+    gi = tr.g.cpu().numpy()
+    assert abs(loss.value - Lg) <= 1e-6 * abs(Lg)
+    assert np.linalg.norm(gi - gg) <= 1e-5 * np.linalg.norm(gg)
+    pb = omlp.from_bf16_bits(tr.weights_bf16())
+    Lo, go = omlp.loss_and_grad(pb, X[rows].astype(np.float64), T[rows], W[rows], bf16=True)
+    assert abs(loss.value - Lo) <= 1e-3 * Lo
+    assert np.linalg.norm(gi - go) / np.linalg.norm(go) < 3e-2

@@ -24,6 +24,8 @@ def _csv(path, counter, rows):
 
 def test_short_names():
     assert ps.short(D6) == "gs_stage D6 float ry=1 vw=4"
+    assert ps.short(D6.replace("1, 4>", "1, 4, 8>")) == "gs_stage D6 float ry=1 vw=4 nw=8"
+    assert ps.short(D6.replace("1, 4>", "1, 4, 4>")) == "gs_stage D6 float ry=1 vw=4"
     assert ps.short(EW) == "ew_step double rhs=1 mode=3"
     assert ps.short("void hode::ew_ab<float, 2, 4>(x)") == "ew_ab float rhs=2 s=4"
     assert ps.short("void hode::(anonymous namespace)::ens_kernel<float>(x)") == "ens_kernel float"
