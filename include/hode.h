@@ -468,6 +468,22 @@ int hode_mlp_train_step(const float *X, const float *T, const float *Wt, const i
                         uint16_t *Wb, float *m, float *v, float *grad, double *acc, int64_t step, float lr,
                         double *loss_out, void *stream);
 
+/* hode_mlp_train_step for callers that cannot allocate (code under HIP
+ * graph capture, tight training or serving loops, harnesses that forbid
+ * allocation): no gradient or scratch argument, and the call allocates
+ * nothing.  The gradient (5313 fp32) and the two loss sums live in a
+ * library-owned device array of 21.5 KB per GPU (the GPU running `stream`,
+ * the current device for NULL), set up on the first call on that GPU and
+ * held until the process ends; every call clears it before use.  Calls on
+ * one GPU share that array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller.  B is 1 ..
+ * HODE_MLP_NOALLOC_MAX_B samples (HODE_EINVAL otherwise); other arguments
+ * and results as hode_mlp_train_step. */
+#define HODE_MLP_NOALLOC_MAX_B 2147483647LL
+int hode_mlp_train_step_noalloc(const float *X, const float *T, const float *Wt, const int64_t *idx, int64_t B,
+                                float *Wm, uint16_t *Wb, float *m, float *v, int64_t step, float lr,
+                                double *loss_out, void *stream);
+
 /* Text of the last error on this context (valid until the next call on it;
  * owned by the context). */
 const char *hode_last_error(const hode_ctx *ctx);

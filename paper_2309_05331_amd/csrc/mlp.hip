@@ -17,6 +17,8 @@
 // minibatch is gathered by the kernels as they load it.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "../../include/hode.h"
 #include "hode_dev.h"
 
@@ -277,6 +279,47 @@ __global__ __launch_bounds__(256) void quantize_k(const float* __restrict__ Wm, 
   if (i < MLP_NPARAM) Wb[i] = to_bf16(Wm[i]);
 }
 
+// Scratch of the allocation-free training step: the two loss sums (offset
+// 0) and the gradient of the 5313 parameters (offset 256), one copy per GPU,
+// held until the process ends.  Host code never passes this array's name to
+// a kernel: it stands for the device copy only in device code, so the host
+// resolves each GPU's address once (noalloc_scratch) and passes that.
+constexpr size_t kScratchAccOff = 0, kScratchGradOff = 256;
+constexpr size_t kScratchBytes = (kScratchGradOff + sizeof(float) * MLP_NPARAM + 255) / 256 * 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the GPU that runs `stream` (the current
+// device for the null stream), resolved on the first call per device with
+// that device current and cached.
+int noalloc_scratch(hipStream_t stream, unsigned char** out) {
+  int dev = -1;
+  if (stream) {
+    hipDevice_t d;
+    if (hipStreamGetDevice(stream, &d) != hipSuccess) return HODE_EHIP;
+    dev = (int)d;
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return HODE_EHIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return HODE_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return HODE_EHIP;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return HODE_EHIP;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev && hipSetDevice(cur) != hipSuccess) return HODE_EHIP;
+    if (e != hipSuccess || !p) return HODE_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (unsigned char*)g_scratch_ptr[dev];
+  return HODE_OK;
+}
+
 }  // namespace
 }  // namespace hode
 
@@ -337,6 +380,20 @@ int hode_mlp_train_step(const float* X, const float* T, const float* Wt, const i
     *loss_out = h[1];
   }
   return HODE_OK;
+}
+
+int hode_mlp_train_step_noalloc(const float* X, const float* T, const float* Wt, const int64_t* idx, int64_t B,
+                                float* Wm, uint16_t* Wb, float* m, float* v, int64_t step, float lr,
+                                double* loss_out, void* stream) {
+  if (!X || !T || !Wt || !Wb || !Wm || !m || !v || step < 1 || !(lr > 0)) return HODE_EINVAL;
+  if (B < 1 || B > HODE_MLP_NOALLOC_MAX_B) return HODE_EINVAL;  // outside 1 .. 2^31 - 1 samples
+  unsigned char* base = nullptr;
+  const int rc = noalloc_scratch((hipStream_t)stream, &base);
+  if (rc) return rc;
+  // the same kernels as hode_mlp_train_step, with the gradient and the loss
+  // sums in this GPU's scratch (cleared by the first kernel of every call)
+  return hode_mlp_train_step(X, T, Wt, idx, B, Wm, Wb, m, v, (float*)(base + kScratchGradOff),
+                             (double*)(base + kScratchAccOff), step, lr, loss_out, stream);
 }
 
 }  // extern "C"

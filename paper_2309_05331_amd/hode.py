@@ -137,6 +137,7 @@ def lib():
             "hode_mlp_quantize": ([P, P, P], I),
             "hode_mlp_loss_grad": ([P, P, P, P, P, I64, P, P, C.POINTER(D), P], I),
             "hode_mlp_train_step": ([P, P, P, P, I64, P, P, P, P, P, P, I64, C.c_float, C.POINTER(D), P], I),
+            "hode_mlp_train_step_noalloc": ([P, P, P, P, I64, P, P, P, P, I64, C.c_float, C.POINTER(D), P], I),
             "hode_last_error": ([P], C.c_char_p),
             "hode_trace_width": ([], I),
         }
