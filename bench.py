@@ -15,7 +15,8 @@ each, three runs each in alternating order, mean and sd, their ratio, and
 each one's final error against an FP64 run at rtol 1e-8; `--ab T1` sets
 the horizon, `--ab 0` skips it).
 
-Other workloads (--workload): gs256-dp5, gs256-rk4, gs512-ck54, gs512-f78,
+Other workloads (--workload): gs512-dp5-fp64 (the same grid in FP64, the
+paper's precision), gs256-dp5, gs256-rk4, gs512-ck54, gs512-f78,
 gs512-ab4, gs32-rk4-fp64, ew24-dp5, ew24-dp5-fp32 and ens512-dp5 (the
 512-instance batched ensemble, edges 16..96, rtol 1e-5, t 0 -> 2000; one
 step integrates the whole horizon from the initial conditions).
@@ -68,6 +69,8 @@ STAGES = {"rk4": [0, 1, 2, 3], "dp5": [4, 5, 6, 7, 8, 9], "ck54": [0, 4, 5, 11, 
 WORKLOADS = {
     "gs512-dp5": dict(kind="gs", N=512, dtype="f32", method="dp5", window=10.0, seed=5, dt0=0.1),
     "gs256-dp5": dict(kind="gs", N=256, dtype="f32", method="dp5", window=10.0, seed=3, dt0=0.1),
+    # the paper's precision on the stencil path: FP64 state and arithmetic
+    "gs512-dp5-fp64": dict(kind="gs", N=512, dtype="f64", method="dp5", window=10.0, seed=5, dt0=0.1),
     "gs512-ck54": dict(kind="gs", N=512, dtype="f32", method="ck54", window=10.0, seed=5, dt0=0.1),
     "gs512-f78": dict(kind="gs", N=512, dtype="f32", method="f78", window=10.0, seed=5, dt0=0.1),
     # Adams-Bashforth 4 at h lambda_max = 0.25 (its real stability interval is 0.3)
@@ -252,7 +255,7 @@ def cpu_baseline_leg(wl, check=None, budget_s=10.0):
         t0, units, i, t = time.perf_counter(), 0, 0, 0.0
         while time.perf_counter() - t0 < budget_s and i < wl["n"]:
             N = edges[i]
-            y = inputs.ensemble_ic(4000 + i, N).astype(np.float64).ravel()
+            y = inputs.ensemble_ic(i, N).astype(np.float64).ravel()
             sysd = oracle.gs_system(N, GS_PRM[0], GS_PRM[1], F[i], k[i], GS_PRM[4])
             _, st, _ = oracle.integrate_adaptive(sysd, y, 0.0, wl["t1"], wl["dt0"], wl["rtol"], wl["rtol"],
                                                  max_steps=20)
@@ -312,11 +315,15 @@ def run_ens(wl, steps, warmup):
     n = wl["n"]
     edges, F, k = inputs.ensemble_draws(n, seed=wl["seed"])
     prms = [[GS_PRM[0], GS_PRM[1], F[i], k[i], GS_PRM[4]] for i in range(n)]
-    ics = [torch.from_numpy(inputs.ensemble_ic(4000 + i, N).ravel()).to("cuda:0") for i, N in enumerate(edges)]
+    # instance i starts from the initial condition of seed 4000 + i
+    ics = [torch.from_numpy(inputs.ensemble_ic(i, N).ravel()).to("cuda:0") for i, N in enumerate(edges)]
     ens = hode.Ensemble(edges, prms, dtype=hode.F32)
     ens.set_tolerances(wl["rtol"], wl["rtol"])
     ens.set_controller(hode.CTRL_PI)
-    ens.autotune(3)  # the persistent kernel timed per grid edge: vector width and planes per tile
+    if wl.get("tiles", "auto") == "auto":
+        ens.autotune(3)  # the persistent kernel timed per grid edge: vector width and planes per tile
+    if wl.get("epoch"):
+        ens.set_epoch(wl["epoch"], wl["epoch"])
     tiles = {}
     for i, N in enumerate(edges):
         tiles.setdefault(str(N), list(ens.instance_tile(i)))
@@ -461,9 +468,11 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     if method in (hode.CASHKARP54, hode.FEHLBERG78):
         ctx.set_stepper(method)
     if tile is None:
-        ctx.autotune(method, 3)  # project autotuner: fastest (ry, zc) for this grid
+        ctx.autotune(method, 3)  # project autotuner: fastest (ry, zc, nw) per stage for this grid
     else:
-        ctx.set_tile(*tile)
+        if len(tile) == 3:
+            ctx.set_tile_waves(tile[2])
+        ctx.set_tile(tile[0], tile[1])
     state = {"t": 0.0, "dt": wl.get("dt0", 0.1), "acc": 0, "rej": 0}
 
     def one_step():
@@ -701,7 +710,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip timing the plain streaming copy beside the workload")
-    ap.add_argument("--tile", default="auto", help="auto (autotune) or RY,ZC")
+    ap.add_argument("--tile", default="auto", help="auto (autotune) or RY,ZC[,NW]; ensemble: auto or default "
+                                                   "(the kernel's own plane-chunk sizing, no autotuning)")
+    ap.add_argument("--ens-epoch", type=int, default=0,
+                    help="ensemble: attempts per launch (0: one launch for the whole integration)")
     ap.add_argument("--ab", type=float, default=None, metavar="T1",
                     help="also integrate the workload grid from 0 to T1 with PI and with the learned controller "
                          "(default: T1 = 2000 for the default workload, the metric's wall-time comparison over "
@@ -735,6 +747,7 @@ def main():
     ctrl = {"pi": hode.CTRL_PI, "i": hode.CTRL_I}[args.controller]
     if wl["kind"] == "gs":
         tile = None if args.tile == "auto" else tuple(int(v) for v in args.tile.split(","))
+        assert tile is None or len(tile) in (2, 3), "--tile RY,ZC or RY,ZC,NW"
         r = run_gs(wl, args.steps, args.warmup, ctrl, tile=tile)
         unit = "cell-updates/s"
         cfg = {"workload": args.workload, "grid": [wl["N"]] * 3, "fields": 2,
@@ -745,7 +758,8 @@ def main():
                "stage_tiles_ry_zc_nw": r["kind_tiles"],
                "params": {"Du": GS_PRM[0], "Dv": GS_PRM[1], "F": GS_PRM[2], "k": GS_PRM[3], "L": GS_PRM[4]}}
     elif wl["kind"] == "ens":
-        r = run_ens(wl, args.steps, args.warmup)
+        r = run_ens(dict(wl, tiles="auto" if args.tile == "auto" else "default", epoch=args.ens_epoch), args.steps,
+                    args.warmup)
         unit = "cell-updates/s"
         cfg = {"workload": args.workload, "instances": wl["n"], "edges": "uniform over 16..96 step 8", "fields": 2,
                "method": "dopri5-adaptive", "rtol": wl["rtol"], "controller": "pi", "t": [0.0, wl["t1"]],

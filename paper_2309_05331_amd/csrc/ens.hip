@@ -36,12 +36,20 @@ __device__ inline bool ens_error(const EnsSched& s) {
   return __hip_atomic_load(s.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
+// Two-level arrival: a workgroup counts itself on its XCD's line (workgroups
+// are dealt round-robin to the 8 XCDs), the last arrival of each XCD counts
+// the XCD on the global line, and every workgroup waits for all XCDs there:
+// 8 arrival atomics per barrier on the global line instead of one per
+// workgroup.
 __device__ inline void grid_sync(const EnsSched& s, uint64_t& gen) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();  // release this workgroup's outputs
-    atomicAdd((unsigned long long*)s.bar, 1ull);
-    const uint64_t target = (gen + 1) * (uint64_t)gridDim.x;
+    const uint32_t x = blockIdx.x & 7;
+    const uint64_t per_xcd = (gridDim.x - x + 7) / 8;  // workgroups of this XCD
+    const uint64_t mine = atomicAdd((unsigned long long*)(s.xbar + 16 * x), 1ull) + 1;
+    if (mine == (gen + 1) * per_xcd) atomicAdd((unsigned long long*)s.bar, 1ull);
+    const uint64_t target = (gen + 1) * (uint64_t)(gridDim.x < 8 ? gridDim.x : 8);
     int64_t spins = 0;
     while (__hip_atomic_load(s.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(2);
@@ -136,7 +144,7 @@ __device__ inline bool ens_running(const EnsInst* I) {
 template <typename T>
 __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst, const EnsSched s) {
   __shared__ __align__(16) char smem[kTileSmem];
-  __shared__ int s_claim, s_run;
+  __shared__ int s_claim, s_run, s_last;
   const EnsParams prm = *s.params;
   const int xcd = blockIdx.x & 7;  // workgroups are dealt round-robin to the 8 XCDs
   uint64_t gen = 0;
@@ -178,7 +186,27 @@ __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst,
         if (t >= cnt) break;
         if (run) {
           const EnsTile tl = s.tiles[base + t];
-          ens_tile<T, K>(&inst[tl.inst], smem, tl);
+          EnsInst* I = &inst[tl.inst];
+          ens_tile<T, K>(I, smem, tl);
+          if constexpr (K == K_D7) {
+            // the workgroup that finishes the instance's last tile of the
+            // attempt runs its step control: the error maxima of every tile
+            // are device-scope atomics made before their count
+            __syncthreads();
+            if (threadIdx.x == 0) {
+              __threadfence();
+              s_last = atomicAdd(&I->last_done, 1u) + 1 == (uint32_t)I->ntiles;
+            }
+            __syncthreads();
+            if (s_last) {
+              if (threadIdx.x == 0) {
+                __threadfence();
+                __hip_atomic_store(&I->last_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              }
+              ctrl_step(&I->ctrl);
+              if (threadIdx.x == 0 && ens_running(I)) atomicAdd(&s.live[round & 1], 1u);
+            }
+          }
         }
       }
     }
@@ -194,22 +222,8 @@ __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst,
     if (!stage_phase(std::integral_constant<int, K_D4>(), r)) return;
     if (!stage_phase(std::integral_constant<int, K_D5>(), r)) return;
     if (!stage_phase(std::integral_constant<int, K_D6>(), r)) return;
+    // (the last phase also ran every instance's step control)
     if (!stage_phase(std::integral_constant<int, K_D7>(), r)) return;
-    // control phase: the members' error maxima are device-scope atomics made
-    // before the barrier above; the controller reads them with an atomic
-    for (int i = blockIdx.x; i < prm.n_inst; i += gridDim.x) {
-      EnsInst* I = &inst[i];
-      if (threadIdx.x == 0) s_run = ens_running(I);
-      __syncthreads();
-      const int run = s_run;
-      __syncthreads();
-      if (run) {
-        ctrl_step(&I->ctrl);
-        if (threadIdx.x == 0 && ens_running(I)) atomicAdd(&s.live[r & 1], 1u);
-      }
-    }
-    grid_sync(s, gen);
-    if (ens_error(s)) return;
     // every instance finished or paused: leave early (uniform: all read after the barrier)
     if (__hip_atomic_load(&s.live[r & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
   }

@@ -1358,8 +1358,18 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
   for (int nz = 1; nz <= 12; ++nz) zcs.push_back((c->N + nz - 1) / nz);
   std::sort(zcs.begin(), zcs.end());
   zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
+  // Adams-Bashforth starts a fresh history with Fehlberg 7(8) steps: its
+  // stage kinds get their own tuned tiles first
+  if (method >= HODE_AB1 && method <= HODE_AB8) {
+    rc = hode_autotune(c, HODE_FEHLBERG78, reps, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+  }
   int seq[16];
   const int ns = stage_seq(method, seq);
+  // the tiles of the kinds this search does not time stay as they were (the
+  // search sets every kind's tile while it times)
+  int keep_ry[hode::K_ALL], keep_zc[hode::K_ALL], keep_nw[hode::K_ALL];
+  for (int k = 0; k < hode::K_ALL; ++k) { keep_ry[k] = c->kry[k]; keep_zc[k] = c->kzc[k]; keep_nw[k] = c->knw[k]; }
   // every stage kind keeps its own fastest tile: rows per wavefront,
   // planes, and four or (16-byte lanes, one or two rows) eight wavefronts
   double best[16];
@@ -1386,6 +1396,7 @@ int hode_autotune(hode_ctx* c, int method, int reps, int* best_ry, int* best_zc,
       }
     }
   }
+  for (int k = 0; k < hode::K_ALL; ++k) { c->kry[k] = keep_ry[k]; c->kzc[k] = keep_zc[k]; c->knw[k] = keep_nw[k]; }
   double tot = 0;
   for (int i = 0; i < ns; ++i) {
     c->kry[seq[i]] = bry[i];
@@ -1740,10 +1751,12 @@ int hode_ensemble_timing(hode_ctx* c, double* kernel_ms, int* launches) {
 
 // Device block of the launch bookkeeping, sized for `rounds` rounds.
 // The ensemble's bookkeeping block: queue offsets, launch parameters, then
-// (cleared before every launch) the barrier counter, the error flag, the two
+// (cleared before every launch) the barrier's global counter, its eight
+// per-XCD counters (one 128-byte line each), the error flag, the two
 // running-instance counts and the two sets of claim counters.
 struct SyncLayout {
-  size_t qoff = 0, params = 64, bar = 128, error = 136, live = 140, qctr = 148, bytes = 148 + 4 * 16;
+  size_t qoff = 0, params = 64, bar = 128, xbar = 256, error = 256 + 8 * 128, live = error + 4, qctr = live + 8,
+         bytes = qctr + 4 * 16;
 };
 
 int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double dt0, int64_t max_steps,
@@ -1810,8 +1823,11 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     for (int i : active) {
       hode::EnsInst& I = e->inst[i];
       I.pause_at = I.ctrl.attempts + rounds;
+      I.ntiles = 0;
+      I.last_done = 0;
       need_d1 = need_d1 || !I.k1_valid;
     }
+    for (const hode::EnsTile& tl : tiles) ++e->inst[tl.inst].ntiles;
     const hode::EnsParams prm{rounds, need_d1 ? 1 : 0, e->n, 0};
     HIPCHK(c, hipMemcpy(e->d_tiles, tiles.data(), sizeof(hode::EnsTile) * tiles.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemsetAsync(sb + L.bar, 0, L.bytes - L.bar, c->stream));
@@ -1826,6 +1842,7 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
                          (const int32_t*)(sb + L.qoff),
                          (uint32_t*)(sb + L.qctr),
                          (uint64_t*)(sb + L.bar),
+                         (uint64_t*)(sb + L.xbar),
                          (uint32_t*)(sb + L.live),
                          (uint32_t*)(sb + L.error),
                          (const hode::EnsParams*)(sb + L.params),

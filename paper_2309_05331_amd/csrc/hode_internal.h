@@ -104,10 +104,12 @@ hipError_t launch_ew_rhs(int dtype, int rhs, const void* y, void* out, int64_t n
 struct EnsInst {
   GSLaunch a;
   DevCtrl ctrl;
-  int64_t pause_at;  // the instance sits out the rest of a launch once ctrl.attempts reaches this
-  int32_t vw;        // cells per lane for this instance's tiles
-  int32_t k1_valid;  // k1 = f(y) is already in the first-same-as-last slot (resumed instance)
-  int32_t seg;       // > 1: segmented rows (vw = 16 bytes / element, one row per 64/seg lanes)
+  int64_t pause_at;   // the instance sits out the rest of a launch once ctrl.attempts reaches this
+  int32_t vw;         // cells per lane for this instance's tiles
+  int32_t k1_valid;   // k1 = f(y) is already in the first-same-as-last slot (resumed instance)
+  int32_t seg;        // > 1: segmented rows (vw = 16 bytes / element, one row per 64/seg lanes)
+  int32_t ntiles;     // tiles of this instance in a stage phase
+  uint32_t last_done; // last-stage tiles of the current round finished (zero at launch)
   int32_t pad;
 };
 
@@ -131,7 +133,8 @@ struct EnsSched {
   const EnsTile* tiles;     // tiles, grouped in eight queues (one per XCD)
   const int32_t* qoff;      // queue x holds tiles[qoff[x] .. qoff[x+1])
   uint32_t* qctr;           // claim counters: two alternating sets of 8 (zero at launch)
-  uint64_t* bar;            // grid barrier arrivals (zero at launch)
+  uint64_t* bar;            // grid barrier: XCDs whose workgroups have all arrived (zero at launch)
+  uint64_t* xbar;           // grid barrier: arrivals per XCD, one 128-byte line each (zero at launch)
   uint32_t* live;           // instances still running after a round: two alternating (zero at launch)
   uint32_t* error;          // set when a barrier waited past spin_limit
   const EnsParams* params;
