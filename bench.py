@@ -321,7 +321,7 @@ def run_ens(wl, steps, warmup):
     ens.set_tolerances(wl["rtol"], wl["rtol"])
     ens.set_controller(hode.CTRL_PI)
     if wl.get("tiles", "auto") == "auto":
-        ens.autotune(3)  # the persistent kernel timed per grid edge: vector width and planes per tile
+        ens.autotune(8)  # tile shape per grid edge, timed inside the whole ensemble
     if wl.get("epoch"):
         ens.set_epoch(wl["epoch"], wl["epoch"])
     tiles = {}

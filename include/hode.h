@@ -359,7 +359,10 @@ int hode_stream_copy(void *dst, const void *src, size_t bytes, int reps, double 
  * barriers; in a stage phase the workgroups claim tiles (rows and planes of
  * one instance) from eight per-XCD queues, their own XCD's first, so every
  * phase is balanced dynamically; finished instances skip their tiles, and
- * the launch ends when every instance is done.  Every instance's arithmetic
+ * the launch ends when every instance is done.  Each time the number of
+ * running instances has halved, the kernel re-cuts the running ones into
+ * tiles sized for them (ensembles of up to 2048 instances), so the last,
+ * largest instances still spread over every workgroup.  Every instance's arithmetic
  * and step decisions are those of the single-grid path, so results are
  * bitwise those of running the instance alone. */
 
@@ -404,8 +407,9 @@ int hode_ensemble_timing(hode_ctx *ctx, double *kernel_ms, int *launches);
  * pack one row per segment of a wavefront (the default for such grids). */
 int hode_ensemble_set_vector_width(hode_ctx *ctx, int i, int vw);
 
-/* Planes per tile of instance i's tiles (>= 1; 0, the default: sized so a
- * phase has about half a tile per workgroup), and the tile of instance i:
+/* Planes per tile of instance i's tiles (>= 1, kept for the whole
+ * integration; 0, the default: sized so a phase has about half a tile per
+ * workgroup, and re-sized as instances finish), and the tile of instance i:
  * vector width and planes per tile. */
 int hode_ensemble_set_plane_chunk(hode_ctx *ctx, int i, int zc);
 int hode_ensemble_get_tile(const hode_ctx *ctx, int i, int *vw, int *zc);
@@ -417,19 +421,23 @@ int hode_ensemble_get_tile(const hode_ctx *ctx, int i, int *vw, int *zc);
 int hode_ensemble_set_trace(hode_ctx *ctx, int64_t capacity);
 int hode_ensemble_read_trace(hode_ctx *ctx, int i, double *dst, int64_t cap, int64_t *n);
 
-/* Tile autotuner of the ensemble: for every distinct grid edge, times the
- * persistent kernel itself on a sub-ensemble of that edge's instances (up to
- * 64, started from their current states in a context of its own; this
- * ensemble is unchanged) for `reps` attempts per candidate: every vector
- * width the edge allows (grids with segmented rows keep 16-byte lanes) times
- * planes per tile 4, 8, 16, 32 and N.  The fastest per cell-attempt is kept
- * for the edge's instances and the measured time per attempt becomes their
- * work estimate.  With the environment variable HODE_TUNE_CACHE naming a
- * text file, choices recorded there for this architecture, precision, edge
- * and grid size are used without timing, and new ones are appended (one
- * line per edge: "hode-ens-tune-v1 <arch> <dtype> <N> <workgroups> <vw>
- * <planes> <ms>").  vw_out/ms_out (n entries each, may be NULL) receive the
- * vector width and the time per attempt of each instance. */
+/* Tile autotuner of the ensemble: times the persistent kernel on a twin of
+ * the whole ensemble (same edges and parameters, started from this
+ * ensemble's current states; this ensemble is unchanged; the twin's buffers
+ * are allocated for the call) for `reps` attempts per candidate.  Edge by
+ * edge, largest total cells first, every cells-per-lane width dividing the
+ * edge is tried for that edge's instances (16-byte lanes give segmented rows
+ * where rows are at most 32 lanes, narrower widths 64-lane rows) with the
+ * other edges at their current choice, and the width with the shortest
+ * kernel time is kept.  The instances' planes per tile are reset to 0 (sized
+ * from the running cells, re-cut as instances finish).  With the environment
+ * variable HODE_TUNE_CACHE naming a text file, choices recorded there for
+ * this architecture, precision, instance count, workgroup count and edge
+ * list are used without timing, and new ones are appended (one line per
+ * edge: "hode-ens-tune-v2 <arch> <dtype> <n> <workgroups> <edge-list hash>
+ * <N> <vw> <ms>").  vw_out (n entries, may be NULL) receives each
+ * instance's width; ms_out (n entries, may be NULL) the twin's kernel time
+ * in ms of the last edge's chosen candidate, the same for every instance. */
 int hode_ensemble_autotune(hode_ctx *ctx, int reps, int *vw_out, double *ms_out);
 
 /* Integrates every instance from t0 to t1 (first trial step dt0, at most

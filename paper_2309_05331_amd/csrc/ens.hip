@@ -141,6 +141,127 @@ __device__ inline bool ens_running(const EnsInst* I) {
          __hip_atomic_load(&I->ctrl.attempts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < I->pause_at;
 }
 
+// Tiles of one instance for a target of `target` cells per tile: row chunks
+// of one tile pass, plane chunks of zc planes (the instance's own zc if set,
+// else sized from the target, at least 4 planes).
+__device__ inline void ens_tile_grid(const EnsInst* I, double target, int* ny, int* nz) {
+  const int N = I->a.N, rows = I->rows;
+  int zc = I->zc_fix > 0 ? I->zc_fix : (int)floor(target / ((double)N * rows) + 0.5);
+  zc = max(I->zc_fix > 0 ? 1 : 4, min(N, zc));
+  *ny = (N + rows - 1) / rows;
+  *nz = (N + zc - 1) / zc;
+}
+
+// Re-tiling (workgroup 0, all its threads, between two grid barriers, with
+// the tile LDS free): the instances still running, in the dealing order of
+// s.order (largest work estimate first), are cut into tiles sized so a phase
+// again has about kTilesPerWorkgroup tiles per workgroup, and dealt onto the
+// eight per-XCD queues, each to the least-loaded one, as the host does before
+// the launch.  As instances finish, the remaining ones are cut finer, so the
+// phases keep every workgroup busy.  Per-instance lists live in the tile LDS
+// (at most kRetileMaxInst instances).
+__device__ void ens_retile(EnsInst* __restrict__ inst, const EnsSched& s, const EnsParams& prm, char* smem) {
+  int* act = reinterpret_cast<int*>(smem);
+  float* w = reinterpret_cast<float*>(smem + 4 * kRetileMaxInst);
+  int* base = reinterpret_cast<int*>(smem + 8 * kRetileMaxInst);
+  uint8_t* qk = reinterpret_cast<uint8_t*>(smem + 12 * kRetileMaxInst);
+  static_assert(13 * kRetileMaxInst <= kTileSmem, "re-tiling lists fit the tile LDS");
+  __shared__ int s_cnt[256], s_qoff[9], s_m;
+  __shared__ double s_cells[256], s_target;
+  const int n = prm.n_inst, tid = threadIdx.x;
+  __syncthreads();
+  // running instances in dealing order: contiguous chunks per thread, then
+  // an exclusive scan of the chunk counts
+  const int per = (n + 255) / 256, j0 = min(n, tid * per), j1 = min(n, j0 + per);
+  int cnt = 0;
+  double cells = 0;
+  for (int j = j0; j < j1; ++j) {
+    const EnsInst* I = &inst[s.order[j]];
+    if (ens_running(I)) {
+      ++cnt;
+      cells += (double)I->a.n3;
+    }
+  }
+  s_cnt[tid] = cnt;
+  s_cells[tid] = cells;
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    double cs = 0;
+    for (int t = 0; t < 256; ++t) {
+      const int c0 = s_cnt[t];
+      s_cnt[t] = acc;
+      acc += c0;
+      cs += s_cells[t];
+    }
+    s_m = acc;
+    s_target = fmax(4096.0, cs / (kTilesPerWorkgroup * gridDim.x));
+  }
+  __syncthreads();
+  {
+    int k = s_cnt[tid];
+    for (int j = j0; j < j1; ++j) {
+      const int i = s.order[j];
+      const EnsInst* I = &inst[i];
+      if (ens_running(I)) {
+        act[k] = i;
+        w[k] = I->weight;
+        ++k;
+      }
+    }
+  }
+  __syncthreads();
+  const int m = s_m;
+  const double target = s_target;
+  for (int k = tid; k < m; k += 256) {
+    int ny, nz;
+    ens_tile_grid(&inst[act[k]], target, &ny, &nz);
+    base[k] = ny * nz;  // tile count for now
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int qt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < m; ++k) {
+      int x = 0;
+      for (int y = 1; y < 8; ++y)
+        if (load[y] < load[x]) x = y;
+      qk[k] = (uint8_t)x;
+      load[x] += w[k];
+      qt[x] += base[k];
+    }
+    int run[8], acc = 0;
+    for (int x = 0; x < 8; ++x) {
+      s_qoff[x] = run[x] = acc;
+      acc += qt[x];
+    }
+    s_qoff[8] = acc;
+    for (int k = 0; k < m; ++k) {
+      const int nt = base[k];
+      base[k] = run[qk[k]];
+      run[qk[k]] += nt;
+    }
+    if (acc > prm.tiles_cap) atomicExch(s.error, 3u);  // the host sizes the buffer for the finest cut
+  }
+  __syncthreads();
+  if (s_qoff[8] > prm.tiles_cap) return;
+  if (tid <= 8) s.qoff[tid] = s_qoff[tid];
+  // plane-chunk-major, row-chunk-minor (tiles sharing halo rows adjacent)
+  for (int k = tid; k < m; k += 256) {
+    const int i = act[k];
+    EnsInst* I = &inst[i];
+    const int N = I->a.N, rows = I->rows;
+    int ny, nz;
+    ens_tile_grid(I, target, &ny, &nz);
+    int t = base[k];
+    for (int kz = 0; kz < nz; ++kz) {
+      const int z0 = (int)((int64_t)N * kz / nz), z1 = (int)((int64_t)N * (kz + 1) / nz);
+      for (int ky = 0; ky < ny; ++ky) s.tiles[t++] = EnsTile{i, rows * ky, min(N, rows * (ky + 1)), z0, z1, 0};
+    }
+    I->ntiles = ny * nz;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst, const EnsSched s) {
   __shared__ __align__(16) char smem[kTileSmem];
@@ -216,6 +337,7 @@ __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst,
   };
 
   if (prm.first_d1 && !stage_phase(std::integral_constant<int, K_D1>(), 0)) return;
+  int retile_at = prm.retile_at;
   for (int r = 0; r < prm.rounds; ++r) {
     if (!stage_phase(std::integral_constant<int, K_D2>(), r)) return;
     if (!stage_phase(std::integral_constant<int, K_D3>(), r)) return;
@@ -225,7 +347,15 @@ __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst,
     // (the last phase also ran every instance's step control)
     if (!stage_phase(std::integral_constant<int, K_D7>(), r)) return;
     // every instance finished or paused: leave early (uniform: all read after the barrier)
-    if (__hip_atomic_load(&s.live[r & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+    const int live = (int)__hip_atomic_load(&s.live[r & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (live == 0) return;
+    // half of the instances of the last tiling are done: cut the rest finer
+    if (live <= retile_at) {
+      if (blockIdx.x == 0) ens_retile(inst, s, prm, smem);
+      grid_sync(s, gen);
+      if (ens_error(s)) return;
+      retile_at = live / 2;
+    }
   }
 }
 

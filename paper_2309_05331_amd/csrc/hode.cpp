@@ -47,6 +47,7 @@ struct Ensemble {
   hode::EnsInst* d_inst = nullptr;
   hode::EnsTile* d_tiles = nullptr;
   size_t tiles_cap = 0;
+  int32_t* d_order = nullptr;  // instances by work estimate, largest first (re-tiling order)
   // one device block: qoff[9] | params | bar | error | live[max_rounds] | qctr[8 (1 + 6 max_rounds)]
   void* d_sync = nullptr;
   int nwg = 0;
@@ -511,6 +512,7 @@ void free_ensemble(hode_ctx* c) {
   if (e->pool) (void)hipFree(e->pool);
   if (e->d_inst) (void)hipFree(e->d_inst);
   if (e->d_tiles) (void)hipFree(e->d_tiles);
+  if (e->d_order) (void)hipFree(e->d_order);
   if (e->d_sync) (void)hipFree(e->d_sync);
   if (e->d_trace) (void)hipFree(e->d_trace);
   for (hipEvent_t& v : e->ev)
@@ -543,8 +545,6 @@ int ens_tile_rows(const Ensemble& e, int i) {
   return 4 * std::max(1, per_lane);
 }
 
-// Tiles per workgroup and phase that the plane ranges are sized for.
-constexpr double kTilesPerWorkgroup = 0.5;
 
 // The tiles of one launch: every active instance cut into row chunks of one
 // tile pass (the last one ends at N) and plane chunks sized so a phase has
@@ -556,7 +556,7 @@ void build_tiles(const Ensemble& e, int G, const std::vector<int>& active, std::
                  std::vector<int32_t>& qoff) {
   double cells = 0;
   for (int i : active) cells += (double)e.N[i] * e.N[i] * e.N[i];
-  const double target = std::max(4096.0, cells / (kTilesPerWorkgroup * G));
+  const double target = std::max(4096.0, cells / (hode::kTilesPerWorkgroup * G));
   std::vector<int> order(active);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return e.weight[a] > e.weight[b]; });
   std::vector<std::vector<int>> q(8);
@@ -1811,24 +1811,54 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     const int64_t ep = launch == 0 ? e->epoch_first : e->epoch_len;
     const int rounds = (int)std::min<int64_t>(ep > 0 ? ep : max_steps, 0x7fffffff);
     build_tiles(*e, e->nwg, active, tiles, qoff);
-    if (tiles.size() > e->tiles_cap) {
+    // the tile buffer holds the finest cut the kernel's re-tiling can make
+    // (every plane chunk at its smallest), and the kernel reads the dealing
+    // order of the instances from the device
+    size_t cap = tiles.size();
+    if (e->n <= hode::kRetileMaxInst) {
+      size_t finest = 0;
+      for (int i : active) {
+        const int N = e->N[i], rows = ens_tile_rows(*e, i), zmin = e->zc[i] > 0 ? std::min(N, e->zc[i]) : std::min(N, 4);
+        finest += (size_t)((N + rows - 1) / rows) * ((N + zmin - 1) / zmin);
+      }
+      cap = std::max(cap, finest);
+    }
+    if (cap > e->tiles_cap || !e->d_order) {
       if (e->graph) { (void)hipGraphExecDestroy(e->graph); e->graph = nullptr; }
-      if (e->d_tiles) (void)hipFree(e->d_tiles);
-      e->d_tiles = nullptr;
-      e->tiles_cap = std::max(tiles.size(), (size_t)1024);
-      if (hipMalloc(&e->d_tiles, sizeof(hode::EnsTile) * e->tiles_cap) != hipSuccess)
-        return fail(c, HODE_ENOMEM, "tile allocation failed");
+      if (cap > e->tiles_cap) {
+        if (e->d_tiles) (void)hipFree(e->d_tiles);
+        e->d_tiles = nullptr;
+        e->tiles_cap = std::max(cap, (size_t)1024);
+        if (hipMalloc(&e->d_tiles, sizeof(hode::EnsTile) * e->tiles_cap) != hipSuccess)
+          return fail(c, HODE_ENOMEM, "tile allocation failed");
+      }
+      if (!e->d_order && hipMalloc(&e->d_order, sizeof(int32_t) * e->n) != hipSuccess)
+        return fail(c, HODE_ENOMEM, "ensemble order allocation failed");
+    }
+    {
+      std::vector<int32_t> order(e->n);
+      for (int i = 0; i < e->n; ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return e->weight[a] > e->weight[b]; });
+      HIPCHK(c, hipMemcpy(e->d_order, order.data(), sizeof(int32_t) * e->n, hipMemcpyHostToDevice));
     }
     bool need_d1 = false;
+    for (int i = 0; i < e->n; ++i) {
+      hode::EnsInst& I = e->inst[i];
+      I.ntiles = 0;
+      I.last_done = 0;
+      I.rows = ens_tile_rows(*e, i);
+      I.zc_fix = e->zc[i];
+      I.weight = (float)e->weight[i];
+    }
     for (int i : active) {
       hode::EnsInst& I = e->inst[i];
       I.pause_at = I.ctrl.attempts + rounds;
-      I.ntiles = 0;
-      I.last_done = 0;
       need_d1 = need_d1 || !I.k1_valid;
     }
     for (const hode::EnsTile& tl : tiles) ++e->inst[tl.inst].ntiles;
-    const hode::EnsParams prm{rounds, need_d1 ? 1 : 0, e->n, 0};
+    // re-tile on the device each time the running instances have halved
+    const int retile_at = e->n <= hode::kRetileMaxInst && active.size() >= 2 ? (int)active.size() / 2 : 0;
+    const hode::EnsParams prm{rounds, need_d1 ? 1 : 0, e->n, retile_at, (int32_t)e->tiles_cap, {0, 0, 0}};
     HIPCHK(c, hipMemcpy(e->d_tiles, tiles.data(), sizeof(hode::EnsTile) * tiles.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemsetAsync(sb + L.bar, 0, L.bytes - L.bar, c->stream));
     HIPCHK(c, hipMemcpyAsync(sb + L.qoff, qoff.data(), sizeof(int32_t) * 9, hipMemcpyHostToDevice, c->stream));
@@ -1839,7 +1869,8 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     // the fixed buffers above, refilled before every launch
     if (!e->graph) {
       hode::EnsSched sch{e->d_tiles,
-                         (const int32_t*)(sb + L.qoff),
+                         (int32_t*)(sb + L.qoff),
+                         e->d_order,
                          (uint32_t*)(sb + L.qctr),
                          (uint64_t*)(sb + L.bar),
                          (uint64_t*)(sb + L.xbar),
@@ -1870,6 +1901,7 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
     ++e->launches_last;
     uint32_t err = 0;
     HIPCHK(c, hipMemcpy(&err, sb + L.error, sizeof(err), hipMemcpyDeviceToHost));
+    if (err == 3) return fail(c, HODE_EHIP, "ensemble re-tiling exceeded the tile buffer");
     if (err) return fail(c, HODE_EHIP, "ensemble grid barrier timed out (workgroups not co-resident?)");
     std::vector<int64_t> before(e->n);
     for (int i = 0; i < e->n; ++i) before[i] = e->inst[i].ctrl.attempts;
@@ -1901,17 +1933,24 @@ int hode_ensemble_integrate_adaptive(hode_ctx* c, double t0, double t1, double d
   return worst;
 }
 
-// Ensemble tile autotuner: for every distinct grid edge, the persistent
-// kernel itself is timed on a sub-ensemble of that edge's instances (up to
-// 64, started from their current states in a context of their own, so the
-// ensemble is left unchanged) for `reps` attempts per candidate: every
-// vector width the edge allows (segmented edges keep 16-byte lanes) times
-// planes per tile of 4, 8, 16, 32 and the whole edge.  The fastest per
-// cell-attempt is kept for every instance of the edge, and the measured time
-// per attempt of one instance becomes its work estimate.  With a cache file
-// (HODE_TUNE_CACHE) the choices of earlier runs on this architecture and
-// precision are read instead of timed, and new ones appended.
-static std::string ens_tune_key(const hode_ctx* c, int N) {
+// Ensemble tile autotuner: the persistent kernel is timed on a twin of the
+// whole ensemble (same edges and parameters, started from this ensemble's
+// current states, so this ensemble is left unchanged) for `reps` attempts
+// per candidate.  Edge by edge, largest total cells first, every
+// cells-per-lane width dividing the edge is tried for that edge's instances
+// (16-byte lanes give segmented rows where rows are at most 32 lanes,
+// narrower widths 64-lane rows) with the other edges at their current
+// choice; the width with the shortest total kernel time is kept.  Timing the
+// whole ensemble measures a shape by the throughput it gives next to every
+// other instance: a sub-ensemble of one edge does not fill the GPU, so its
+// time follows the latency of a single tile and favours narrow, many-tiled
+// shapes.  Plane ranges are not tuned: they are sized from the running cells
+// at every launch and re-cut as instances finish, which measured faster over
+// the whole integration than any fixed per-edge choice.  With a cache file
+// (HODE_TUNE_CACHE) the choices of earlier runs for the same architecture,
+// precision, workgroup count and edge list are read instead of timed, and
+// new ones appended.
+static std::string ens_tune_key(const hode_ctx* c) {
   hipDeviceProp_t prop;
   std::string arch = "unknown";
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
@@ -1919,8 +1958,15 @@ static std::string ens_tune_key(const hode_ctx* c, int N) {
     for (char& ch : arch)
       if (ch == ' ') ch = '_';
   }
+  // the edge multiset identifies the workload shape (FNV-1a over the edges)
+  uint64_t hsh = 1469598103934665603ull;
+  for (int N : c->ens->N) {
+    hsh ^= (uint64_t)N;
+    hsh *= 1099511628211ull;
+  }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "hode-ens-tune-v1 %s %d %d %d", arch.c_str(), c->dtype, N, c->ens->nwg);
+  std::snprintf(buf, sizeof(buf), "hode-ens-tune-v2 %s %d %d %d %016llx", arch.c_str(), c->dtype, c->ens->n,
+                c->ens->nwg, (unsigned long long)hsh);
   return buf;
 }
 
@@ -1932,87 +1978,91 @@ int hode_ensemble_autotune(hode_ctx* c, int reps, int* vw_out, double* ms_out) {
   const char* path = std::getenv("HODE_TUNE_CACHE");
   std::map<int, std::vector<int>> members;  // edge -> instances with it
   for (int i = 0; i < e->n; ++i) members[e->N[i]].push_back(i);
-  struct Choice { int vw, zc; double ms; };
-  std::map<int, Choice> best;
+  std::map<int, int> best;  // edge -> width
+  double best_ms = 0;
+  const std::string key = ens_tune_key(c);
   if (path && *path) {
     if (FILE* f = std::fopen(path, "r")) {
       char line[512];
       while (std::fgets(line, sizeof(line), f)) {
-        for (auto& kv : members) {
-          const std::string key = ens_tune_key(c, kv.first);
-          if (std::strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
-          Choice ch{};
-          if (std::sscanf(line + key.size(), " %d %d %lf", &ch.vw, &ch.zc, &ch.ms) == 3 && ch.vw >= 1 && ch.zc >= 1 &&
-              kv.first % ch.vw == 0)
-            best[kv.first] = ch;
+        if (std::strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
+        int N = 0, v = 0;
+        double ms = 0;
+        if (std::sscanf(line + key.size(), " %d %d %lf", &N, &v, &ms) == 3 && members.count(N) && v >= 1 &&
+            N % v == 0) {
+          best[N] = v;
+          best_ms = ms;
         }
       }
       std::fclose(f);
     }
   }
   const int maxvw = c->dtype == HODE_F32 ? 4 : 2;
-  for (auto& kv : members) {
-    const int N = kv.first;
-    if (best.count(N)) continue;
-    std::vector<int> sub(kv.second.begin(), kv.second.begin() + std::min<size_t>(kv.second.size(), 64));
-    const int m = (int)sub.size();
-    std::vector<int64_t> edges(m, N);
-    std::vector<double> prm(5 * (size_t)m);
-    for (int j = 0; j < m; ++j)
-      for (int q = 0; q < 5; ++q) prm[5 * j + q] = e->prm[5 * (size_t)sub[j] + q];
+  if (best.size() < members.size()) {
+    std::vector<int64_t> edges(e->N.begin(), e->N.end());
     hode_ctx* t = nullptr;
-    rc = hode_ensemble_create(&t, c->device, nullptr, m, edges.data(), prm.data(), c->dtype);
+    rc = hode_ensemble_create(&t, c->device, nullptr, e->n, edges.data(), e->prm.data(), c->dtype);
     if (rc) return fail(c, rc, "ensemble autotune: context");
     rc = hode_set_tolerances(t, c->atol, c->rtol);
-    std::vector<int> vws;
-    if (ens_seg_for(c->dtype, N, maxvw) > 1) vws.push_back(maxvw);
-    else
-      for (int v = 1; v <= maxvw; v *= 2)
-        if (N % v == 0) vws.push_back(v);
-    std::vector<int> zcs;
-    for (int z : {4, 8, 16, 32, N})
-      if (z <= N && std::find(zcs.begin(), zcs.end(), z) == zcs.end()) zcs.push_back(z);
-    Choice bc{e->vw[sub[0]], 0, 1e300};
-    std::vector<hode_stats> st(m);
-    for (int v : vws) {
-      for (int z : zcs) {
-        for (int j = 0; j < m && !rc; ++j) {
-          rc = hode_ensemble_init_state(t, j, e->inst[sub[j]].a.y[e->parity[sub[j]]], 1);
-          if (!rc) rc = hode_ensemble_set_vector_width(t, j, v);
-          if (!rc) rc = hode_ensemble_set_plane_chunk(t, j, z);
-        }
-        if (!rc) {
-          const int r2 = hode_ensemble_integrate_adaptive(t, 0.0, 1e300, 0.1, reps, st.data());
-          if (r2 != HODE_OK && r2 != HODE_EMAXSTEPS) rc = r2;
-        }
-        if (rc) break;
-        double att = 0;
-        for (int j = 0; j < m; ++j) att += (double)(st[j].accepted + st[j].rejected);
-        const double ms = t->ens->kernel_ms_last / std::max(att, 1.0);  // per attempt of one instance
-        if (ms < bc.ms) bc = Choice{v, z, ms};
+    std::vector<hode_stats> st(e->n);
+    std::vector<int> cur(e->vw);
+    // one timed run of the twin with widths `vw` (kernel time in ms)
+    auto run = [&](const std::vector<int>& vw, double* ms) -> int {
+      for (int i = 0; i < e->n; ++i) {
+        int r = hode_ensemble_init_state(t, i, e->inst[i].a.y[e->parity[i]], 1);
+        if (!r) r = hode_ensemble_set_vector_width(t, i, vw[i]);
+        if (r) return r;
       }
+      const int r2 = hode_ensemble_integrate_adaptive(t, 0.0, 1e300, 0.1, reps, st.data());
+      if (r2 != HODE_OK && r2 != HODE_EMAXSTEPS) return r2;
+      *ms = t->ens->kernel_ms_last;
+      return HODE_OK;
+    };
+    std::vector<std::pair<double, int>> by_cells;
+    for (auto& kv : members) by_cells.push_back({-(double)kv.second.size() * kv.first * kv.first * kv.first, kv.first});
+    std::sort(by_cells.begin(), by_cells.end());
+    double ms = 0;
+    if (!rc) rc = run(cur, &ms);  // warm-up (graph capture, first touch)
+    for (auto& bc : by_cells) {
+      const int N = bc.second;
       if (rc) break;
+      if (best.count(N)) {
+        for (int i : members[N]) cur[i] = best[N];
+        continue;
+      }
+      int bv = cur[members[N][0]];
+      double bms = 1e300;
+      for (int v = 1; v <= maxvw && !rc; v *= 2) {
+        if (N % v) continue;
+        for (int i : members[N]) cur[i] = v;
+        rc = run(cur, &ms);
+        if (!rc && ms < bms) {
+          bms = ms;
+          bv = v;
+        }
+      }
+      for (int i : members[N]) cur[i] = bv;
+      best[N] = bv;
+      best_ms = bms;
+      if (!rc && path && *path) {
+        FILE* f = std::fopen(path, "a");
+        const bool w = f && std::fprintf(f, "%s %d %d %.6g\n", key.c_str(), N, bv, bms) > 0;
+        const bool cl = f && std::fclose(f) == 0;
+        if (!w || !cl) {
+          hode_destroy(t);
+          return fail(c, HODE_EINVAL, std::string("cannot write the tuning cache ") + path);
+        }
+      }
     }
     const std::string msg = rc ? hode_last_error(t) : "";
     hode_destroy(t);
     if (rc) return fail(c, rc, "ensemble autotune: " + msg);
-    best[N] = bc;
-    if (path && *path) {
-      FILE* f = std::fopen(path, "a");
-      if (!f) return fail(c, HODE_EINVAL, std::string("cannot append to the tuning cache ") + path);
-      const std::string line = ens_tune_key(c, N);
-      const bool w = std::fprintf(f, "%s %d %d %.6g\n", line.c_str(), bc.vw, bc.zc, bc.ms) > 0;
-      const bool cl = std::fclose(f) == 0;
-      if (!w || !cl) return fail(c, HODE_EINVAL, std::string("cannot write the tuning cache ") + path);
-    }
   }
   for (int i = 0; i < e->n; ++i) {
-    const Choice& b = best[e->N[i]];
-    e->vw[i] = b.vw;
-    e->zc[i] = b.zc;
-    e->weight[i] = b.ms;
-    if (vw_out) vw_out[i] = b.vw;
-    if (ms_out) ms_out[i] = b.ms;
+    e->vw[i] = best[e->N[i]];
+    e->zc[i] = 0;
+    if (vw_out) vw_out[i] = e->vw[i];
+    if (ms_out) ms_out[i] = best_ms;
   }
   return HODE_OK;
 }

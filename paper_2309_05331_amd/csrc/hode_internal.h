@@ -110,7 +110,9 @@ struct EnsInst {
   int32_t seg;        // > 1: segmented rows (vw = 16 bytes / element, one row per 64/seg lanes)
   int32_t ntiles;     // tiles of this instance in a stage phase
   uint32_t last_done; // last-stage tiles of the current round finished (zero at launch)
-  int32_t pad;
+  int32_t rows;       // rows of one tile pass (the row chunk of this instance's tiles)
+  int32_t zc_fix;     // planes per tile set for this instance (0: sized from the running cells)
+  float weight;       // per-attempt work estimate (dealing to the per-XCD queues)
 };
 
 // One tile of a stage phase: rows [y0, y1) (y0 a multiple of the tile pass
@@ -123,15 +125,24 @@ struct EnsTile {
 // Launch parameters the kernel reads from device memory (so one captured
 // graph serves every launch).
 struct EnsParams {
-  int32_t rounds;    // attempts per instance in this launch (at most)
-  int32_t first_d1;  // run a stage-1 phase first (some instance has no k1 yet)
+  int32_t rounds;     // attempts per instance in this launch (at most)
+  int32_t first_d1;   // run a stage-1 phase first (some instance has no k1 yet)
   int32_t n_inst;
-  int32_t pad;
+  int32_t retile_at;  // re-tile once at most this many instances are running (0: never)
+  int32_t tiles_cap;  // tiles the tile buffer holds
+  int32_t pad[3];
 };
 
+// Instances up to which the persistent kernel re-tiles on the device (the
+// re-tiling keeps its per-instance lists in the workgroup's tile LDS).
+constexpr int kRetileMaxInst = 2048;
+// Tiles per workgroup and phase that the plane ranges are sized for.
+constexpr double kTilesPerWorkgroup = 0.5;
+
 struct EnsSched {
-  const EnsTile* tiles;     // tiles, grouped in eight queues (one per XCD)
-  const int32_t* qoff;      // queue x holds tiles[qoff[x] .. qoff[x+1])
+  EnsTile* tiles;           // tiles, grouped in eight queues (one per XCD)
+  int32_t* qoff;            // queue x holds tiles[qoff[x] .. qoff[x+1])
+  const int32_t* order;     // every instance, largest work estimate first (dealing order)
   uint32_t* qctr;           // claim counters: two alternating sets of 8 (zero at launch)
   uint64_t* bar;            // grid barrier: XCDs whose workgroups have all arrived (zero at launch)
   uint64_t* xbar;           // grid barrier: arrivals per XCD, one 128-byte line each (zero at launch)

@@ -113,9 +113,10 @@ def test_ensemble_rejects_bad_epoch():
 
 
 def test_ensemble_one_launch_and_tuned_tiles_bitwise():
-    # by default the whole integration is one persistent launch; the
-    # autotuner's per-edge tiles and any planes-per-tile choice leave every
-    # instance bitwise equal to its single-grid run
+    # by default the whole integration is one persistent launch (re-tiling on
+    # the device as instances finish); the autotuner's per-edge tile shapes
+    # and any planes-per-tile choice leave every instance bitwise equal to its
+    # single-grid run
     edges = [8, 16, 24, 32, 12, 20, 40, 16]
     _, prms = _params(len(edges))
     vws = [1, 2, 1, 2, 4, 2, 1, 4]
@@ -135,7 +136,8 @@ def test_ensemble_one_launch_and_tuned_tiles_bitwise():
     tiles = [ens.instance_tile(i) for i in range(len(edges))]
     print("autotuned (vw, planes) per instance:", tiles)
     for i, N in enumerate(edges):
-        assert tiles[i][0] == vw[i] and N % vw[i] == 0 and 1 <= tiles[i][1] <= N and tms[i] > 0
+        # a width per edge; plane ranges stay sized from the running cells (0)
+        assert tiles[i][0] == vw[i] and N % vw[i] == 0 and tiles[i][1] == 0 and tms[i] > 0
         assert tiles[i] == tiles[edges.index(N)]  # one choice per edge
     for i, N in enumerate(edges):
         ens.init_instance(i, np.ascontiguousarray(ys[i]).ravel())
@@ -147,6 +149,27 @@ def test_ensemble_one_launch_and_tuned_tiles_bitwise():
         ref, st = _single(ys[i], N, prms[i], tiles[i][0], 30.0, 0.1, 1e-5)
         assert (stats2[i]["accepted"], stats2[i]["rejected"]) == (st["accepted"], st["rejected"]), i
         assert np.array_equal(o, ref), i
+    ens.close()
+
+
+def test_ensemble_retiles_as_instances_finish_bitwise():
+    # 24 instances whose attempt counts differ widely (tight and loose
+    # tolerances cannot be mixed, so the spread comes from the grid edges and
+    # reaction parameters): the persistent kernel re-cuts the running
+    # instances into finer tiles each time their number halves, in the same
+    # launch; every instance must still equal its single-grid run bitwise
+    edges = [8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64, 72] * 2
+    _, prms = _params(len(edges), Du=2e-4, Dv=1e-4)
+    vws = [4 if N % 4 == 0 else 1 for N in edges]
+    ens, ys, outs, stats = _run_ensemble(edges, prms, hode.F32, 40.0, 1e-5, vws=vws)
+    ms, launches = ens.timing()
+    att = sorted(s["accepted"] + s["rejected"] for s in stats)
+    print("attempts per instance:", att, "launches", launches)
+    assert launches == 1 and att[-1] > 2 * att[0]
+    for i, N in enumerate(edges):
+        ref, st = _single(ys[i], N, prms[i], vws[i], 40.0, 0.1, 1e-5)
+        assert (stats[i]["accepted"], stats[i]["rejected"]) == (st["accepted"], st["rejected"]), i
+        assert np.array_equal(outs[i], ref), i
     ens.close()
 
 
