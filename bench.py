@@ -226,30 +226,39 @@ def cpu_baseline_leg(wl, check=None, budget_s=10.0):
         err = oracle_error(oracle, wl, check)
         err["oracle_seconds"] = round(time.perf_counter() - t0, 1)
     if wl["kind"] == "gs":
-        Ns = min(wl["N"], 128)
+        # the workload's own grid and start, continued from call to call, k
+        # steps or attempts per call (about 2.5e8 cell-updates, so the
+        # oracle's per-call set-up of its stage arrays is shared by several;
+        # Adams-Bashforth on a 128^3 grid, each call restarting a history of 3
+        # Fehlberg start-up steps and 97 steps), at least two calls, each
+        # timed for the spread
+        Ns = wl["N"] if wl["method"] != "ab4" else min(wl["N"], 128)
+        k = 100 if wl["method"] == "ab4" else max(2, -(-250000000 // Ns ** 3))
         y = inputs.gray_scott_ic(Ns, seed=wl["seed"]).ravel()
         sysd = oracle.gs_system(Ns, *GS_PRM)
-        done, t0, units, t = 0, time.perf_counter(), 0, 0.0
-        while time.perf_counter() - t0 < budget_s:
-            if wl["method"] == "rk4":
-                y, t = oracle.integrate_n_steps(sysd, oracle.RK4, y, t, 0.1, 5)
-                units += 5 * Ns ** 3
-            elif wl["method"] == "ab4":
-                # one fresh history per call: 3 Fehlberg start-up steps, then 97 AB4 steps
-                y, t = oracle.integrate_n_steps(sysd, oracle.AB(4), y, t, wl["dt"], 100)
-                units += 100 * Ns ** 3
+        done, t0, units, t, dt, rates = 0, time.perf_counter(), 0, 0.0, wl.get("dt0", 0.1), []
+        while done < 2 or time.perf_counter() - t0 < budget_s:
+            tc, u = time.perf_counter(), 0
+            if wl["method"] in ("rk4", "ab4"):
+                y, t = oracle.integrate_n_steps(sysd, oracle.RK4 if wl["method"] == "rk4" else oracle.AB(4), y, t,
+                                                wl["dt"], k)
+                u = k * Ns ** 3
             else:
                 om = {"ck54": oracle.CASHKARP, "f78": oracle.FEHLBERG78}.get(wl["method"], oracle.DOPRI5)
-                y, st, _ = oracle.integrate_adaptive(sysd, y, t, 1e9, 0.3, 1e-6, 1e-6, max_steps=4, method=om)
-                t = st["t"]
-                units += st["accepted"] * Ns ** 3
+                y, st, _ = oracle.integrate_adaptive(sysd, y, t, 1e9, dt, 1e-6, 1e-6, max_steps=k, method=om)
+                t, dt = st["t"], st["dt_next"]
+                u = st["accepted"] * Ns ** 3
+            rates.append(u / (time.perf_counter() - tc))
+            units += u
             done += 1
         el = time.perf_counter() - t0
-        what = {"rk4": "RK4 steps", "dp5": "adaptive Dopri5 accepted steps",
-                "ck54": "adaptive Cash-Karp accepted steps", "f78": "adaptive Fehlberg 7(8) accepted steps",
-                "ab4": "Adams-Bashforth 4 steps (100 per call, each call with 3 Fehlberg start-up steps)"}[wl["method"]]
-        sample = "%s on a %d^3 grid (same parameters), %d calls, %.1f s" % (what, Ns, done, el)
+        what = {"rk4": "RK4 steps", "dp5": "adaptive Dopri5 attempts", "ck54": "adaptive Cash-Karp attempts",
+                "f78": "adaptive Fehlberg 7(8) attempts",
+                "ab4": "Adams-Bashforth 4 steps (each call with 3 Fehlberg start-up steps)"}[wl["method"]]
+        sample = "%s, %d per call, on the %d^3 grid of the workload (same start and parameters), %d calls, %.1f s" % (
+            what, k, Ns, done, el)
         unit = "cell-updates/s"
+        sd = float(np.std(rates, ddof=1))
     elif wl["kind"] == "ens":
         edges, F, k = inputs.ensemble_draws(wl["n"], seed=wl["seed"])
         t0, units, i, t = time.perf_counter(), 0, 0, 0.0
@@ -276,8 +285,11 @@ def cpu_baseline_leg(wl, check=None, budget_s=10.0):
         el = time.perf_counter() - t0
         sample = "%d adaptive Dopri5 runs t 0->5 on 2^20 components, %.1f s" % (reps, el)
         unit = "component-updates/s"
-    return ({"value": units / el, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle", "sample": sample,
-             "cpu_model": cpu_model()}, err)
+    cb = {"value": units / el, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle", "sample": sample,
+          "cpu_model": cpu_model()}
+    if wl["kind"] == "gs":
+        cb["sd_between_calls"] = sd
+    return cb, err
 
 
 def cpu_model():
