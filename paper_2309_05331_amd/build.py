@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhode.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-SOURCES = ["hode.cpp", "ew.hip", "gs.hip", "gsx.hip", "ens.hip", "copy.hip", "mlp.hip"]
+SOURCES = ["hode.cpp", "ew.hip", "gs.hip", "gsx.hip", "gsf.hip", "ens.hip", "copy.hip", "mlp.hip"]
 ARCH = os.environ.get("HODE_ARCH", "gfx950")
 
 

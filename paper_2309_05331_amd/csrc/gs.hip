@@ -41,18 +41,23 @@ bool gs_ry_supported(int ry) { return ry == 1 || ry == 2 || ry == 4; }
 bool gs_tile_supported(int kind, int dtype, int ry, int vw, int nw, int N) {
   if (!gs_ry_supported(ry)) return false;
   if (nw == 4) return true;
-  // eight wavefronts: the kinds of this file, one- and two-row strips,
-  // 16-byte lanes (vw 0 picks the widest lanes that divide N)
+  // eight wavefronts: the kinds of this file with one- and two-row strips,
+  // the Fehlberg kinds (gsf.hip) with one-row strips; 16-byte lanes (vw 0
+  // picks the widest lanes that divide N)
   const int wide = dtype == 1 ? 4 : 2;
   const int v = vw ? vw : (N % wide == 0 ? wide : 1);
-  return nw == 8 && kind <= K_COUNT && ry <= 2 && v == wide;
+  return nw == 8 && v == wide && ((kind <= K_COUNT && ry <= 2) || (gsf_kind(kind) && ry == 1));
 }
 
 // kind K_COUNT is the fixed-step stage 6 (new state only).  vw: cells per
 // lane (0 = widest that divides N: 16-byte loads when possible).  nw:
-// wavefronts per workgroup (4, or 8 for 16-byte lanes and ry <= 2).
+// wavefronts per workgroup (4, or 8 for 16-byte lanes and ry <= 2; the
+// Fehlberg kinds ry = 1).
 hipError_t launch_gs(int kind, int dtype, int ry, int vw, int nw, const GSLaunch& a, DevCtrl* c, hipStream_t s) {
-  if (kind > K_COUNT) return nw == 4 ? launch_gsx(kind, dtype, ry, vw, a, c, s) : hipErrorInvalidValue;
+  if (kind > K_COUNT) {
+    if (nw == 8) return launch_gsf8(kind, dtype, ry, vw, a, c, s);
+    return nw == 4 ? launch_gsx(kind, dtype, ry, vw, a, c, s) : hipErrorInvalidValue;
+  }
   if (a.N < 1 || a.zc < 1 || kind < 0) return hipErrorInvalidValue;
   if (dtype == 1) {
     if (vw == 0) vw = a.N % 4 == 0 ? 4 : (a.N % 2 == 0 ? 2 : 1);

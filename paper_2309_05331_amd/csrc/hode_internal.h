@@ -67,6 +67,10 @@ __host__ __device__ inline void* const* xk(const GSLaunch& a) { return (void* co
 hipError_t launch_gs(int kind, int dtype, int ry, int vw, int nw, const GSLaunch& a, DevCtrl* c, hipStream_t s);
 // The Fehlberg and Adams-Bashforth kinds (K_F1 .. K_AB8), four wavefronts.
 hipError_t launch_gsx(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s);
+// The Fehlberg kinds (K_F1 .. K_F13F) with eight wavefronts: one-row strips,
+// 16-byte lanes.
+hipError_t launch_gsf8(int kind, int dtype, int ry, int vw, const GSLaunch& a, DevCtrl* c, hipStream_t s);
+bool gsf_kind(int kind);
 bool gs_ry_supported(int ry);
 bool gs_tile_supported(int kind, int dtype, int ry, int vw, int nw, int N);
 

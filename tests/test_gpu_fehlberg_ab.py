@@ -214,12 +214,19 @@ def test_adams_bashforth_history_across_calls(orc, gs):
 
 @pytest.mark.parametrize("method", ["F78", "AB8", "AB3"])
 def test_new_stencil_kernels_tile_independent(orc, method):
-    N = 40
+    # every tile shape, eight-wavefront Fehlberg tiles included (N = 44: a
+    # ragged last row of eight-row tiles), gives bitwise the same steps
+    N = 44
     y0 = inputs.gray_scott_ic(N, seed=77)
     ref = None
     m = hode.FEHLBERG78 if method == "F78" else hode.AB(int(method[2]))
-    for tile in (None, (1, 8), (2, 16), (4, 40), (1, 13)):
-        ctx = gs_ctx(y0, N, PRM_D, tile=tile)
+    for tile in (None, (1, 8), (2, 16), (4, 44), (1, 13), (1, 16, 8), (1, 44, 8)):
+        ctx = gs_ctx(y0, N, PRM_D, tile=tile[:2] if tile else None)
+        if tile and len(tile) == 3:
+            ctx.set_tile_waves(tile[2])
+            ctx.set_tile(tile[0], tile[1])
+            if method == "F78":
+                assert ctx.kind_tile(hode.K_F[12])[2] == 8
         ctx.integrate_n_steps(m, 0.0, 0.01, 12)
         g = read(ctx, np.float64, 2 * N ** 3)
         ctx.close()

@@ -228,15 +228,19 @@ def test_eight_wavefront_tiles_bitwise(dtype):
             ctx.close()
         for o in outs[1:]:
             assert o[1:] == outs[0][1:] and np.array_equal(o[0], outs[0][0]), N
-    # kinds without eight-wavefront tiles (Fehlberg) keep four, and a vector
-    # width other than 16-byte lanes drops the others back to four
+    # kinds without eight-wavefront tiles at a row count (Fehlberg: one-row
+    # strips only; Adams-Bashforth: none) keep four, and a vector width other
+    # than 16-byte lanes drops the others back to four
     y0 = inputs.gray_scott_ic(64, seed=41, dtype=np.float32)
     ctx = gs_ctx(y0, 64, PRM_D)
     ctx.set_tile_waves(8)
     ctx.set_tile(1, 64)
+    assert ctx.kind_tile(hode.K_D6)[2] == 8 and ctx.kind_tile(hode.K_F[0])[2] == 8
+    assert ctx.kind_tile(hode.K_AB[3])[2] == 4
+    ctx.set_tile(2, 64)
     assert ctx.kind_tile(hode.K_D6)[2] == 8 and ctx.kind_tile(hode.K_F[0])[2] == 4
     ctx.set_vector_width(2)
-    assert ctx.kind_tile(hode.K_D6)[2] == 4
+    assert ctx.kind_tile(hode.K_D6)[2] == 4 and ctx.kind_tile(hode.K_F[0])[2] == 4
     with pytest.raises(hode.HodeError):
         ctx.set_tile_waves(16)
     ctx.close()
