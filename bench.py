@@ -227,13 +227,13 @@ def cpu_baseline_leg(wl, check=None, budget_s=10.0):
         err["oracle_seconds"] = round(time.perf_counter() - t0, 1)
     if wl["kind"] == "gs":
         # the workload's own grid and start, continued from call to call, k
-        # steps or attempts per call (about 2.5e8 cell-updates, so the
+        # steps or attempts per call (about 5e8 cell-updates, so the
         # oracle's per-call set-up of its stage arrays is shared by several;
         # Adams-Bashforth on a 128^3 grid, each call restarting a history of 3
         # Fehlberg start-up steps and 97 steps), at least two calls, each
         # timed for the spread
         Ns = wl["N"] if wl["method"] != "ab4" else min(wl["N"], 128)
-        k = 100 if wl["method"] == "ab4" else max(2, -(-250000000 // Ns ** 3))
+        k = 100 if wl["method"] == "ab4" else max(2, -(-500000000 // Ns ** 3))
         y = inputs.gray_scott_ic(Ns, seed=wl["seed"]).ravel()
         sysd = oracle.gs_system(Ns, *GS_PRM)
         done, t0, units, t, dt, rates = 0, time.perf_counter(), 0, 0.0, wl.get("dt0", 0.1), []
