@@ -45,3 +45,33 @@ def test_cache_miss_then_hit(tmp_path, monkeypatch):
     with pytest.raises(hode.HodeError):
         c.autotune_cached(hode.CASHKARP54, 1, tmp_path)  # a directory: cannot append
     c.close()
+
+
+def test_ensemble_tile_cache(tmp_path, monkeypatch):
+    # The ensemble's tile autotuner (timed inside the whole ensemble) appends
+    # one line per grid edge to HODE_TUNE_CACHE; a second ensemble of the same
+    # edge list reads the widths back without timing, and the file is
+    # unchanged.  Another edge list is another key.
+    edges = [16, 24, 16, 32, 24]
+    prms = [[2e-3, 1e-3, 0.04 + 0.002 * i, 0.06, 2.5] for i in range(len(edges))]
+    path = tmp_path / "ens.txt"
+    monkeypatch.setenv("HODE_TUNE_CACHE", str(path))
+
+    def tuned(es):
+        ens = hode.Ensemble(es, prms[:len(es)], dtype=hode.F32)
+        for i, N in enumerate(es):
+            ens.init_instance(i, inputs.ensemble_ic(i, N).ravel())
+        ens.set_tolerances(1e-5, 1e-5)
+        vw, ms = ens.autotune(2)
+        tiles = [ens.instance_tile(i) for i in range(len(es))]
+        ens.close()
+        return list(vw), tiles
+
+    vw1, t1 = tuned(edges)
+    lines = path.read_text().splitlines()
+    assert len(lines) == len(set(edges)) and all(l.startswith("hode-ens-tune-v2 ") for l in lines)
+    assert all(N % v == 0 for N, v in zip(edges, vw1)) and all(t[1] == 0 for t in t1)
+    vw2, t2 = tuned(edges)
+    assert vw2 == vw1 and t2 == t1 and path.read_text().splitlines() == lines
+    tuned(edges[:3])  # edges 16, 24, 16: another instance count and edge list
+    assert len(path.read_text().splitlines()) == len(lines) + 2
