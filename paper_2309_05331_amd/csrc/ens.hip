@@ -9,6 +9,12 @@ namespace hode {
 
 namespace {
 
+constexpr int kEnsThreads = 64 * kEnsNW;
+// LDS of the ensemble's largest tile: the row slots of two-row strips of
+// 16-byte lanes, and the x-halo cells of up to four-row strips of 8-byte
+// cells (every tile checks its own size against this).
+constexpr int kEnsSmem = 2 * 2 * (2 * kEnsNW + 2) * 64 * 16 + 2 * 2 * 2 * (kEnsNW * 4) * 8;
+
 // ---- the persistent ensemble kernel -------------------------------------------
 // One launch steps every unfinished instance for up to `rounds` attempts in
 // lock step (by default the whole integration: the launch ends when every
@@ -103,7 +109,8 @@ template <typename T, int KIND, int VW, int SEG = 1>
 __device__ __noinline__ void ens_tile_vw(EnsInst* I, char* smem, int y0, int y1, int z0, int z1) {
   // segmented rows: two register rows of SEG rows each (stage 6, the widest, one)
   constexpr int RY = SEG == 1 ? ens_rows<T, KIND, VW>() : (KIND == K_D6 ? 1 : 2);
-  constexpr int TY = 4 * RY * SEG;
+  constexpr int TY = kEnsNW * RY * SEG;
+  static_assert(tile_smem<T, VW, RY, kEnsNW, SEG>() <= kEnsSmem, "the tile fits the kernel's LDS");
   const GSLaunch a = uniform_copy(I->a);
   DevCtrl* c = uniform_copy(&I->ctrl);
   y0 = __builtin_amdgcn_readfirstlane(y0);
@@ -112,7 +119,7 @@ __device__ __noinline__ void ens_tile_vw(EnsInst* I, char* smem, int y0, int y1,
   z1 = __builtin_amdgcn_readfirstlane(z1);
   const int nx = (a.N + 64 * VW - 1) / (64 * VW);
   for (int ty = y0 / TY; ty * TY < y1; ++ty)
-    for (int tx = 0; tx < nx; ++tx) stage_tile<T, KIND, RY, VW, SEG>(a, c, smem, tx, ty, z0, z1);
+    for (int tx = 0; tx < nx; ++tx) stage_tile<T, KIND, RY, VW, SEG, kEnsNW>(a, c, smem, tx, ty, z0, z1);
 }
 
 template <typename T, int KIND>
@@ -165,14 +172,14 @@ __device__ void ens_retile(EnsInst* __restrict__ inst, const EnsSched& s, const 
   float* w = reinterpret_cast<float*>(smem + 4 * kRetileMaxInst);
   int* base = reinterpret_cast<int*>(smem + 8 * kRetileMaxInst);
   uint8_t* qk = reinterpret_cast<uint8_t*>(smem + 12 * kRetileMaxInst);
-  static_assert(13 * kRetileMaxInst <= kTileSmem, "re-tiling lists fit the tile LDS");
-  __shared__ int s_cnt[256], s_qoff[9], s_m;
-  __shared__ double s_cells[256], s_target;
+  static_assert(13 * kRetileMaxInst <= kEnsSmem, "re-tiling lists fit the tile LDS");
+  __shared__ int s_cnt[kEnsThreads], s_qoff[9], s_m;
+  __shared__ double s_cells[kEnsThreads], s_target;
   const int n = prm.n_inst, tid = threadIdx.x;
   __syncthreads();
   // running instances in dealing order: contiguous chunks per thread, then
   // an exclusive scan of the chunk counts
-  const int per = (n + 255) / 256, j0 = min(n, tid * per), j1 = min(n, j0 + per);
+  const int per = (n + kEnsThreads - 1) / kEnsThreads, j0 = min(n, tid * per), j1 = min(n, j0 + per);
   int cnt = 0;
   double cells = 0;
   for (int j = j0; j < j1; ++j) {
@@ -188,7 +195,7 @@ __device__ void ens_retile(EnsInst* __restrict__ inst, const EnsSched& s, const 
   if (tid == 0) {
     int acc = 0;
     double cs = 0;
-    for (int t = 0; t < 256; ++t) {
+    for (int t = 0; t < kEnsThreads; ++t) {
       const int c0 = s_cnt[t];
       s_cnt[t] = acc;
       acc += c0;
@@ -213,7 +220,7 @@ __device__ void ens_retile(EnsInst* __restrict__ inst, const EnsSched& s, const 
   __syncthreads();
   const int m = s_m;
   const double target = s_target;
-  for (int k = tid; k < m; k += 256) {
+  for (int k = tid; k < m; k += kEnsThreads) {
     int ny, nz;
     ens_tile_grid(&inst[act[k]], target, &ny, &nz);
     base[k] = ny * nz;  // tile count for now
@@ -247,7 +254,7 @@ __device__ void ens_retile(EnsInst* __restrict__ inst, const EnsSched& s, const 
   if (s_qoff[8] > prm.tiles_cap) return;
   if (tid <= 8) s.qoff[tid] = s_qoff[tid];
   // plane-chunk-major, row-chunk-minor (tiles sharing halo rows adjacent)
-  for (int k = tid; k < m; k += 256) {
+  for (int k = tid; k < m; k += kEnsThreads) {
     const int i = act[k];
     EnsInst* I = &inst[i];
     const int N = I->a.N, rows = I->rows;
@@ -263,8 +270,8 @@ __device__ void ens_retile(EnsInst* __restrict__ inst, const EnsSched& s, const 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst, const EnsSched s) {
-  __shared__ __align__(16) char smem[kTileSmem];
+__global__ __launch_bounds__(kEnsThreads, 1) void ens_kernel(EnsInst* __restrict__ inst, const EnsSched s) {
+  __shared__ __align__(16) char smem[kEnsSmem];
   __shared__ int s_claim, s_run, s_last;
   const EnsParams prm = *s.params;
   const int xcd = blockIdx.x & 7;  // workgroups are dealt round-robin to the 8 XCDs
@@ -363,15 +370,15 @@ __global__ __launch_bounds__(256, 2) void ens_kernel(EnsInst* __restrict__ inst,
 
 hipError_t launch_ensemble(int dtype, EnsInst* inst, EnsSched s, int nwg, hipStream_t st) {
   if (nwg < 1) return hipErrorInvalidValue;
-  if (dtype == 1) ens_kernel<float><<<nwg, 256, 0, st>>>(inst, s);
-  else ens_kernel<double><<<nwg, 256, 0, st>>>(inst, s);
+  if (dtype == 1) ens_kernel<float><<<nwg, kEnsThreads, 0, st>>>(inst, s);
+  else ens_kernel<double><<<nwg, kEnsThreads, 0, st>>>(inst, s);
   return hipGetLastError();
 }
 
 int ensemble_blocks_per_cu(int dtype) {
   int n = 0;
-  hipError_t e = dtype == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<float>, 256, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<double>, 256, 0);
+  hipError_t e = dtype == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<float>, kEnsThreads, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ens_kernel<double>, kEnsThreads, 0);
   return e == hipSuccess ? n : 0;
 }
 

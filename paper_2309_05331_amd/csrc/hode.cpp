@@ -534,15 +534,15 @@ int ens_seg_for(int dtype, int N, int vw) {
   return 64 / sl;
 }
 
-// Rows one pass of the ensemble's stage tiles covers for instance i (four
+// Rows one pass of the ensemble's stage tiles covers for instance i (kEnsNW
 // waves of 16 bytes of state per lane and field, or of two register rows of
 // seg rows each; stage 6 excepted): a tile of exactly this many rows needs
 // one pass, so no halo row of it is read twice.
 int ens_tile_rows(const Ensemble& e, int i) {
   const int seg = ens_seg_for(e.dtype, e.N[i], e.vw[i]);
-  if (seg > 1) return 8 * seg;
+  if (seg > 1) return 2 * hode::kEnsNW * seg;
   const int per_lane = (e.dtype == HODE_F32 ? 4 : 2) / e.vw[i];
-  return 4 * std::max(1, per_lane);
+  return hode::kEnsNW * std::max(1, per_lane);
 }
 
 

@@ -137,6 +137,10 @@ struct EnsParams {
   int32_t pad[3];
 };
 
+// Wavefronts per workgroup of the persistent ensemble kernel: eight, so a
+// tile pass covers twice the rows of a four-wavefront tile (half the halo
+// rows per cell) at the same occupancy (two waves per SIMD either way).
+constexpr int kEnsNW = 8;
 // Instances up to which the persistent kernel re-tiles on the device (the
 // re-tiling keeps its per-instance lists in the workgroup's tile LDS).
 constexpr int kRetileMaxInst = 2048;

@@ -278,14 +278,12 @@ __host__ __device__ constexpr int tile_smem() {
   return 2 * 2 * row_slots<RY, NW>() * 64 * (int)sizeof(Pk<T, VW>) +
          2 * 2 * 2 * (SEG == 1 ? NW * RY : 1) * (int)sizeof(T);
 }
-// The largest tile of four wavefronts (RY <= 4, 16-byte lanes): the LDS the
-// persistent ensemble kernel reserves for its tiles.
-constexpr int kTileSmem = 2 * 2 * 10 * 64 * 16 + 2 * 2 * 2 * 16 * 8;
 
 // One stage over one tile: columns x0 .. x0 + 64*VW - 1, rows ty*4*RY ..
 // (ty+1)*4*RY - 1, planes zbeg .. zend - 1 of the grid described by `a`, with
 // step h, parity and first-same-as-last slot taken from the control block.
-// Called by all 256 threads of a workgroup; smem is kTileSmem bytes of LDS.
+// Called by all 64*NW threads of a workgroup; smem holds at least
+// tile_smem<T, VW, RY, NW, SEG>() bytes of LDS.
 //
 // Segmented rows (SEG > 1, for grids whose rows are at most 64*VW/SEG cells):
 // each wavefront is cut into SEG segments of 64/SEG lanes and every segment
