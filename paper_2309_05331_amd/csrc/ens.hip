@@ -127,8 +127,12 @@ __device__ void ens_tile(EnsInst* I, char* smem, const EnsTile& t) {
   constexpr int VF = (int)(16 / sizeof(T));  // cells per 16-byte lane
   switch (I->seg) {
     case 2: return ens_tile_vw<T, KIND, VF, 2>(I, smem, t.y0, t.y1, t.z0, t.z1);
+    case 3: return ens_tile_vw<T, KIND, VF, 3>(I, smem, t.y0, t.y1, t.z0, t.z1);
     case 4: return ens_tile_vw<T, KIND, VF, 4>(I, smem, t.y0, t.y1, t.z0, t.z1);
+    case 5: return ens_tile_vw<T, KIND, VF, 5>(I, smem, t.y0, t.y1, t.z0, t.z1);
+    case 6: return ens_tile_vw<T, KIND, VF, 6>(I, smem, t.y0, t.y1, t.z0, t.z1);
     case 8: return ens_tile_vw<T, KIND, VF, 8>(I, smem, t.y0, t.y1, t.z0, t.z1);
+    case 10: return ens_tile_vw<T, KIND, VF, 10>(I, smem, t.y0, t.y1, t.z0, t.z1);
     case 16: return ens_tile_vw<T, KIND, VF, 16>(I, smem, t.y0, t.y1, t.z0, t.z1);
     default: break;
   }

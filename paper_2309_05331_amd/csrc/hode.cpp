@@ -522,16 +522,17 @@ void free_ensemble(hode_ctx* c) {
 }
 
 // Segments per wavefront of an ensemble instance's tiles: rows of at most
-// 32 16-byte lanes are packed one per segment of 64/seg lanes (seg 2 .. 16,
-// at least 4 lanes a segment); 1 = ordinary tiles.
+// 32 16-byte lanes are packed one per segment of 64/seg lanes (rounded down),
+// as many segments as hold a row (seg 2, 3, 4, 5, 6, 8, 10 or 16; at least 4
+// lanes a segment); 1 = ordinary tiles.
 int ens_seg_for(int dtype, int N, int vw) {
   const int vf = dtype == HODE_F32 ? 4 : 2;
   if (vw != vf || N % vw) return 1;
   const int nl = N / vw;
   if (nl > 32) return 1;
-  int sl = 4;
-  while (sl < nl) sl *= 2;
-  return 64 / sl;
+  for (int seg : {16, 10, 8, 6, 5, 4, 3})
+    if (64 / seg >= nl) return seg;
+  return 2;
 }
 
 // Rows one pass of the ensemble's stage tiles covers for instance i (kEnsNW

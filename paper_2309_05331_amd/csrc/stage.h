@@ -286,8 +286,10 @@ __host__ __device__ constexpr int tile_smem() {
 // tile_smem<T, VW, RY, NW, SEG>() bytes of LDS.
 //
 // Segmented rows (SEG > 1, for grids whose rows are at most 64*VW/SEG cells):
-// each wavefront is cut into SEG segments of 64/SEG lanes and every segment
-// of a register row holds one whole x-row, so register row r of a wave holds
+// each wavefront is cut into SEG segments of 64/SEG lanes (rounded down;
+// lanes left over load wrapped cells and write nothing, and SEG need not be a
+// power of two) and every segment of a register row holds one whole x-row, so
+// register row r of a wave holds
 // rows r*SEG .. r*SEG + SEG - 1 of its strip of RY*SEG rows, and the tile is
 // the full width of the grid (tx = 0).  x neighbours wrap inside the
 // segment; the rows above and below come from the neighbouring segment, or
@@ -300,9 +302,9 @@ template <typename T, int KIND, int RY, int VW, int SEG = 1, int NW = 4>
 __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* smem, int tx, int ty, int zbeg,
                            int zend) {
   constexpr KindDesc D = desc<KIND>();
-  static_assert(SEG == 1 || 64 % SEG == 0, "segments split the wavefront evenly");
+  static_assert(SEG >= 1 && 64 / SEG >= 4, "segments of at least four lanes");
   static_assert(NW >= 3, "three wavefronts carry the halo roles");
-  constexpr int SL = 64 / SEG;  // lanes per segment
+  constexpr int SL = 64 / SEG;  // lanes per segment (lanes SEG*SL .. 63 idle)
   constexpr int TX = 64 * VW;
   constexpr int TY = NW * RY * SEG;
   constexpr int TYX = SEG == 1 ? TY : 1;  // x-halo cells per column (ordinary tiles only)
@@ -593,7 +595,7 @@ __device__ void stage_tile(const GSLaunch& a, DevCtrl* __restrict__ c, char* sme
         fo[0].v[e] = Du * lu - uvv + F * ((T)1 - u);
         fo[1].v[e] = Dv * lv + uvv - Fk * v;
       }
-      const bool valid = xval && (y0 + r * SEG < N);
+      const bool valid = xval && (64 % SEG == 0 || seg < SEG) && (y0 + r * SEG < N);
       if (valid) {
         const int64_t g = zb + rowoff[r] + gx;
         if (D.out >= 0) {

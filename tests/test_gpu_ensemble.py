@@ -70,6 +70,27 @@ def test_ensemble_matches_single_runs_bitwise(dtype):
     ens.close()
 
 
+@pytest.mark.parametrize("dtype", [hode.F32, hode.F64])
+def test_ensemble_every_segment_count_bitwise(dtype):
+    # 16-byte lanes: rows of nl lanes are packed into as many segments of a
+    # wavefront as hold one (64/seg >= nl): seg 2, 3, 4, 5, 6, 8, 10 and 16,
+    # where seg 3, 5, 6 and 10 leave lanes of the wavefront over
+    vf = 4 if dtype == hode.F32 else 2
+    nls = [24, 18, 14, 12, 10, 8, 6, 4]  # -> seg 2, 3, 4, 5, 6, 8, 10, 16
+    edges = [vf * nl for nl in nls]
+    if dtype == hode.F64:
+        edges += [vf * 21, vf * 11, vf * 5]  # the widest rows of seg 3, 5 and 10
+    _, prms = _params(len(edges))
+    vws = [vf] * len(edges)
+    ens, ys, outs, stats = _run_ensemble(edges, prms, dtype, 12.0, 1e-5, vws=vws)
+    for i, N in enumerate(edges):
+        assert stats[i]["status"] == 0 and stats[i]["t"] == 12.0
+        ref, st = _single(ys[i], N, prms[i], 1, 12.0, 0.1, 1e-5)
+        assert (stats[i]["accepted"], stats[i]["rejected"]) == (st["accepted"], st["rejected"]), i
+        assert np.array_equal(outs[i], ref), (i, N)
+    ens.close()
+
+
 def test_ensemble_paused_launches_bitwise():
     # a few attempts per launch, so every instance is paused and resumed many
     # times (resumed instances skip stage 1: k1 is in the first-same-as-last
