@@ -390,7 +390,9 @@ int hode_ensemble_set_weights(hode_ctx *ctx, const double *w);
 int hode_ensemble_set_epoch(hode_ctx *ctx, int first, int rest);
 
 /* Polls a grid barrier of the persistent ensemble kernel makes before it
- * gives up (at least 1; default 2^30, about a minute).  A barrier that gives
+ * gives up (at least 1; default 2^24: each poll sleeps briefly and re-reads
+ * the barrier's device-scope counter, so a wait that no legitimate phase
+ * needs ends in seconds, not minutes).  A barrier that gives
  * up sets an error flag on which every workgroup leaves the kernel, and the
  * integration returns HODE_EHIP; the instances' states are then undefined
  * until they are initialised again.  This bounds every wait of the kernel

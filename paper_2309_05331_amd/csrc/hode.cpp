@@ -42,7 +42,7 @@ struct Ensemble {
   double kernel_ms_last = 0;  // summed launch durations of the last integration
   int launches_last = 0;
   int epoch_first = 0, epoch_len = 0;  // attempts per instance per launch (0: the whole integration)
-  int64_t barrier_polls = (int64_t)1 << 30;  // polls before a grid barrier gives up
+  int64_t barrier_polls = (int64_t)1 << 24;  // polls before a grid barrier gives up
   void* pool = nullptr;
   hode::EnsInst* d_inst = nullptr;
   hode::EnsTile* d_tiles = nullptr;
