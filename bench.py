@@ -481,7 +481,10 @@ def run_gs(wl, steps, warmup, ctrl_kind, weights=None, tile=None):
     if method in (hode.CASHKARP54, hode.FEHLBERG78):
         ctx.set_stepper(method)
     if tile is None:
-        ctx.autotune(method, 3)  # project autotuner: fastest (ry, zc, nw) per stage for this grid
+        # project autotuner: fastest (ry, zc, nw) per stage for this grid;
+        # with HODE_TUNE_CACHE set, a rerun of the same command (a profiled
+        # one) restores the tiles of the first run without timing
+        ctx.autotune_cached(method, 3)
     else:
         if len(tile) == 3:
             ctx.set_tile_waves(tile[2])
@@ -723,8 +726,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip timing the plain streaming copy beside the workload")
-    ap.add_argument("--tile", default="auto", help="auto (autotune) or RY,ZC[,NW]; ensemble: auto or default "
-                                                   "(the kernel's own plane-chunk sizing, no autotuning)")
+    ap.add_argument("--tile", default="auto", help="auto (autotune; through $HODE_TUNE_CACHE when set) or "
+                                                   "RY,ZC[,NW]; ensemble: auto or default (the kernel's own "
+                                                   "plane-chunk sizing, no autotuning)")
     ap.add_argument("--ens-epoch", type=int, default=0,
                     help="ensemble: attempts per launch (0: one launch for the whole integration)")
     ap.add_argument("--ab", type=float, default=None, metavar="T1",

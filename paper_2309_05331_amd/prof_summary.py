@@ -7,7 +7,8 @@
 kernel-trace: per-kernel dispatch count, mean/min/max duration over real
 dispatches only.  The integration loop launches graph chunks whose kernels
 return at once after the run has finished; those empty launches (shorter than
---min-us) are counted separately instead of diluting the mean.
+--min-us, or than 5% of the median of the kernel's longer launches) are counted
+separately instead of diluting the mean.
 
 counters: per-kernel mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch, real
 dispatches only, as above) from two rocprofv3 --pmc runs, scaled by the factors the reference copy kernel
@@ -41,17 +42,31 @@ def short(name: str) -> str:
     return (m.group(1) if m else name)[:60]
 
 
+EMPTY_FRAC = 0.05
+
+
+def _split_empty(durations, min_us):
+    """Flags of the dispatches that did work: at least min_us long and at
+    least EMPTY_FRAC of the median of the kernel's dispatches that are."""
+    longer = sorted(d for d in durations if d >= min_us)
+    cut = max(min_us, EMPTY_FRAC * longer[len(longer) // 2]) if longer else min_us
+    return [d >= cut for d in durations]
+
+
 def kernel_trace(db: str, min_us: float):
     con = sqlite3.connect(db)
     rows = list(con.execute("select name, start, end from kernels"))
+    per = collections.defaultdict(list)
+    for name, s, e in rows:
+        per[short(name)].append((e - s) / 1e3)
     agg = collections.defaultdict(list)
     empty = collections.Counter()
-    for name, s, e in rows:
-        us = (e - s) / 1e3
-        if us < min_us:
-            empty[short(name)] += 1
-        else:
-            agg[short(name)].append(us)
+    for k, ds in per.items():
+        for d, real in zip(ds, _split_empty(ds, min_us)):
+            if real:
+                agg[k].append(d)
+            else:
+                empty[k] += 1
     lines = ["%-40s %8s %12s %12s %12s %8s" % ("kernel", "calls", "mean_us", "min_us", "max_us", "empty")]
     for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
         lines.append("%-40s %8d %12.2f %12.2f %12.2f %8d" % (k, len(v), sum(v) / len(v), min(v), max(v), empty[k]))
@@ -63,15 +78,19 @@ def kernel_trace(db: str, min_us: float):
 
 def _load(path, cname, min_us=20.0):
     """Counter values per kernel over real dispatches only: graph-chunk
-    launches that return at once (shorter than min_us) are left out, as in
-    the kernel trace, so they do not dilute the per-dispatch means."""
-    agg = collections.defaultdict(list)
+    launches that return at once are left out by the kernel trace's rule, so
+    they do not dilute the per-dispatch means."""
+    per = collections.defaultdict(list)
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != cname:
             continue
-        if (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 < min_us:
-            continue
-        agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        per[short(r["Kernel_Name"])].append((us, float(r["Counter_Value"])))
+    agg = collections.defaultdict(list)
+    for k, rows in per.items():
+        for (_, v), real in zip(rows, _split_empty([us for us, _ in rows], min_us)):
+            if real:
+                agg[k].append(v)
     return agg
 
 

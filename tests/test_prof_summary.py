@@ -50,3 +50,22 @@ def test_counter_means_skip_empty_dispatches(tmp_path):
                              per="run")
     assert run["hbm_bytes_per_run"] == (9000 * 2 + 3 * 2048) * 1024
     json.dumps(rec)
+
+
+def test_early_exit_launch_above_the_absolute_cut_is_still_empty(tmp_path):
+    # a graph-chunk launch that returns at once can take a little over 20 us
+    # on a large grid; next to 1.5 ms launches of the same kernel it is
+    # empty all the same (below 5% of the median of the longer ones), while a
+    # kernel whose every launch is short keeps them all
+    fe, wr = tmp_path / "f.csv", tmp_path / "w.csv"
+    short_k = D6.replace("1, 4>", "2, 4>")
+    _csv(fe, "FETCH_SIZE", [(D6, 3000.0, 1500), (D6, 40.0, 20.5), (D6, 3000.0, 1490), (short_k, 100.0, 45),
+                            (short_k, 100.0, 44)])
+    _csv(wr, "WRITE_SIZE", [(D6, 2048.0, 1500), (D6, 0.0, 20.5), (D6, 2048.0, 1495), (short_k, 50.0, 45),
+                            (short_k, 50.0, 44)])
+    rec = ps.counters_record(str(fe), str(wr), 2.0, 1.0, "gs_stage D6 float ry=1 vw=4", "D6", "w", "stage.h")
+    assert rec["dispatches"] == 2 and rec["fetch_kib"] == 3000.0 and rec["write_kib"] == 2048.0
+    rec2 = ps.counters_record(str(fe), str(wr), 2.0, 1.0, "gs_stage D6 float ry=2 vw=4", "D6", "w", "stage.h")
+    assert rec2["dispatches"] == 2 and rec2["fetch_kib"] == 100.0
+    assert ps._split_empty([1500.0, 20.5, 1490.0, 3.0], 20.0) == [True, False, True, False]
+    assert ps._split_empty([45.0, 44.0, 21.0], 20.0) == [True, True, True]
