@@ -111,7 +111,7 @@ struct EnsInst {
   int64_t pause_at;   // the instance sits out the rest of a launch once ctrl.attempts reaches this
   int32_t vw;         // cells per lane for this instance's tiles
   int32_t k1_valid;   // k1 = f(y) is already in the first-same-as-last slot (resumed instance)
-  int32_t seg;        // > 1: segmented rows (vw = 16 bytes / element, one row per 64/seg lanes)
+  int32_t seg;        // > 1: segmented rows (vw = 16 bytes / element, one row per 64/seg lanes, rounded down)
   int32_t ntiles;     // tiles of this instance in a stage phase
   uint32_t last_done; // last-stage tiles of the current round finished (zero at launch)
   int32_t rows;       // rows of one tile pass (the row chunk of this instance's tiles)

@@ -279,19 +279,18 @@ __host__ __device__ constexpr int tile_smem() {
          2 * 2 * 2 * (SEG == 1 ? NW * RY : 1) * (int)sizeof(T);
 }
 
-// One stage over one tile: columns x0 .. x0 + 64*VW - 1, rows ty*4*RY ..
-// (ty+1)*4*RY - 1, planes zbeg .. zend - 1 of the grid described by `a`, with
-// step h, parity and first-same-as-last slot taken from the control block.
-// Called by all 64*NW threads of a workgroup; smem holds at least
-// tile_smem<T, VW, RY, NW, SEG>() bytes of LDS.
+// One stage over one tile: columns tx*64*VW .. (tx+1)*64*VW - 1, rows
+// ty*TY .. (ty+1)*TY - 1 (TY = NW*RY*SEG), planes zbeg .. zend - 1 of the
+// grid described by `a`, with step h, parity and first-same-as-last slot
+// taken from the control block.  Called by all 64*NW threads of a workgroup;
+// smem holds at least tile_smem<T, VW, RY, NW, SEG>() bytes of LDS.
 //
 // Segmented rows (SEG > 1, for grids whose rows are at most 64*VW/SEG cells):
-// each wavefront is cut into SEG segments of 64/SEG lanes (rounded down;
-// lanes left over load wrapped cells and write nothing, and SEG need not be a
-// power of two) and every segment of a register row holds one whole x-row, so
-// register row r of a wave holds
-// rows r*SEG .. r*SEG + SEG - 1 of its strip of RY*SEG rows, and the tile is
-// the full width of the grid (tx = 0).  x neighbours wrap inside the
+// each wavefront is cut into SEG segments of 64/SEG lanes (rounded down: SEG
+// need not divide 64, and the lanes left over load wrapped cells and write
+// nothing) and every segment of a register row holds one whole x-row, so
+// register row r of a wave holds rows r*SEG .. r*SEG + SEG - 1 of its strip
+// of RY*SEG rows, and the tile is the full width of the grid (tx = 0).  x neighbours wrap inside the
 // segment; the rows above and below come from the neighbouring segment, or
 // the last/first segment of the neighbouring register row, by cross-lane
 // permutes, and across strips from the LDS row slots as for the ordinary
